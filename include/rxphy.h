@@ -1,0 +1,177 @@
+/*
+ * librxphy: OFDM massive-MIMO uplink receiver on one MI355X (gfx950).
+ *
+ * The four forward calls are the DSP stages whose names (fft, csi, equal,
+ * demod) open the paper's preamble.  The paper defines the segment FFT
+ * (Section III-A1: a non-overlapping N_FFT-point FFT over consecutive I/Q
+ * segments, F = N_FFT bins per segment; Section IV-D: 32-bit floating-point
+ * I/Q, time-parallel across segments) and gives the other three stages only
+ * their names; they follow the textbook per-subcarrier uplink model
+ * y = H x + n (comb-pilot least squares, ZF / MMSE linear detection,
+ * max-log soft demapping).
+ *
+ * Conventions shared by every call
+ *  - All tensor pointers are DEVICE pointers to densely packed row-major
+ *    arrays; complex values are interleaved (re, im) float32 pairs ("c64").
+ *  - n_frames frames of the same shape are stacked on a leading [F] axis.
+ *  - The used-subcarrier index i in [0, n_sc) is the fastest-varying index of
+ *    every frequency-domain tensor.  Used subcarrier i sits on FFT bin
+ *    (i - n_sc/2) mod n_fft (a centred block, DC kept).
+ *  - Symbol 0 of every frame carries comb pilots: used subcarrier i carries
+ *    user (i mod K)'s pilot.  Symbols 1 .. n_sym-1 carry data (D = n_sym-1).
+ *  - Every call is asynchronous on `stream`, never synchronises and never
+ *    allocates device memory; the caller owns every buffer.  The first call
+ *    on a device uploads a 32 KiB twiddle table to it (a blocking copy).
+ *  - Shape, range and pointer errors return a status before any launch and
+ *    write nothing.  A failed launch returns RXPHY_EHIP.  Numerical trouble
+ *    never fails a call: it is reported per subcarrier in `flags`.
+ *  - Calls are thread-safe; calls that write the same buffers race.
+ */
+#ifndef RXPHY_H
+#define RXPHY_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RXPHY_OK = 0,
+  RXPHY_EINVAL = 1,        /* bad pointer, size or shape                        */
+  RXPHY_EUNSUPPORTED = 2,  /* shape outside the supported range (see below)     */
+  RXPHY_EWORKSPACE = 3,    /* workspace missing or smaller than required        */
+  RXPHY_EHIP = 4           /* a HIP runtime call or kernel launch failed        */
+} rxphy_status;
+
+typedef enum { RXPHY_ZF = 0, RXPHY_MMSE = 1 } rxphy_detector;
+
+typedef enum { RXPHY_FP32 = 0, RXPHY_BF16 = 1, RXPHY_FP16 = 2 } rxphy_precision;
+
+/* per-subcarrier flags written by rxphy_detect */
+enum {
+  RXPHY_FLAG_REFINED = 1u,    /* re-solved in FP64 (condition estimate above threshold)     */
+  RXPHY_FLAG_BREAKDOWN = 2u,  /* Cholesky pivot <= 0 or not finite, or MMSE gain mu <= 0    */
+  RXPHY_FLAG_NONFINITE = 4u   /* a channel or data input of this subcarrier was not finite  */
+};
+
+/* Shape of one frame.  Supported: 1 <= K <= 16, K <= M <= 64;
+ * n_fft in {512, 1024, 2048, 4096}; K <= n_sc <= n_fft; 2 <= n_sym <= 17;
+ * 0 <= cp_len <= n_fft; qam_bits in {2, 4, 6}; detector a rxphy_detector;
+ * n0 > 0 and finite: noise variance per resource element per antenna after
+ * the unscaled FFT. */
+typedef struct {
+  int32_t M;          /* base-station antennas                                   */
+  int32_t K;          /* users                                                   */
+  int32_t n_fft;      /* FFT size                                                */
+  int32_t n_sc;       /* used subcarriers                                        */
+  int32_t n_sym;      /* OFDM symbols per frame, symbol 0 = comb pilots          */
+  int32_t cp_len;     /* cyclic-prefix samples skipped before each symbol        */
+  int32_t qam_bits;   /* bits per QAM symbol: 2 (QPSK), 4 (16QAM), 6 (64QAM)      */
+  int32_t detector;   /* RXPHY_ZF or RXPHY_MMSE                                  */
+  float n0;           /* noise variance N0                                       */
+} rxphy_frame;
+
+/* fft stage (Section III-A1 segment FFT; `fft` macro of the preamble).
+ * For each frame f, antenna m, symbol s: skip cp_len samples, take the
+ * unscaled forward DFT X[k] = sum_n x[n] exp(-j 2 pi k n / n_fft) and keep
+ * the used bins:  yf[f][m][s][i] = X[(i - n_sc/2) mod n_fft].
+ *   x  : c64 [F][M][n_sym][cp_len + n_fft]   (read)
+ *   yf : c64 [F][M][n_sym][n_sc]             (written)                       */
+rxphy_status rxphy_fft(const rxphy_frame* frame, int32_t n_frames,
+                       const void* x, void* yf, hipStream_t stream);
+
+/* csi stage (`csi` macro): least-squares channel estimate from the comb
+ * pilots of symbol 0, held over each pilot group.  G = n_sc / K groups;
+ * subcarrier i belongs to group g(i) = min(i / K, G - 1) and
+ *   h[f][m][u][i] = yf[f][m][0][q] * conj(p[f][q]) / |p[f][q]|^2,  q = g(i) K + u.
+ * A zero pilot yields non-finite estimates (flagged later by rxphy_detect).
+ *   yf     : c64 [F][M][n_sym][n_sc]  (only symbol 0 is read)
+ *   pilots : c64 [F][n_sc]
+ *   h      : c64 [F][M][K][n_sc]      (written)                              */
+rxphy_status rxphy_csi(const rxphy_frame* frame, int32_t n_frames,
+                       const void* yf, const void* pilots, void* h, hipStream_t stream);
+
+/* equal stage (`equal` macro): per subcarrier, A = H^H H (ZF) or
+ * H^H H + n0 I (MMSE); A = L L^H (Cholesky); z_s = H^H y_s and
+ * x_hat_s = A^{-1} z_s for every data symbol s; d_u = [A^{-1}]_uu.
+ *   ZF  : xt = x_hat,            nu_u = n0 d_u
+ *   MMSE: mu_u = 1 - n0 d_u,     xt_u = x_hat_u / mu_u,   nu_u = (1 - mu_u) / mu_u
+ * (unbiased symbol estimates and their post-detection noise variances).
+ * Broken-down or non-finite subcarriers are erased: xt = 0, nu = +inf.
+ * precision RXPHY_FP32: FP32 products on MFMA and an FP32 factorisation.
+ * precision RXPHY_BF16 / RXPHY_FP16: the Gram and matched-filter products
+ * take BF16 / FP16 operands (rounded to nearest even from FP32) with FP32
+ * accumulation, the Cholesky runs in FP32, and every subcarrier whose
+ * condition estimate (max L_ii / min L_ii)^2 exceeds cond_threshold is
+ * re-solved in FP64 from the FP32 inputs with one step of iterative
+ * refinement (flag RXPHY_FLAG_REFINED).  cond_threshold is ignored for FP32.
+ *   h     : c64 [F][M][K][n_sc]
+ *   yf    : c64 [F][M][n_sym][n_sc]   (symbols 1 .. n_sym-1 are read)
+ *   xt    : c64 [F][K][n_sym-1][n_sc] (written)
+ *   nu    : f32 [F][K][n_sc]          (written)
+ *   flags : u8  [F][n_sc]             (written; may be NULL)
+ *   ws    : workspace of rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT,
+ *           precision) bytes (NULL when that is 0)                            */
+rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames,
+                          const void* h, const void* yf, void* xt, float* nu, uint8_t* flags,
+                          rxphy_precision precision, float cond_threshold,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* demod stage (`demod` macro): max-log LLRs over the Gray square-QAM set
+ * with unit average energy (bits b0 .. b_{Q-1}; b0, b2, b4 select the
+ * in-phase level, b1, b3, b5 the quadrature level):
+ *   llr_j = (min_{c: b_j = 1} |xt - c|^2 - min_{c: b_j = 0} |xt - c|^2) / nu,
+ * i.e. ln P(b_j = 0) / P(b_j = 1) under max-log; an erased stream (nu = +inf)
+ * gives 0.
+ *   xt  : c64 [F][K][n_sym-1][n_sc]
+ *   nu  : f32 [F][K][n_sc]
+ *   llr : f32 [F][K][n_sym-1][n_sc][qam_bits]  (written)                      */
+rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames,
+                         const void* xt, const float* nu, float* llr, hipStream_t stream);
+
+/* Intermediate results of the forward stages that rxphy_backward may reuse;
+ * any member may be NULL, in which case it is recomputed into the workspace. */
+typedef struct {
+  const void* yf;    /* c64 [F][M][n_sym][n_sc]  */
+  const void* h;     /* c64 [F][M][K][n_sc]      */
+} rxphy_saved;
+
+/* Adjoint of the whole forward map x -> llr (FP32 forward), for gradients
+ * with PyTorch's complex convention grad = dL/dRe + j dL/dIm.  Given
+ * dllr = dL/dllr it runs the demod adjoint (through the argmin points, ties
+ * to the lowest point index, and through nu), the detector adjoint
+ *   dL/dY = H V,  dL/dH = Y V^H - H (X_hat V^H + V X_hat^H + 2 A^{-1} diag(e) A^{-1})
+ * (V = A^{-1} dL/dx_hat; e the weights of d_u), the CSI adjoint (pilot-group
+ * sums times p / |p|^2 into symbol 0) and the inverse-direction unscaled DFT
+ * of the used-bin gradient into the samples (cyclic-prefix samples get 0).
+ * The Cholesky factors are always recomputed, never stored.
+ *   x      : c64 [F][M][n_sym][cp_len + n_fft]   pilots: c64 [F][n_sc]
+ *   saved  : may be NULL
+ *   dllr   : f32 [F][K][n_sym-1][n_sc][qam_bits]
+ *   dx     : c64 like x (written)
+ *   dh     : c64 [F][M][K][n_sc] gradient w.r.t. the channel estimate (written; may be NULL)
+ *   ws     : rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_BACKWARD, RXPHY_FP32) bytes */
+rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames,
+                            const void* x, const void* pilots, const rxphy_saved* saved,
+                            const float* dllr, void* dx, void* dh,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1 };
+
+/* Workspace bytes needed by rxphy_detect (which = RXPHY_WS_DETECT) or
+ * rxphy_backward (RXPHY_WS_BACKWARD); 0 if none or if the shape is invalid. */
+size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
+                             rxphy_precision precision);
+
+/* Human-readable name of a status, and thread-local detail of the last
+ * non-OK status returned on the calling thread (empty string if none). */
+const char* rxphy_status_string(rxphy_status status);
+const char* rxphy_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RXPHY_H */

@@ -1,0 +1,247 @@
+"""Python face of librxphy, the MI355X OFDM massive-MIMO uplink receiver.
+
+Argument marshalling only: every stage runs in the HIP kernels of
+``librxphy.so`` (built in-tree by ``__graft_entry__.build()``), launched on
+torch's current stream.  PyTorch provides device memory and streams.  There
+is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librxphy.so")
+
+ZF, MMSE = 0, 1
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+FLAG_REFINED, FLAG_BREAKDOWN, FLAG_NONFINITE = 1, 2, 4
+WS_DETECT, WS_BACKWARD = 0, 1
+
+
+class RxphyError(RuntimeError):
+    pass
+
+
+class _Frame(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("K", ctypes.c_int32), ("n_fft", ctypes.c_int32),
+                ("n_sc", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("cp_len", ctypes.c_int32),
+                ("qam_bits", ctypes.c_int32), ("detector", ctypes.c_int32), ("n0", ctypes.c_float)]
+
+
+class _Saved(ctypes.Structure):
+    _fields_ = [("yf", ctypes.c_void_p), ("h", ctypes.c_void_p)]
+
+
+@dataclasses.dataclass(frozen=True)
+class Frame:
+    """Shape of one frame (mirrors ``rxphy_frame``)."""
+    M: int
+    K: int
+    n_fft: int
+    n_sc: int
+    n_sym: int = 14
+    cp_len: int = 0
+    qam_bits: int = 2
+    detector: int = ZF
+    n0: float = 1.0
+
+    @property
+    def n_data(self) -> int:
+        return self.n_sym - 1
+
+    def c(self) -> _Frame:
+        return _Frame(self.M, self.K, self.n_fft, self.n_sc, self.n_sym, self.cp_len,
+                      self.qam_bits, self.detector, self.n0)
+
+    @staticmethod
+    def of(shape, detector=ZF, n0=1.0) -> "Frame":
+        """From any object with M, K, n_fft, n_sc, n_sym, cp_len, qam_bits."""
+        return Frame(shape.M, shape.K, shape.n_fft, shape.n_sc, shape.n_sym, shape.cp_len,
+                     shape.qam_bits, int(detector), float(n0))
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librxphy.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RxphyError("librxphy.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, F32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+    FR = ctypes.POINTER(_Frame)
+    sigs = {
+        "rxphy_fft": [FR, I32, P, P, P],
+        "rxphy_csi": [FR, I32, P, P, P, P],
+        "rxphy_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
+        "rxphy_demod": [FR, I32, P, P, P, P],
+        "rxphy_backward": [FR, I32, P, P, ctypes.POINTER(_Saved), P, P, P, P, SZ, P],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rxphy_workspace_bytes.argtypes = [FR, I32, I32, I32]
+    lib.rxphy_workspace_bytes.restype = SZ
+    lib.rxphy_status_string.argtypes = [ctypes.c_int]
+    lib.rxphy_status_string.restype = ctypes.c_char_p
+    lib.rxphy_last_error.argtypes = []
+    lib.rxphy_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        lib = load()
+        raise RxphyError("%s: %s (%s)" % (what, lib.rxphy_status_string(st).decode(),
+                                          lib.rxphy_last_error().decode()))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, name, shape, dtype):
+    if t.device.type != "cuda":
+        raise RxphyError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise RxphyError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise RxphyError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise RxphyError("%s must be contiguous" % name)
+
+
+def _nf(t):
+    return t.shape[0]
+
+
+def _empty(shape, dtype, like):
+    return torch.empty(shape, dtype=dtype, device=like.device)
+
+
+# ------------------------------------------------------------------- stages
+def fft(fr: Frame, x, yf=None):
+    """x c64 [F][M][n_sym][cp+N] -> yf c64 [F][M][n_sym][n_sc]."""
+    F = _nf(x)
+    _need(x, "x", (F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft), torch.complex64)
+    if yf is None:
+        yf = _empty((F, fr.M, fr.n_sym, fr.n_sc), torch.complex64, x)
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _check(load().rxphy_fft(ctypes.byref(fr.c()), F, _ptr(x), _ptr(yf), _stream()), "rxphy_fft")
+    return yf
+
+
+def csi(fr: Frame, yf, pilots, h=None):
+    """yf c64 [F][M][n_sym][n_sc], pilots c64 [F][n_sc] -> h c64 [F][M][K][n_sc]."""
+    F = _nf(yf)
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    if h is None:
+        h = _empty((F, fr.M, fr.K, fr.n_sc), torch.complex64, yf)
+    _need(h, "h", (F, fr.M, fr.K, fr.n_sc), torch.complex64)
+    _check(load().rxphy_csi(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots), _ptr(h), _stream()),
+           "rxphy_csi")
+    return h
+
+
+def workspace_bytes(fr: Frame, n_frames: int, which: int, precision: str = "fp32") -> int:
+    return int(load().rxphy_workspace_bytes(ctypes.byref(fr.c()), n_frames, which,
+                                            PRECISIONS[precision]))
+
+
+def detect(fr: Frame, h, yf, precision: str = "fp32", cond_threshold: float = 1e3,
+           xt=None, nu=None, flags=None, ws=None):
+    """-> (xt c64 [F][K][D][n_sc], nu f32 [F][K][n_sc], flags u8 [F][n_sc])."""
+    F = _nf(h)
+    D = fr.n_data
+    _need(h, "h", (F, fr.M, fr.K, fr.n_sc), torch.complex64)
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    xt = _empty((F, fr.K, D, fr.n_sc), torch.complex64, h) if xt is None else xt
+    nu = _empty((F, fr.K, fr.n_sc), torch.float32, h) if nu is None else nu
+    flags = _empty((F, fr.n_sc), torch.uint8, h) if flags is None else flags
+    _need(xt, "xt", (F, fr.K, D, fr.n_sc), torch.complex64)
+    _need(nu, "nu", (F, fr.K, fr.n_sc), torch.float32)
+    _need(flags, "flags", (F, fr.n_sc), torch.uint8)
+    need = workspace_bytes(fr, F, WS_DETECT, precision)
+    if need and ws is None:
+        ws = _empty((need,), torch.uint8, h)
+    _check(load().rxphy_detect(ctypes.byref(fr.c()), F, _ptr(h), _ptr(yf), _ptr(xt), _ptr(nu),
+                               _ptr(flags), PRECISIONS[precision], float(cond_threshold),
+                               _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+           "rxphy_detect")
+    return xt, nu, flags
+
+
+def demod(fr: Frame, xt, nu, llr=None):
+    """-> llr f32 [F][K][D][n_sc][qam_bits]."""
+    F = _nf(xt)
+    D = fr.n_data
+    _need(xt, "xt", (F, fr.K, D, fr.n_sc), torch.complex64)
+    _need(nu, "nu", (F, fr.K, fr.n_sc), torch.float32)
+    if llr is None:
+        llr = _empty((F, fr.K, D, fr.n_sc, fr.qam_bits), torch.float32, xt)
+    _need(llr, "llr", (F, fr.K, D, fr.n_sc, fr.qam_bits), torch.float32)
+    _check(load().rxphy_demod(ctypes.byref(fr.c()), F, _ptr(xt), _ptr(nu), _ptr(llr), _stream()),
+           "rxphy_demod")
+    return llr
+
+
+def forward(fr: Frame, x, pilots, precision: str = "fp32", cond_threshold: float = 1e3):
+    """All four stages; returns a dict of every intermediate."""
+    yf = fft(fr, x)
+    h = csi(fr, yf, pilots)
+    xt, nu, flags = detect(fr, h, yf, precision, cond_threshold)
+    llr = demod(fr, xt, nu)
+    return dict(yf=yf, h=h, xt=xt, nu=nu, flags=flags, llr=llr)
+
+
+def backward(fr: Frame, x, pilots, dllr, saved=None, want_dh: bool = False):
+    """Adjoint of forward(): dL/dllr -> dL/dx (and dL/dh if asked)."""
+    F = _nf(x)
+    _need(x, "x", (F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    _need(dllr, "dllr", (F, fr.K, fr.n_data, fr.n_sc, fr.qam_bits), torch.float32)
+    dx = torch.empty_like(x)
+    dh = _empty((F, fr.M, fr.K, fr.n_sc), torch.complex64, x) if want_dh else None
+    sv = None
+    if saved is not None:
+        sv = _Saved(saved["yf"].data_ptr() if saved.get("yf") is not None else None,
+                    saved["h"].data_ptr() if saved.get("h") is not None else None)
+    need = workspace_bytes(fr, F, WS_BACKWARD)
+    ws = _empty((max(need, 1),), torch.uint8, x)
+    _check(load().rxphy_backward(ctypes.byref(fr.c()), F, _ptr(x), _ptr(pilots),
+                                 ctypes.byref(sv) if sv is not None else None, _ptr(dllr),
+                                 _ptr(dx), _ptr(dh), _ptr(ws), need, _stream()),
+           "rxphy_backward")
+    return (dx, dh) if want_dh else dx
+
+
+class RxphyFunction(torch.autograd.Function):
+    """llr = RxphyFunction.apply(x, pilots, frame): the FP32 forward chain with
+    the hand-written adjoint of librxphy as its backward (gradient w.r.t. x)."""
+
+    @staticmethod
+    def forward(ctx, x, pilots, fr):
+        out = forward(fr, x.detach(), pilots)
+        ctx.fr = fr
+        ctx.save_for_backward(x.detach(), pilots, out["yf"], out["h"])
+        return out["llr"]
+
+    @staticmethod
+    def backward(ctx, dllr):
+        x, pilots, yf, h = ctx.saved_tensors
+        dx = backward(ctx.fr, x, pilots, dllr.contiguous(), saved=dict(yf=yf, h=h))
+        return dx, None, None

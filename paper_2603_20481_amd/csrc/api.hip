@@ -1,0 +1,160 @@
+// Host side of the C ABI: validation, error reporting, per-device tables and
+// the public entry points that dispatch to the stage launchers.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace rxphy {
+
+static thread_local char g_err[512];
+
+rxphy_status fail(rxphy_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+rxphy_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(RXPHY_EINVAL, "%s is NULL", name);
+  return RXPHY_OK;
+}
+
+rxphy_status check_frame(const rxphy_frame* fr, int32_t n_frames) {
+  if (!fr) return fail(RXPHY_EINVAL, "frame is NULL");
+  if (n_frames < 0) return fail(RXPHY_EINVAL, "n_frames = %d < 0", n_frames);
+  const rxphy_frame& f = *fr;
+  if (f.K < 1 || f.M < 1) return fail(RXPHY_EINVAL, "M = %d, K = %d must be >= 1", f.M, f.K);
+  if (f.K > 16) return fail(RXPHY_EUNSUPPORTED, "K = %d > 16", f.K);
+  if (f.M > 64) return fail(RXPHY_EUNSUPPORTED, "M = %d > 64", f.M);
+  if (f.K > f.M) return fail(RXPHY_EINVAL, "K = %d > M = %d", f.K, f.M);
+  if (f.n_fft != 512 && f.n_fft != 1024 && f.n_fft != 2048 && f.n_fft != 4096)
+    return fail(f.n_fft > 0 && (f.n_fft & (f.n_fft - 1)) == 0 ? RXPHY_EUNSUPPORTED : RXPHY_EINVAL,
+                "n_fft = %d not in {512, 1024, 2048, 4096}", f.n_fft);
+  if (f.n_sc < f.K || f.n_sc > f.n_fft)
+    return fail(RXPHY_EINVAL, "n_sc = %d outside [K, n_fft] = [%d, %d]", f.n_sc, f.K, f.n_fft);
+  if (f.n_sym < 2) return fail(RXPHY_EINVAL, "n_sym = %d < 2", f.n_sym);
+  if (f.n_sym > 17) return fail(RXPHY_EUNSUPPORTED, "n_sym = %d > 17", f.n_sym);
+  if (f.cp_len < 0 || f.cp_len > f.n_fft)
+    return fail(RXPHY_EINVAL, "cp_len = %d outside [0, n_fft]", f.cp_len);
+  if (f.qam_bits != 2 && f.qam_bits != 4 && f.qam_bits != 6)
+    return fail(RXPHY_EINVAL, "qam_bits = %d not in {2, 4, 6}", f.qam_bits);
+  if (f.detector != RXPHY_ZF && f.detector != RXPHY_MMSE)
+    return fail(RXPHY_EINVAL, "detector = %d", f.detector);
+  if (!(std::isfinite(f.n0) && f.n0 > 0.0f)) return fail(RXPHY_EINVAL, "n0 = %g must be finite and > 0", f.n0);
+  return RXPHY_OK;
+}
+
+// Twiddle table exp(-j 2 pi t / 4096), t = 0..4095, computed in FP64 and
+// rounded once to FP32; every FFT size indexes it with a stride.
+static __device__ float2 g_tw4096[4096];
+
+rxphy_status ensure_device_tables(const float2** tw) {
+  static std::mutex mu;
+  static std::vector<const float2*> done;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RXPHY_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, nullptr);
+  if (!done[dev]) {
+    std::vector<float2> h(4096);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int t = 0; t < 4096; ++t) {
+      double a = -two_pi * (double)t / 4096.0;
+      h[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_tw4096), h.data(), sizeof(float2) * 4096, 0,
+                                     hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(RXPHY_EHIP, "twiddle upload: %s", hipGetErrorString(e));
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_tw4096));
+    if (e != hipSuccess) return fail(RXPHY_EHIP, "twiddle address: %s", hipGetErrorString(e));
+    done[dev] = (const float2*)p;
+  }
+  *tw = done[dev];
+  return RXPHY_OK;
+}
+
+}  // namespace rxphy
+
+using namespace rxphy;
+
+extern "C" {
+
+const char* rxphy_status_string(rxphy_status st) {
+  switch (st) {
+    case RXPHY_OK: return "RXPHY_OK";
+    case RXPHY_EINVAL: return "RXPHY_EINVAL";
+    case RXPHY_EUNSUPPORTED: return "RXPHY_EUNSUPPORTED";
+    case RXPHY_EWORKSPACE: return "RXPHY_EWORKSPACE";
+    case RXPHY_EHIP: return "RXPHY_EHIP";
+  }
+  return "RXPHY_UNKNOWN";
+}
+
+const char* rxphy_last_error(void) { return g_err; }
+
+rxphy_status rxphy_fft(const rxphy_frame* frame, int32_t n_frames, const void* x, void* yf,
+                       hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(x, "x")) || (st = check_ptr(yf, "yf"))) return st;
+  int64_t n_tr = (int64_t)n_frames * frame->M * frame->n_sym;
+  return launch_fft(*frame, n_tr, (const float2*)x, (float2*)yf, false, stream);
+}
+
+rxphy_status rxphy_csi(const rxphy_frame* frame, int32_t n_frames, const void* yf,
+                       const void* pilots, void* h, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(h, "h")))
+    return st;
+  return launch_csi(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (float2*)h, stream);
+}
+
+rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames, const void* h,
+                          const void* yf, void* xt, float* nu, uint8_t* flags,
+                          rxphy_precision precision, float cond_threshold, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
+    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
+    return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
+  size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT, precision);
+  if (need && (!ws || ws_bytes < need))
+    return fail(RXPHY_EWORKSPACE, "detect needs %zu workspace bytes, got %zu", need, ws_bytes);
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(h, "h")) || (st = check_ptr(yf, "yf")) || (st = check_ptr(xt, "xt")) ||
+      (st = check_ptr(nu, "nu")))
+    return st;
+  return launch_detect(*frame, n_frames, (const float2*)h, (const float2*)yf, (float2*)xt, nu,
+                       flags, precision, cond_threshold, stream);
+}
+
+rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames, const void* xt,
+                         const float* nu, float* llr, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(xt, "xt")) || (st = check_ptr(nu, "nu")) || (st = check_ptr(llr, "llr")))
+    return st;
+  return launch_demod(*frame, n_frames, (const float2*)xt, nu, llr, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Internal helpers shared by the librxphy translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/rxphy.h"
+
+namespace rxphy {
+
+// ------------------------------------------------------------------ host side
+// Records a message for rxphy_last_error() and returns `st`.
+rxphy_status fail(rxphy_status st, const char* fmt, ...);
+void clear_error();
+
+// Shape validation shared by every entry point.
+rxphy_status check_frame(const rxphy_frame* fr, int32_t n_frames);
+rxphy_status check_ptr(const void* p, const char* name);
+
+// Per-device one-time set-up (twiddle table upload).  Returns the table.
+rxphy_status ensure_device_tables(const float2** tw4096);
+
+inline rxphy_status launch_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RXPHY_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return RXPHY_OK;
+}
+
+// Launchers implemented per stage (device pointers, validated shapes).
+rxphy_status launch_fft(const rxphy_frame& fr, int64_t n_tr, const float2* x, float2* out,
+                        bool inverse, hipStream_t s);
+rxphy_status launch_csi(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                        float2* h, hipStream_t s);
+rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
+                           float2* xt, float* nu, uint8_t* flags, rxphy_precision prec,
+                           float thr, hipStream_t s);
+rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, const float* nu,
+                          float* llr, hipStream_t s);
+
+inline int64_t sym_len(const rxphy_frame& f) { return (int64_t)f.cp_len + f.n_fft; }
+
+// ---------------------------------------------------------------- device side
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+}  // namespace rxphy

@@ -1,0 +1,110 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rxphy.h")
+LIB = os.path.join(ROOT, "paper_2603_20481_amd", "librxphy.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rxphy_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librxphy.so not built; run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_stage_calls():
+    names = declared_functions()
+    for n in ("rxphy_fft", "rxphy_csi", "rxphy_detect", "rxphy_demod", "rxphy_backward",
+              "rxphy_workspace_bytes", "rxphy_status_string", "rxphy_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("K", ctypes.c_int32), ("n_fft", ctypes.c_int32),
+                ("n_sc", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("cp_len", ctypes.c_int32),
+                ("qam_bits", ctypes.c_int32), ("detector", ctypes.c_int32), ("n0", ctypes.c_float)]
+
+
+GOOD = dict(M=64, K=16, n_fft=2048, n_sc=1200, n_sym=14, cp_len=0, qam_bits=4, detector=0, n0=1.0)
+
+
+def frame(**kw):
+    d = dict(GOOD)
+    d.update(kw)
+    return Frame(**d)
+
+
+BAD = [
+    (dict(K=0), 1), (dict(K=17), 2), (dict(M=65), 2), (dict(K=9, M=8), 1),
+    (dict(n_fft=1000), 1), (dict(n_fft=256), 2), (dict(n_fft=8192), 2),
+    (dict(n_sc=15), 1), (dict(n_sc=2049), 1), (dict(n_sym=1), 1), (dict(n_sym=18), 2),
+    (dict(cp_len=-1), 1), (dict(cp_len=2049), 1), (dict(qam_bits=3), 1), (dict(detector=2), 1),
+    (dict(n0=0.0), 1), (dict(n0=float("nan")), 1), (dict(n0=float("inf")), 1),
+]
+
+
+@pytest.mark.parametrize("kw,code", BAD)
+def test_bad_shapes_rejected_before_launch(lib, kw, code):
+    fr = frame(**kw)
+    p = ctypes.c_void_p(16)      # never dereferenced: validation fails first
+    lib.rxphy_fft.restype = ctypes.c_int
+    assert lib.rxphy_fft(ctypes.byref(fr), 1, p, p, None) == code
+    lib.rxphy_last_error.restype = ctypes.c_char_p
+    assert lib.rxphy_last_error()  # a message was recorded
+    lib.rxphy_demod.restype = ctypes.c_int
+    assert lib.rxphy_demod(ctypes.byref(fr), 1, p, p, p, None) == code
+
+
+def test_null_pointers_and_counts(lib):
+    fr = frame()
+    p = ctypes.c_void_p(16)
+    assert lib.rxphy_fft(None, 1, p, p, None) == 1
+    assert lib.rxphy_fft(ctypes.byref(fr), -1, p, p, None) == 1
+    assert lib.rxphy_fft(ctypes.byref(fr), 1, None, p, None) == 1
+    assert lib.rxphy_csi(ctypes.byref(fr), 1, p, None, p, None) == 1
+    # zero frames is a valid no-op that touches nothing
+    assert lib.rxphy_fft(ctypes.byref(fr), 0, None, None, None) == 0
+    assert lib.rxphy_demod(ctypes.byref(fr), 0, None, None, None, None) == 0
+
+
+def test_detect_argument_checks(lib):
+    fr = frame()
+    p = ctypes.c_void_p(16)
+    lib.rxphy_detect.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32] + [ctypes.c_void_p] * 5 + \
+        [ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.rxphy_detect.restype = ctypes.c_int
+    assert lib.rxphy_detect(ctypes.byref(fr), 1, p, p, p, p, p, 7, 1e3, None, 0, None) == 1
+    assert lib.rxphy_detect(ctypes.byref(fr), 1, p, p, p, p, p, 1, -1.0, None, 0, None) == 1
+    assert lib.rxphy_detect(ctypes.byref(fr), 1, None, p, p, p, p, 0, 1e3, None, 0, None) == 1
+    assert lib.rxphy_detect(ctypes.byref(fr), 0, None, None, None, None, None, 0, 1e3, None, 0, None) == 0
+
+
+def test_status_strings(lib):
+    lib.rxphy_status_string.restype = ctypes.c_char_p
+    assert lib.rxphy_status_string(0) == b"RXPHY_OK"
+    assert lib.rxphy_status_string(3) == b"RXPHY_EWORKSPACE"
+
+
+def test_python_binding_refuses_without_library(tmp_path):
+    import paper_2603_20481_amd as rx
+    with pytest.raises(rx.RxphyError):
+        rx._lib = None
+        rx.load(str(tmp_path / "missing.so"))
+    rx._lib = None

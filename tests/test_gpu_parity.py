@@ -1,0 +1,198 @@
+"""GPU parity: every stage of librxphy against the FP64 oracle on the same
+seeded inputs (per stage, with the GPU's own upstream output as the common
+input, and for the whole chain from the complex64 samples)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity_util import evm_rel, hard_bits_outside_guard, llr_rel, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def frames_to_device(frs):
+    x = dev(np.stack([f.x for f in frs]))
+    p = dev(np.stack([f.pilots for f in frs]))
+    return x, p
+
+
+# ------------------------------------------------------------------ stage: fft
+@pytest.mark.parametrize("N,n_sc,cp", [(512, 300, 0), (1024, 601, 7), (2048, 1200, 0),
+                                       (4096, 3276, 0), (4096, 4096, 288), (512, 17, 36)])
+def test_fft_stage(rx, N, n_sc, cp):
+    say("fft", N, n_sc, cp)
+    rng = np.random.default_rng(N + n_sc)
+    M, S, F = 3, 4, 2
+    x = (rng.standard_normal((F, M, S, cp + N)) + 1j * rng.standard_normal((F, M, S, cp + N))).astype(np.complex64)
+    fr = rx.Frame(M, 1, N, n_sc, S, cp, 2)
+    yf = host(rx.fft(fr, dev(x)))
+    torch.cuda.synchronize()
+    ref = O.fft_stage(x, N, n_sc, cp)
+    e = rel_rms(yf, ref)
+    say("  rel rms", e, "max abs", float(np.max(np.abs(yf - ref))))
+    assert e < 2e-6
+    assert np.max(np.abs(yf - ref)) < 1e-5 * np.max(np.abs(ref))
+
+
+def test_fft_impulse_and_tone(rx):
+    N, n_sc = 2048, 1200
+    x = np.zeros((1, 1, 2, N), np.complex64)
+    x[0, 0, 0, 5] = 1.0
+    i0 = 77
+    k0 = (i0 - n_sc // 2) % N
+    x[0, 0, 1] = np.exp(2j * np.pi * k0 * np.arange(N) / N).astype(np.complex64)
+    yf = host(rx.fft(rx.Frame(1, 1, N, n_sc, 2, 0, 2), dev(x)))
+    k = (np.arange(n_sc) - n_sc // 2) % N
+    np.testing.assert_allclose(yf[0, 0, 0], np.exp(-2j * np.pi * k * 5 / N), atol=2e-6)
+    ref = np.zeros(n_sc, complex)
+    ref[i0] = N
+    np.testing.assert_allclose(yf[0, 0, 1], ref, atol=2e-3)
+
+
+# ------------------------------------------------------------------ stage: csi
+@pytest.mark.parametrize("M,K,n_sc", [(8, 2, 300), (64, 16, 1200), (12, 5, 301), (4, 1, 40), (16, 16, 99)])
+def test_csi_stage(rx, M, K, n_sc):
+    say("csi", M, K, n_sc)
+    rng = np.random.default_rng(M * K + n_sc)
+    F, S = 2, 3
+    yf = (rng.standard_normal((F, M, S, n_sc)) + 1j * rng.standard_normal((F, M, S, n_sc))).astype(np.complex64)
+    p = synth.qam_map(rng.integers(0, 2, (F, n_sc, 2)), 2).astype(np.complex64) * np.float32(1.3)
+    fr = rx.Frame(M, K, 512, n_sc, S, 0, 2)
+    h = host(rx.csi(fr, dev(yf), dev(p)))
+    for f in range(F):
+        ref = O.csi_stage(yf[f, :, 0, :], p[f], K)
+        assert rel_rms(h[f], ref) < 1e-6
+
+
+# --------------------------------------------------------------- stage: detect
+DETECT_CASES = [
+    # M, K, n_sc, n_sym, detector, snr range
+    (8, 2, 300, 14, O.ZF, (20, 20)),
+    (64, 16, 1200, 14, O.ZF, (10, 30)),
+    (64, 16, 1200, 14, O.MMSE, (10, 30)),
+    (12, 5, 77, 14, O.MMSE, (0, 15)),      # M not a multiple of 8, ragged tile
+    (16, 16, 50, 14, O.ZF, (25, 25)),      # K = M
+    (8, 1, 33, 5, O.ZF, (5, 5)),           # one user, short frame
+    (64, 16, 41, 17, O.MMSE, (10, 30)),    # 16 data symbols
+    (3, 3, 20, 2, O.MMSE, (10, 10)),       # tiny M, one data symbol
+]
+
+
+@pytest.mark.parametrize("M,K,n_sc,S,det,snr", DETECT_CASES)
+def test_detect_stage(rx, M, K, n_sc, S, det, snr):
+    say("detect", M, K, n_sc, S, det, snr)
+    N = 512 if n_sc <= 512 else 2048
+    sh = synth.Shape(M, K, N, n_sc, S, 0, 4)
+    frs = [synth.make_frame(11, f, shape=sh, snr=snr) for f in range(2)]
+    x, p = frames_to_device(frs)
+    fr = rx.Frame.of(sh, det, 1.0)
+    yf = rx.fft(fr, x)
+    h = rx.csi(fr, yf, p)
+    xt, nu, fl = rx.detect(fr, h, yf)
+    torch.cuda.synchronize()
+    yf, h, xt, nu, fl = host(yf), host(h), host(xt), host(nu), host(fl)
+    for f in range(2):
+        ref = O.detect_stage(h[f], yf[f, :, 1:, :], 1.0, det, want_kappa=True)
+        good = (ref["kappa"] <= 1e3) & (ref["flags"] == 0)
+        assert np.array_equal(fl[f], ref["flags"])
+        e = evm_rel(xt[f], ref["xt"], good)
+        en = rel_rms(nu[f][:, good], ref["nu"][:, good])
+        say("  frame", f, "evm_rel", e, "nu_rel", en, "kappa max", float(ref["kappa"].max()))
+        assert e < 1e-4
+        assert en < 1e-4
+
+
+def test_detect_flags_and_erasures(rx):
+    M, K, n_sc, S = 8, 3, 40, 4
+    rng = np.random.default_rng(3)
+    h = (rng.standard_normal((1, M, K, n_sc)) + 1j * rng.standard_normal((1, M, K, n_sc))).astype(np.complex64)
+    yf = (rng.standard_normal((1, M, S, n_sc)) + 1j * rng.standard_normal((1, M, S, n_sc))).astype(np.complex64)
+    h[0, :, 1, 5] = 0          # zero column -> breakdown (ZF) / mu = 0 (MMSE)
+    h[0, 2, 0, 9] = np.nan     # non-finite channel
+    yf[0, 4, 2, 20] = np.inf   # non-finite data
+    for det in (O.ZF, O.MMSE):
+        fr = rx.Frame(M, K, 512, n_sc, S, 0, 2, det, 1.0)
+        xt, nu, fl = (host(t) for t in rx.detect(fr, dev(h), dev(yf)))
+        ref = O.detect_stage(h[0], yf[0, :, 1:, :], 1.0, det)
+        assert np.array_equal(fl[0], ref["flags"]), (fl[0], ref["flags"])
+        bad = ref["flags"] != 0
+        assert np.all(xt[0][..., bad] == 0) and np.all(np.isinf(nu[0][:, bad]))
+        llr = host(rx.demod(fr, dev(xt), dev(nu)))
+        assert np.all(llr[0][:, :, bad] == 0)
+
+
+# ---------------------------------------------------------------- stage: demod
+@pytest.mark.parametrize("q", [2, 4, 6])
+def test_demod_stage(rx, q):
+    say("demod", q)
+    rng = np.random.default_rng(q)
+    F, K, D, n_sc = 2, 3, 5, 333
+    xt = (rng.standard_normal((F, K, D, n_sc)) + 1j * rng.standard_normal((F, K, D, n_sc))).astype(np.complex64)
+    nu = rng.uniform(0.01, 3.0, (F, K, n_sc)).astype(np.float32)
+    nu[0, 1, 7] = np.inf
+    fr = rx.Frame(8, K, 512, n_sc, D + 1, 0, q)
+    llr = host(rx.demod(fr, dev(xt), dev(nu)))
+    for f in range(F):
+        ref = O.demod_stage(xt[f], nu[f], q)
+        assert llr_rel(llr[f], ref) < 1e-5
+        mism, band = hard_bits_outside_guard(llr[f], ref)
+        assert mism == 0
+
+
+# ------------------------------------------------------------------ full chain
+CHAIN_CASES = [(1, O.ZF, 1), (2, O.ZF, 2), (2, O.MMSE, 2), (3, O.ZF, 1)]
+
+
+@pytest.mark.parametrize("cfg,det,nfr", CHAIN_CASES)
+def test_chain_vs_oracle(rx, cfg, det, nfr):
+    say("chain", cfg, det, nfr)
+    frs = synth.make_frames(cfg, nfr)
+    sh = frs[0].shape
+    x, p = frames_to_device(frs)
+    fr = rx.Frame.of(sh, det, 1.0)
+    out = {k: host(v) for k, v in rx.forward(fr, x, p).items()}
+    for f, fo in enumerate(frs):
+        ref = O.forward(fo.x, fo.pilots, sh, 1.0, det, want_kappa=True)
+        good = (ref["kappa"] <= 1e3) & (ref["flags"] == 0)
+        e = evm_rel(out["xt"][f], ref["xt"], good)
+        l = llr_rel(out["llr"][f], ref["llr"])
+        mism, band = hard_bits_outside_guard(out["llr"][f], ref["llr"])
+        ber = float(np.mean(O.hard_bits(out["llr"][f]) != fo.bits))
+        say("  frame", f, "evm_rel", e, "llr_rel", l, "hard mismatches", mism, "in band", band, "BER", ber)
+        assert np.array_equal(out["flags"][f], ref["flags"])
+        assert e < 1e-4
+        assert l < 1e-3
+        assert mism == 0
+
+
+def test_deterministic(rx):
+    frs = synth.make_frames(2, 1)
+    x, p = frames_to_device(frs)
+    fr = rx.Frame.of(frs[0].shape, O.MMSE, 1.0)
+    a = rx.forward(fr, x, p)
+    b = rx.forward(fr, x, p)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_zero_frames_and_shape_errors(rx):
+    fr = rx.Frame(8, 2, 512, 300, 14, 0, 2)
+    x = torch.empty((0, 8, 14, 512), dtype=torch.complex64, device="cuda")
+    assert rx.fft(fr, x).shape == (0, 8, 14, 300)
+    with pytest.raises(rx.RxphyError):
+        rx.fft(fr, torch.empty((1, 8, 14, 500), dtype=torch.complex64, device="cuda"))
