@@ -155,28 +155,41 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   const bool in_range = ic < n_sc;
   const int u = l & 15, kq = l >> 4;
 
-  for (int m0 = 0; m0 < M; m0 += MC) {
+  // chunk loads go to registers first (all issued back to back) and the next
+  // chunk is prefetched while the current one feeds the MFMAs
+  float2 hv[8], yv[8];
+  auto load_chunk = [&](int m0) {
     const int mc = min(MC, M - m0);
     const int rh = mc * K, ry = mc * D;
-    // stage H rows (antenna m0 + r / K, user r % K) and data rows (antenna, symbol)
-    for (int r = tid >> 4; r < rh; r += 16) {
-      float2 v = make_float2(0.f, 0.f);
-      if (in_range) {
-        v = Hf[(int64_t)(m0 * K + r) * n_sc + ic];
-        if (!finite2(v)) nonfin[c16] = 1;
-      }
-      Hs[r * PITCH + c16] = v;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int r = (tid >> 4) + 16 * it;
+      hv[it] = (in_range && r < rh) ? Hf[(int64_t)(m0 * K + r) * n_sc + ic] : make_float2(0.f, 0.f);
     }
-    for (int r = tid >> 4; r < ry; r += 16) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int r = (tid >> 4) + 16 * it;
       const int ml = r / D, s = r - ml * D;
-      float2 v = make_float2(0.f, 0.f);
-      if (in_range) {
-        v = Yff[(int64_t)((m0 + ml) * S + 1 + s) * n_sc + ic];
-        if (!finite2(v)) nonfin[c16] = 1;
-      }
-      Ys[r * PITCH + c16] = v;
+      yv[it] = (in_range && r < ry) ? Yff[(int64_t)((m0 + ml) * S + 1 + s) * n_sc + ic]
+                                    : make_float2(0.f, 0.f);
     }
+  };
+  load_chunk(0);
+  for (int m0 = 0; m0 < M; m0 += MC) {
+    const int mc = min(MC, M - m0);
+    bool bad = false;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int r = (tid >> 4) + 16 * it;
+      bad |= !finite2(hv[it]) || !finite2(yv[it]);
+      if (r < ROWS) {
+        Hs[r * PITCH + c16] = hv[it];
+        Ys[r * PITCH + c16] = yv[it];
+      }
+    }
+    if (bad) nonfin[c16] = 1;
     __syncthreads();
+    if (m0 + MC < M) load_chunk(m0 + MC);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if (4 * a < mc) {
@@ -264,8 +277,9 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   if (row < K) {
     float nv;
     if (mmse) {
-      const float m = 1.0f - n0 * dl;
-      nv = (1.0f - m) / m;
+      // (1 - mu) / mu with 1 - mu = N0 d formed directly: subtracting mu from 1
+      // would cancel most digits for strong users (mu close to 1)
+      nv = n0 * dl / (1.0f - n0 * dl);
     } else {
       nv = n0 * dl;
     }

@@ -86,22 +86,17 @@ struct Geom {
   static constexpr int NMID = REM == 1 ? N8 - 2 : N8 - 1;  // LDS-to-LDS radix-8 passes
 };
 
-template <int N, bool INV>
-__global__ void __launch_bounds__(Geom<N>::WG)
-fft_kernel(const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
-           int64_t n_tr, int sym_len, int cp, int n_sc) {
-  using G = Geom<N>;
-  constexpr int T = G::T;
-  __shared__ float2 lds[G::TPW * G::LDSN];
-  const int sub = threadIdx.x / T;
-  const int tid = threadIdx.x - sub * T;
-  const int64_t tr = (int64_t)blockIdx.x * G::TPW + sub;
-  const bool active = tr < n_tr;
-  float2* buf = lds + sub * G::LDSN;
-  const int half = n_sc >> 1;
+// Each workgroup runs PER_WG transforms per transform slot in a loop: the
+// twiddles a thread needs are the same for every transform, so they are
+// loaded into registers once, and the next segment's input is fetched while
+// the current one moves through LDS.
+constexpr int PER_WG = 8;
 
-  // pass 0: radix 8, Ns = 1 (no twiddles); input element tid + r T
-  float2 v[8];
+template <int N, bool INV>
+__device__ __forceinline__ void load_input(const float2* __restrict__ in, int64_t tr, bool active,
+                                           int tid, int sym_len, int cp, int n_sc, float2* v) {
+  constexpr int T = N / 8;
+  const int half = n_sc >> 1;
   if (!INV) {
     const float2* src = in + (active ? tr : 0) * sym_len + cp;
 #pragma unroll
@@ -110,65 +105,112 @@ fft_kernel(const float2* __restrict__ in, float2* __restrict__ out, const float2
     const float2* src = in + (active ? tr : 0) * n_sc;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      int i = (tid + r * T + half) & (N - 1);
+      const int i = (tid + r * T + half) & (N - 1);
       v[r] = (active && i < n_sc) ? src[i] : make_float2(0.f, 0.f);
     }
   }
-  dft8<INV>(v);
-#pragma unroll
-  for (int r = 0; r < 8; ++r) buf[padi(tid * 8 + r)] = v[r];
-  __syncthreads();
+}
 
-  // middle radix-8 passes, Ns = 8, 64, ...
-  int Ns = 8;
-#pragma unroll
-  for (int p = 0; p < G::NMID; ++p) {
-#pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = buf[padi(tid + r * (N / 8))];
-    const int k = tid & (Ns - 1);
-    const int step = 4096 / (Ns * 8);
-#pragma unroll
-    for (int r = 1; r < 8; ++r) v[r] = twid<INV>(v[r], tw[r * k * step]);
-    dft8<INV>(v);
-    __syncthreads();
-    const int o = (tid - k) * 8 + k;  // (tid / Ns) * Ns * 8 + k
-#pragma unroll
-    for (int r = 0; r < 8; ++r) buf[padi(o + r * Ns)] = v[r];
-    __syncthreads();
-    Ns *= 8;
-  }
-
-  // last pass: radix R, Ns = N / R; each thread does 8 / R butterflies j
+template <int N, bool INV>
+__global__ void __launch_bounds__(Geom<N>::WG)
+fft_kernel(const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
+           int64_t n_tr, int sym_len, int cp, int n_sc) {
+  using G = Geom<N>;
+  constexpr int T = G::T;
   constexpr int R = G::LAST_R;
   constexpr int NS = N / R;
-  const int step = 4096 / N;
+  constexpr int NMID = G::NMID;
+  __shared__ float2 lds[G::TPW * G::LDSN];
+  const int sub = threadIdx.x / T;
+  const int tid = threadIdx.x - sub * T;
+  float2* buf = lds + sub * G::LDSN;
+  const int half = n_sc >> 1;
+
+  // twiddles of this thread: middle passes (Ns = 8, 64, ...) and the last pass
+  float2 twm[NMID > 0 ? NMID : 1][7];
+  float2 twl[8 / R][R - 1];
+  {
+    int Ns = 8;
 #pragma unroll
-  for (int b = 0; b < 8 / R; ++b) {
-    const int j = tid + b * T;
-    float2 w[R];
+    for (int p = 0; p < NMID; ++p) {
+      const int k = tid & (Ns - 1);
+      const int step = 4096 / (Ns * 8);
 #pragma unroll
-    for (int r = 0; r < R; ++r) w[r] = buf[padi(j + r * NS)];
+      for (int r = 1; r < 8; ++r) twm[p][r - 1] = tw[r * k * step];
+      Ns *= 8;
+    }
 #pragma unroll
-    for (int r = 1; r < R; ++r) w[r] = twid<INV>(w[r], tw[r * j * step]);
-    dftR<R, INV>(w);
-    if (active) {
-      if (!INV) {
-        float2* dst = out + tr * n_sc;
+    for (int b = 0; b < 8 / R; ++b) {
+      const int j = tid + b * T;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          int i = (j + r * NS + half) & (N - 1);
-          if (i < n_sc) dst[i] = w[r];
-        }
-      } else {
-        float2* dst = out + tr * sym_len + cp;
-#pragma unroll
-        for (int r = 0; r < R; ++r) dst[j + r * NS] = w[r];
-      }
+      for (int r = 1; r < R; ++r) twl[b][r - 1] = tw[r * j * (4096 / N)];
     }
   }
-  if (INV && active) {
-    float2* dst = out + tr * sym_len;
-    for (int n = tid; n < cp; n += T) dst[n] = make_float2(0.f, 0.f);
+
+  const int64_t base = (int64_t)blockIdx.x * G::TPW * PER_WG + sub;
+  float2 v[8], vn[8];
+  load_input<N, INV>(in, base, base < n_tr, tid, sym_len, cp, n_sc, v);
+  for (int it = 0; it < PER_WG; ++it) {
+    const int64_t tr = base + (int64_t)it * G::TPW;
+    const bool active = tr < n_tr;
+    // pass 0: radix 8, Ns = 1 (no twiddles); input element tid + r T
+    dft8<INV>(v);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[padi(tid * 8 + r)] = v[r];
+    __syncthreads();
+    if (it + 1 < PER_WG) {
+      const int64_t tn = tr + G::TPW;
+      load_input<N, INV>(in, tn, tn < n_tr, tid, sym_len, cp, n_sc, vn);
+    }
+    // middle radix-8 passes, Ns = 8, 64, ...
+    int Ns = 8;
+#pragma unroll
+    for (int p = 0; p < NMID; ++p) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = buf[padi(tid + r * (N / 8))];
+      const int k = tid & (Ns - 1);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) v[r] = twid<INV>(v[r], twm[p][r - 1]);
+      dft8<INV>(v);
+      __syncthreads();
+      const int o = (tid - k) * 8 + k;  // (tid / Ns) * Ns * 8 + k
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[padi(o + r * Ns)] = v[r];
+      __syncthreads();
+      Ns *= 8;
+    }
+    // last pass: radix R, Ns = N / R; each thread does 8 / R butterflies j
+#pragma unroll
+    for (int b = 0; b < 8 / R; ++b) {
+      const int j = tid + b * T;
+      float2 w[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) w[r] = buf[padi(j + r * NS)];
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[r] = twid<INV>(w[r], twl[b][r - 1]);
+      dftR<R, INV>(w);
+      if (active) {
+        if (!INV) {
+          float2* dst = out + tr * n_sc;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int i = (j + r * NS + half) & (N - 1);
+            if (i < n_sc) dst[i] = w[r];
+          }
+        } else {
+          float2* dst = out + tr * sym_len + cp;
+#pragma unroll
+          for (int r = 0; r < R; ++r) dst[j + r * NS] = w[r];
+        }
+      }
+    }
+    if (INV && active) {
+      float2* dst = out + tr * sym_len;
+      for (int n = tid; n < cp; n += T) dst[n] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();   // the next transform's pass 0 overwrites this LDS slab
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = vn[r];
   }
 }
 
@@ -176,7 +218,8 @@ template <int N, bool INV>
 rxphy_status run(int64_t n_tr, const float2* in, float2* out, const float2* tw, int sym_len,
                  int cp, int n_sc, hipStream_t s) {
   using G = Geom<N>;
-  int64_t blocks = (n_tr + G::TPW - 1) / G::TPW;
+  const int64_t per = (int64_t)G::TPW * PER_WG;
+  int64_t blocks = (n_tr + per - 1) / per;
   if (blocks > 0x7fffffff) return fail(RXPHY_EUNSUPPORTED, "too many transforms (%lld)", (long long)n_tr);
   hipLaunchKernelGGL((fft_kernel<N, INV>), dim3((unsigned)blocks), dim3(G::WG), 0, s, in, out, tw,
                      n_tr, sym_len, cp, n_sc);
