@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the plain device copy timed as the bandwidth reference (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: frames are independent, so more GPUs would each "
@@ -182,6 +184,25 @@ def main():
                                       / HBM_PEAK_GBS, 4),
         "gen_seconds": round(gen_s, 1),
     }
+    if args.copy_mib > 0:
+        # plain device-to-device copy of a known size: the achievable-bandwidth
+        # reference, and the calibration kernel for the HBM byte counters
+        n = args.copy_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(2):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        out["copy_reference"] = {"bytes_per_launch": 2 * n, "us": round(ms * 1e3, 1),
+                                 "GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, det, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -31,21 +31,33 @@ constexpr int MC = 8;               // antennas per staged chunk
 constexpr int PITCH = TS + 1;       // float2 per staged row (bank spread)
 constexpr int ROWS = MC * 16;       // staged rows per tensor (K, D <= 16)
 constexpr int PP = 17;              // float2 per row of a 16x16 matrix in the slab
-constexpr int PMAT = 16 * PP;       // float2 per matrix
-constexpr int SMEM = 2 * ROWS * PITCH;
-static_assert(16 * PMAT <= SMEM, "post-phase slab must fit in the staging area");
+constexpr int PMAT = 16 * PP + 4;   // float2 per matrix (the 4 matrices of a wave land on distinct banks)
+constexpr int SMEM = (2 * ROWS * PITCH > 16 * PMAT) ? 2 * ROWS * PITCH : 16 * PMAT;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int L>
 __device__ __forceinline__ float bc(float v) {   // lane L of each 16-lane row, to the whole row
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + L, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + L, 0xF, 0xF, true));
 }
 template <int L>
 __device__ __forceinline__ float2 bc2(float2 v) { return make_float2(bc<L>(v.x), bc<L>(v.y)); }
 
-__device__ __forceinline__ float2 cmul_cj(float2 a, float2 b) {   // conj(a) * b
-  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+// Complex multiply-subtract kernels written as four FMAs each.
+__device__ __forceinline__ float2 cms(float2 s, float2 a, float2 b) {      // s - a b
+  s.x = fmaf(-a.x, b.x, s.x); s.x = fmaf(a.y, b.y, s.x);
+  s.y = fmaf(-a.x, b.y, s.y); s.y = fmaf(-a.y, b.x, s.y);
+  return s;
+}
+__device__ __forceinline__ float2 cms_bc(float2 s, float2 a, float2 b) {   // s - a conj(b)
+  s.x = fmaf(-a.x, b.x, s.x); s.x = fmaf(-a.y, b.y, s.x);
+  s.y = fmaf(-a.y, b.x, s.y); s.y = fmaf(a.x, b.y, s.y);
+  return s;
+}
+__device__ __forceinline__ float2 cms_ac(float2 s, float2 a, float2 b) {   // s - conj(a) b
+  s.x = fmaf(-a.x, b.x, s.x); s.x = fmaf(-a.y, b.y, s.x);
+  s.y = fmaf(-a.x, b.y, s.y); s.y = fmaf(a.y, b.x, s.y);
+  return s;
 }
 
 __device__ __forceinline__ bool finite2(float2 v) {
@@ -57,34 +69,42 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
 }
 
 // Cholesky-Crout of the row-distributed A (lane `row` holds a[c] = A[row][c]).
-// On exit a[c] = L[row][c] for c <= row and inv[j] = 1 / L[j][j] in every lane.
-template <int J>
-__device__ __forceinline__ void crout_step(float2* a, float* inv, int row, int K, bool& ok) {
-  if (J >= K) return;
-  float2 s = a[J];
+// On exit a[c] = L[row][c] for c < row and inv[j] = 1 / L[j][j] in every lane.
+// Step J also advances L V = I by one row: row J of L (k < J) is final after
+// step J-1 and is already being broadcast, so v[J] = (v[J] - sum_k L[J][k] v[k]) / L[J][J].
+template <int J, int KP>
+__device__ __forceinline__ void crout_step(float2* a, float2* v, float* inv, int row, bool& ok) {
+  if constexpr (J < KP) {
+    float2 s = a[J], sv = v[J];
 #pragma unroll
-  for (int k = 0; k < J; ++k) s = csub(s, cmulc(a[k], bc2<J>(a[k])));   // - L[row][k] conj(L[J][k])
-  const float d = bc<J>(s.x);                                            // pivot from lane J
-  ok = ok && (d > 0.f) && __builtin_isfinite(d);
-  const float ljj = sqrtf(d);
-  const float iv = 1.0f / ljj;
-  inv[J] = iv;
-  a[J] = row == J ? make_float2(ljj, 0.f) : (row > J ? cscale(s, iv) : a[J]);
+    for (int k = 0; k < J; ++k) {
+      const float2 ljk = bc2<J>(a[k]);                                   // L[J][k]
+      s = cms_bc(s, a[k], ljk);                                          // - L[row][k] conj(L[J][k])
+      sv = cms(sv, ljk, v[k]);
+    }
+    const float d = bc<J>(s.x);                                          // pivot from lane J
+    ok = ok && (d > 0.f) && __builtin_isfinite(d);
+    const float iv = __builtin_amdgcn_rsqf(d);                           // 1 / L[J][J]
+    inv[J] = iv;
+    // every lane scales: rows above J produce upper-triangle values and the
+    // diagonal lane gets ~(L[J][J], 0); neither is ever read (solves use inv[])
+    a[J] = cscale(s, iv);
+    v[J] = cscale(sv, iv);
+    __builtin_amdgcn_sched_barrier(0);   // keep the steps' live ranges apart
+  }
 }
 
-// Forward substitution of two right-hand sides held per lane (w, v).
-template <int I>
-__device__ __forceinline__ void fwd_step(const float2* a, const float* inv, float2* w, float2* v, int K) {
-  if (I >= K) return;
-  float2 sw = w[I], sv = v[I];
+// Forward substitution L W = Z for the right-hand side held by this lane; row
+// I of L is read from the wave's LDS slab (the 16 lanes of a row read the same
+// address, a broadcast).
+template <int I, int KP>
+__device__ __forceinline__ void fwd_step(const float2* Lm, const float* inv, float2* w) {
+  if constexpr (I >= KP) return;
+  float2 sw = w[I];
 #pragma unroll
-  for (int k = 0; k < I; ++k) {
-    const float2 lik = bc2<I>(a[k]);                                     // L[I][k]
-    sw = csub(sw, cmul(lik, w[k]));
-    sv = csub(sv, cmul(lik, v[k]));
-  }
+  for (int k = 0; k < I; ++k) sw = cms(sw, Lm[I * PP + k], w[k]);      // - L[I][k] w[k]
   w[I] = cscale(sw, inv[I]);
-  v[I] = cscale(sv, inv[I]);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int... Js>
@@ -92,44 +112,43 @@ struct Seq {};
 using Seq16 = Seq<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
 
 // Back substitution L^H x = w (in place): x[I] = (w[I] - sum_{k>I} conj(L[k][I]) x[k]) / L[I][I].
-template <int I, int KK>
-__device__ __forceinline__ void bwd_term(const float2* a, const float2* w, float2& sx, int K) {
-  if constexpr (KK > I) {
-    if (KK < K) sx = csub(sx, cmul_cj(bc2<KK>(a[I]), w[KK]));
-  }
-}
-template <int I, int... Ks>
-__device__ __forceinline__ void bwd_terms(Seq<Ks...>, const float2* a, const float2* w, float2& sx, int K) {
-  (bwd_term<I, Ks>(a, w, sx, K), ...);
-}
-template <int I>
-__device__ __forceinline__ void bwd_step(const float2* a, const float* inv, float2* w, int K) {
-  if (I >= K) return;
+template <int I, int KP>
+__device__ __forceinline__ void bwd_step(const float2* Lm, const float* inv, float2* w) {
+  if constexpr (I >= KP) return;
   float2 sx = w[I];
-  bwd_terms<I>(Seq16{}, a, w, sx, K);
+#pragma unroll
+  for (int k = I + 1; k < KP; ++k) sx = cms_ac(sx, Lm[k * PP + I], w[k]);
   w[I] = cscale(sx, inv[I]);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int... Js>
-__device__ __forceinline__ void crout_all(Seq<Js...>, float2* a, float* inv, int row, int K, bool& ok) {
-  (crout_step<Js>(a, inv, row, K, ok), ...);
+template <int KP, int... Js>
+__device__ __forceinline__ void crout_all(Seq<Js...>, float2* a, float2* v, float* inv, int row, bool& ok) {
+  (crout_step<Js, KP>(a, v, inv, row, ok), ...);
 }
-template <int... Is>
-__device__ __forceinline__ void fwd_all(Seq<Is...>, const float2* a, const float* inv, float2* w, float2* v, int K) {
-  (fwd_step<Is>(a, inv, w, v, K), ...);
+template <int KP, int... Is>
+__device__ __forceinline__ void fwd_all(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
+  (fwd_step<Is, KP>(Lm, inv, w), ...);
 }
-template <int... Is>
-__device__ __forceinline__ void bwd_all(Seq<Is...>, const float2* a, const float* inv, float2* w, int K) {
-  (bwd_step<15 - Is>(a, inv, w, K), ...);
+template <int KP, int... Is>
+__device__ __forceinline__ void bwd_all(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
+  (bwd_step<15 - Is, KP>(Lm, inv, w), ...);
 }
-template <int U>
-__device__ __forceinline__ void bcast_mu(float dl, float n0, float* mu) { mu[U] = 1.0f - n0 * bc<U>(dl); }
-template <int... Us>
-__device__ __forceinline__ void bcast_mu_all(Seq<Us...>, float dl, float n0, float* mu) {
-  (bcast_mu<Us>(dl, n0, mu), ...);
+// MMSE: x_tilde_u = x_hat_u / mu_u with mu_u = 1 - N0 d_u, d_u held by lane u.
+template <int U, int KP>
+__device__ __forceinline__ void unbias(float dl, float n0, float2* z) {
+  if constexpr (U < KP) z[U] = cscale(z[U], __builtin_amdgcn_rcpf(1.0f - n0 * bc<U>(dl)));
+}
+template <int KP, int... Us>
+__device__ __forceinline__ void unbias_all(Seq<Us...>, float dl, float n0, float2* z) {
+  (unbias<Us, KP>(dl, n0, z), ...);
 }
 
-__global__ void __launch_bounds__(256)
+// KP = K rounded up to 4, 8 or 16: the system is padded with an identity block
+// (A_pad = diag(A, I), zero matched-filter rows), which leaves the solution of
+// the real K x K block unchanged and keeps phase 2 free of runtime bounds.
+template <int KP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
                    float2* __restrict__ xt, float* __restrict__ nu, uint8_t* __restrict__ flags,
                    int M, int K, int S, int n_sc, float n0, int mmse) {
@@ -190,26 +209,30 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
     if (bad) nonfin[c16] = 1;
     __syncthreads();
     if (m0 + MC < M) load_chunk(m0 + MC);
+    // branch-free: rows past this chunk are zero in LDS, rows of absent users
+    // or symbols are masked by selects (row indices stay below ROWS)
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      if (4 * a < mc) {
-        const int ml = 4 * a + kq;
-        const bool okh = ml < mc && u < K;
-        const bool oky = ml < mc && u < D;
+      const int ml = 4 * a + kq;
+      const bool okh = ml < mc && u < K;
+      const bool oky = ml < mc && u < D;
+      const int hrow = ml * K + u;
+      const int yrow = ml * D + u;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int sc = 4 * w + t;
-          const float2 h = okh ? Hs[(ml * K + u) * PITCH + sc] : make_float2(0.f, 0.f);
-          const float2 y = oky ? Ys[(ml * D + u) * PITCH + sc] : make_float2(0.f, 0.f);
-          gr[t] = mfma(h.x, h.x, gr[t]);
-          gr[t] = mfma(h.y, h.y, gr[t]);
-          gi[t] = mfma(h.x, h.y, gi[t]);
-          gi[t] = mfma(-h.y, h.x, gi[t]);
-          zr[t] = mfma(h.x, y.x, zr[t]);
-          zr[t] = mfma(h.y, y.y, zr[t]);
-          zi[t] = mfma(h.x, y.y, zi[t]);
-          zi[t] = mfma(-h.y, y.x, zi[t]);
-        }
+      for (int t = 0; t < 4; ++t) {
+        const int sc = 4 * w + t;
+        const float2 hr = Hs[hrow * PITCH + sc];
+        const float2 yr = Ys[yrow * PITCH + sc];
+        const float hx = okh ? hr.x : 0.f, hy = okh ? hr.y : 0.f;
+        const float yx = oky ? yr.x : 0.f, yy = oky ? yr.y : 0.f;
+        gr[t] = mfma(hx, hx, gr[t]);
+        gr[t] = mfma(hy, hy, gr[t]);
+        gi[t] = mfma(hx, hy, gi[t]);
+        gi[t] = mfma(-hy, hx, gi[t]);
+        zr[t] = mfma(hx, yx, zr[t]);
+        zr[t] = mfma(hy, yy, zr[t]);
+        zi[t] = mfma(hx, yy, zi[t]);
+        zi[t] = mfma(-hy, yx, zi[t]);
       }
     }
     __syncthreads();
@@ -219,6 +242,7 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   float2* P = smem + w * 4 * PMAT;
   const int col = l & 15, g4 = (l >> 4) * 4;      // MFMA output: rows g4 + r, column col
   const int scl = l >> 4, row = l & 15;           // phase-2 lane: subcarrier scl, index row
+  float2* Pm = P + scl * PMAT;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -227,35 +251,41 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   float2 a[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    a[c] = P[scl * PMAT + row * PP + c];
-    if (mmse && c == row) a[c].x += n0;
+    a[c] = Pm[row * PP + c];                       // row `row` of A
+    if (c == row) a[c].x = row < K ? a[c].x + (mmse ? n0 : 0.f) : 1.0f;
   }
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) P[t * PMAT + (g4 + r) * PP + col] = make_float2(zr[t][r], zi[t][r]);
-  __syncthreads();
-  float2 z[16], v[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    z[k] = P[scl * PMAT + k * PP + row];          // column `row` of Z
-    v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);  // column `row` of I
-  }
 
+  // Cholesky-Crout with L V = I folded in (V = L^{-1}, column `row` per lane)
   bool ok = true;
   float inv[16];
-  crout_all(Seq16{}, a, inv, row, K, ok);
-  fwd_all(Seq16{}, a, inv, z, v, K);
-  bwd_all(Seq16{}, a, inv, z, K);
+  float2 v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);
+  crout_all<KP>(Seq16{}, a, v, inv, row, ok);     // a[c] = L[row][c] for c <= row
   float dl = 0.f;                                  // d_row = sum_k |L^{-1}[k][row]|^2
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (k < K) dl += v[k].x * v[k].x + v[k].y * v[k].y;
+  for (int k = 0; k < KP; ++k) dl += v[k].x * v[k].x + v[k].y * v[k].y;
 
-  float mu[16];
-  bcast_mu_all(Seq16{}, dl, n0, mu);
-  bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
+  __syncthreads();                                 // Z is in the slab
+  float2 z[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) z[k] = Pm[k * PP + row];   // column `row` of Z
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) Pm[row * PP + c] = a[c];   // L, row by row
+  __syncthreads();
+
+  // L W = Z, then L^H X = W
+  fwd_all<KP>(Seq16{}, Pm, inv, z);
+  bwd_all<KP>(Seq16{}, Pm, inv, z);
+  if (mmse) unbias_all<KP>(Seq16{}, dl, n0, z);
+
+  const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
   const uint64_t bal = __ballot(mu_bad);
   if ((bal >> (16 * scl)) & 0xffffull) ok = false;
 
@@ -268,7 +298,6 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
     for (int uu = 0; uu < 16; ++uu) {
       if (uu < K) {
         float2 x = z[uu];
-        if (mmse) x = cscale(x, 1.0f / mu[uu]);
         if (erase) x = make_float2(0.f, 0.f);
         xt[((int64_t)(f * K + uu) * D + row) * n_sc + i] = x;
       }
@@ -279,7 +308,7 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
     if (mmse) {
       // (1 - mu) / mu with 1 - mu = N0 d formed directly: subtracting mu from 1
       // would cancel most digits for strong users (mu close to 1)
-      nv = n0 * dl / (1.0f - n0 * dl);
+      nv = n0 * dl * __builtin_amdgcn_rcpf(1.0f - n0 * dl);
     } else {
       nv = n0 * dl;
     }
@@ -297,8 +326,16 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
   if (prec != RXPHY_FP32) return fail(RXPHY_EUNSUPPORTED, "precision %d not built yet", (int)prec);
   dim3 grid((fr.n_sc + TS - 1) / TS, nf);
-  hipLaunchKernelGGL(detect_fp32_kernel, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
-                     fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
+  if (fr.K <= 4)
+    hipLaunchKernelGGL(detect_fp32_kernel<4>, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
+                       fr.n_sym, fr.n_sc, fr.n0, mmse);
+  else if (fr.K <= 8)
+    hipLaunchKernelGGL(detect_fp32_kernel<8>, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
+                       fr.n_sym, fr.n_sc, fr.n0, mmse);
+  else
+    hipLaunchKernelGGL(detect_fp32_kernel<16>, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
+                       fr.n_sym, fr.n_sc, fr.n0, mmse);
   return launch_status("detect kernel");
 }
 
