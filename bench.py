@@ -55,6 +55,20 @@ def stage_bytes(s):
     }
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(cfg, det, budget_s):
     import oracle as O
     try:
@@ -178,7 +192,8 @@ def main():
                    "detector": "zf", "precision": "fp32"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic(dom), "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes": sb[dom] * F},
         "stages": stages,
         "staged_roofline_frac": round(sum(sb.values()) * F / (sum(per_stage.values()) * 1e-3) / 1e9
                                       / HBM_PEAK_GBS, 4),
