@@ -347,7 +347,8 @@ def detect_adjoint(H, Y, n0: float, detector: int, gxt, gnu):
 
 def csi_adjoint(gH, pilots, n_sc: int):
     """dL/dYf0[m][q] = p[q]/|p[q]|^2 * sum_{i in group g} dL/dH[m][u][i] for
-    q = g K + u; pilot subcarriers past the last full group get 0."""
+    q = g K + u; pilot subcarriers past the last full group get 0, and so do
+    zero pilots (their estimates are non-finite and erased downstream)."""
     gH = np.asarray(gH, dtype=np.complex128)
     M, K, _ = gH.shape
     p = np.asarray(pilots).astype(np.complex128)
@@ -358,7 +359,9 @@ def csi_adjoint(gH, pilots, n_sc: int):
         acc = np.zeros((M, G), dtype=np.complex128)
         np.add.at(acc.T, g, gH[:, u, :].T)
         q = np.arange(G) * K + u
-        out[:, q] = acc * (p[q] / np.abs(p[q]) ** 2)[None, :]
+        pp = np.abs(p[q]) ** 2
+        scale = np.where(pp > 0, p[q] / np.where(pp > 0, pp, 1.0), 0.0)
+        out[:, q] = acc * scale[None, :]
     return out
 
 

@@ -1,5 +1,355 @@
-// Adjoint of the forward receiver map and workspace sizing.
-#include "common.h"
+// Adjoint of the receiver map x -> LLR (FP32), and workspace sizing.
+//
+// Gradients use PyTorch's complex convention g = dL/dRe + j dL/dIm.  The
+// backward pass recomputes the forward quantities it needs (the Cholesky
+// factors are recomputed per subcarrier, never stored) and runs, in order:
+//   demod adjoint   dLLR_j/dx = 2 (l0 - l1) / nu on the bit's axis (l_b the
+//                   nearest level with bit b, ties to the lowest point index),
+//                   dLLR_j/dnu = -LLR_j / nu;
+//   detect adjoint  with A = H^H H (+ N0 I), X_hat = A^{-1} H^H Y,
+//                   G_hat = dL/dX_hat (MMSE: dL/dx_tilde / mu), e_u the weight
+//                   of d_u = [A^{-1}]_uu (ZF: N0 dL/dnu_u; MMSE:
+//                   N0 (Re sum_s conj(g_su) x_hat_su + dL/dnu_u) / mu_u^2),
+//                   V = A^{-1} G_hat and C = X_hat V^H + V X_hat^H + 2 A^{-1} E A^{-1}:
+//                   dL/dY = H V,  dL/dH = Y V^H - H C;
+//   csi adjoint     dL/dYf0[q] = p[q] / |p[q]|^2 * sum over the pilot group of
+//                   dL/dH[m][u][i] (q = g K + u; 0 past the last full group
+//                   and where the pilot is zero);
+//   fft adjoint     the unscaled inverse-direction DFT of the used-bin gradient
+//                   (zero-padded grid), cyclic-prefix samples get 0.
+#include <cstring>
+
+#include "detect_core.h"
+
+namespace rxphy {
+namespace {
+
+using namespace det;
+
+// ----------------------------------------------------------------- demod adjoint
+template <int Q>
+__device__ __forceinline__ float lvl(int code) {
+  constexpr int B = Q / 2;
+  if constexpr (B == 1) {
+    return (code & 1) ? -0.70710678118654752f : 0.70710678118654752f;
+  } else if constexpr (B == 2) {
+    const float s0 = (code & 2) ? -1.f : 1.f, s1 = (code & 1) ? -1.f : 1.f;
+    return s0 * (2.f - s1) * 0.31622776601683793f;
+  } else {
+    const float s0 = (code & 4) ? -1.f : 1.f, s1 = (code & 2) ? -1.f : 1.f, s2 = (code & 1) ? -1.f : 1.f;
+    return s0 * (4.f - s1 * (2.f - s2)) * 0.15430334996209191f;
+  }
+}
+
+// Nearest levels with bit t = 0 / 1 on one axis (strict < keeps the lowest code).
+template <int Q>
+__device__ __forceinline__ void axis_argmin(float x, float* l0, float* l1) {
+  constexpr int B = Q / 2;
+  float d0[B], d1[B];
+#pragma unroll
+  for (int t = 0; t < B; ++t) { d0[t] = d1[t] = INFINITY; l0[t] = l1[t] = 0.f; }
+#pragma unroll
+  for (int code = 0; code < (1 << B); ++code) {
+    const float lv = lvl<Q>(code);
+    const float d = (x - lv) * (x - lv);
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+      if ((code >> (B - 1 - t)) & 1) { if (d < d1[t]) { d1[t] = d; l1[t] = lv; } }
+      else                           { if (d < d0[t]) { d0[t] = d; l0[t] = lv; } }
+    }
+  }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256)
+demod_adjoint_kernel(const float2* __restrict__ xt, const float* __restrict__ nu,
+                     const float* __restrict__ dllr, float2* __restrict__ gxt,
+                     float* __restrict__ gnu, int64_t n_fu, int D, int n_sc) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (f, u, i)
+  if (idx >= n_fu * n_sc) return;
+  const int64_t fu = idx / n_sc;
+  const int i = (int)(idx - fu * n_sc);
+  const float v = nu[idx];
+  const bool erased = __builtin_isinf(v);
+  const float inv = erased ? 0.f : 1.0f / v;
+  float gn = 0.f;
+  for (int s = 0; s < D; ++s) {
+    const int64_t e = (fu * D + s) * n_sc + i;
+    const float2 x = xt[e];
+    const float* dl = dllr + e * Q;
+    float re0[Q / 2], re1[Q / 2], im0[Q / 2], im1[Q / 2];
+    axis_argmin<Q>(x.x, re0, re1);
+    axis_argmin<Q>(x.y, im0, im1);
+    float gr = 0.f, gi = 0.f;
+#pragma unroll
+    for (int t = 0; t < Q / 2; ++t) {
+      const float a = dl[2 * t], b = dl[2 * t + 1];
+      const float lr = (re0[t] - re1[t]) * (2.f * x.x - re0[t] - re1[t]) * inv;
+      const float li = (im0[t] - im1[t]) * (2.f * x.y - im0[t] - im1[t]) * inv;
+      gr += a * 2.f * (re0[t] - re1[t]) * inv;
+      gi += b * 2.f * (im0[t] - im1[t]) * inv;
+      gn -= (a * lr + b * li) * inv;
+    }
+    gxt[e] = erased ? make_float2(0.f, 0.f) : make_float2(gr, gi);
+  }
+  gnu[idx] = erased ? 0.f : gn;
+}
+
+// ---------------------------------------------------------------- detect adjoint
+// Sum of v over the 16 lanes of each DPP row, returned in every lane of the row.
+__device__ __forceinline__ float row_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xF, 0xF, true));  // row_shr:1
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x112, 0xF, 0xF, true));  // row_shr:2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x114, 0xF, 0xF, true));  // row_shr:4
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x118, 0xF, 0xF, true));  // row_shr:8
+  return bc<15>(v);
+}
+
+// MMSE gains of every user in every lane of the row; padded users (U >= K)
+// get 1 so that their zero rows stay exactly zero.
+template <int U>
+__device__ __forceinline__ void gather_mu(float dl, float n0, int mmse, int K, float* mu) {
+  const float m = 1.0f - n0 * bc<U>(dl);
+  mu[U] = (mmse && U < K) ? m : 1.0f;
+}
+template <int... Us>
+__device__ __forceinline__ void gather_mu_all(Seq<Us...>, float dl, float n0, int mmse, int K, float* mu) {
+  (gather_mu<Us>(dl, n0, mmse, K, mu), ...);
+}
+template <int U>
+__device__ __forceinline__ void gather_e(float e, float* ek) { ek[U] = bc<U>(e); }
+template <int... Us>
+__device__ __forceinline__ void gather_e_all(Seq<Us...>, float e, float* ek) { (gather_e<Us>(e, ek), ...); }
+
+// Per subcarrier (one 16-lane row of a wave each): recompute the factor and
+// X_hat, then solve V = A^{-1} G_hat (lane = data symbol) and A^{-1} (lane =
+// column).  Writes X_hat and V [F][n_sc][K][D], A^{-1} [F][n_sc][K][K] and the
+// weights e [F][n_sc][K]; all zero for erased subcarriers.
+template <int KP>
+__global__ void __launch_bounds__(256)
+detect_adjoint_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
+                      const float2* __restrict__ gxt, const float* __restrict__ gnu,
+                      float2* __restrict__ Xw, float2* __restrict__ Vw, float2* __restrict__ Aw,
+                      float* __restrict__ Ew, int M, int K, int S, int n_sc, float n0, int mmse) {
+  __shared__ float2 smem[SMEM];
+  __shared__ int nonfin[TS];
+  const int f = blockIdx.y;
+  const int i0 = blockIdx.x * TS;
+  const int D = S - 1;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  if (tid < TS) nonfin[tid] = 0;
+  __syncthreads();
+
+  f32x4 gr[4], gi[4], zr[4], zi[4];
+  gram_mf(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
+          nonfin, gr, gi, zr, zi);
+  float2* P = smem + w * 4 * PMAT;
+  const int col = l & 15, g4 = (l >> 4) * 4;
+  const int scl = l >> 4, row = l & 15;
+  float2* Pm = P + scl * PMAT;                       // holds L after factor_solve
+  float2 x[16], v[16];
+  float inv[16], dl;
+  bool ok;
+  factor_solve<KP>(P, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, x, v, inv, dl, ok);
+
+  const int i = i0 + 4 * w + scl;
+  const bool in_i = i < n_sc;
+  float mu[16];
+  gather_mu_all(Seq16{}, dl, n0, mmse, K, mu);
+  const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
+  const uint64_t bal = __ballot(mu_bad);
+  if ((bal >> (16 * scl)) & 0xffffull) ok = false;
+  const bool erase = !in_i || nonfin[4 * w + scl] != 0 || !ok;
+  const int64_t sub = (int64_t)f * n_sc + i;
+
+  // incoming gradients: lane `row` = symbol s holds column s of dL/dx_tilde
+  float2 g[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    g[u] = (!erase && row < D && u < K) ? gxt[((int64_t)(f * K + u) * D + row) * n_sc + i]
+                                       : make_float2(0.f, 0.f);
+    if (erase) x[u] = make_float2(0.f, 0.f);
+  }
+  const float gn = (!erase && row < K) ? gnu[(int64_t)(f * K + row) * n_sc + i] : 0.f;
+
+  // e_row, the weight of d_row, and G_hat
+  float e;
+  if (mmse) {
+    float mine = 0.f, mr = 1.f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const float t = row_sum(g[u].x * x[u].x + g[u].y * x[u].y);   // sum_s Re(conj(g_su) x_su)
+      if (u == row) { mine = t; mr = mu[u]; }
+    }
+    e = n0 * (mine + gn) / (mr * mr);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) g[u] = cscale(g[u], 1.0f / mu[u]);
+  } else {
+    e = n0 * gn;
+  }
+  if (in_i && row < D) {
+#pragma unroll
+    for (int u = 0; u < KP; ++u) if (u < K) Xw[(sub * K + u) * D + row] = x[u];
+  }
+  if (in_i && row < K) Ew[sub * K + row] = erase ? 0.f : e;
+
+  fwd_all<KP>(Seq16{}, Pm, inv, g);                // V column s = A^{-1} G_hat column s
+  bwd_all<KP>(Seq16{}, Pm, inv, g);
+  bwd_all<KP>(Seq16{}, Pm, inv, v);                // column `row` of A^{-1} = L^{-H} L^{-1} e_row
+  if (!in_i) return;
+  if (row < D) {
+#pragma unroll
+    for (int u = 0; u < KP; ++u) if (u < K) Vw[(sub * K + u) * D + row] = erase ? make_float2(0.f, 0.f) : g[u];
+  }
+  if (row < K) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) if (k < K) Aw[(sub * K + k) * K + row] = erase ? make_float2(0.f, 0.f) : v[k];
+  }
+}
+
+// C = X_hat V^H + V X_hat^H + 2 A^{-1} diag(e) A^{-1}, one thread per
+// (frame, subcarrier, column j).  Cw: [F][n_sc][K][K].
+__global__ void __launch_bounds__(256)
+detect_adjoint_c_kernel(const float2* __restrict__ Xw, const float2* __restrict__ Vw,
+                        const float2* __restrict__ Aw, const float* __restrict__ Ew,
+                        float2* __restrict__ Cw, int64_t n_sub, int K, int D) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_sub * K) return;
+  const int64_t sub = t / K;
+  const int j = (int)(t - sub * K);
+  const float2* X = Xw + sub * K * D;
+  const float2* V = Vw + sub * K * D;
+  const float2* A = Aw + sub * K * K;
+  const float* E = Ew + sub * K;
+  for (int ii = 0; ii < K; ++ii) {
+    float2 acc = make_float2(0.f, 0.f);
+    for (int s = 0; s < D; ++s) {
+      acc = cms_bc(acc, X[ii * D + s], make_float2(-V[j * D + s].x, -V[j * D + s].y));  // + x[ii][s] conj(v[j][s])
+      acc = cms_bc(acc, V[ii * D + s], make_float2(-X[j * D + s].x, -X[j * D + s].y));  // + v[ii][s] conj(x[j][s])
+    }
+    for (int k = 0; k < K; ++k) {
+      const float2 a = A[k * K + ii];
+      acc = cms_ac(acc, make_float2(-a.x, -a.y), cscale(A[k * K + j], 2.f * E[k]));  // + conj(A[k][ii]) 2 e_k A[k][j]
+    }
+    Cw[(sub * K + ii) * K + j] = acc;
+  }
+}
+
+// dL/dY = H V into the data symbols of gyf, dL/dH = Y V^H - H C into gh.
+// Workgroup: 16 subcarriers x 16 antennas of one frame; V and C of the 16
+// subcarriers are staged in LDS.
+template <int KP>
+__global__ void __launch_bounds__(256)
+detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
+                            const float2* __restrict__ Vw, const float2* __restrict__ Cw,
+                            float2* __restrict__ gyf, float2* __restrict__ gh, int M, int K,
+                            int S, int n_sc) {
+  __shared__ float2 sv[16 * KP * 16];
+  __shared__ float2 sc[16 * KP * KP];
+  const int D = S - 1;
+  const int f = blockIdx.z;
+  const int i0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+  const int il = threadIdx.x & 15, ml = threadIdx.x >> 4;
+  const int ntile = min(16, n_sc - i0);
+  for (int e = threadIdx.x; e < ntile * K * D; e += 256) {
+    const int t = e / (K * D), r = e - t * (K * D);
+    const int u = r / D, s = r - u * D;
+    sv[(t * KP + u) * 16 + s] = Vw[((int64_t)f * n_sc + i0 + t) * K * D + r];
+  }
+  for (int e = threadIdx.x; e < ntile * K * K; e += 256) {
+    const int t = e / (K * K), r = e - t * (K * K);
+    const int a = r / K, b = r - a * K;
+    sc[(t * KP + a) * KP + b] = Cw[((int64_t)f * n_sc + i0 + t) * K * K + r];
+  }
+  __syncthreads();
+  const int i = i0 + il, m = m0 + ml;
+  if (i >= n_sc || m >= M) return;
+  float2 h[KP], y[16];
+#pragma unroll
+  for (int u = 0; u < KP; ++u)
+    h[u] = u < K ? H[((int64_t)(f * M + m) * K + u) * n_sc + i] : make_float2(0.f, 0.f);
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    y[s] = s < D ? Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] : make_float2(0.f, 0.f);
+  const float2* V = sv + il * KP * 16;
+  const float2* C = sc + il * KP * KP;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if (s < D) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < KP; ++u) if (u < K) acc = cms(acc, h[u], make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y));
+      gyf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] = acc;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (u < K) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        if (s < D) acc = cms_bc(acc, y[s], make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y));  // + y conj(V)
+#pragma unroll
+      for (int v2 = 0; v2 < KP; ++v2)
+        if (v2 < K) acc = cms(acc, h[v2], C[v2 * KP + u]);                                    // - H C
+      gh[((int64_t)(f * M + m) * K + u) * n_sc + i] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ csi adjoint
+__global__ void __launch_bounds__(256)
+csi_adjoint_kernel(const float2* __restrict__ gh, const float2* __restrict__ pil,
+                   float2* __restrict__ gyf, int M, int K, int S, int n_sc) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_sc) return;
+  const int m = blockIdx.y, f = blockIdx.z;
+  const int G = n_sc / K;
+  float2 out = make_float2(0.f, 0.f);
+  if (q < G * K) {
+    const int g = q / K, u = q - g * K;
+    const int lo = g * K, hi = (g == G - 1) ? n_sc : lo + K;
+    const float2* row = gh + ((int64_t)(f * M + m) * K + u) * n_sc;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int i = lo; i < hi; ++i) acc = cadd(acc, row[i]);
+    const float2 p = pil[(int64_t)f * n_sc + q];
+    const float pp = p.x * p.x + p.y * p.y;
+    if (pp > 0.f) out = cmul(acc, make_float2(p.x / pp, p.y / pp));
+  }
+  gyf[((int64_t)(f * M + m) * S) * n_sc + q] = out;
+}
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct BwdLayout {
+  size_t yf, h, xt, nu, flags, gxt, gnu, xh, v, a, e, c, gyf, gh, total;
+};
+
+BwdLayout layout(const rxphy_frame& f, int32_t F) {
+  const size_t n = (size_t)F, M = f.M, K = f.K, S = f.n_sym, D = f.n_sym - 1, sc = f.n_sc;
+  BwdLayout L{};
+  size_t o = 0;
+  L.yf = o; o += up(n * M * S * sc * 8);
+  L.h = o; o += up(n * M * K * sc * 8);
+  L.xt = o; o += up(n * K * D * sc * 8);
+  L.nu = o; o += up(n * K * sc * 4);
+  L.flags = o; o += up(n * sc);
+  L.gxt = o; o += up(n * K * D * sc * 8);
+  L.gnu = o; o += up(n * K * sc * 4);
+  L.xh = o; o += up(n * sc * K * D * 8);
+  L.v = o; o += up(n * sc * K * D * 8);
+  L.a = o; o += up(n * sc * K * K * 8);
+  L.e = o; o += up(n * sc * K * 4);
+  L.c = o; o += up(n * sc * K * K * 8);
+  L.gyf = o; o += up(n * M * S * sc * 8);
+  L.gh = o; o += up(n * M * K * sc * 8);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+}  // namespace rxphy
 
 using namespace rxphy;
 
@@ -10,16 +360,81 @@ size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t
   (void)precision;
   if (check_frame(frame, n_frames) != RXPHY_OK) return 0;
   if (which == RXPHY_WS_DETECT) return 0;
+  if (which == RXPHY_WS_BACKWARD) return layout(*frame, n_frames).total;
   return 0;
 }
 
 rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const void* x,
                             const void* pilots, const rxphy_saved* saved, const float* dllr,
                             void* dx, void* dh, void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)frame; (void)n_frames; (void)x; (void)pilots; (void)saved; (void)dllr; (void)dx;
-  (void)dh; (void)ws; (void)ws_bytes; (void)stream;
   clear_error();
-  return fail(RXPHY_EUNSUPPORTED, "rxphy_backward is not built yet");
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(x, "x")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(dllr, "dllr")) ||
+      (st = check_ptr(dx, "dx")))
+    return st;
+  if (n_frames > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", n_frames);
+  const rxphy_frame& fr = *frame;
+  const BwdLayout L = layout(fr, n_frames);
+  if (!ws || ws_bytes < L.total)
+    return fail(RXPHY_EWORKSPACE, "backward needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  char* w = (char*)ws;
+  const float2* yf = (saved && saved->yf) ? (const float2*)saved->yf : (const float2*)(w + L.yf);
+  const float2* h = (saved && saved->h) ? (const float2*)saved->h : (const float2*)(w + L.h);
+  float2* xt = (float2*)(w + L.xt);
+  float* nu = (float*)(w + L.nu);
+  uint8_t* flags = (uint8_t*)(w + L.flags);
+  float2* gxt = (float2*)(w + L.gxt);
+  float* gnu = (float*)(w + L.gnu);
+  float2* Xw = (float2*)(w + L.xh);
+  float2* Vw = (float2*)(w + L.v);
+  float2* Aw = (float2*)(w + L.a);
+  float* Ew = (float*)(w + L.e);
+  float2* Cw = (float2*)(w + L.c);
+  float2* gyf = (float2*)(w + L.gyf);
+  float2* gh = dh ? (float2*)dh : (float2*)(w + L.gh);
+  const int64_t n_tr = (int64_t)n_frames * fr.M * fr.n_sym;
+
+  if (!(saved && saved->yf))
+    if ((st = launch_fft(fr, n_tr, (const float2*)x, (float2*)(w + L.yf), false, stream))) return st;
+  if (!(saved && saved->h))
+    if ((st = launch_csi(fr, n_frames, yf, (const float2*)pilots, (float2*)(w + L.h), stream))) return st;
+  if ((st = launch_detect(fr, n_frames, h, yf, xt, nu, flags, RXPHY_FP32, 0.f, stream))) return st;
+
+  const int D = fr.n_sym - 1;
+  const int64_t n_fu = (int64_t)n_frames * fr.K;
+  const unsigned blocks = (unsigned)((n_fu * fr.n_sc + 255) / 256);
+  switch (fr.qam_bits) {
+    case 2: hipLaunchKernelGGL(demod_adjoint_kernel<2>, dim3(blocks), dim3(256), 0, stream, xt, nu, dllr, gxt, gnu, n_fu, D, fr.n_sc); break;
+    case 4: hipLaunchKernelGGL(demod_adjoint_kernel<4>, dim3(blocks), dim3(256), 0, stream, xt, nu, dllr, gxt, gnu, n_fu, D, fr.n_sc); break;
+    default: hipLaunchKernelGGL(demod_adjoint_kernel<6>, dim3(blocks), dim3(256), 0, stream, xt, nu, dllr, gxt, gnu, n_fu, D, fr.n_sc); break;
+  }
+  if ((st = launch_status("demod adjoint kernel"))) return st;
+
+  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
+  dim3 g1((fr.n_sc + TS - 1) / TS, n_frames);
+  dim3 g2((fr.n_sc + 15) / 16, (fr.M + 15) / 16, n_frames);
+  const int64_t n_sub = (int64_t)n_frames * fr.n_sc;
+  const unsigned gc = (unsigned)((n_sub * fr.K + 255) / 256);
+#define RXPHY_ADJ(KP)                                                                               \
+  hipLaunchKernelGGL(detect_adjoint_kernel<KP>, g1, dim3(256), 0, stream, h, yf, gxt, gnu, Xw, Vw,  \
+                     Aw, Ew, fr.M, fr.K, fr.n_sym, fr.n_sc, fr.n0, mmse);                          \
+  if ((st = launch_status("detect adjoint kernel"))) return st;                                     \
+  hipLaunchKernelGGL(detect_adjoint_c_kernel, dim3(gc), dim3(256), 0, stream, Xw, Vw, Aw, Ew, Cw,   \
+                     n_sub, fr.K, D);                                                              \
+  if ((st = launch_status("detect adjoint c kernel"))) return st;                                   \
+  hipLaunchKernelGGL(detect_adjoint_apply_kernel<KP>, g2, dim3(256), 0, stream, h, yf, Vw, Cw, gyf, \
+                     gh, fr.M, fr.K, fr.n_sym, fr.n_sc);
+  if (fr.K <= 4) { RXPHY_ADJ(4) } else if (fr.K <= 8) { RXPHY_ADJ(8) } else { RXPHY_ADJ(16) }
+#undef RXPHY_ADJ
+  if ((st = launch_status("detect adjoint apply kernel"))) return st;
+
+  dim3 g3((fr.n_sc + 255) / 256, fr.M, n_frames);
+  hipLaunchKernelGGL(csi_adjoint_kernel, g3, dim3(256), 0, stream, gh, (const float2*)pilots, gyf,
+                     fr.M, fr.K, fr.n_sym, fr.n_sc);
+  if ((st = launch_status("csi adjoint kernel"))) return st;
+  return launch_fft(fr, n_tr, gyf, (float2*)dx, true, stream);
 }
 
 }  // extern "C"

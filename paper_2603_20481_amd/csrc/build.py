@@ -9,6 +9,7 @@ PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "librxphy.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "demod.hip", "backward.hip"]
+HEADERS = ["common.h", "detect_core.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -1,152 +1,14 @@
-// equal stage: per-subcarrier ZF / MMSE detection for gfx950.
-//
-// Workgroup = 4 wavefronts = a tile of 16 consecutive subcarriers of one
-// frame; each wavefront owns 4 of them.
-//
-// Phase 1 (products on MFMA).  H and the data symbols are streamed through
-// LDS in chunks of 8 antennas: 16 threads load the 16 subcarriers of one
-// (antenna, user) or (antenna, symbol) row as one 128-byte coalesced segment.
-// Per subcarrier the wave accumulates, with v_mfma_f32_16x16x4_f32 and the
-// antenna index as the reduction axis (4 antennas per instruction),
-//   Re G = A^T A + B^T B,   Im G = A^T B - B^T A        (H = A + jB)
-//   Re Z = A^T C + B^T D,   Im Z = A^T D - B^T C        (Y = C + jD)
-// i.e. the Gram matrix G = H^H H and the matched filter Z = H^H Y, each lane
-// supplying one (antenna, user) channel value and one (antenna, symbol) data
-// value per step; both operands of the Gram come from the same register.
-//
-// Phase 2 (small dense algebra on VALU).  G and Z go through a wave-private
-// LDS slab so that, for each subcarrier, lane t of its 16-lane row holds row t
-// of A (= G, or G + N0 I) and column t of Z.  A Cholesky-Crout factorisation
-// runs column by column with the row of L being used broadcast by DPP
-// row_newbcast; forward substitution solves L W = Z and L V = I together (V
-// is L^{-1}, whose squared column norms are d = diag(A^{-1})), then back
-// substitution solves L^H X = W.
-#include "common.h"
+// equal stage: per-subcarrier ZF / MMSE detection for gfx950 (phase 1 and the
+// factorisation live in detect_core.h).  The forward kernel adds the MMSE
+// unbiasing x_tilde = x_hat / mu, the noise variances, the flags and the
+// erasures, and writes x_tilde [F][K][D][n_sc], nu [F][K][n_sc], flags [F][n_sc].
+#include "detect_core.h"
 
 namespace rxphy {
 namespace {
 
-constexpr int TS = 16;              // subcarriers per workgroup tile
-constexpr int MC = 8;               // antennas per staged chunk
-constexpr int PITCH = TS + 1;       // float2 per staged row (bank spread)
-constexpr int ROWS = MC * 16;       // staged rows per tensor (K, D <= 16)
-constexpr int PP = 17;              // float2 per row of a 16x16 matrix in the slab
-constexpr int PMAT = 16 * PP + 4;   // float2 per matrix (the 4 matrices of a wave land on distinct banks)
-constexpr int SMEM = (2 * ROWS * PITCH > 16 * PMAT) ? 2 * ROWS * PITCH : 16 * PMAT;
+using namespace det;
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <int L>
-__device__ __forceinline__ float bc(float v) {   // lane L of each 16-lane row, to the whole row
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + L, 0xF, 0xF, true));
-}
-template <int L>
-__device__ __forceinline__ float2 bc2(float2 v) { return make_float2(bc<L>(v.x), bc<L>(v.y)); }
-
-// Complex multiply-subtract kernels written as four FMAs each.
-__device__ __forceinline__ float2 cms(float2 s, float2 a, float2 b) {      // s - a b
-  s.x = fmaf(-a.x, b.x, s.x); s.x = fmaf(a.y, b.y, s.x);
-  s.y = fmaf(-a.x, b.y, s.y); s.y = fmaf(-a.y, b.x, s.y);
-  return s;
-}
-__device__ __forceinline__ float2 cms_bc(float2 s, float2 a, float2 b) {   // s - a conj(b)
-  s.x = fmaf(-a.x, b.x, s.x); s.x = fmaf(-a.y, b.y, s.x);
-  s.y = fmaf(-a.y, b.x, s.y); s.y = fmaf(a.x, b.y, s.y);
-  return s;
-}
-__device__ __forceinline__ float2 cms_ac(float2 s, float2 a, float2 b) {   // s - conj(a) b
-  s.x = fmaf(-a.x, b.x, s.x); s.x = fmaf(-a.y, b.y, s.x);
-  s.y = fmaf(-a.x, b.y, s.y); s.y = fmaf(a.y, b.x, s.y);
-  return s;
-}
-
-__device__ __forceinline__ bool finite2(float2 v) {
-  return __builtin_isfinite(v.x) && __builtin_isfinite(v.y);
-}
-
-__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Cholesky-Crout of the row-distributed A (lane `row` holds a[c] = A[row][c]).
-// On exit a[c] = L[row][c] for c < row and inv[j] = 1 / L[j][j] in every lane.
-// Step J also advances L V = I by one row: row J of L (k < J) is final after
-// step J-1 and is already being broadcast, so v[J] = (v[J] - sum_k L[J][k] v[k]) / L[J][J].
-template <int J, int KP>
-__device__ __forceinline__ void crout_step(float2* a, float2* v, float* inv, int row, bool& ok) {
-  if constexpr (J < KP) {
-    float2 s = a[J], sv = v[J];
-#pragma unroll
-    for (int k = 0; k < J; ++k) {
-      const float2 ljk = bc2<J>(a[k]);                                   // L[J][k]
-      s = cms_bc(s, a[k], ljk);                                          // - L[row][k] conj(L[J][k])
-      sv = cms(sv, ljk, v[k]);
-    }
-    const float d = bc<J>(s.x);                                          // pivot from lane J
-    ok = ok && (d > 0.f) && __builtin_isfinite(d);
-    const float iv = __builtin_amdgcn_rsqf(d);                           // 1 / L[J][J]
-    inv[J] = iv;
-    // every lane scales: rows above J produce upper-triangle values and the
-    // diagonal lane gets ~(L[J][J], 0); neither is ever read (solves use inv[])
-    a[J] = cscale(s, iv);
-    v[J] = cscale(sv, iv);
-    __builtin_amdgcn_sched_barrier(0);   // keep the steps' live ranges apart
-  }
-}
-
-// Forward substitution L W = Z for the right-hand side held by this lane; row
-// I of L is read from the wave's LDS slab (the 16 lanes of a row read the same
-// address, a broadcast).
-template <int I, int KP>
-__device__ __forceinline__ void fwd_step(const float2* Lm, const float* inv, float2* w) {
-  if constexpr (I >= KP) return;
-  float2 sw = w[I];
-#pragma unroll
-  for (int k = 0; k < I; ++k) sw = cms(sw, Lm[I * PP + k], w[k]);      // - L[I][k] w[k]
-  w[I] = cscale(sw, inv[I]);
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int... Js>
-struct Seq {};
-using Seq16 = Seq<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
-
-// Back substitution L^H x = w (in place): x[I] = (w[I] - sum_{k>I} conj(L[k][I]) x[k]) / L[I][I].
-template <int I, int KP>
-__device__ __forceinline__ void bwd_step(const float2* Lm, const float* inv, float2* w) {
-  if constexpr (I >= KP) return;
-  float2 sx = w[I];
-#pragma unroll
-  for (int k = I + 1; k < KP; ++k) sx = cms_ac(sx, Lm[k * PP + I], w[k]);
-  w[I] = cscale(sx, inv[I]);
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int KP, int... Js>
-__device__ __forceinline__ void crout_all(Seq<Js...>, float2* a, float2* v, float* inv, int row, bool& ok) {
-  (crout_step<Js, KP>(a, v, inv, row, ok), ...);
-}
-template <int KP, int... Is>
-__device__ __forceinline__ void fwd_all(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
-  (fwd_step<Is, KP>(Lm, inv, w), ...);
-}
-template <int KP, int... Is>
-__device__ __forceinline__ void bwd_all(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
-  (bwd_step<15 - Is, KP>(Lm, inv, w), ...);
-}
-// MMSE: x_tilde_u = x_hat_u / mu_u with mu_u = 1 - N0 d_u, d_u held by lane u.
-template <int U, int KP>
-__device__ __forceinline__ void unbias(float dl, float n0, float2* z) {
-  if constexpr (U < KP) z[U] = cscale(z[U], __builtin_amdgcn_rcpf(1.0f - n0 * bc<U>(dl)));
-}
-template <int KP, int... Us>
-__device__ __forceinline__ void unbias_all(Seq<Us...>, float dl, float n0, float2* z) {
-  (unbias<Us, KP>(dl, n0, z), ...);
-}
-
-// KP = K rounded up to 4, 8 or 16: the system is padded with an identity block
-// (A_pad = diag(A, I), zero matched-filter rows), which leaves the solution of
-// the real K x K block unchanged and keeps phase 2 free of runtime bounds.
 template <int KP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
@@ -162,128 +24,19 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   __syncthreads();
 
   f32x4 gr[4], gi[4], zr[4], zi[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) gr[t] = gi[t] = zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  gram_mf(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
+          nonfin, gr, gi, zr, zi);
 
-  float2* Hs = smem;
-  float2* Ys = smem + ROWS * PITCH;
-  const float2* Hf = H + (int64_t)f * M * K * n_sc;
-  const float2* Yff = Yf + (int64_t)f * M * S * n_sc;
-  const int c16 = tid & 15;
-  const int ic = i0 + c16;
-  const bool in_range = ic < n_sc;
-  const int u = l & 15, kq = l >> 4;
-
-  // chunk loads go to registers first (all issued back to back) and the next
-  // chunk is prefetched while the current one feeds the MFMAs
-  float2 hv[8], yv[8];
-  auto load_chunk = [&](int m0) {
-    const int mc = min(MC, M - m0);
-    const int rh = mc * K, ry = mc * D;
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int r = (tid >> 4) + 16 * it;
-      hv[it] = (in_range && r < rh) ? Hf[(int64_t)(m0 * K + r) * n_sc + ic] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int r = (tid >> 4) + 16 * it;
-      const int ml = r / D, s = r - ml * D;
-      yv[it] = (in_range && r < ry) ? Yff[(int64_t)((m0 + ml) * S + 1 + s) * n_sc + ic]
-                                    : make_float2(0.f, 0.f);
-    }
-  };
-  load_chunk(0);
-  for (int m0 = 0; m0 < M; m0 += MC) {
-    const int mc = min(MC, M - m0);
-    bool bad = false;
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int r = (tid >> 4) + 16 * it;
-      bad |= !finite2(hv[it]) || !finite2(yv[it]);
-      if (r < ROWS) {
-        Hs[r * PITCH + c16] = hv[it];
-        Ys[r * PITCH + c16] = yv[it];
-      }
-    }
-    if (bad) nonfin[c16] = 1;
-    __syncthreads();
-    if (m0 + MC < M) load_chunk(m0 + MC);
-    // branch-free: rows past this chunk are zero in LDS, rows of absent users
-    // or symbols are masked by selects (row indices stay below ROWS)
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int ml = 4 * a + kq;
-      const bool okh = ml < mc && u < K;
-      const bool oky = ml < mc && u < D;
-      const int hrow = ml * K + u;
-      const int yrow = ml * D + u;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int sc = 4 * w + t;
-        const float2 hr = Hs[hrow * PITCH + sc];
-        const float2 yr = Ys[yrow * PITCH + sc];
-        const float hx = okh ? hr.x : 0.f, hy = okh ? hr.y : 0.f;
-        const float yx = oky ? yr.x : 0.f, yy = oky ? yr.y : 0.f;
-        gr[t] = mfma(hx, hx, gr[t]);
-        gr[t] = mfma(hy, hy, gr[t]);
-        gi[t] = mfma(hx, hy, gi[t]);
-        gi[t] = mfma(-hy, hx, gi[t]);
-        zr[t] = mfma(hx, yx, zr[t]);
-        zr[t] = mfma(hy, yy, zr[t]);
-        zi[t] = mfma(hx, yy, zi[t]);
-        zi[t] = mfma(-hy, yx, zi[t]);
-      }
-    }
-    __syncthreads();
-  }
-
-  // ---- phase 2: G and Z of this wave's 4 subcarriers through its LDS slab
+  // ---- phase 2
   float2* P = smem + w * 4 * PMAT;
   const int col = l & 15, g4 = (l >> 4) * 4;      // MFMA output: rows g4 + r, column col
   const int scl = l >> 4, row = l & 15;           // phase-2 lane: subcarrier scl, index row
   float2* Pm = P + scl * PMAT;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) P[t * PMAT + (g4 + r) * PP + col] = make_float2(gr[t][r], gi[t][r]);
-  __syncthreads();
-  float2 a[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    a[c] = Pm[row * PP + c];                       // row `row` of A
-    if (c == row) a[c].x = row < K ? a[c].x + (mmse ? n0 : 0.f) : 1.0f;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) P[t * PMAT + (g4 + r) * PP + col] = make_float2(zr[t][r], zi[t][r]);
-
-  // Cholesky-Crout with L V = I folded in (V = L^{-1}, column `row` per lane)
-  bool ok = true;
-  float inv[16];
-  float2 v[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);
-  crout_all<KP>(Seq16{}, a, v, inv, row, ok);     // a[c] = L[row][c] for c <= row
-  float dl = 0.f;                                  // d_row = sum_k |L^{-1}[k][row]|^2
-#pragma unroll
-  for (int k = 0; k < KP; ++k) dl += v[k].x * v[k].x + v[k].y * v[k].y;
-
-  __syncthreads();                                 // Z is in the slab
-  float2 z[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) z[k] = Pm[k * PP + row];   // column `row` of Z
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 16; ++c) Pm[row * PP + c] = a[c];   // L, row by row
-  __syncthreads();
-
-  // L W = Z, then L^H X = W
-  fwd_all<KP>(Seq16{}, Pm, inv, z);
-  bwd_all<KP>(Seq16{}, Pm, inv, z);
-  if (mmse) unbias_all<KP>(Seq16{}, dl, n0, z);
+  float2 z[16], v[16];
+  float inv[16], dl;
+  bool ok;
+  factor_solve<KP>(P, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
+  if (mmse) unbias_all<KP>(Seq16{}, dl, n0, K, z);
 
   const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
   const uint64_t bal = __ballot(mu_bad);

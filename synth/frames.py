@@ -83,9 +83,9 @@ CONFIGS = {
     4: dict(name="256 uneven frames, Rayleigh 5-30dB",
             shape=None, channel="rayleigh", snr=(5.0, 30.0), frames=256,
             detector="mmse"),
-    5: dict(name="64x8 N2048 1200sc 16QAM cascaded(256 phases) 15dB",
+    5: dict(name="64x8 N2048 1200sc 16QAM cascaded(256 phases) 5dB",
             shape=Shape(64, 8, 2048, 1200, 14, 0, 4), channel="cascaded",
-            snr=(15.0, 15.0), frames=1, detector="mmse"),
+            snr=(5.0, 5.0), frames=1, detector="mmse"),
 }
 
 

@@ -470,3 +470,21 @@ def test_snr_definition():
     yf = O.fft_stage(fr.x, sh.n_fft, sh.n_sc)
     p = np.mean(np.abs(yf[:, 1:, :]) ** 2) - fr.n0
     assert p == pytest.approx(200.0, rel=0.2)
+
+
+def test_torch_cascade_synthesis_matches_frames_and_oracle_theta_grad():
+    torch = pytest.importorskip("torch")
+    from synth.torch_cascade import cascaded_x
+    sh = synth.Shape(8, 2, 128, 60, 14, 0, 4)
+    fr = synth.make_frame(5, 0, shape=sh, keep_noise=True)
+    th = torch.tensor(fr.extra["theta"], dtype=torch.float64, requires_grad=True)
+    x = cascaded_x(th, fr, device="cpu")
+    np.testing.assert_allclose(x.detach().numpy()[0], fr.x, atol=1e-6)
+    # the generator's own adjoint (autograd) agrees with the oracle's hand-written one
+    rng = np.random.default_rng(16)
+    gx = (rng.standard_normal(fr.x.shape) + 1j * rng.standard_normal(fr.x.shape))
+    L = torch.real(torch.sum(torch.tensor(np.conj(gx)[None], dtype=torch.complex128) * x.to(torch.complex128)))
+    L.backward()
+    ref = O.cascaded_theta_grad(gx, sh, fr.extra["theta"], fr.extra["G"], fr.extra["F"],
+                                fr.extra["amp"], fr.symbols, fr.pilots)
+    np.testing.assert_allclose(th.grad.numpy(), ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
