@@ -143,7 +143,7 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames, const void
       (st = check_ptr(nu, "nu")))
     return st;
   return launch_detect(*frame, n_frames, (const float2*)h, (const float2*)yf, (float2*)xt, nu,
-                       flags, precision, cond_threshold, stream);
+                       flags, precision, cond_threshold, ws, stream);
 }
 
 rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames, const void* xt,

@@ -359,7 +359,7 @@ size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t
                              rxphy_precision precision) {
   (void)precision;
   if (check_frame(frame, n_frames) != RXPHY_OK) return 0;
-  if (which == RXPHY_WS_DETECT) return 0;
+  if (which == RXPHY_WS_DETECT) return detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_BACKWARD) return layout(*frame, n_frames).total;
   return 0;
 }
@@ -400,7 +400,7 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
     if ((st = launch_fft(fr, n_tr, (const float2*)x, (float2*)(w + L.yf), false, stream))) return st;
   if (!(saved && saved->h))
     if ((st = launch_csi(fr, n_frames, yf, (const float2*)pilots, (float2*)(w + L.h), stream))) return st;
-  if ((st = launch_detect(fr, n_frames, h, yf, xt, nu, flags, RXPHY_FP32, 0.f, stream))) return st;
+  if ((st = launch_detect(fr, n_frames, h, yf, xt, nu, flags, RXPHY_FP32, 0.f, nullptr, stream))) return st;
 
   const int D = fr.n_sym - 1;
   const int64_t n_fu = (int64_t)n_frames * fr.K;

@@ -34,7 +34,8 @@ rxphy_status launch_csi(const rxphy_frame& fr, int32_t nf, const float2* yf, con
                         float2* h, hipStream_t s);
 rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
                            float2* xt, float* nu, uint8_t* flags, rxphy_precision prec,
-                           float thr, hipStream_t s);
+                           float thr, void* ws, hipStream_t s);
+size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec);
 rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, const float* nu,
                           float* llr, hipStream_t s);
 

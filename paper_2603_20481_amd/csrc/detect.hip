@@ -2,6 +2,8 @@
 // factorisation live in detect_core.h).  The forward kernel adds the MMSE
 // unbiasing x_tilde = x_hat / mu, the noise variances, the flags and the
 // erasures, and writes x_tilde [F][K][D][n_sc], nu [F][K][n_sc], flags [F][n_sc].
+// K is padded to KP in {4, 8, 16} (an identity block: same solution,
+// straight-line phase 2).
 #include "detect_core.h"
 
 namespace rxphy {
@@ -9,11 +11,20 @@ namespace {
 
 using namespace det;
 
-template <int KP>
+// P: operand precision of the phase-1 products (detect_core.h).  For BF16 and
+// FP16, subcarriers whose condition estimate kappa = (max L_ii / min L_ii)^2
+// exceeds the threshold, or whose low-precision factorisation breaks down,
+// are handed to the FP64 refinement kernel: their x_hat (before the MMSE
+// unbiasing) is written to xt and the subcarrier is appended to a device-side
+// list (rlist[0] = count, entries from rlist[RL_OFF]).
+constexpr int RL_OFF = 64;
+
+template <int KP, int P>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
-                   float2* __restrict__ xt, float* __restrict__ nu, uint8_t* __restrict__ flags,
-                   int M, int K, int S, int n_sc, float n0, int mmse) {
+detect_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
+              float2* __restrict__ xt, float* __restrict__ nu, uint8_t* __restrict__ flags,
+              int M, int K, int S, int n_sc, float n0, int mmse, float thr,
+              uint32_t* __restrict__ rlist) {
   __shared__ float2 smem[SMEM];
   __shared__ int nonfin[TS];
   const int f = blockIdx.y;
@@ -24,27 +35,48 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   __syncthreads();
 
   f32x4 gr[4], gi[4], zr[4], zi[4];
-  gram_mf(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
-          nonfin, gr, gi, zr, zi);
+  gram_mf<P>(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
+             nonfin, gr, gi, zr, zi);
 
   // ---- phase 2
-  float2* P = smem + w * 4 * PMAT;
+  float2* Pw = smem + w * 4 * PMAT;
   const int col = l & 15, g4 = (l >> 4) * 4;      // MFMA output: rows g4 + r, column col
   const int scl = l >> 4, row = l & 15;           // phase-2 lane: subcarrier scl, index row
-  float2* Pm = P + scl * PMAT;
+  float2* Pm = Pw + scl * PMAT;
   float2 z[16], v[16];
   float inv[16], dl;
   bool ok;
-  factor_solve<KP>(P, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
-  if (mmse) unbias_all<KP>(Seq16{}, dl, n0, K, z);
+  factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
 
   const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
   const uint64_t bal = __ballot(mu_bad);
   if ((bal >> (16 * scl)) & 0xffffull) ok = false;
-
   const int i = i0 + 4 * w + scl;
-  if (i >= n_sc) return;
   const bool nf = nonfin[4 * w + scl] != 0;
+  bool refine = false;
+  if constexpr (P != P_FP32) {
+    float imax = 0.f, imin = INFINITY;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (k < K) { imax = fmaxf(imax, inv[k]); imin = fminf(imin, inv[k]); }
+    const float r = imax / imin;                  // = max L_ii / min L_ii
+    refine = !nf && (!ok || !(r * r <= thr));
+  }
+  if (mmse) unbias_all<KP>(Seq16{}, dl, n0, K, refine, z);
+  if (i >= n_sc) return;
+
+  if (refine) {                                   // finished in FP64 by refine_kernel
+    if (row == 0) {
+      const uint32_t slot = atomicAdd(rlist, 1u);
+      rlist[RL_OFF + slot] = (uint32_t)((int64_t)f * n_sc + i);
+    }
+    if (row < D) {
+#pragma unroll
+      for (int uu = 0; uu < 16; ++uu)
+        if (uu < K) xt[((int64_t)(f * K + uu) * D + row) * n_sc + i] = z[uu];
+    }
+    return;
+  }
   const bool erase = nf || !ok;
   if (row < D) {
 #pragma unroll
@@ -70,26 +102,185 @@ detect_fp32_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   if (row == 0 && flags) flags[(int64_t)f * n_sc + i] = nf ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
 }
 
+__global__ void clear_count_kernel(uint32_t* rlist) {
+  if (threadIdx.x == 0) rlist[0] = 0u;
+}
+
+// ------------------------------------------------------------ FP64 refinement
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 dmulcj(double2 a, double2 b) {   // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 dsc(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+constexpr int RP = 17;   // row pitch (double2) of the 16 x 16 work matrices
+
+// One wavefront per listed subcarrier (grid-stride over the list): A and
+// b = H^H y are re-formed in FP64 from the FP32 inputs, A = L L^H in FP64, one
+// refinement step x1 = x0 + A^{-1} (b - A x0) from the low-precision x0, and
+// d = diag(A^{-1}) from the FP64 factor; then the unbiasing, nu and flags.
+__global__ void __launch_bounds__(64)
+refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf, float2* __restrict__ xt,
+              float* __restrict__ nu, uint8_t* __restrict__ flags, const uint32_t* __restrict__ rlist,
+              int M, int K, int S, int n_sc, float n0f, int mmse) {
+  __shared__ double2 Hs[64 * 16];
+  __shared__ double2 Ys[64 * 16];
+  __shared__ double2 A[16 * RP];
+  __shared__ double2 R[16 * RP];
+  __shared__ double2 X[16 * RP];
+  __shared__ double2 V[16 * RP];
+  __shared__ double dd[16];
+  __shared__ int bad;
+  const int D = S - 1;
+  const int tid = threadIdx.x;
+  const double n0 = (double)n0f;
+  const uint32_t count = rlist[0];
+  for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+    const uint32_t sub = rlist[RL_OFF + e];
+    const int f = (int)(sub / (uint32_t)n_sc), i = (int)(sub - (uint32_t)f * n_sc);
+    for (int q = tid; q < M * K; q += 64) {
+      const int m = q / K, u = q - m * K;
+      Hs[m * 16 + u] = d2(H[((int64_t)(f * M + m) * K + u) * n_sc + i]);
+    }
+    for (int q = tid; q < M * D; q += 64) {
+      const int m = q / D, s = q - m * D;
+      Ys[m * 16 + s] = d2(Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i]);
+    }
+    for (int q = tid; q < K * D; q += 64) {
+      const int u = q / D, s = q - u * D;
+      X[u * RP + s] = d2(xt[((int64_t)(f * K + u) * D + s) * n_sc + i]);
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int q = tid; q < K * K; q += 64) {                       // A = H^H H (+ N0 I)
+      const int r = q / K, c = q - r * K;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int m = 0; m < M; ++m) acc = dadd(acc, dmulcj(Hs[m * 16 + r], Hs[m * 16 + c]));
+      if (r == c && mmse) acc.x += n0;
+      A[r * RP + c] = acc;
+    }
+    for (int q = tid; q < K * D; q += 64) {                       // b = H^H Y
+      const int r = q / D, s = q - r * D;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int m = 0; m < M; ++m) acc = dadd(acc, dmulcj(Hs[m * 16 + r], Ys[m * 16 + s]));
+      R[r * RP + s] = acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < K * D; q += 64) {                       // residual b - A x0
+      const int r = q / D, s = q - r * D;
+      double2 acc = R[r * RP + s];
+      for (int k = 0; k < K; ++k) acc = dsub(acc, dmul(A[r * RP + k], X[k * RP + s]));
+      R[r * RP + s] = acc;
+    }
+    __syncthreads();
+    for (int j = 0; j < K; ++j) {                                 // A = L L^H in place
+      if (tid == 0) {
+        const double dj = A[j * RP + j].x;
+        if (!(dj > 0.0) || !isfinite(dj)) bad = 1;
+        A[j * RP + j] = make_double2(sqrt(dj), 0.0);
+      }
+      __syncthreads();
+      const double ljj = A[j * RP + j].x;
+      for (int r = j + 1 + tid; r < K; r += 64) A[r * RP + j] = dsc(A[r * RP + j], 1.0 / ljj);
+      __syncthreads();
+      const int w2 = K - j - 1;
+      for (int q = tid; q < w2 * w2; q += 64) {
+        const int r = j + 1 + q / w2, c = j + 1 + q % w2;
+        if (c <= r) A[r * RP + c] = dsub(A[r * RP + c], dmul(A[r * RP + j], make_double2(A[c * RP + j].x, -A[c * RP + j].y)));
+      }
+      __syncthreads();
+    }
+    if (tid < D) {                                                // delta = A^{-1} residual, per column
+      const int s = tid;
+      for (int r = 0; r < K; ++r) {
+        double2 acc = R[r * RP + s];
+        for (int k = 0; k < r; ++k) acc = dsub(acc, dmul(A[r * RP + k], R[k * RP + s]));
+        R[r * RP + s] = dsc(acc, 1.0 / A[r * RP + r].x);
+      }
+      for (int r = K - 1; r >= 0; --r) {
+        double2 acc = R[r * RP + s];
+        for (int k = r + 1; k < K; ++k) acc = dsub(acc, dmulcj(A[k * RP + r], R[k * RP + s]));
+        R[r * RP + s] = dsc(acc, 1.0 / A[r * RP + r].x);
+        X[r * RP + s] = dadd(X[r * RP + s], R[r * RP + s]);
+      }
+    } else if (tid >= 32 && tid - 32 < K) {                       // column u of L^{-1}: d_u
+      const int u = tid - 32;
+      double acc2 = 0.0;
+      for (int r = 0; r < K; ++r) {
+        double2 acc = make_double2(r == u ? 1.0 : 0.0, 0.0);
+        for (int k = u; k < r; ++k) acc = dsub(acc, dmul(A[r * RP + k], V[k * RP + u]));
+        const double2 vr = r < u ? make_double2(0.0, 0.0) : dsc(acc, 1.0 / A[r * RP + r].x);
+        V[r * RP + u] = vr;
+        acc2 += vr.x * vr.x + vr.y * vr.y;
+      }
+      dd[u] = acc2;
+      if (mmse && !(1.0 - n0 * acc2 > 0.0)) bad = 1;
+    }
+    __syncthreads();
+    const bool erase = bad != 0;
+    for (int q = tid; q < K * D; q += 64) {
+      const int u = q / D, s = q - u * D;
+      double2 x = X[u * RP + s];
+      if (mmse) x = dsc(x, 1.0 / (1.0 - n0 * dd[u]));
+      xt[((int64_t)(f * K + u) * D + s) * n_sc + i] = erase ? make_float2(0.f, 0.f) : make_float2((float)x.x, (float)x.y);
+    }
+    for (int u = tid; u < K; u += 64) {
+      const double d = dd[u];
+      const double nv = mmse ? n0 * d / (1.0 - n0 * d) : n0 * d;
+      nu[(int64_t)(f * K + u) * n_sc + i] = erase ? INFINITY : (float)nv;
+    }
+    if (tid == 0 && flags) flags[(int64_t)f * n_sc + i] = erase ? RXPHY_FLAG_BREAKDOWN : RXPHY_FLAG_REFINED;
+    __syncthreads();
+  }
+}
+
+template <int KP, int P>
+void launch_one(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, float2* xt,
+                float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
+  dim3 grid((fr.n_sc + TS - 1) / TS, nf);
+  hipLaunchKernelGGL((detect_kernel<KP, P>), grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
+                     fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0, thr, rl);
+}
+
+template <int P>
+void launch_p(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, float2* xt,
+              float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
+  if (fr.K <= 4) launch_one<4, P>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+  else if (fr.K <= 8) launch_one<8, P>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+  else launch_one<16, P>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+}
+
 }  // namespace
+
+size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
+  if (prec == RXPHY_FP32) return 0;
+  return (size_t)RL_OFF * 4 + (size_t)nf * fr.n_sc * 4;
+}
 
 rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
                            float2* xt, float* nu, uint8_t* flags, rxphy_precision prec, float thr,
-                           hipStream_t s) {
-  (void)thr;
+                           void* ws, hipStream_t s) {
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
-  if (prec != RXPHY_FP32) return fail(RXPHY_EUNSUPPORTED, "precision %d not built yet", (int)prec);
-  dim3 grid((fr.n_sc + TS - 1) / TS, nf);
-  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
-  if (fr.K <= 4)
-    hipLaunchKernelGGL(detect_fp32_kernel<4>, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
-                       fr.n_sym, fr.n_sc, fr.n0, mmse);
-  else if (fr.K <= 8)
-    hipLaunchKernelGGL(detect_fp32_kernel<8>, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
-                       fr.n_sym, fr.n_sc, fr.n0, mmse);
-  else
-    hipLaunchKernelGGL(detect_fp32_kernel<16>, grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
-                       fr.n_sym, fr.n_sc, fr.n0, mmse);
-  return launch_status("detect kernel");
+  if (prec == RXPHY_FP32) {
+    launch_p<P_FP32>(fr, nf, h, yf, xt, nu, flags, thr, nullptr, s);
+    return launch_status("detect kernel");
+  }
+  uint32_t* rl = (uint32_t*)ws;
+  hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(64), 0, s, rl);
+  if (prec == RXPHY_BF16) launch_p<P_BF16>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+  else launch_p<P_FP16>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+  rxphy_status st = launch_status("detect kernel");
+  if (st) return st;
+  const int64_t n_sub = (int64_t)nf * fr.n_sc;
+  const unsigned blocks = (unsigned)(n_sub < 4096 ? n_sub : 4096);
+  hipLaunchKernelGGL(refine_kernel, dim3(blocks), dim3(64), 0, s, h, yf, xt, nu, flags, rl, fr.M, fr.K,
+                     fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  return launch_status("refine kernel");
 }
 
 }  // namespace rxphy

@@ -72,6 +72,30 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Operand precision of the phase-1 products.
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x16 product with 4 operand values per lane (k = 4 (lane / 16) + v),
+// operands rounded to nearest even from FP32, FP32 accumulation.
+template <int P>
+__device__ __forceinline__ f32x4 mfma_lp(float a0, float a1, float a2, float a3, float b0, float b1,
+                                         float b2, float b3, f32x4 c) {
+  if constexpr (P == P_BF16) {
+    const bf16x4 a = {(__bf16)a0, (__bf16)a1, (__bf16)a2, (__bf16)a3};
+    const bf16x4 b = {(__bf16)b0, (__bf16)b1, (__bf16)b2, (__bf16)b3};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                     __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+  } else {
+    const f16x4 a = {(_Float16)a0, (_Float16)a1, (_Float16)a2, (_Float16)a3};
+    const f16x4 b = {(_Float16)b0, (_Float16)b1, (_Float16)b2, (_Float16)b3};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+}
+
 // Cholesky-Crout of the row-distributed A (lane `row` holds a[c] = A[row][c]).
 // On exit a[c] = L[row][c] for c < row and inv[j] = 1 / L[j][j] in every lane.
 // Step J also advances L V = I by one row: row J of L (k < J) is final after
@@ -146,15 +170,15 @@ __device__ __forceinline__ void bwd_all(Seq<Is...>, const float2* Lm, const floa
 // MMSE: x_tilde_u = x_hat_u / mu_u with mu_u = 1 - N0 d_u, d_u held by lane u
 // (padded users, u >= K, are left as they are).
 template <int U, int KP>
-__device__ __forceinline__ void unbias(float dl, float n0, int K, float2* z) {
+__device__ __forceinline__ void unbias(float dl, float n0, int K, bool keep, float2* z) {
   if constexpr (U < KP) {
-    const float r = __builtin_amdgcn_rcpf(1.0f - n0 * bc<U>(dl));
-    if (U < K) z[U] = cscale(z[U], r);
+    const float r = __builtin_amdgcn_rcpf(1.0f - n0 * bc<U>(dl));   // every lane joins the DPP
+    if (U < K && !keep) z[U] = cscale(z[U], r);
   }
 }
 template <int KP, int... Us>
-__device__ __forceinline__ void unbias_all(Seq<Us...>, float dl, float n0, int K, float2* z) {
-  (unbias<Us, KP>(dl, n0, K, z), ...);
+__device__ __forceinline__ void unbias_all(Seq<Us...>, float dl, float n0, int K, bool keep, float2* z) {
+  (unbias<Us, KP>(dl, n0, K, keep, z), ...);
 }
 
 
@@ -162,6 +186,7 @@ __device__ __forceinline__ void unbias_all(Seq<Us...>, float dl, float n0, int K
 // that frame).  Accumulators: gr/gi = Re/Im G, zr/zi = Re/Im Z, one per
 // subcarrier of the wave, in MFMA output layout (lane l: rows 4(l/16)+r,
 // column l%16).  nonfin[c] is set for tile subcarriers with non-finite input.
+template <int P = P_FP32>
 __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
                                         int M, int K, int S, int n_sc, int i0, float2* smem,
                                         int* nonfin, f32x4* gr, f32x4* gi, f32x4* zr, f32x4* zi) {
@@ -214,30 +239,55 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
     if (bad) nonfin[c16] = 1;
     __syncthreads();
     if (m0 + MC < M) load_chunk(m0 + MC);
-    // branch-free: rows past this chunk are zero in LDS, rows of absent users
-    // or symbols are masked by selects (row indices stay below ROWS)
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int ml = 4 * a + kq;
-      const bool okh = ml < mc && u < K;
-      const bool oky = ml < mc && u < D;
-      const int hrow = ml * K + u;
-      const int yrow = ml * D + u;
+    if constexpr (P == P_FP32) {
+      // branch-free: rows past this chunk are zero in LDS, rows of absent users
+      // or symbols are masked by selects (row indices stay below ROWS)
+  #pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int ml = 4 * a + kq;
+        const bool okh = ml < mc && u < K;
+        const bool oky = ml < mc && u < D;
+        const int hrow = ml * K + u;
+        const int yrow = ml * D + u;
+  #pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int sc = 4 * w + t;
+          const float2 hr = Hs[hrow * PITCH + sc];
+          const float2 yr = Ys[yrow * PITCH + sc];
+          const float hx = okh ? hr.x : 0.f, hy = okh ? hr.y : 0.f;
+          const float yx = oky ? yr.x : 0.f, yy = oky ? yr.y : 0.f;
+          gr[t] = mfma(hx, hx, gr[t]);
+          gr[t] = mfma(hy, hy, gr[t]);
+          gi[t] = mfma(hx, hy, gi[t]);
+          gi[t] = mfma(-hy, hx, gi[t]);
+          zr[t] = mfma(hx, yx, zr[t]);
+          zr[t] = mfma(hy, yy, zr[t]);
+          zi[t] = mfma(hx, yy, zi[t]);
+          zi[t] = mfma(-hy, yx, zi[t]);
+        }
+      }
+    } else {
+      // one 16x16x16 instruction per product covers the whole 8-antenna chunk:
+      // lane (kq, u) supplies antennas 2 kq and 2 kq + 1 as (re, im, re, im);
+      // Re G = X^T X, Im G = X^T X', Re Z = X^T Y, Im Z = X^T Y' with
+      // X' = (b, -a) and Y' = (d, -c) per antenna.
+      const int ml0 = 2 * kq, ml1 = 2 * kq + 1;
+      const bool okh0 = ml0 < mc && u < K, okh1 = ml1 < mc && u < K;
+      const bool oky0 = ml0 < mc && u < D, oky1 = ml1 < mc && u < D;
+      const int hr0 = ml0 * K + u, hr1 = ml1 * K + u, yr0 = ml0 * D + u, yr1 = ml1 * D + u;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int sc = 4 * w + t;
-        const float2 hr = Hs[hrow * PITCH + sc];
-        const float2 yr = Ys[yrow * PITCH + sc];
-        const float hx = okh ? hr.x : 0.f, hy = okh ? hr.y : 0.f;
-        const float yx = oky ? yr.x : 0.f, yy = oky ? yr.y : 0.f;
-        gr[t] = mfma(hx, hx, gr[t]);
-        gr[t] = mfma(hy, hy, gr[t]);
-        gi[t] = mfma(hx, hy, gi[t]);
-        gi[t] = mfma(-hy, hx, gi[t]);
-        zr[t] = mfma(hx, yx, zr[t]);
-        zr[t] = mfma(hy, yy, zr[t]);
-        zi[t] = mfma(hx, yy, zi[t]);
-        zi[t] = mfma(-hy, yx, zi[t]);
+        const float2 a0 = Hs[hr0 * PITCH + sc], a1 = Hs[hr1 * PITCH + sc];
+        const float2 c0 = Ys[yr0 * PITCH + sc], c1 = Ys[yr1 * PITCH + sc];
+        const float h0x = okh0 ? a0.x : 0.f, h0y = okh0 ? a0.y : 0.f;
+        const float h1x = okh1 ? a1.x : 0.f, h1y = okh1 ? a1.y : 0.f;
+        const float y0x = oky0 ? c0.x : 0.f, y0y = oky0 ? c0.y : 0.f;
+        const float y1x = oky1 ? c1.x : 0.f, y1y = oky1 ? c1.y : 0.f;
+        gr[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, h0x, h0y, h1x, h1y, gr[t]);
+        gi[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, h0y, -h0x, h1y, -h1x, gi[t]);
+        zr[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, y0x, y0y, y1x, y1y, zr[t]);
+        zi[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, y0y, -y0x, y1y, -y1x, zi[t]);
       }
     }
     __syncthreads();
