@@ -166,6 +166,95 @@ enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1 };
 size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
                              rxphy_precision precision);
 
+/* ---------------------------------------------------------------------------
+ * Batched uneven frames.  A plan holds frames of differing shape (each one a
+ * valid rxphy_frame) and runs all four forward stages of all of them in ONE
+ * persistent launch: a fixed grid of workgroups pulls work items (a group of
+ * FFT segments, of CSI tiles, of detector subcarrier tiles or of demod
+ * elements of one frame) from a device queue in stage-major order, and an
+ * item of stage s of frame f starts once every item of stage s-1 of frame f
+ * has finished (per-frame stage counters).  Each frame's results are those of
+ * the four single-frame calls (FP32 detector) on that frame, bit for bit when
+ * the frame's detector uses the same K padding as rxphy_detect.
+ *
+ * Buffers are packed: frame f's tensor T (laid out as in the single-frame
+ * calls with F = 1) starts at byte offset offsets[f].T of the one buffer for
+ * T; every offset is a multiple of 256.  rxphy_plan_layout gives the offsets
+ * and the buffer sizes.  Plans own a small device allocation (descriptor
+ * table, work list, counters) made by rxphy_plan_create; running a plan
+ * allocates nothing.  Two runs of one plan must not overlap in time (they
+ * share the counters); different plans are independent.
+ * ------------------------------------------------------------------------- */
+
+typedef struct rxphy_plan rxphy_plan;   /* opaque */
+
+/* Work-item sizes of one frame (0 = default).  Any values >= 1 give the same
+ * results except det_kp, which changes the detector's arithmetic padding. */
+typedef struct {
+  int32_t fft_iters;   /* FFT item = fft_iters rounds of max(1, 2048 / n_fft) segments                 */
+  int32_t csi_tiles;   /* CSI item = csi_tiles consecutive (antenna, 512-subcarrier) tiles              */
+  int32_t det_tiles;   /* detector item = det_tiles consecutive 16-subcarrier tiles                     */
+  int32_t det_kp;      /* K padding of the detector: 0 = smallest of {4, 8, 16} >= K, else 4, 8 or 16   */
+  int32_t dem_groups;  /* demod item = dem_groups x 256 consecutive (user, symbol, subcarrier) elements  */
+} rxphy_tiles;
+
+enum {
+  RXPHY_STAGE_FFT = 1, RXPHY_STAGE_CSI = 2, RXPHY_STAGE_DETECT = 4, RXPHY_STAGE_DEMOD = 8,
+  RXPHY_STAGE_ALL = 15
+};
+
+typedef struct {
+  int32_t stages;      /* RXPHY_STAGE_* mask of the stages to run (0 = all); a stage left out is
+                          not waited for, so its outputs must already be in the buffers          */
+  int32_t grid;        /* workgroups of the persistent launch (0 = every resident slot)       */
+  uint32_t spin_limit; /* polls of a stage counter (about 0.1 us apart) before a wait gives up
+                          (0 = 2^22, about half a second)                                   */
+} rxphy_plan_options;
+
+/* Byte offsets of one frame's tensors in the packed buffers (or, for the
+ * totals, the byte size of each buffer). */
+typedef struct {
+  int64_t x, pilots, yf, h, xt, nu, flags, llr;
+} rxphy_offsets;
+
+/* Device pointers of the packed buffers (flags may be NULL). */
+typedef struct {
+  const void* x;
+  const void* pilots;
+  void* yf;
+  void* h;
+  void* xt;
+  float* nu;
+  uint8_t* flags;
+  float* llr;
+} rxphy_batch;
+
+/* Status bits of rxphy_plan_device_status */
+enum { RXPHY_PLAN_WAIT_TIMEOUT = 1u };
+
+/* Validates every frame (1 <= n_frames <= 16384), sizes the work items
+ * (tiles: n_frames entries or NULL for defaults; options may be NULL) and
+ * uploads the descriptor table and work list to the current device.        */
+rxphy_status rxphy_plan_create(const rxphy_frame* frames, int32_t n_frames, const rxphy_tiles* tiles,
+                               const rxphy_plan_options* options, rxphy_plan** plan);
+/* per_frame: n_frames entries (may be NULL); totals: buffer sizes (may be NULL) */
+rxphy_status rxphy_plan_layout(const rxphy_plan* plan, rxphy_offsets* per_frame, rxphy_offsets* totals);
+/* Number of work items per stage (counts[4], FFT .. demod) and the grid. */
+rxphy_status rxphy_plan_info(const rxphy_plan* plan, int64_t* counts, int32_t* grid);
+/* Runs the plan on `stream` (a counter-reset kernel, then the persistent
+ * kernel; no memset and no allocation, so the call may be stream-captured). */
+rxphy_status rxphy_plan_forward(rxphy_plan* plan, const rxphy_batch* buffers, hipStream_t stream);
+/* Builds (or rebuilds) a hipGraph of the same two launches bound to
+ * `buffers`, owned by the plan; rxphy_plan_replay launches it on `stream`. */
+rxphy_status rxphy_plan_graph(rxphy_plan* plan, const rxphy_batch* buffers);
+rxphy_status rxphy_plan_replay(rxphy_plan* plan, hipStream_t stream);
+/* Reads the device status word of the last run with a blocking copy; call it
+ * after that run has completed (e.g. after synchronising its stream).
+ * 0 = clean; RXPHY_PLAN_WAIT_TIMEOUT = a dependency wait hit spin_limit and
+ * the results of that run are not to be trusted. */
+rxphy_status rxphy_plan_device_status(rxphy_plan* plan, uint32_t* status);
+void rxphy_plan_destroy(rxphy_plan* plan);
+
 /* Human-readable name of a status, and thread-local detail of the last
  * non-OK status returned on the calling thread (empty string if none). */
 const char* rxphy_status_string(rxphy_status status);

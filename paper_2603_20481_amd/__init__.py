@@ -36,6 +36,27 @@ class _Saved(ctypes.Structure):
     _fields_ = [("yf", ctypes.c_void_p), ("h", ctypes.c_void_p)]
 
 
+class _Tiles(ctypes.Structure):
+    _fields_ = [("fft_iters", ctypes.c_int32), ("csi_tiles", ctypes.c_int32),
+                ("det_tiles", ctypes.c_int32), ("det_kp", ctypes.c_int32),
+                ("dem_groups", ctypes.c_int32)]
+
+
+class _PlanOptions(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("grid", ctypes.c_int32), ("spin_limit", ctypes.c_uint32)]
+
+
+_TENSORS = ("x", "pilots", "yf", "h", "xt", "nu", "flags", "llr")
+
+
+class _Offsets(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in _TENSORS]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in _TENSORS]
+
+
 @dataclasses.dataclass(frozen=True)
 class Frame:
     """Shape of one frame (mirrors ``rxphy_frame``)."""
@@ -88,6 +109,23 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    PL = ctypes.c_void_p
+    plan_sigs = {
+        "rxphy_plan_create": [FR, I32, ctypes.POINTER(_Tiles), ctypes.POINTER(_PlanOptions),
+                              ctypes.POINTER(PL)],
+        "rxphy_plan_layout": [PL, ctypes.POINTER(_Offsets), ctypes.POINTER(_Offsets)],
+        "rxphy_plan_info": [PL, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I32)],
+        "rxphy_plan_forward": [PL, ctypes.POINTER(_Batch), P],
+        "rxphy_plan_graph": [PL, ctypes.POINTER(_Batch)],
+        "rxphy_plan_replay": [PL, P],
+        "rxphy_plan_device_status": [PL, ctypes.POINTER(ctypes.c_uint32)],
+    }
+    for name, args in plan_sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rxphy_plan_destroy.argtypes = [PL]
+    lib.rxphy_plan_destroy.restype = None
     lib.rxphy_workspace_bytes.argtypes = [FR, I32, I32, I32]
     lib.rxphy_workspace_bytes.restype = SZ
     lib.rxphy_status_string.argtypes = [ctypes.c_int]
@@ -245,3 +283,118 @@ class RxphyFunction(torch.autograd.Function):
         x, pilots, yf, h = ctx.saved_tensors
         dx = backward(ctx.fr, x, pilots, dllr.contiguous(), saved=dict(yf=yf, h=h))
         return dx, None, None
+
+
+# ------------------------------------------------------------ batched plans
+STAGE_FFT, STAGE_CSI, STAGE_DETECT, STAGE_DEMOD, STAGE_ALL = 1, 2, 4, 8, 15
+PLAN_WAIT_TIMEOUT = 1
+
+
+@dataclasses.dataclass(frozen=True)
+class Tiles:
+    """Work-item sizes of one frame in a plan (0 = the library default)."""
+    fft_iters: int = 0
+    csi_tiles: int = 0
+    det_tiles: int = 0
+    det_kp: int = 0
+    dem_groups: int = 0
+
+    def c(self) -> _Tiles:
+        return _Tiles(self.fft_iters, self.csi_tiles, self.det_tiles, self.det_kp, self.dem_groups)
+
+
+class Plan:
+    """Frames of differing shape run by one persistent launch (rxphy_plan_*).
+
+    Buffers are packed byte tensors (one per tensor name in ``TENSORS``);
+    ``view(bufs, name, f)`` is frame f's tensor inside them, shaped as the
+    single-frame calls shape it with F = 1."""
+
+    TENSORS = _TENSORS
+
+    def __init__(self, frames, tiles=None, stages: int = 0, grid: int = 0, spin_limit: int = 0):
+        lib = load()
+        self.frames = list(frames)
+        n = len(self.frames)
+        arr = (_Frame * n)(*[f.c() for f in self.frames])
+        if tiles is None:
+            tarr = None
+        else:
+            tl = list(tiles) if isinstance(tiles, (list, tuple)) else [tiles] * n
+            if len(tl) != n:
+                raise RxphyError("tiles needs one entry per frame")
+            tarr = (_Tiles * n)(*[t.c() for t in tl])
+        opt = _PlanOptions(int(stages), int(grid), int(spin_limit))
+        h = ctypes.c_void_p()
+        _check(lib.rxphy_plan_create(arr, n, tarr, ctypes.byref(opt), ctypes.byref(h)),
+               "rxphy_plan_create")
+        self._h = h
+        offs = (_Offsets * n)()
+        tot = _Offsets()
+        _check(lib.rxphy_plan_layout(h, offs, ctypes.byref(tot)), "rxphy_plan_layout")
+        self.offsets = [{k: int(getattr(o, k)) for k in _TENSORS} for o in offs]
+        self.totals = {k: int(getattr(tot, k)) for k in _TENSORS}
+        counts = (ctypes.c_int64 * 4)()
+        g = ctypes.c_int32()
+        _check(lib.rxphy_plan_info(h, counts, ctypes.byref(g)), "rxphy_plan_info")
+        self.counts = [int(c) for c in counts]
+        self.grid = int(g.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rxphy_plan_destroy(h)
+            self._h = None
+
+    # ---- buffers
+    def shape(self, name: str, f: int):
+        fr = self.frames[f]
+        return {"x": (fr.M, fr.n_sym, fr.cp_len + fr.n_fft), "pilots": (fr.n_sc,),
+                "yf": (fr.M, fr.n_sym, fr.n_sc), "h": (fr.M, fr.K, fr.n_sc),
+                "xt": (fr.K, fr.n_data, fr.n_sc), "nu": (fr.K, fr.n_sc), "flags": (fr.n_sc,),
+                "llr": (fr.K, fr.n_data, fr.n_sc, fr.qam_bits)}[name]
+
+    @staticmethod
+    def dtype(name: str):
+        return {"x": torch.complex64, "pilots": torch.complex64, "yf": torch.complex64,
+                "h": torch.complex64, "xt": torch.complex64, "nu": torch.float32,
+                "flags": torch.uint8, "llr": torch.float32}[name]
+
+    def alloc(self, device="cuda"):
+        return {k: torch.empty((max(self.totals[k], 1),), dtype=torch.uint8, device=device)
+                for k in _TENSORS}
+
+    def view(self, bufs, name: str, f: int):
+        shp = self.shape(name, f)
+        dt = self.dtype(name)
+        n = 1
+        for d in shp:
+            n *= d
+        nbytes = n * torch.empty((), dtype=dt).element_size()
+        o = self.offsets[f][name]
+        return bufs[name][o:o + nbytes].view(dt).view(shp)
+
+    def _batch(self, bufs) -> _Batch:
+        for k in _TENSORS:
+            t = bufs[k]
+            if t.device.type != "cuda" or t.numel() * t.element_size() < self.totals[k]:
+                raise RxphyError("buffer %s must be a device tensor of >= %d bytes" % (k, self.totals[k]))
+        return _Batch(*[bufs[k].data_ptr() for k in _TENSORS])
+
+    # ---- runs
+    def forward(self, bufs):
+        b = self._batch(bufs)
+        _check(load().rxphy_plan_forward(self._h, ctypes.byref(b), _stream()), "rxphy_plan_forward")
+
+    def graph(self, bufs):
+        b = self._batch(bufs)
+        _check(load().rxphy_plan_graph(self._h, ctypes.byref(b)), "rxphy_plan_graph")
+        self._graph_bufs = bufs      # keep the bound buffers alive
+
+    def replay(self):
+        _check(load().rxphy_plan_replay(self._h, _stream()), "rxphy_plan_replay")
+
+    def device_status(self) -> int:
+        v = ctypes.c_uint32()
+        _check(load().rxphy_plan_device_status(self._h, ctypes.byref(v)), "rxphy_plan_device_status")
+        return int(v.value)

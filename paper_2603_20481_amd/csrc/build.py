@@ -8,19 +8,28 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "librxphy.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "demod.hip", "backward.hip"]
-HEADERS = ["common.h", "detect_core.h"]
+SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "demod.hip", "backward.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # keep the compiler from forming packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # fuse a*b+c only within one source expression, never across them:
+         # the same tile body then rounds the same way in every kernel that
+         # inlines it (the batched kernel reproduces the per-stage kernels)
+         "-ffp-contract=on",
          "-Wall", "-Wno-unused-function"]
+
+
+# Per-source extra flags.  The persistent batched kernel holds every stage body
+# in one item loop; machine-level loop-invariant code motion would hoist the
+# constants of all of them out of that loop and run out of SGPRs.
+EXTRA = {"batch.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(HERE, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))

@@ -42,6 +42,15 @@ rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, c
 inline int64_t sym_len(const rxphy_frame& f) { return (int64_t)f.cp_len + f.n_fft; }
 
 // ---------------------------------------------------------------- device side
+// threadIdx.x behind an empty asm: the tile bodies read it through this so that
+// nothing derived from it is hoisted out of the persistent kernel's item loop
+// (where it would stay live, and spill, across every stage's body).
+__device__ __forceinline__ int tid_x() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -1,0 +1,56 @@
+// CSI tile body (least-squares channel estimate from comb pilots, held over
+// the pilot group), shared by the per-stage CSI kernel and the persistent
+// batched kernel.
+//
+// A tile is one antenna and CSI_TILE consecutive subcarriers.  The LS value
+// Yf0[q] conj(p[q]) / |p[q]|^2 is formed once per pilot subcarrier q that the
+// tile needs and parked in LDS; every thread then writes two subcarriers of
+// each user's row of H, so each store instruction of a wave covers 512
+// contiguous bytes.
+#pragma once
+
+#include "common.h"
+
+namespace rxphy {
+namespace csik {
+
+constexpr int CSI_TILE = 512;
+constexpr int CSI_WG = 256;
+constexpr int CSI_LDS = CSI_TILE + 32;
+
+// y0: the antenna's pilot-symbol row Yf[m][0][:]; pf: the frame's pilot row;
+// hm: H[m][0][0] of the frame ([K][n_sc] rows follow).  256 threads.
+__device__ __forceinline__ void csi_tile(const float2* __restrict__ y0, const float2* __restrict__ pf,
+                                         float2* __restrict__ hm, int K, int n_sc, int i0,
+                                         float2* ls) {
+  const int tx = tid_x();
+  const int G = n_sc / K;
+  const int i_last = min(i0 + CSI_TILE, n_sc) - 1;
+  const int q0 = min(i0 / K, G - 1) * K;                     // first pilot subcarrier needed
+  const int q1 = min(i_last / K, G - 1) * K + K;             // one past the last
+  for (int q = q0 + tx; q < q1; q += CSI_WG) {
+    const float2 y = y0[q];
+    const float2 p = pf[q];
+    const float pp = p.x * p.x + p.y * p.y;
+    // y conj(p) / |p|^2 ; a zero pilot gives 0/0 = NaN, flagged downstream
+    ls[q - q0] = make_float2((y.x * p.x + y.y * p.y) / pp, (y.y * p.x - y.x * p.y) / pp);
+  }
+  __syncthreads();
+  int gq[2];
+  bool ok[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = i0 + tx + e * CSI_WG;
+    ok[e] = i < n_sc;
+    gq[e] = ok[e] ? min(i / K, G - 1) * K - q0 : 0;
+  }
+  float2* hp = hm + i0 + tx;
+  for (int u = 0; u < K; ++u) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ok[e]) hp[(int64_t)u * n_sc + e * CSI_WG] = ls[gq[e] + u];
+  }
+}
+
+}  // namespace csik
+}  // namespace rxphy

@@ -1,55 +1,13 @@
-// demod stage: max-log LLRs over the Gray square-QAM set.
-//
-// The constellation is the Cartesian product of two Gray PAM axes (b0, b2, b4
-// on the in-phase axis, b1, b3, b5 on the quadrature axis), so for a bit on one
-// axis the other axis contributes the same minimum to both sides and cancels:
-// each LLR is an exact max-log value computed from one axis alone,
-//   llr = ((x - l1)^2 - (x - l0)^2) / nu = (l0 - l1)(2x - l0 - l1) / nu,
-// with l_b the nearest level whose bit is b (the product form avoids the
-// cancellation of the two squares).  One thread per (frame, user, symbol,
-// subcarrier); consecutive threads write consecutive LLR groups.
-#include "common.h"
+// demod stage: max-log LLRs, one thread per (frame, user, symbol, subcarrier);
+// consecutive threads write consecutive LLR groups.  The body is
+// demk::demod_elem (frames are contiguous, so the frame index folds into the
+// user index).
+#include "demod_core.h"
 
 namespace rxphy {
 namespace {
 
-template <int Q>
-__device__ __forceinline__ float axis_level(int code) {
-  // code bit (B-1-t) is the axis' t-th bit; t = 0 is the sign bit
-  constexpr int B = Q / 2;
-  if constexpr (B == 1) {
-    return (code & 1) ? -0.70710678118654752f : 0.70710678118654752f;
-  } else if constexpr (B == 2) {
-    const float s0 = (code & 2) ? -1.f : 1.f, s1 = (code & 1) ? -1.f : 1.f;
-    return s0 * (2.f - s1) * 0.31622776601683793f;      // 1/sqrt(10)
-  } else {
-    const float s0 = (code & 4) ? -1.f : 1.f, s1 = (code & 2) ? -1.f : 1.f, s2 = (code & 1) ? -1.f : 1.f;
-    return s0 * (4.f - s1 * (2.f - s2)) * 0.15430334996209191f;   // 1/sqrt(42)
-  }
-}
-
-// LLRs of the B bits carried by one axis at coordinate x (out[t] for axis bit t).
-template <int Q>
-__device__ __forceinline__ void axis_llr(float x, float inv_nu, float* out) {
-  constexpr int B = Q / 2;
-  constexpr int NL = 1 << B;
-  float d0[B], d1[B], l0[B], l1[B];
-#pragma unroll
-  for (int t = 0; t < B; ++t) { d0[t] = d1[t] = INFINITY; l0[t] = l1[t] = 0.f; }
-#pragma unroll
-  for (int code = 0; code < NL; ++code) {   // increasing code = increasing point index
-    const float lv = axis_level<Q>(code);
-    const float d = (x - lv) * (x - lv);
-#pragma unroll
-    for (int t = 0; t < B; ++t) {
-      const bool one = (code >> (B - 1 - t)) & 1;
-      if (one) { if (d < d1[t]) { d1[t] = d; l1[t] = lv; } }
-      else     { if (d < d0[t]) { d0[t] = d; l0[t] = lv; } }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < B; ++t) out[t] = (l0[t] - l1[t]) * (2.f * x - l0[t] - l1[t]) * inv_nu;
-}
+using namespace demk;
 
 template <int Q>
 __global__ void __launch_bounds__(256)
@@ -57,25 +15,7 @@ demod_kernel(const float2* __restrict__ xt, const float* __restrict__ nu, float*
              int64_t total, int D, int n_sc) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= total) return;
-  const int64_t fu = idx / ((int64_t)D * n_sc);
-  const int i = (int)(idx % n_sc);
-  const float2 x = xt[idx];
-  const float v = nu[fu * n_sc + i];
-  float o[Q];
-  if (__builtin_isinf(v)) {
-#pragma unroll
-    for (int j = 0; j < Q; ++j) o[j] = 0.f;
-  } else {
-    const float inv = 1.0f / v;
-    float re[Q / 2], im[Q / 2];
-    axis_llr<Q>(x.x, inv, re);
-    axis_llr<Q>(x.y, inv, im);
-#pragma unroll
-    for (int t = 0; t < Q / 2; ++t) { o[2 * t] = re[t]; o[2 * t + 1] = im[t]; }
-  }
-  float* dst = llr + idx * Q;
-#pragma unroll
-  for (int t = 0; t < Q / 2; ++t) reinterpret_cast<float2*>(dst)[t] = make_float2(o[2 * t], o[2 * t + 1]);
+  demod_elem<Q>(xt, nu, llr, idx, D, n_sc);
 }
 
 }  // namespace

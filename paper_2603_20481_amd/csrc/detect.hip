@@ -11,14 +11,6 @@ namespace {
 
 using namespace det;
 
-// P: operand precision of the phase-1 products (detect_core.h).  For BF16 and
-// FP16, subcarriers whose condition estimate kappa = (max L_ii / min L_ii)^2
-// exceeds the threshold, or whose low-precision factorisation breaks down,
-// are handed to the FP64 refinement kernel: their x_hat (before the MMSE
-// unbiasing) is written to xt and the subcarrier is appended to a device-side
-// list (rlist[0] = count, entries from rlist[RL_OFF]).
-constexpr int RL_OFF = 64;
-
 template <int KP, int P>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
@@ -27,79 +19,10 @@ detect_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
               uint32_t* __restrict__ rlist) {
   __shared__ float2 smem[SMEM];
   __shared__ int nonfin[TS];
-  const int f = blockIdx.y;
-  const int i0 = blockIdx.x * TS;
-  const int D = S - 1;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  if (tid < TS) nonfin[tid] = 0;
-  __syncthreads();
-
-  f32x4 gr[4], gi[4], zr[4], zi[4];
-  gram_mf<P>(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
-             nonfin, gr, gi, zr, zi);
-
-  // ---- phase 2
-  float2* Pw = smem + w * 4 * PMAT;
-  const int col = l & 15, g4 = (l >> 4) * 4;      // MFMA output: rows g4 + r, column col
-  const int scl = l >> 4, row = l & 15;           // phase-2 lane: subcarrier scl, index row
-  float2* Pm = Pw + scl * PMAT;
-  float2 z[16], v[16];
-  float inv[16], dl;
-  bool ok;
-  factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
-
-  const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
-  const uint64_t bal = __ballot(mu_bad);
-  if ((bal >> (16 * scl)) & 0xffffull) ok = false;
-  const int i = i0 + 4 * w + scl;
-  const bool nf = nonfin[4 * w + scl] != 0;
-  bool refine = false;
-  if constexpr (P != P_FP32) {
-    float imax = 0.f, imin = INFINITY;
-#pragma unroll
-    for (int k = 0; k < KP; ++k)
-      if (k < K) { imax = fmaxf(imax, inv[k]); imin = fminf(imin, inv[k]); }
-    const float r = imax / imin;                  // = max L_ii / min L_ii
-    refine = !nf && (!ok || !(r * r <= thr));
-  }
-  if (mmse) unbias_all<KP>(Seq16{}, dl, n0, K, refine, z);
-  if (i >= n_sc) return;
-
-  if (refine) {                                   // finished in FP64 by refine_kernel
-    if (row == 0) {
-      const uint32_t slot = atomicAdd(rlist, 1u);
-      rlist[RL_OFF + slot] = (uint32_t)((int64_t)f * n_sc + i);
-    }
-    if (row < D) {
-#pragma unroll
-      for (int uu = 0; uu < 16; ++uu)
-        if (uu < K) xt[((int64_t)(f * K + uu) * D + row) * n_sc + i] = z[uu];
-    }
-    return;
-  }
-  const bool erase = nf || !ok;
-  if (row < D) {
-#pragma unroll
-    for (int uu = 0; uu < 16; ++uu) {
-      if (uu < K) {
-        float2 x = z[uu];
-        if (erase) x = make_float2(0.f, 0.f);
-        xt[((int64_t)(f * K + uu) * D + row) * n_sc + i] = x;
-      }
-    }
-  }
-  if (row < K) {
-    float nv;
-    if (mmse) {
-      // (1 - mu) / mu with 1 - mu = N0 d formed directly: subtracting mu from 1
-      // would cancel most digits for strong users (mu close to 1)
-      nv = n0 * dl * __builtin_amdgcn_rcpf(1.0f - n0 * dl);
-    } else {
-      nv = n0 * dl;
-    }
-    nu[(int64_t)(f * K + row) * n_sc + i] = erase ? INFINITY : nv;
-  }
-  if (row == 0 && flags) flags[(int64_t)f * n_sc + i] = nf ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
+  const int64_t f = blockIdx.y;
+  detect_tile<KP, P>(H + f * M * K * n_sc, Yf + f * M * S * n_sc, xt + f * K * (S - 1) * n_sc,
+                     nu + f * K * n_sc, flags ? flags + f * n_sc : nullptr, M, K, S, n_sc, n0, mmse,
+                     thr, rlist, (uint32_t)(f * n_sc), blockIdx.x * TS, smem, nonfin);
 }
 
 __global__ void clear_count_kernel(uint32_t* rlist) {

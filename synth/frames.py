@@ -244,6 +244,27 @@ def make_frames(cfg: int, n: int, start: int = 0, **kw) -> list:
     return [make_frame(cfg, start + f, **kw) for f in range(n)]
 
 
+def _draw_inputs(args):
+    cfg, f, shape = args
+    fr = make_frame(cfg, f, shape=shape)
+    return fr.x, fr.pilots
+
+
+def draw_inputs(cfg: int, frames, shapes=None, workers: int = 8) -> list:
+    """[(x, pilots)] of the listed frame numbers of workload ``cfg`` (optional
+    explicit shapes), drawn in forked worker processes; same values as
+    make_frame."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    frames = list(frames)
+    shapes = list(shapes) if shapes is not None else [None] * len(frames)
+    jobs = [(cfg, f, s) for f, s in zip(frames, shapes)]
+    if workers <= 1 or len(jobs) <= 1:
+        return [_draw_inputs(j) for j in jobs]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_draw_inputs, jobs, chunksize=max(1, len(jobs) // (4 * workers))))
+
+
 def draw_batch_shapes(n: int, cfg: int = 4) -> list:
     """Uneven frame shapes: M in {8,16,32,64}, K in 1..min(16,M), n_sc in
     [300, 3276], n_fft the next power of two >= 1.2 n_sc, QPSK/16/64-QAM."""

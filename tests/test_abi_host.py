@@ -108,3 +108,53 @@ def test_python_binding_refuses_without_library(tmp_path):
         rx._lib = None
         rx.load(str(tmp_path / "missing.so"))
     rx._lib = None
+
+
+class Tiles(ctypes.Structure):
+    _fields_ = [("fft_iters", ctypes.c_int32), ("csi_tiles", ctypes.c_int32),
+                ("det_tiles", ctypes.c_int32), ("det_kp", ctypes.c_int32),
+                ("dem_groups", ctypes.c_int32)]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("grid", ctypes.c_int32), ("spin_limit", ctypes.c_uint32)]
+
+
+def _plan_create(lib, frames, tiles=None, opts=None):
+    lib.rxphy_plan_create.restype = ctypes.c_int
+    arr = (Frame * len(frames))(*frames) if frames else None
+    tarr = (Tiles * len(tiles))(*tiles) if tiles else None
+    h = ctypes.c_void_p(123)
+    st = lib.rxphy_plan_create(arr, len(frames), tarr, ctypes.byref(opts) if opts else None,
+                               ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("case,code", [
+    ("no frames", 1), ("bad frame", 1), ("unsupported frame", 2), ("negative tile", 1),
+    ("kp below K", 1), ("kp not a size", 1), ("bad stage mask", 1), ("negative grid", 1),
+])
+def test_plan_create_rejects_before_touching_the_device(lib, case, code):
+    fr = [frame(), frame(M=8, K=2, n_fft=512, n_sc=300, qam_bits=2)]
+    tiles, opts = None, None
+    if case == "no frames":
+        fr = []
+    elif case == "bad frame":
+        fr[1] = frame(qam_bits=5)
+    elif case == "unsupported frame":
+        fr[0] = frame(K=17)
+    elif case == "negative tile":
+        tiles = [Tiles(0, 0, -1, 0, 0), Tiles()]
+    elif case == "kp below K":
+        tiles = [Tiles(0, 0, 0, 8, 0), Tiles()]          # frame 0 has K = 16
+    elif case == "kp not a size":
+        tiles = [Tiles(), Tiles(0, 0, 0, 5, 0)]
+    elif case == "bad stage mask":
+        opts = PlanOptions(16, 0, 0)
+    elif case == "negative grid":
+        opts = PlanOptions(0, -1, 0)
+    st, h = _plan_create(lib, fr, tiles, opts)
+    assert st == code, (case, st)
+    assert h.value is None                              # *plan cleared on failure
+    lib.rxphy_last_error.restype = ctypes.c_char_p
+    assert lib.rxphy_last_error()
