@@ -2,20 +2,27 @@
 """Throughput of the uplink receiver (fft -> csi -> ZF detect -> max-log demod)
 on one MI355X, in subcarrier-detections per second.
 
-One step = the whole receiver over one batch of 100 frames of the
+Headline step = the whole receiver over one batch of 100 frames of the
 64-antenna, 16-user workload (N_FFT 2048, 1200 used subcarriers, 14 symbols,
-16-QAM, i.i.d. Rayleigh, per-user SNR uniform in [10, 30] dB), with the
-complex64 samples already resident in HBM.  One subcarrier-detection is one
-(frame, data symbol, used subcarrier) turned into K*Q LLRs.
+16-QAM, i.i.d. Rayleigh, per-user SNR uniform in [10, 30] dB), plain FP32 ZF,
+with the complex64 samples already resident in HBM.  One
+subcarrier-detection is one (frame, data symbol, used subcarrier) turned into
+K*Q LLRs.
 
-Prints one JSON line.  Per-stage kernel times come from HIP events recorded
-on the stream the kernels run on; the dominant stage is priced against the
-HBM roofline.  The FP64 oracle is timed on a bounded sample on the host.
+Beside the headline the same line reports the other forms, each timed the same
+way: MMSE on the same frames; the BF16 / FP16 detector with FP64 refinement on
+the 64x16 N_FFT 4096 64-QAM correlated workload (and plain FP32 there); 256
+uneven frames in one persistent launch replayed from a hipGraph, with
+autotuned and default item sizes and against a loop of per-frame calls; and
+forward + adjoint on the 64x8 cascaded-channel workload.
+
+Prints one JSON line.  Kernel times come from HIP events recorded on the
+stream the kernels run on; the dominant stage is priced against the HBM
+roofline.  The FP64 oracle is timed on a bounded sample on the host.
 """
 import argparse
-import concurrent.futures as cf
+import hashlib
 import json
-import multiprocessing as mp
 import os
 import sys
 import time
@@ -29,17 +36,11 @@ import synth  # noqa: E402
 
 METRIC = "subcarrier-detections/s (64×16, FFT→ZF→LLR), mixed/batched vs plain FP32"
 HBM_PEAK_GBS = 8000.0
+NAMES = ["fft", "csi", "detect", "demod"]
 
 
-def _gen(args):
-    cfg, f = args
-    fr = synth.make_frame(cfg, f)
-    return fr.x, fr.pilots
-
-
-def gen_frames(cfg, n, workers):
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
-        res = list(ex.map(_gen, [(cfg, f) for f in range(n)], chunksize=max(1, n // (4 * workers))))
+def gen_frames(cfg, n, workers, shape=None):
+    res = synth.draw_inputs(cfg, range(n), [shape] * n if shape is not None else None, workers)
     return np.stack([r[0] for r in res]), np.stack([r[1] for r in res])
 
 
@@ -57,14 +58,15 @@ def stage_bytes(s):
 
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel's source has changed since the counters were taken."""
-    import hashlib
+    None when a source of the kernel has changed since the counters were taken."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -93,12 +95,202 @@ def cpu_baseline(cfg, det, budget_s):
                       (n, "ZF" if det == 0 else "MMSE", t_total)}
 
 
+class Chain:
+    """Device buffers of F same-shape frames and the four stage calls."""
+
+    def __init__(self, rx, torch, shape, x_h, p_h):
+        self.rx, self.torch, self.shape = rx, torch, shape
+        F = x_h.shape[0]
+        self.F = F
+        dev = "cuda"
+        D = shape.n_data
+        self.x = torch.from_numpy(x_h).to(dev)
+        self.p = torch.from_numpy(p_h).to(dev)
+        c64, f32 = torch.complex64, torch.float32
+        self.yf = torch.empty((F, shape.M, shape.n_sym, shape.n_sc), dtype=c64, device=dev)
+        self.h = torch.empty((F, shape.M, shape.K, shape.n_sc), dtype=c64, device=dev)
+        self.xt = torch.empty((F, shape.K, D, shape.n_sc), dtype=c64, device=dev)
+        self.nu = torch.empty((F, shape.K, shape.n_sc), dtype=f32, device=dev)
+        self.fl = torch.empty((F, shape.n_sc), dtype=torch.uint8, device=dev)
+        self.llr = torch.empty((F, shape.K, D, shape.n_sc, shape.qam_bits), dtype=f32, device=dev)
+        self.ws = None
+
+    def step(self, fr, prec="fp32", ev=None):
+        rx = self.rx
+        if ev: ev[0].record()
+        rx.fft(fr, self.x, self.yf)
+        if ev: ev[1].record()
+        rx.csi(fr, self.yf, self.p, self.h)
+        if ev: ev[2].record()
+        need = rx.workspace_bytes(fr, self.F, rx.WS_DETECT, prec)
+        if need and (self.ws is None or self.ws.numel() < need):
+            self.ws = self.torch.empty((need,), dtype=self.torch.uint8, device="cuda")
+        rx.detect(fr, self.h, self.yf, prec, 1e3, self.xt, self.nu, self.fl,
+                  self.ws if need else None)
+        if ev: ev[3].record()
+        rx.demod(fr, self.xt, self.nu, self.llr)
+        if ev: ev[4].record()
+
+    def time(self, fr, prec, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(fr, prec)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            self.step(fr, prec, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = {n: 0.0 for n in NAMES}
+        for ev in evs:
+            for j, n in enumerate(NAMES):
+                per[n] += ev[j].elapsed_time(ev[j + 1]) / steps   # ms
+        return wall * 1e3 / steps, per
+
+
+def stage_report(shape, F, per):
+    sb = stage_bytes(shape)
+    return {n: {"us": round(per[n] * 1e3, 2),
+                "GBps": round(sb[n] * F / (per[n] * 1e-3) / 1e9, 1),
+                "bytes_per_launch": sb[n] * F} for n in NAMES}
+
+
+def form_summary(shape, F, ms, per, extra=None):
+    sb = stage_bytes(shape)
+    dets = F * shape.detections
+    out = {"value": dets / (ms * 1e-3), "unit": "subcarrier-detections/s", "ms_per_step": round(ms, 4),
+           "frames": F, "stages": stage_report(shape, F, per),
+           "hbm_frac": round(sum(sb.values()) * F / (sum(per.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def run_batched(rx, torch, args):
+    """256 uneven frames: one persistent launch, replayed from a hipGraph."""
+    from paper_2603_20481_amd.autotune import Tuner
+    shapes = synth.draw_batch_shapes(args.batch_frames)
+    frames = [rx.Frame.of(s, rx.MMSE, 1.0) for s in shapes]
+    t0 = time.time()
+    inputs = synth.draw_inputs(4, range(len(shapes)), shapes, args.workers)
+    gen_s = time.time() - t0
+    tuner = Tuner(args.tile_cache)
+    tinfo = tuner.tune(frames)
+    tuner.save()
+    res = {}
+    dets = sum(s.detections for s in shapes)
+    byts = sum(sum(stage_bytes(s).values()) for s in shapes)
+    bufs = None
+    for label, tiles in (("tuned", tuner.tiles_for(frames)), ("default", None)):
+        plan = rx.Plan(frames, tiles=tiles)
+        if bufs is None:
+            bufs = plan.alloc()
+            for f, (x, p) in enumerate(inputs):
+                plan.view(bufs, "x", f).copy_(torch.from_numpy(x))
+                plan.view(bufs, "pilots", f).copy_(torch.from_numpy(p))
+        plan.graph(bufs)
+        for _ in range(args.warmup):
+            plan.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.form_steps):
+            plan.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / args.form_steps
+        ms = e0.elapsed_time(e1) / args.form_steps
+        status = plan.device_status()
+        res[label] = {"value": dets / (ms * 1e-3), "ms_per_step": round(ms, 4),
+                      "wall_ms_per_step": round(wall, 4), "items": plan.counts, "grid": plan.grid,
+                      "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "device_status": status}
+        del plan
+    # the same frames as a loop of per-frame single-frame calls (4 launches each)
+    plan = rx.Plan(frames)
+    views = []
+    for f, fr in enumerate(frames):
+        views.append({k: plan.view(bufs, k, f)[None] for k in plan.TENSORS})
+
+    def loop():
+        for fr, v in zip(frames, views):
+            rx.fft(fr, v["x"], v["yf"])
+            rx.csi(fr, v["yf"], v["pilots"], v["h"])
+            rx.detect(fr, v["h"], v["yf"], "fp32", 1e3, v["xt"], v["nu"], v["flags"])
+            rx.demod(fr, v["xt"], v["nu"], v["llr"])
+    loop()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.form_steps):
+        loop()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.form_steps
+    res["per_frame_calls"] = {"value": dets / (ms * 1e-3), "ms_per_step": round(ms, 4),
+                              "launches_per_step": 4 * len(frames)}
+    out = dict(res["tuned"])
+    out.update({"frames": len(frames), "detections_per_step": dets, "algorithmic_bytes": byts,
+                "default_tiles": res["default"], "per_frame_calls": res["per_frame_calls"],
+                "autotune": tinfo, "gen_seconds": round(gen_s, 1),
+                "workload": "256 uneven frames: M in {8,16,32,64}, K in 1..min(16,M), "
+                            "300..3276 subcarriers, N_FFT next power of two >= 1.2 n_sc, "
+                            "QPSK/16/64-QAM, Rayleigh, SNR U[5,30] dB, MMSE, FP32"})
+    del bufs, views, plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_fwd_bwd(rx, torch, args):
+    cfg = 5
+    shape = synth.config_shape(cfg)
+    F = args.bwd_frames
+    x_h, p_h = gen_frames(cfg, F, args.workers)
+    fr = rx.Frame.of(shape, rx.MMSE, 1.0)
+    x = torch.from_numpy(x_h).cuda()
+    p = torch.from_numpy(p_h).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    dllr = torch.randn((F, shape.K, shape.n_data, shape.n_sc, shape.qam_bits), generator=g,
+                       device="cuda")
+
+    def step():
+        out = rx.forward(fr, x, p)
+        rx.backward(fr, x, p, dllr, saved=dict(yf=out["yf"], h=out["h"]))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.form_steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.form_steps
+    out = {"value": F * shape.detections / (ms * 1e-3), "unit": "subcarrier-detections/s",
+           "ms_per_step": round(ms, 4), "frames": F,
+           "workload": "64x8 MIMO, N_FFT 2048, 1200 subcarriers, 16-QAM, cascaded channel "
+                       "(256-element phase vector), 5 dB, MMSE; forward + adjoint to dL/dx, FP32"}
+    del x, p, dllr
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--form-steps", type=int, default=10)
+    ap.add_argument("--mixed-frames", type=int, default=100)
+    ap.add_argument("--batch-frames", type=int, default=256)
+    ap.add_argument("--bwd-frames", type=int, default=50)
+    ap.add_argument("--forms", default="mmse,mixed,batched,fwd_bwd",
+                    help="comma list of extra forms to time ('' for the headline only)")
+    ap.add_argument("--tile-cache", default=None)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
@@ -110,6 +302,7 @@ def main():
               "run this same single-GPU path on their own share of frames (see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    forms = [f for f in args.forms.split(",") if f]
 
     cfg, det = 2, 0
     shape = synth.config_shape(cfg)
@@ -122,55 +315,16 @@ def main():
     import paper_2603_20481_amd as rx
     rx.load()
     torch.cuda.init()
+    chain = Chain(rx, torch, shape, x_h, p_h)
+    del x_h, p_h
     fr = rx.Frame.of(shape, det, 1.0)
-    x = torch.from_numpy(x_h).cuda()
-    p = torch.from_numpy(p_h).cuda()
-    del x_h
-    D = shape.n_data
-    yf = torch.empty((F, shape.M, shape.n_sym, shape.n_sc), dtype=torch.complex64, device="cuda")
-    h = torch.empty((F, shape.M, shape.K, shape.n_sc), dtype=torch.complex64, device="cuda")
-    xt = torch.empty((F, shape.K, D, shape.n_sc), dtype=torch.complex64, device="cuda")
-    nu = torch.empty((F, shape.K, shape.n_sc), dtype=torch.float32, device="cuda")
-    fl = torch.empty((F, shape.n_sc), dtype=torch.uint8, device="cuda")
-    llr = torch.empty((F, shape.K, D, shape.n_sc, shape.qam_bits), dtype=torch.float32, device="cuda")
-
-    names = ["fft", "csi", "detect", "demod"]
-
-    def step(ev=None):
-        if ev: ev[0].record()
-        rx.fft(fr, x, yf)
-        if ev: ev[1].record()
-        rx.csi(fr, yf, p, h)
-        if ev: ev[2].record()
-        rx.detect(fr, h, yf, "fp32", 1e3, xt, nu, fl)
-        if ev: ev[3].record()
-        rx.demod(fr, xt, nu, llr)
-        if ev: ev[4].record()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per_stage = {n: 0.0 for n in names}
-    for ev in evs:
-        for j, n in enumerate(names):
-            per_stage[n] += ev[j].elapsed_time(ev[j + 1]) / args.steps   # ms
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step, per_stage = chain.time(fr, "fp32", args.steps, args.warmup)
     dets = F * shape.detections
     value = dets / (ms_per_step * 1e-3)
 
     sb = stage_bytes(shape)
-    dom = max(names, key=lambda n: per_stage[n])
+    dom = max(NAMES, key=lambda n: per_stage[n])
     achieved = sb[dom] * F / (per_stage[dom] * 1e-3) / 1e9
-    stages = {n: {"us": round(per_stage[n] * 1e3, 2),
-                  "GBps": round(sb[n] * F / (per_stage[n] * 1e-3) / 1e9, 1),
-                  "bytes_per_launch": sb[n] * F} for n in names}
 
     out = {
         "metric": METRIC,
@@ -194,11 +348,44 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom), "traffic_unit": "bytes/launch",
                      "algorithmic_bytes": sb[dom] * F},
-        "stages": stages,
+        "stages": stage_report(shape, F, per_stage),
         "staged_roofline_frac": round(sum(sb.values()) * F / (sum(per_stage.values()) * 1e-3) / 1e9
                                       / HBM_PEAK_GBS, 4),
         "gen_seconds": round(gen_s, 1),
+        "forms": {},
     }
+    print("[bench] headline %.4g det/s (%.3f ms/step)" % (value, ms_per_step), file=sys.stderr, flush=True)
+    if "mmse" in forms:
+        frm = rx.Frame.of(shape, rx.MMSE, 1.0)
+        ms, per = chain.time(frm, "fp32", args.form_steps, 1)
+        out["forms"]["mmse_fp32"] = form_summary(shape, F, ms, per, {"workload": "as the headline, MMSE"})
+        print("[bench] mmse done", file=sys.stderr, flush=True)
+    del chain
+    torch.cuda.empty_cache()
+    if "mixed" in forms:
+        s3 = synth.config_shape(3)
+        x3, p3 = gen_frames(3, args.mixed_frames, args.workers)
+        c3 = Chain(rx, torch, s3, x3, p3)
+        del x3, p3
+        fr3 = rx.Frame.of(s3, rx.ZF, 1.0)
+        for prec in ("fp32", "bf16", "fp16"):
+            ms, per = c3.time(fr3, prec, args.form_steps, 1)
+            refined = int((c3.fl & rx.FLAG_REFINED).ne(0).sum().item())
+            out["forms"]["c3_" + prec] = form_summary(
+                s3, args.mixed_frames, ms, per,
+                {"refined_subcarriers": refined, "refined_fraction": refined / c3.fl.numel(),
+                 "workload": "64x16 MIMO, N_FFT 4096, 3276 subcarriers, 64-QAM, Kronecker "
+                             "(0.7, 0.3), 25 dB, ZF, %s products, FP64 refinement above "
+                             "condition estimate 1e3" % prec})
+        del c3
+        torch.cuda.empty_cache()
+        print("[bench] mixed done", file=sys.stderr, flush=True)
+    if "batched" in forms:
+        out["forms"]["batched_fp32"] = run_batched(rx, torch, args)
+        print("[bench] batched done", file=sys.stderr, flush=True)
+    if "fwd_bwd" in forms:
+        out["forms"]["fwd_bwd_fp32"] = run_fwd_bwd(rx, torch, args)
+        print("[bench] fwd+bwd done", file=sys.stderr, flush=True)
     if args.copy_mib > 0:
         # plain device-to-device copy of a known size: the achievable-bandwidth
         # reference, and the calibration kernel for the HBM byte counters

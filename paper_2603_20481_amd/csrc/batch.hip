@@ -15,7 +15,9 @@
 // Memory ordering.  Each XCD has its own L2, so a producer publishes with an
 // agent-scope release (its stores complete and its L2 is written back before
 // the counter moves) and a consumer acquires at agent scope (its L1 and L2
-// copies are invalidated) before it reads the producer's data.
+// copies are invalidated) before it reads the producer's data.  Releases are
+// batched per workgroup (see publish below): an L2 writeback per item would
+// cost more than the items themselves.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -132,11 +134,46 @@ reset_kernel(Header* __restrict__ hdr, uint32_t* __restrict__ ctl, int n, const 
   for (int i = blockIdx.x * WGS + threadIdx.x; i < n; i += gridDim.x * WGS) ctl[i] = 0u;
 }
 
+// Publishing finished items.  A workgroup does not bump a frame's stage
+// counter after every item: it keeps its finished (frame, stage) counts in LDS
+// and publishes them together, with one agent-scope release (one L2
+// writeback), when it moves on to an item of another stage, before it would
+// block on a dependency, when the list is full, and at exit.  Because the list
+// is stage-major, nobody can be waiting for a stage-s count before the first
+// stage-(s+1) item is popped, and every holder of stage-s counts publishes as
+// soon as its current item ends; a workgroup never blocks while holding
+// unpublished counts, so the no-deadlock argument above still holds.
+constexpr int PEND = 64;
+
+struct Pending {
+  uint32_t slot[PEND];      // CTL_DONE + 4 f + s
+  uint32_t count[PEND];
+  int n, stage;
+};
+
+// All threads call this (uniform); on return the counts are published.
+__device__ __forceinline__ void publish(Pending& pd, uint32_t* __restrict__ ctl) {
+  __builtin_amdgcn_s_waitcnt(0);                   // this wave's stores have reached L2
+  __syncthreads();
+  const int n = pd.n;
+  if (n > 0 && threadIdx.x < 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");    // L2 written back
+    for (int e = threadIdx.x; e < n; e += 64)
+      __hip_atomic_fetch_add(&ctl[pd.slot[e]], pd.count[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) pd.n = 0;
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(3)))
 batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
   __shared__ float2 pool[POOL];
   __shared__ int nonfin[det::TS];
   __shared__ uint32_t s_item;
+  __shared__ int s_ready;
+  __shared__ Pending pd;
+  if (threadIdx.x == 0) { pd.n = 0; pd.stage = -1; }
   for (;;) {
     // reload the header per item (it is small), through a pointer the compiler
     // cannot hoist loads across, so that its fields do not stay live in SGPRs
@@ -147,27 +184,40 @@ batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
       s_item = __hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint32_t q = __builtin_amdgcn_readfirstlane(s_item);
-    if (q >= hp->n_items) break;
+    if (q >= hp->n_items) {
+      publish(pd, ctl);
+      break;
+    }
     const uint32_t code = hp->items[q];
     const int stage = (int)(code >> 30), f = (int)((code >> 16) & 0x3fffu), tile = (int)(code & 0xffffu);
     const BFrame& d = *(const BFrame*)(hp->frames + f);
+    if (__builtin_amdgcn_readfirstlane(pd.n) > 0 && __builtin_amdgcn_readfirstlane(pd.stage) != stage)
+      publish(pd, ctl);
     if (stage > 0) {
       const uint32_t need = (uint32_t)d.need[stage - 1];
-      if (threadIdx.x == 0 && need > 0) {
-        uint32_t* cnt = &ctl[CTL_DONE + 4 * f + stage - 1];
-        const uint32_t limit = hp->spin_limit;
-        uint32_t spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          if (++spins > limit) {
-            __hip_atomic_fetch_or(&ctl[1], (uint32_t)RXPHY_PLAN_WAIT_TIMEOUT, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            break;
+      uint32_t* cnt = &ctl[CTL_DONE + 4 * f + stage - 1];
+      if (threadIdx.x == 0)
+        s_ready = need == 0 || __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+      __syncthreads();
+      if (!__builtin_amdgcn_readfirstlane(s_ready)) {
+        publish(pd, ctl);                          // never block holding unpublished counts
+        if (threadIdx.x == 0) {
+          const uint32_t limit = hp->spin_limit;
+          uint32_t spins = 0;
+          while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (++spins > limit) {
+              __hip_atomic_fetch_or(&ctl[1], (uint32_t)RXPHY_PLAN_WAIT_TIMEOUT, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(4);
           }
-          __builtin_amdgcn_s_sleep(4);
         }
       }
+      // acquire: this CU's L1 and this XCD's L2 drop what they may hold of the
+      // producers' data (one wave's invalidate serves the whole workgroup)
+      if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     switch (stage) {
       case 0: {
@@ -208,12 +258,23 @@ batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
         break;
       }
     }
-    // publish: every wave's stores complete and reach memory, then the counter
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // record the finished item; publish when the list is full
     __syncthreads();
-    if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(&ctl[CTL_DONE + 4 * f + stage], 1u, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      const uint32_t slot = (uint32_t)(CTL_DONE + 4 * f + stage);
+      const int n = pd.n;
+      if (n > 0 && pd.slot[n - 1] == slot) {
+        pd.count[n - 1] += 1u;
+      } else {
+        pd.slot[n] = slot;
+        pd.count[n] = 1u;
+        pd.n = n + 1;
+      }
+      pd.stage = stage;
+      s_ready = pd.n == PEND;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_ready)) publish(pd, ctl);
   }
 }
 

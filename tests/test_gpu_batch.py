@@ -210,3 +210,21 @@ def test_batch_uneven_256_frames_full_size(rx):
             if a.is_complex():
                 a, b = torch.view_as_real(a), torch.view_as_real(b)
             assert torch.equal(a, b), (f, fr, k)
+
+
+def test_autotuned_tiles_keep_results_bitwise(rx, batch, refs, tmp_path):
+    from paper_2603_20481_amd.autotune import Tuner
+    frames, inputs = batch
+    t = Tuner(str(tmp_path / "tiles.json"))
+    info = t.tune(frames, copies=4, reps=2)
+    say("autotune", info, "entries", len(t.entries))
+    assert info["classes_tuned"] == len(t.entries) > 0
+    t.save()
+    t2 = Tuner(str(tmp_path / "tiles.json"))
+    assert t2.tune(frames)["classes_tuned"] == 0          # everything cached
+    plan = rx.Plan(frames, tiles=t2.tiles_for(frames))
+    bufs = pack(rx, plan, inputs)
+    plan.forward(bufs)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    assert_frames_equal(plan, bufs, refs)
