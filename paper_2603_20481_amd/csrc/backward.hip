@@ -141,8 +141,9 @@ detect_adjoint_kernel(const float2* __restrict__ H, const float2* __restrict__ Y
   __syncthreads();
 
   f32x4 gr[4], gi[4], zr[4], zi[4];
+  float2 hv[8], yv[8];
   gram_mf(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
-          nonfin, gr, gi, zr, zi);
+          nonfin, gr, gi, zr, zi, hv, yv);
   float2* P = smem + w * 4 * PMAT;
   const int col = l & 15, g4 = (l >> 4) * 4;
   const int scl = l >> 4, row = l & 15;

@@ -11,18 +11,31 @@ namespace {
 
 using namespace det;
 
+constexpr int TPB = 1;   // tiles per workgroup
+
 template <int KP, int P>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
               float2* __restrict__ xt, float* __restrict__ nu, uint8_t* __restrict__ flags,
               int M, int K, int S, int n_sc, float n0, int mmse, float thr,
               uint32_t* __restrict__ rlist) {
-  __shared__ float2 smem[SMEM];
+  __shared__ float2 smem[SMEM_ALL];
   __shared__ int nonfin[TS];
   const int64_t f = blockIdx.y;
-  detect_tile<KP, P>(H + f * M * K * n_sc, Yf + f * M * S * n_sc, xt + f * K * (S - 1) * n_sc,
-                     nu + f * K * n_sc, flags ? flags + f * n_sc : nullptr, M, K, S, n_sc, n0, mmse,
-                     thr, rlist, (uint32_t)(f * n_sc), blockIdx.x * TS, smem, nonfin);
+  // TPB consecutive tiles per workgroup: the first chunk of the next tile is
+  // loaded while the current tile is being factored and solved
+  const int nt = (n_sc + TS - 1) / TS;
+  const int t0 = blockIdx.x * TPB;
+  const int t1 = min(t0 + TPB, nt);
+  float2 hv[8], yv[8];
+  bool have0 = false;
+  for (int t = t0; t < t1; ++t) {
+    if (t > t0) __syncthreads();
+    detect_tile<KP, P>(H + f * M * K * n_sc, Yf + f * M * S * n_sc, xt + f * K * (S - 1) * n_sc,
+                       nu + f * K * n_sc, flags ? flags + f * n_sc : nullptr, M, K, S, n_sc, n0, mmse,
+                       thr, rlist, (uint32_t)(f * n_sc), t * TS, smem, nonfin, hv, yv, have0,
+                       t + 1 < t1 ? (t + 1) * TS : -1);
+  }
 }
 
 __global__ void clear_count_kernel(uint32_t* rlist) {
@@ -165,7 +178,7 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf, float
 template <int KP, int P>
 void launch_one(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, float2* xt,
                 float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
-  dim3 grid((fr.n_sc + TS - 1) / TS, nf);
+  dim3 grid(((fr.n_sc + TS - 1) / TS + TPB - 1) / TPB, nf);
   hipLaunchKernelGGL((detect_kernel<KP, P>), grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
                      fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0, thr, rl);
 }

@@ -38,6 +38,19 @@ constexpr int PP = 17;              // float2 per row of a 16x16 matrix in the s
 constexpr int PMAT = 16 * PP + 4;   // float2 per matrix (the 4 matrices of a wave land on distinct banks)
 constexpr int SMEM = (2 * ROWS * PITCH > 16 * PMAT) ? 2 * ROWS * PITCH : 16 * PMAT;
 
+// LDS of the shared-factor path (tiles whose 16 subcarriers carry one
+// channel matrix): the four waves' partial Gram matrices, the one factor L,
+// 1 / L_kk, d_k = [A^-1]_kk and the tile's flags.
+struct SharedFactor {
+  float2 part[4][16 * PP];
+  float2 L[16 * PP];
+  float inv[16];
+  float dl[16];
+  int ok;
+  int uniform;
+};
+constexpr int SMEM_ALL = SMEM + (int)((sizeof(SharedFactor) + sizeof(float2) - 1) / sizeof(float2));
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int L>
@@ -186,84 +199,101 @@ __device__ __forceinline__ void unbias_all(Seq<Us...>, float dl, float n0, int K
 // that frame).  Accumulators: gr/gi = Re/Im G, zr/zi = Re/Im Z, one per
 // subcarrier of the wave, in MFMA output layout (lane l: rows 4(l/16)+r,
 // column l%16).  nonfin[c] is set for tile subcarriers with non-finite input.
+// Byte-offset buffer loads: a lane whose offset is at or past the end of the
+// buffer reads zero without touching memory (the hardware range check of a
+// raw buffer resource), so absent rows and subcarriers need neither a branch
+// nor a select.
+constexpr uint32_t OOB = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+// Loads 8-antenna chunk m0 of the tile at i0 into registers: lane (rb, c16)
+// with rb = tid / 16 gets slot rb of antenna m0 + it for it = 0..7, i.e.
+// H[m0 + it][rb][i0 + c16] and Y[m0 + it][1 + rb][i0 + c16]; absent slots,
+// antennas and subcarriers read zero.  The byte offsets are a lane constant
+// plus it times a uniform stride, and all 16 loads are issued back to back.
+__device__ __forceinline__ void load_chunk(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
+                                           int M, int K, int S, int n_sc, int i0, int m0, float2* hv,
+                                           float2* yv) {
+  const int tid = tid_x();
+  const int rb = tid >> 4, ic = i0 + (tid & 15);
+  const int D = S - 1;
+  const __amdgpu_buffer_rsrc_t hrs = rsrc(Hf, (uint32_t)M * K * n_sc * 8u);
+  const __amdgpu_buffer_rsrc_t yrs = rsrc(Yff, (uint32_t)M * S * n_sc * 8u);
+  const bool in_range = ic < n_sc;
+  const uint32_t h_lane = in_range && rb < K ? (uint32_t)(rb * n_sc + ic) * 8u : OOB;
+  const uint32_t y_lane = in_range && rb < D ? (uint32_t)((1 + rb) * n_sc + ic) * 8u : OOB;
+  const uint32_t h_ant = (uint32_t)K * n_sc * 8u, y_ant = (uint32_t)S * n_sc * 8u;
+  const int mc = min(MC, M - m0);
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const uint32_t a = (uint32_t)(m0 + it);
+    hv[it] = ld2(hrs, it < mc ? h_lane + a * h_ant : OOB);
+    yv[it] = ld2(yrs, it < mc ? y_lane + a * y_ant : OOB);
+  }
+}
+
+// Phase 1: Gram matrix and matched filter of the tile's 16 subcarriers.
+// H and the data symbols are staged per 8-antenna chunk as [antenna][16 slots]
+// rows (slot = user for H, data symbol for Y; absent slots, antennas and
+// subcarriers hold zero), so the MFMA loop reads them unmasked.  A
+// subcarrier with a non-finite input gets nonfin[c] = 1.
 template <int P = P_FP32>
 __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
                                         int M, int K, int S, int n_sc, int i0, float2* smem,
-                                        int* nonfin, f32x4* gr, f32x4* gi, f32x4* zr, f32x4* zi) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) gr[t] = gi[t] = zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+                                        int* nonfin, f32x4* gr, f32x4* gi, f32x4* zr, f32x4* zi,
+                                        float2* hv, float2* yv, bool have0 = false, int i0n = -1) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) gr[t] = gi[t] = zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int tid = tid_x(), w = tid >> 6, l = tid & 63;
-  const int D = S - 1;
   float2* Hs = smem;
   float2* Ys = smem + ROWS * PITCH;
   const int c16 = tid & 15;
-  const int ic = i0 + c16;
-  const bool in_range = ic < n_sc;
   const int u = l & 15, kq = l >> 4;
-
-  // chunk loads go to registers first (all issued back to back) and the next
-  // chunk is prefetched while the current one feeds the MFMAs
-  float2 hv[8], yv[8];
-  auto load_chunk = [&](int m0) {
-    const int mc = min(MC, M - m0);
-    const int rh = mc * K, ry = mc * D;
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int r = (tid >> 4) + 16 * it;
-      hv[it] = (in_range && r < rh) ? Hf[(int64_t)(m0 * K + r) * n_sc + ic] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int r = (tid >> 4) + 16 * it;
-      const int ml = r / D, s = r - ml * D;
-      yv[it] = (in_range && r < ry) ? Yff[(int64_t)((m0 + ml) * S + 1 + s) * n_sc + ic]
-                                    : make_float2(0.f, 0.f);
-    }
-  };
-  load_chunk(0);
+  const int rb = tid >> 4;
+  // chunk 0 may already be in hv/yv (prefetched by the previous tile); the
+  // next chunk is loaded while the current one feeds the MFMAs, and after
+  // the last chunk the first chunk of tile i0n (if >= 0) is prefetched
+  float probe = 0.f;
+  if (!have0) load_chunk(Hf, Yff, M, K, S, n_sc, i0, 0, hv, yv);
   for (int m0 = 0; m0 < M; m0 += MC) {
-    const int mc = min(MC, M - m0);
-    bool bad = false;
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
-      const int r = (tid >> 4) + 16 * it;
-      bad |= !finite2(hv[it]) || !finite2(yv[it]);
-      if (r < ROWS) {
-        Hs[r * PITCH + c16] = hv[it];
-        Ys[r * PITCH + c16] = yv[it];
-      }
+      const int r = rb + 16 * it;
+      probe = __builtin_fmaf(hv[it].x, 0.f, probe);
+      probe = __builtin_fmaf(hv[it].y, 0.f, probe);
+      probe = __builtin_fmaf(yv[it].x, 0.f, probe);
+      probe = __builtin_fmaf(yv[it].y, 0.f, probe);
+      Hs[r * PITCH + c16] = hv[it];
+      Ys[r * PITCH + c16] = yv[it];
     }
-    if (bad) nonfin[c16] = 1;
     __syncthreads();
-    if (m0 + MC < M) load_chunk(m0 + MC);
+    if (m0 + MC < M) load_chunk(Hf, Yff, M, K, S, n_sc, i0, m0 + MC, hv, yv);
+    else if (i0n >= 0) load_chunk(Hf, Yff, M, K, S, n_sc, i0n, 0, hv, yv);
     if constexpr (P == P_FP32) {
-      // branch-free: rows past this chunk are zero in LDS, rows of absent users
-      // or symbols are masked by selects (row indices stay below ROWS)
-  #pragma unroll
+#pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const int ml = 4 * a + kq;
-        const bool okh = ml < mc && u < K;
-        const bool oky = ml < mc && u < D;
-        const int hrow = ml * K + u;
-        const int yrow = ml * D + u;
-  #pragma unroll
+        const int row = (4 * a + kq) * 16 + u;     // antenna 4a + kq, slot u
+#pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int sc = 4 * w + t;
-          const float2 hr = Hs[hrow * PITCH + sc];
-          const float2 yr = Ys[yrow * PITCH + sc];
-          const float hx = okh ? hr.x : 0.f, hy = okh ? hr.y : 0.f;
-          const float yx = oky ? yr.x : 0.f, yy = oky ? yr.y : 0.f;
-          gr[t] = mfma(hx, hx, gr[t]);
-          gr[t] = mfma(hy, hy, gr[t]);
-          gi[t] = mfma(hx, hy, gi[t]);
-          gi[t] = mfma(-hy, hx, gi[t]);
-          zr[t] = mfma(hx, yx, zr[t]);
-          zr[t] = mfma(hy, yy, zr[t]);
-          zi[t] = mfma(hx, yy, zi[t]);
-          zi[t] = mfma(-hy, yx, zi[t]);
+          const float2 hr = Hs[row * PITCH + sc];
+          const float2 yr = Ys[row * PITCH + sc];
+          gr[t] = mfma(hr.x, hr.x, gr[t]);
+          gr[t] = mfma(hr.y, hr.y, gr[t]);
+          gi[t] = mfma(hr.x, hr.y, gi[t]);
+          gi[t] = mfma(-hr.y, hr.x, gi[t]);
+          zr[t] = mfma(hr.x, yr.x, zr[t]);
+          zr[t] = mfma(hr.y, yr.y, zr[t]);
+          zi[t] = mfma(hr.x, yr.y, zi[t]);
+          zi[t] = mfma(-hr.y, yr.x, zi[t]);
         }
       }
     } else {
@@ -271,28 +301,22 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
       // lane (kq, u) supplies antennas 2 kq and 2 kq + 1 as (re, im, re, im);
       // Re G = X^T X, Im G = X^T X', Re Z = X^T Y, Im Z = X^T Y' with
       // X' = (b, -a) and Y' = (d, -c) per antenna.
-      const int ml0 = 2 * kq, ml1 = 2 * kq + 1;
-      const bool okh0 = ml0 < mc && u < K, okh1 = ml1 < mc && u < K;
-      const bool oky0 = ml0 < mc && u < D, oky1 = ml1 < mc && u < D;
-      const int hr0 = ml0 * K + u, hr1 = ml1 * K + u, yr0 = ml0 * D + u, yr1 = ml1 * D + u;
+      const int r0 = (2 * kq) * 16 + u, r1 = (2 * kq + 1) * 16 + u;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int sc = 4 * w + t;
-        const float2 a0 = Hs[hr0 * PITCH + sc], a1 = Hs[hr1 * PITCH + sc];
-        const float2 c0 = Ys[yr0 * PITCH + sc], c1 = Ys[yr1 * PITCH + sc];
-        const float h0x = okh0 ? a0.x : 0.f, h0y = okh0 ? a0.y : 0.f;
-        const float h1x = okh1 ? a1.x : 0.f, h1y = okh1 ? a1.y : 0.f;
-        const float y0x = oky0 ? c0.x : 0.f, y0y = oky0 ? c0.y : 0.f;
-        const float y1x = oky1 ? c1.x : 0.f, y1y = oky1 ? c1.y : 0.f;
-        gr[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, h0x, h0y, h1x, h1y, gr[t]);
-        gi[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, h0y, -h0x, h1y, -h1x, gi[t]);
-        zr[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, y0x, y0y, y1x, y1y, zr[t]);
-        zi[t] = mfma_lp<P>(h0x, h0y, h1x, h1y, y0y, -y0x, y1y, -y1x, zi[t]);
+        const float2 a0 = Hs[r0 * PITCH + sc], a1 = Hs[r1 * PITCH + sc];
+        const float2 c0 = Ys[r0 * PITCH + sc], c1 = Ys[r1 * PITCH + sc];
+        gr[t] = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, a0.x, a0.y, a1.x, a1.y, gr[t]);
+        gi[t] = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, a0.y, -a0.x, a1.y, -a1.x, gi[t]);
+        zr[t] = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, c0.x, c0.y, c1.x, c1.y, zr[t]);
+        zi[t] = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, c0.y, -c0.x, c1.y, -c1.x, zi[t]);
       }
     }
     __syncthreads();
   }
-
+  if (!(probe == 0.f)) nonfin[c16] = 1;
+  __syncthreads();
 }
 
 // Phase 2 up to the ZF/MMSE solution: consumes the accumulators of gram_mf.
@@ -347,35 +371,200 @@ __device__ __forceinline__ void factor_solve(float2* P, float2* Pm, const f32x4*
 // are handed to the FP64 refinement kernel: their x_hat (before the MMSE
 // unbiasing) is written to xt and the subcarrier is appended to a device-side
 // list (rlist[0] = count, entries from rlist[RL_OFF]).
+// Phase 1 of the shared-factor path.  Same staging as gram_mf; the matched
+// filter is accumulated for every subcarrier, the Gram matrix only once: for
+// the tile's first subcarrier, each wave over every fourth 8-antenna chunk
+// (g0r/g0i, a partial sum).  Every in-range H value is compared with the
+// tile's first subcarrier (DPP broadcast of lane 0 of each 16-lane row); any
+// difference, including a NaN, clears sf->uniform and the caller falls back
+// to the per-subcarrier path.
+__device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
+                                               int M, int K, int S, int n_sc, int i0, float2* smem,
+                                               int* nonfin, SharedFactor* sf, f32x4* zr, f32x4* zi,
+                                               f32x4& g0r, f32x4& g0i, float2* hv, float2* yv, bool have0,
+                                               int i0n) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  g0r = g0i = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int tid = tid_x(), w = tid >> 6, l = tid & 63;
+  float2* Hs = smem;
+  float2* Ys = smem + ROWS * PITCH;
+  const int c16 = tid & 15;
+  const int ic = i0 + c16;
+  const int u = l & 15, kq = l >> 4;
+  const int rb = tid >> 4;
+  const bool in_range = ic < n_sc;
+  float probe = 0.f;
+  bool differ = false;
+  if (!have0) load_chunk(Hf, Yff, M, K, S, n_sc, i0, 0, hv, yv);
+  for (int m0 = 0; m0 < M; m0 += MC) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int r = rb + 16 * it;
+      probe = __builtin_fmaf(hv[it].x, 0.f, probe);
+      probe = __builtin_fmaf(hv[it].y, 0.f, probe);
+      probe = __builtin_fmaf(yv[it].x, 0.f, probe);
+      probe = __builtin_fmaf(yv[it].y, 0.f, probe);
+      const float fx = bc<0>(hv[it].x), fy = bc<0>(hv[it].y);
+      differ |= in_range && (hv[it].x != fx || hv[it].y != fy);
+      Hs[r * PITCH + c16] = hv[it];
+      Ys[r * PITCH + c16] = yv[it];
+    }
+    __syncthreads();
+    if (m0 + MC < M) load_chunk(Hf, Yff, M, K, S, n_sc, i0, m0 + MC, hv, yv);
+    else if (i0n >= 0) load_chunk(Hf, Yff, M, K, S, n_sc, i0n, 0, hv, yv);
+    const bool gram_here = ((m0 / MC) & 3) == w;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int row = (4 * a + kq) * 16 + u;
+      if (gram_here) {
+        const float2 h0 = Hs[row * PITCH];
+        g0r = mfma(h0.x, h0.x, g0r);
+        g0r = mfma(h0.y, h0.y, g0r);
+        g0i = mfma(h0.x, h0.y, g0i);
+        g0i = mfma(-h0.y, h0.x, g0i);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int sc = 4 * w + t;
+        const float2 hr = Hs[row * PITCH + sc];
+        const float2 yr = Ys[row * PITCH + sc];
+        zr[t] = mfma(hr.x, yr.x, zr[t]);
+        zr[t] = mfma(hr.y, yr.y, zr[t]);
+        zi[t] = mfma(hr.x, yr.y, zi[t]);
+        zi[t] = mfma(-hr.y, yr.x, zi[t]);
+      }
+    }
+    __syncthreads();
+  }
+  if (!(probe == 0.f)) nonfin[c16] = 1;
+  if (differ) sf->uniform = 0;
+  __syncthreads();
+}
+
+// Phase 2 of the shared-factor path: wave wf sums the partial Gram matrices,
+// factors A once and publishes L, 1 / L_kk, d and ok; every wave then solves
+// for its own subcarriers with that L.  Outputs as factor_solve; prefetch()
+// is called once by every wave, with no register of the factorisation live.  (Wave w of
+// every workgroup sits on SIMD w, so callers rotate wf from tile to tile to
+// spread the factorisations over the four SIMDs.)
+template <int KP, class Prefetch>
+__device__ __forceinline__ void factor_solve_shared(float2* Pw, float2* Pm, SharedFactor* sf, int w, int wf,
+                                                    const f32x4& g0r, const f32x4& g0i, const f32x4* zr,
+                                                    const f32x4* zi, int K, float n0, int mmse, int row,
+                                                    int col, int g4, float2* x, float* inv, float& dl,
+                                                    bool& ok, Prefetch prefetch) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sf->part[w][(g4 + r) * PP + col] = make_float2(g0r[r], g0i[r]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Pw[t * PMAT + (g4 + r) * PP + col] = make_float2(zr[t][r], zi[t][r]);
+  __syncthreads();
+  if (w == wf) {
+    float2 a[16], v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      float2 s = sf->part[0][row * PP + c];
+      s = cadd(s, sf->part[1][row * PP + c]);
+      s = cadd(s, sf->part[2][row * PP + c]);
+      s = cadd(s, sf->part[3][row * PP + c]);
+      if (c == row) s.x = row < K ? s.x + (mmse ? n0 : 0.f) : 1.0f;
+      a[c] = s;
+    }
+    bool okw = true;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);
+    crout_all<KP>(Seq16{}, a, v, inv, row, okw);
+    float d = 0.f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) d += v[k].x * v[k].x + v[k].y * v[k].y;
+    if (g4 == 0) {                                       // lanes 0..15: one copy
+#pragma unroll
+      for (int c = 0; c < 16; ++c) sf->L[row * PP + c] = a[c];
+      sf->dl[row] = d;
+      sf->inv[row] = inv[row];
+      if (row == 0) sf->ok = okw ? 1 : 0;
+    }
+  }
+  // the next tile's first chunk: the factoring wave after its factorisation,
+  // the others right away, so the loads fly during the wait and the solves
+  prefetch();
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = Pm[k * PP + row];   // column `row` of Z
+#pragma unroll
+  for (int k = 0; k < 16; ++k) inv[k] = sf->inv[k];
+  dl = sf->dl[row];
+  ok = sf->ok != 0;
+  fwd_all<KP>(Seq16{}, sf->L, inv, x);                  // L W = Z
+  bwd_all<KP>(Seq16{}, sf->L, inv, x);                  // L^H X = W
+}
+
 constexpr int RL_OFF = 64;
 
 // One tile of TS subcarriers from i0 of one frame (H [M][K][n_sc], Yf
 // [M][S][n_sc], xt [K][D][n_sc], nu [K][n_sc], flags [n_sc] of that frame);
-// 256 threads; smem holds SMEM slots, nonfin TS.  A refined subcarrier i is
-// listed as sub_base + i.  The caller synchronises before reusing smem.
+// 256 threads; smem holds SMEM_ALL slots, nonfin TS.  A refined subcarrier i is
+// listed as sub_base + i.  hv/yv carry chunk 0 of this tile in when have0 is
+// set; if i0n >= 0 they carry chunk 0 of the tile at i0n (same frame) out,
+// with have0 set, so that its loads fly during this tile's phase 2.  The
+// caller synchronises before reusing smem.
 template <int KP, int P>
 __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const float2* __restrict__ Yf,
                                             float2* __restrict__ xt, float* __restrict__ nu,
                                             uint8_t* __restrict__ flags, int M, int K, int S, int n_sc,
                                             float n0, int mmse, float thr, uint32_t* __restrict__ rlist,
-                                            uint32_t sub_base, int i0, float2* smem, int* nonfin) {
+                                            uint32_t sub_base, int i0, float2* smem, int* nonfin,
+                                            float2* hv, float2* yv, bool& have0, int i0n) {
   const int D = S - 1;
   const int tid = tid_x(), w = tid >> 6, l = tid & 63;
+  SharedFactor* sf = reinterpret_cast<SharedFactor*>(smem + SMEM);
   if (tid < TS) nonfin[tid] = 0;
+  if (tid == 0) sf->uniform = 1;
   __syncthreads();
 
-  f32x4 gr[4], gi[4], zr[4], zi[4];
-  gram_mf<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi);
-
-  // ---- phase 2
   float2* Pw = smem + w * 4 * PMAT;
   const int col = l & 15, g4 = (l >> 4) * 4;      // MFMA output: rows g4 + r, column col
   const int scl = l >> 4, row = l & 15;           // phase-2 lane: subcarrier scl, index row
   float2* Pm = Pw + scl * PMAT;
-  float2 z[16], v[16];
+  float2 z[16];
   float inv[16], dl;
   bool ok;
-  factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
+  // The CSI stage holds the estimate constant over each pilot group of K
+  // subcarriers, so a tile inside one group usually carries one channel
+  // matrix: then the Gram matrix is formed once and A is factored once per
+  // tile (the result equals the per-subcarrier path up to summation order).
+  // (Only a tile of K >= 16 users, or the last pilot group's tile, can lie in
+  // one group, so the path is compiled for the K padding of 16 alone.)
+  bool shared = false;
+  if constexpr (P == P_FP32 && KP == 16) {
+    const int G = n_sc / K;
+    const int last = min(i0 + TS, n_sc) - 1;
+    if (min(i0 / K, G - 1) == min(last / K, G - 1)) {
+      f32x4 zr[4], zi[4], g0r, g0i;
+      gram_mf_shared(H, Yf, M, K, S, n_sc, i0, smem, nonfin, sf, zr, zi, g0r, g0i, hv, yv, have0, -1);
+      have0 = false;
+      shared = __builtin_amdgcn_readfirstlane(sf->uniform) != 0;
+      if (shared) {
+        factor_solve_shared<KP>(Pw, Pm, sf, w, (i0 / TS) & 3, g0r, g0i, zr, zi, K, n0, mmse, row, col, g4,
+                                z, inv, dl, ok, [&]() {
+                                  if (i0n >= 0) load_chunk(H, Yf, M, K, S, n_sc, i0n, 0, hv, yv);
+                                });
+        have0 = i0n >= 0;
+      }
+    }
+  }
+  if (!shared) {
+    // with K padded to 16 this path is the rare fallback and holds no
+    // prefetch across its phase 2 (registers)
+    constexpr bool PREF = !(P == P_FP32 && KP == 16);
+    f32x4 gr[4], gi[4], zr[4], zi[4];
+    gram_mf<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi, hv, yv, have0, PREF ? i0n : -1);
+    have0 = PREF && i0n >= 0;
+    float2 v[16];
+    factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
+  }
 
   const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
   const uint64_t bal = __ballot(mu_bad);

@@ -136,6 +136,35 @@ def test_detect_flags_and_erasures(rx):
         assert np.all(llr[0][:, :, bad] == 0)
 
 
+@pytest.mark.parametrize("det", [O.ZF, O.MMSE])
+def test_detect_shared_factor_tiles(rx, det):
+    """Tiles whose 16 subcarriers carry one channel matrix (a pilot group of
+    K = 16) factor A once; tiles broken by a perturbed or non-finite entry, and
+    groups that break down, must give the per-subcarrier results."""
+    M, K, n_sc, S = 32, 16, 200, 6          # 12 groups, the last one 24 subcarriers wide
+    rng = np.random.default_rng(17 + det)
+    G = n_sc // K
+    hg = (rng.standard_normal((M, K, G)) + 1j * rng.standard_normal((M, K, G))) * 0.7
+    gidx = np.minimum(np.arange(n_sc) // K, G - 1)
+    h = hg[:, :, gidx][None].astype(np.complex64)
+    yf = (rng.standard_normal((1, M, S, n_sc)) + 1j * rng.standard_normal((1, M, S, n_sc))).astype(np.complex64) * 3
+    h[0, 5, 3, 37] *= np.float32(1 + 1e-3)  # tile 2 no longer uniform
+    h[0, 1, 2, 70] = np.nan                 # tile 4: non-finite channel on one subcarrier
+    h[0, :, 9, 96:112] = 0                  # group 6: a zero user column -> breakdown (ZF) / mu = 0 (MMSE)
+    yf[0, 3, 2, 150] = np.inf               # non-finite data on one subcarrier of a uniform tile
+    fr = rx.Frame(M, K, 512, n_sc, S, 0, 2, det, 1.0)
+    xt, nu, fl = (host(t) for t in rx.detect(fr, dev(h), dev(yf)))
+    ref = O.detect_stage(h[0], yf[0, :, 1:, :], 1.0, det, want_kappa=True)
+    assert np.array_equal(fl[0], ref["flags"]), (np.nonzero(fl[0] != ref["flags"]), fl[0], ref["flags"])
+    good = (ref["flags"] == 0) & (ref["kappa"] <= 1e3)
+    e = evm_rel(xt[0], ref["xt"], good)
+    en = rel_rms(nu[0][:, good], ref["nu"][:, good])
+    say("shared-factor tiles", det, "evm_rel", e, "nu_rel", en, "flagged", int(np.sum(~good)))
+    assert e < 1e-4 and en < 1e-4
+    bad = ref["flags"] != 0
+    assert np.all(xt[0][..., bad] == 0) and np.all(np.isinf(nu[0][:, bad]))
+
+
 # ---------------------------------------------------------------- stage: demod
 @pytest.mark.parametrize("q", [2, 4, 6])
 def test_demod_stage(rx, q):
