@@ -195,7 +195,7 @@ typedef struct {
   int32_t csi_tiles;   /* CSI item = csi_tiles consecutive (antenna, 512-subcarrier) tiles              */
   int32_t det_tiles;   /* detector item = det_tiles consecutive 16-subcarrier tiles                     */
   int32_t det_kp;      /* K padding of the detector: 0 = smallest of {4, 8, 16} >= K, else 4, 8 or 16   */
-  int32_t dem_groups;  /* demod item = dem_groups x 256 consecutive (user, symbol, subcarrier) elements  */
+  int32_t dem_groups;  /* demod item = dem_groups x 256 consecutive (user, subcarrier) columns          */
 } rxphy_tiles;
 
 enum {

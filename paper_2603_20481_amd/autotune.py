@@ -29,8 +29,8 @@ STAGES = ("fft", "csi", "detect", "demod")
 STAGE_BIT = {"fft": STAGE_FFT, "csi": STAGE_CSI, "detect": STAGE_DETECT, "demod": STAGE_DEMOD}
 KNOB = {"fft": "fft_iters", "csi": "csi_tiles", "detect": "det_tiles", "demod": "dem_groups"}
 CANDIDATES = {"fft": (1, 2, 4, 8, 16), "csi": (1, 2, 4, 8), "detect": (1, 2, 4),
-              "demod": (4, 8, 16, 32, 64)}
-CACHE_VERSION = 1
+              "demod": (1, 2, 4, 8, 16)}
+CACHE_VERSION = 2
 
 
 def kp_of(K: int) -> int:

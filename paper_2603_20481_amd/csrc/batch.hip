@@ -95,11 +95,15 @@ template <int Q>
 __device__ __forceinline__ void run_demod(const BFrame& d, int tile, const float2* xt, const float* nu,
                                           float* llr) {
   const int D = d.n_sym - 1;
-  const int64_t total = (int64_t)d.K * D * d.n_sc;
-  const int64_t base = (int64_t)tile * d.dem_groups * WGS;
+  const int total = d.K * d.n_sc;                 // (user, subcarrier) columns
+  const int base = tile * d.dem_groups * WGS;
   for (int g = 0; g < d.dem_groups; ++g) {
-    const int64_t idx = base + (int64_t)g * WGS + tid_x();
-    if (idx < total) demk::demod_elem<Q>(xt + d.xt, nu + d.nu, llr + d.llr, idx, D, d.n_sc);
+    const int c = base + g * WGS + tid_x();
+    if (c < total) {
+      const int u = c / d.n_sc, i = c - u * d.n_sc;
+      const uint32_t o = (uint32_t)(u * D) * (uint32_t)d.n_sc + (uint32_t)i;
+      demk::demod_column<Q>(xt + d.xt + o, nu[d.nu + c], llr + d.llr + (int64_t)o * Q, D, d.n_sc);
+    }
   }
 }
 
@@ -433,13 +437,13 @@ rxphy_status rxphy_plan_create(const rxphy_frame* frames, int32_t n_frames, cons
     d.fft_iters = t.fft_iters ? t.fft_iters : 4;
     d.csi_tiles = t.csi_tiles ? t.csi_tiles : 2;
     d.det_tiles = t.det_tiles ? t.det_tiles : 1;
-    d.dem_groups = t.dem_groups ? t.dem_groups : 16;
+    d.dem_groups = t.dem_groups ? t.dem_groups : 4;
     const int64_t D = fr.n_sym - 1;
     const int64_t n_tr = (int64_t)fr.M * fr.n_sym;
     const int64_t per_fft = (int64_t)fft_tpw(fr.n_fft) * d.fft_iters;
     const int64_t nt_csi = (int64_t)fr.M * ((fr.n_sc + csik::CSI_TILE - 1) / csik::CSI_TILE);
     const int64_t nt_det = (fr.n_sc + det::TS - 1) / det::TS;
-    const int64_t n_dem = (int64_t)fr.K * D * fr.n_sc;
+    const int64_t n_dem = (int64_t)fr.K * fr.n_sc;
     const int64_t need[4] = {(n_tr + per_fft - 1) / per_fft, (nt_csi + d.csi_tiles - 1) / d.csi_tiles,
                              (nt_det + d.det_tiles - 1) / d.det_tiles,
                              (n_dem + (int64_t)d.dem_groups * WGS - 1) / ((int64_t)d.dem_groups * WGS)};

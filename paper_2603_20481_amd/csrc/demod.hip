@@ -1,7 +1,7 @@
-// demod stage: max-log LLRs, one thread per (frame, user, symbol, subcarrier);
-// consecutive threads write consecutive LLR groups.  The body is
-// demk::demod_elem (frames are contiguous, so the frame index folds into the
-// user index).
+// demod stage: max-log LLRs, one thread per (frame, user, subcarrier) looping
+// over the data symbols (consecutive threads write consecutive LLR groups of
+// one symbol row).  The body is demk::demod_column; frames are contiguous, so
+// the frame index folds into the user index.
 #include "demod_core.h"
 
 namespace rxphy {
@@ -12,10 +12,11 @@ using namespace demk;
 template <int Q>
 __global__ void __launch_bounds__(256)
 demod_kernel(const float2* __restrict__ xt, const float* __restrict__ nu, float* __restrict__ llr,
-             int64_t total, int D, int n_sc) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= total) return;
-  demod_elem<Q>(xt, nu, llr, idx, D, n_sc);
+             int D, int n_sc) {
+  const int i = blockIdx.x * 256 + tid_x();
+  if (i >= n_sc) return;
+  const int64_t fu = blockIdx.y;                  // frame * K + user (offset by the launcher)
+  demod_column<Q>(xt + fu * D * n_sc + i, nu[fu * n_sc + i], llr + (fu * D * n_sc + i) * Q, D, n_sc);
 }
 
 }  // namespace
@@ -23,16 +24,23 @@ demod_kernel(const float2* __restrict__ xt, const float* __restrict__ nu, float*
 rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, const float* nu,
                           float* llr, hipStream_t s) {
   const int D = fr.n_sym - 1;
-  const int64_t total = (int64_t)nf * fr.K * D * fr.n_sc;
-  const int64_t blocks = (total + 255) / 256;
-  if (blocks > 0x7fffffff) return fail(RXPHY_EUNSUPPORTED, "demod grid too large");
-  switch (fr.qam_bits) {
-    case 2: hipLaunchKernelGGL(demod_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, xt, nu, llr, total, D, fr.n_sc); break;
-    case 4: hipLaunchKernelGGL(demod_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, xt, nu, llr, total, D, fr.n_sc); break;
-    case 6: hipLaunchKernelGGL(demod_kernel<6>, dim3((unsigned)blocks), dim3(256), 0, s, xt, nu, llr, total, D, fr.n_sc); break;
-    default: return fail(RXPHY_EINVAL, "qam_bits = %d", fr.qam_bits);
+  const int64_t cols = (int64_t)nf * fr.K;        // (frame, user) rows, 65535 per launch
+  const unsigned bx = (unsigned)((fr.n_sc + 255) / 256);
+  for (int64_t c0 = 0; c0 < cols; c0 += 65535) {
+    const unsigned by = (unsigned)(cols - c0 < 65535 ? cols - c0 : 65535);
+    const float2* x0 = xt + c0 * D * fr.n_sc;
+    const float* v0 = nu + c0 * fr.n_sc;
+    float* l0 = llr + c0 * D * fr.n_sc * fr.qam_bits;
+    switch (fr.qam_bits) {
+      case 2: hipLaunchKernelGGL(demod_kernel<2>, dim3(bx, by), dim3(256), 0, s, x0, v0, l0, D, fr.n_sc); break;
+      case 4: hipLaunchKernelGGL(demod_kernel<4>, dim3(bx, by), dim3(256), 0, s, x0, v0, l0, D, fr.n_sc); break;
+      case 6: hipLaunchKernelGGL(demod_kernel<6>, dim3(bx, by), dim3(256), 0, s, x0, v0, l0, D, fr.n_sc); break;
+      default: return fail(RXPHY_EINVAL, "qam_bits = %d", fr.qam_bits);
+    }
+    rxphy_status st = launch_status("demod kernel");
+    if (st) return st;
   }
-  return launch_status("demod kernel");
+  return RXPHY_OK;
 }
 
 }  // namespace rxphy

@@ -54,15 +54,10 @@ __device__ __forceinline__ void axis_llr(float x, float inv_nu, float* out) {
 }
 
 
-// Element idx of one frame's x_tilde [K][D][n_sc] (nu [K][n_sc]) to its Q
-// LLRs; an erased subcarrier (nu = inf) gives zeros.
+// LLRs of one equalised symbol x with noise variance v (erased when v = inf)
+// into dst[0 .. Q-1].
 template <int Q>
-__device__ __forceinline__ void demod_elem(const float2* __restrict__ xt, const float* __restrict__ nu,
-                                           float* __restrict__ llr, int64_t idx, int D, int n_sc) {
-  const int64_t fu = idx / ((int64_t)D * n_sc);
-  const int i = (int)(idx % n_sc);
-  const float2 x = xt[idx];
-  const float v = nu[fu * n_sc + i];
+__device__ __forceinline__ void demod_point(float2 x, float v, float* __restrict__ dst) {
   float o[Q];
   if (__builtin_isinf(v)) {
 #pragma unroll
@@ -75,9 +70,24 @@ __device__ __forceinline__ void demod_elem(const float2* __restrict__ xt, const 
 #pragma unroll
     for (int t = 0; t < Q / 2; ++t) { o[2 * t] = re[t]; o[2 * t + 1] = im[t]; }
   }
-  float* dst = llr + idx * Q;
 #pragma unroll
   for (int t = 0; t < Q / 2; ++t) reinterpret_cast<float2*>(dst)[t] = make_float2(o[2 * t], o[2 * t + 1]);
+}
+
+// One (user, subcarrier) column: xc = &x_tilde[u][0][i], lc = &llr[u][0][i][0];
+// nu is read once and the D data symbols are demapped four loads at a time.
+template <int Q>
+__device__ __forceinline__ void demod_column(const float2* __restrict__ xc, float v,
+                                             float* __restrict__ lc, int D, int n_sc) {
+  int d = 0;
+  for (; d + 4 <= D; d += 4) {
+    float2 x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xc[(uint32_t)(d + k) * n_sc];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) demod_point<Q>(x[k], v, lc + (uint32_t)(d + k) * n_sc * Q);
+  }
+  for (; d < D; ++d) demod_point<Q>(xc[(uint32_t)d * n_sc], v, lc + (uint32_t)d * n_sc * Q);
 }
 
 }  // namespace demk

@@ -248,7 +248,8 @@ template <int P = P_FP32>
 __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
                                         int M, int K, int S, int n_sc, int i0, float2* smem,
                                         int* nonfin, f32x4* gr, f32x4* gi, f32x4* zr, f32x4* zi,
-                                        float2* hv, float2* yv, bool have0 = false, int i0n = -1) {
+                                        float2* hv, float2* yv, bool have0 = false, int i0n = -1,
+                                        const float2* Hn = nullptr, const float2* Yn = nullptr) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) gr[t] = gi[t] = zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -276,7 +277,7 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
     }
     __syncthreads();
     if (m0 + MC < M) load_chunk(Hf, Yff, M, K, S, n_sc, i0, m0 + MC, hv, yv);
-    else if (i0n >= 0) load_chunk(Hf, Yff, M, K, S, n_sc, i0n, 0, hv, yv);
+    else if (i0n >= 0) load_chunk(Hn ? Hn : Hf, Yn ? Yn : Yff, M, K, S, n_sc, i0n, 0, hv, yv);
     if constexpr (P == P_FP32) {
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
@@ -383,8 +384,11 @@ __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, co
                                                int* nonfin, SharedFactor* sf, f32x4* zr, f32x4* zi,
                                                f32x4& g0r, f32x4& g0i, float2* hv, float2* yv, bool have0,
                                                int i0n) {
+  // matched filter with three real products per complex one: for h = a + jb,
+  // y = c + jd, conj(h) y = (k1 + b (c + d)) + j (k1 + a (d - c)), k1 = (a - b) c
+  f32x4 zk[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 4; ++t) zr[t] = zi[t] = zk[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   g0r = g0i = f32x4{0.f, 0.f, 0.f, 0.f};
   const int tid = tid_x(), w = tid >> 6, l = tid & 63;
   float2* Hs = smem;
@@ -429,13 +433,17 @@ __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, co
         const int sc = 4 * w + t;
         const float2 hr = Hs[row * PITCH + sc];
         const float2 yr = Ys[row * PITCH + sc];
-        zr[t] = mfma(hr.x, yr.x, zr[t]);
-        zr[t] = mfma(hr.y, yr.y, zr[t]);
-        zi[t] = mfma(hr.x, yr.y, zi[t]);
-        zi[t] = mfma(-hr.y, yr.x, zi[t]);
+        zk[t] = mfma(hr.x - hr.y, yr.x, zk[t]);
+        zr[t] = mfma(hr.y, yr.x + yr.y, zr[t]);
+        zi[t] = mfma(hr.x, yr.y - yr.x, zi[t]);
       }
     }
     __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    zr[t] += zk[t];
+    zi[t] += zk[t];
   }
   if (!(probe == 0.f)) nonfin[c16] = 1;
   if (differ) sf->uniform = 0;
@@ -507,16 +515,17 @@ constexpr int RL_OFF = 64;
 // [M][S][n_sc], xt [K][D][n_sc], nu [K][n_sc], flags [n_sc] of that frame);
 // 256 threads; smem holds SMEM_ALL slots, nonfin TS.  A refined subcarrier i is
 // listed as sub_base + i.  hv/yv carry chunk 0 of this tile in when have0 is
-// set; if i0n >= 0 they carry chunk 0 of the tile at i0n (same frame) out,
-// with have0 set, so that its loads fly during this tile's phase 2.  The
-// caller synchronises before reusing smem.
+// set; if i0n >= 0 they carry chunk 0 of the tile at i0n out (of the frame at
+// Hn/Yn, default this one), with have0 set, so that its loads fly during this
+// tile's phase 2.  The caller synchronises before reusing smem.
 template <int KP, int P>
 __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const float2* __restrict__ Yf,
                                             float2* __restrict__ xt, float* __restrict__ nu,
                                             uint8_t* __restrict__ flags, int M, int K, int S, int n_sc,
                                             float n0, int mmse, float thr, uint32_t* __restrict__ rlist,
                                             uint32_t sub_base, int i0, float2* smem, int* nonfin,
-                                            float2* hv, float2* yv, bool& have0, int i0n) {
+                                            float2* hv, float2* yv, bool& have0, int i0n,
+                                            const float2* Hn = nullptr, const float2* Yn = nullptr) {
   const int D = S - 1;
   const int tid = tid_x(), w = tid >> 6, l = tid & 63;
   SharedFactor* sf = reinterpret_cast<SharedFactor*>(smem + SMEM);
@@ -549,7 +558,7 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
       if (shared) {
         factor_solve_shared<KP>(Pw, Pm, sf, w, (i0 / TS) & 3, g0r, g0i, zr, zi, K, n0, mmse, row, col, g4,
                                 z, inv, dl, ok, [&]() {
-                                  if (i0n >= 0) load_chunk(H, Yf, M, K, S, n_sc, i0n, 0, hv, yv);
+                                  if (i0n >= 0) load_chunk(Hn ? Hn : H, Yn ? Yn : Yf, M, K, S, n_sc, i0n, 0, hv, yv);
                                 });
         have0 = i0n >= 0;
       }
@@ -560,7 +569,8 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
     // prefetch across its phase 2 (registers)
     constexpr bool PREF = !(P == P_FP32 && KP == 16);
     f32x4 gr[4], gi[4], zr[4], zi[4];
-    gram_mf<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi, hv, yv, have0, PREF ? i0n : -1);
+    gram_mf<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi, hv, yv, have0, PREF ? i0n : -1, Hn,
+               Yn);
     have0 = PREF && i0n >= 0;
     float2 v[16];
     factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
