@@ -379,6 +379,7 @@ __device__ __forceinline__ void factor_solve(float2* P, float2* Pm, const f32x4*
 // tile's first subcarrier (DPP broadcast of lane 0 of each 16-lane row); any
 // difference, including a NaN, clears sf->uniform and the caller falls back
 // to the per-subcarrier path.
+template <int P = P_FP32>
 __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
                                                int M, int K, int S, int n_sc, int i0, float2* smem,
                                                int* nonfin, SharedFactor* sf, f32x4* zr, f32x4* zi,
@@ -418,32 +419,53 @@ __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, co
     if (m0 + MC < M) load_chunk(Hf, Yff, M, K, S, n_sc, i0, m0 + MC, hv, yv);
     else if (i0n >= 0) load_chunk(Hf, Yff, M, K, S, n_sc, i0n, 0, hv, yv);
     const bool gram_here = ((m0 / MC) & 3) == w;
+    if constexpr (P == P_FP32) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int row = (4 * a + kq) * 16 + u;
+      for (int a = 0; a < 2; ++a) {
+        const int row = (4 * a + kq) * 16 + u;
+        if (gram_here) {
+          const float2 h0 = Hs[row * PITCH];
+          g0r = mfma(h0.x, h0.x, g0r);
+          g0r = mfma(h0.y, h0.y, g0r);
+          g0i = mfma(h0.x, h0.y, g0i);
+          g0i = mfma(-h0.y, h0.x, g0i);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int sc = 4 * w + t;
+          const float2 hr = Hs[row * PITCH + sc];
+          const float2 yr = Ys[row * PITCH + sc];
+          zk[t] = mfma(hr.x - hr.y, yr.x, zk[t]);
+          zr[t] = mfma(hr.y, yr.x + yr.y, zr[t]);
+          zi[t] = mfma(hr.x, yr.y - yr.x, zi[t]);
+        }
+      }
+    } else {
+      // low precision: one 16x16x16 product per term covers the chunk (as in
+      // gram_mf), the Gram matrix once per tile from its first subcarrier
+      const int r0 = (2 * kq) * 16 + u, r1 = (2 * kq + 1) * 16 + u;
       if (gram_here) {
-        const float2 h0 = Hs[row * PITCH];
-        g0r = mfma(h0.x, h0.x, g0r);
-        g0r = mfma(h0.y, h0.y, g0r);
-        g0i = mfma(h0.x, h0.y, g0i);
-        g0i = mfma(-h0.y, h0.x, g0i);
+        const float2 a0 = Hs[r0 * PITCH], a1 = Hs[r1 * PITCH];
+        g0r = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, a0.x, a0.y, a1.x, a1.y, g0r);
+        g0i = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, a0.y, -a0.x, a1.y, -a1.x, g0i);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int sc = 4 * w + t;
-        const float2 hr = Hs[row * PITCH + sc];
-        const float2 yr = Ys[row * PITCH + sc];
-        zk[t] = mfma(hr.x - hr.y, yr.x, zk[t]);
-        zr[t] = mfma(hr.y, yr.x + yr.y, zr[t]);
-        zi[t] = mfma(hr.x, yr.y - yr.x, zi[t]);
+        const float2 a0 = Hs[r0 * PITCH + sc], a1 = Hs[r1 * PITCH + sc];
+        const float2 c0 = Ys[r0 * PITCH + sc], c1 = Ys[r1 * PITCH + sc];
+        zr[t] = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, c0.x, c0.y, c1.x, c1.y, zr[t]);
+        zi[t] = mfma_lp<P>(a0.x, a0.y, a1.x, a1.y, c0.y, -c0.x, c1.y, -c1.x, zi[t]);
       }
     }
     __syncthreads();
   }
+  if constexpr (P == P_FP32) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    zr[t] += zk[t];
-    zi[t] += zk[t];
+    for (int t = 0; t < 4; ++t) {
+      zr[t] += zk[t];
+      zi[t] += zk[t];
+    }
   }
   if (!(probe == 0.f)) nonfin[c16] = 1;
   if (differ) sf->uniform = 0;
@@ -545,14 +567,16 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
   // matrix: then the Gram matrix is formed once and A is factored once per
   // tile (the result equals the per-subcarrier path up to summation order).
   // (Only a tile of K >= 16 users, or the last pilot group's tile, can lie in
-  // one group, so the path is compiled for the K padding of 16 alone.)
+  // one group, so the path is compiled for the K padding of 16 alone.  With
+  // BF16 / FP16 operands the shared Gram matrix is formed in that precision
+  // too, so the condition estimate and the refinement see the same A.)
   bool shared = false;
-  if constexpr (P == P_FP32 && KP == 16) {
+  if constexpr (KP == 16) {
     const int G = n_sc / K;
     const int last = min(i0 + TS, n_sc) - 1;
     if (min(i0 / K, G - 1) == min(last / K, G - 1)) {
       f32x4 zr[4], zi[4], g0r, g0i;
-      gram_mf_shared(H, Yf, M, K, S, n_sc, i0, smem, nonfin, sf, zr, zi, g0r, g0i, hv, yv, have0, -1);
+      gram_mf_shared<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, sf, zr, zi, g0r, g0i, hv, yv, have0, -1);
       have0 = false;
       shared = __builtin_amdgcn_readfirstlane(sf->uniform) != 0;
       if (shared) {
@@ -567,7 +591,7 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
   if (!shared) {
     // with K padded to 16 this path is the rare fallback and holds no
     // prefetch across its phase 2 (registers)
-    constexpr bool PREF = !(P == P_FP32 && KP == 16);
+    constexpr bool PREF = KP != 16;
     f32x4 gr[4], gi[4], zr[4], zi[4];
     gram_mf<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi, hv, yv, have0, PREF ? i0n : -1, Hn,
                Yn);

@@ -39,8 +39,9 @@ def _inputs(rx, sh, cfg, nfr, channel=None, snr=None, det=O.ZF):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("det", [O.ZF, O.MMSE])
-def test_refine_everything_equals_fp64_solution(rx, prec, det):
-    sh = synth.Shape(32, 12, 1024, 601, 14, 0, 4)
+@pytest.mark.parametrize("K", [12, 16])        # 16: tiles share one channel matrix
+def test_refine_everything_equals_fp64_solution(rx, prec, det, K):
+    sh = synth.Shape(32, K, 1024, 601, 14, 0, 4)
     fr, frs, yf, h = _inputs(rx, sh, 31, 2, snr=(5, 25), det=det)
     xt, nu, fl = (host(t) for t in rx.detect(fr, h, yf, prec, 0.0))
     yfh, hh = host(yf), host(h)
