@@ -208,6 +208,25 @@ def run_batched(rx, torch, args):
                       "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "device_status": status}
         del plan
+    # each stage alone over the same buffers (a plan with one stage in its mask)
+    tiles = tuner.tiles_for(frames)
+    stage_ms = {}
+    for name, bit in (("fft", rx.STAGE_FFT), ("csi", rx.STAGE_CSI), ("detect", rx.STAGE_DETECT),
+                      ("demod", rx.STAGE_DEMOD)):
+        ps = rx.Plan(frames, tiles=tiles, stages=bit)
+        ps.forward(bufs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.form_steps):
+            ps.forward(bufs)
+        e1.record()
+        torch.cuda.synchronize()
+        sms = e0.elapsed_time(e1) / args.form_steps
+        sb = sum(stage_bytes(sh)[name] for sh in shapes)
+        stage_ms[name] = {"us": round(sms * 1e3, 1), "GBps": round(sb / (sms * 1e-3) / 1e9, 1),
+                          "bytes": sb}
+        del ps
     # the same frames as a loop of per-frame single-frame calls (4 launches each)
     plan = rx.Plan(frames)
     views = []
@@ -234,6 +253,7 @@ def run_batched(rx, torch, args):
     out = dict(res["tuned"])
     out.update({"frames": len(frames), "detections_per_step": dets, "algorithmic_bytes": byts,
                 "default_tiles": res["default"], "per_frame_calls": res["per_frame_calls"],
+                "stages_alone": stage_ms,
                 "autotune": tinfo, "gen_seconds": round(gen_s, 1),
                 "workload": "256 uneven frames: M in {8,16,32,64}, K in 1..min(16,M), "
                             "300..3276 subcarriers, N_FFT next power of two >= 1.2 n_sc, "

@@ -211,6 +211,46 @@ def test_chain_vs_oracle(rx, cfg, det, nfr):
         assert mism == 0
 
 
+@pytest.mark.parametrize("det", [O.ZF, O.MMSE])
+def test_chain_at_maximum_shape(rx, det):
+    """M 64, K 16, N 4096 with every bin used, 17 symbols, 64-QAM."""
+    sh = synth.Shape(64, 16, 4096, 4096, 17, 0, 6)
+    fo = synth.make_frame(3, 0, shape=sh, snr=(20, 30))
+    x, p = frames_to_device([fo])
+    fr = rx.Frame.of(sh, det, 1.0)
+    out = {k: host(v) for k, v in rx.forward(fr, x, p).items()}
+    ref = O.forward(fo.x, fo.pilots, sh, 1.0, det, want_kappa=True)
+    good = (ref["kappa"] <= 1e3) & (ref["flags"] == 0)
+    e = evm_rel(out["xt"][0], ref["xt"], good)
+    l = llr_rel(out["llr"][0], ref["llr"])
+    mism, band = hard_bits_outside_guard(out["llr"][0], ref["llr"])
+    say("max shape", det, "evm_rel", e, "llr_rel", l, "hard mismatches", mism, "in band", band)
+    assert np.array_equal(out["flags"][0], ref["flags"])
+    assert e < 1e-4 and l < 1e-3 and mism == 0
+
+
+def test_headline_launch_sampled_frames(rx):
+    """The 100-frame 64x16 batch exactly as the benchmark launches it (one call
+    per stage over all frames); sampled frames checked against the oracle."""
+    sh = synth.config_shape(2)
+    res = synth.draw_inputs(2, range(100), workers=8)
+    x = dev(np.stack([r[0] for r in res]))
+    p = dev(np.stack([r[1] for r in res]))
+    fr = rx.Frame.of(sh, O.ZF, 1.0)
+    out = rx.forward(fr, x, p)
+    torch.cuda.synchronize()
+    for f in (0, 41, 99):
+        ref = O.forward(res[f][0], res[f][1], sh, 1.0, O.ZF, want_kappa=True)
+        good = (ref["kappa"] <= 1e3) & (ref["flags"] == 0)
+        e = evm_rel(host(out["xt"][f]), ref["xt"], good)
+        llr = host(out["llr"][f])
+        l = llr_rel(llr, ref["llr"])
+        mism, band = hard_bits_outside_guard(llr, ref["llr"])
+        say("100-frame launch, frame", f, "evm_rel", e, "llr_rel", l, "hard mismatches", mism)
+        assert np.array_equal(host(out["flags"][f]), ref["flags"])
+        assert e < 1e-4 and l < 1e-3 and mism == 0
+
+
 def test_deterministic(rx):
     frs = synth.make_frames(2, 1)
     x, p = frames_to_device(frs)
