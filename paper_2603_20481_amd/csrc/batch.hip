@@ -65,11 +65,23 @@ __device__ __forceinline__ void run_csi(const BFrame& d, int tile, const float2*
   const int nt = (d.n_sc + csik::CSI_TILE - 1) / csik::CSI_TILE;
   const int p0 = tile * d.csi_tiles;
   const int p1 = min(p0 + d.csi_tiles, d.M * nt);
+  // the next tile's loads are issued before the current tile is finished
+  csik::CsiIn cur, nxt;
+  if (p0 < p1) {
+    const int m = p0 / nt, t = p0 - m * nt;
+    csik::csi_load(yf + d.yf + (int64_t)m * d.n_sym * d.n_sc, pil + d.pil, d.K, d.n_sc,
+                   t * csik::CSI_TILE, cur);
+  }
   for (int p = p0; p < p1; ++p) {
     const int m = p / nt, t = p - m * nt;
+    if (p + 1 < p1) {
+      const int mn = (p + 1) / nt, tn = (p + 1) - mn * nt;
+      csik::csi_load(yf + d.yf + (int64_t)mn * d.n_sym * d.n_sc, pil + d.pil, d.K, d.n_sc,
+                     tn * csik::CSI_TILE, nxt);
+    }
     if (p > p0) __syncthreads();
-    csik::csi_tile(yf + d.yf + (int64_t)m * d.n_sym * d.n_sc, pil + d.pil,
-                   h + d.h + (int64_t)m * d.K * d.n_sc, d.K, d.n_sc, t * csik::CSI_TILE, pool);
+    csik::csi_finish(h + d.h + (int64_t)m * d.K * d.n_sc, d.K, d.n_sc, t * csik::CSI_TILE, cur, pool);
+    cur = nxt;
   }
 }
 

@@ -18,22 +18,52 @@ constexpr int CSI_TILE = 512;
 constexpr int CSI_WG = 256;
 constexpr int CSI_LDS = CSI_TILE + 32;
 
-// y0: the antenna's pilot-symbol row Yf[m][0][:]; pf: the frame's pilot row;
-// hm: H[m][0][0] of the frame ([K][n_sc] rows follow).  256 threads.
-__device__ __forceinline__ void csi_tile(const float2* __restrict__ y0, const float2* __restrict__ pf,
-                                         float2* __restrict__ hm, int K, int n_sc, int i0,
-                                         float2* ls) {
-  const int tx = tid_x();
+// Inputs of one tile: the pilot-symbol values and pilots of the pilot
+// subcarriers q0 .. q1-1 the tile needs (at most 512 + 2K - 1 < 3 x 256).
+struct CsiIn {
+  float2 y[3], p[3];
+};
+
+__device__ __forceinline__ void csi_range(int K, int n_sc, int i0, int& q0, int& q1) {
   const int G = n_sc / K;
   const int i_last = min(i0 + CSI_TILE, n_sc) - 1;
-  const int q0 = min(i0 / K, G - 1) * K;                     // first pilot subcarrier needed
-  const int q1 = min(i_last / K, G - 1) * K + K;             // one past the last
-  for (int q = q0 + tx; q < q1; q += CSI_WG) {
-    const float2 y = y0[q];
-    const float2 p = pf[q];
-    const float pp = p.x * p.x + p.y * p.y;
-    // y conj(p) / |p|^2 ; a zero pilot gives 0/0 = NaN, flagged downstream
-    ls[q - q0] = make_float2((y.x * p.x + y.y * p.y) / pp, (y.y * p.x - y.x * p.y) / pp);
+  q0 = min(i0 / K, G - 1) * K;                               // first pilot subcarrier needed
+  q1 = min(i_last / K, G - 1) * K + K;                       // one past the last
+}
+
+// y0: the antenna's pilot-symbol row Yf[m][0][:]; pf: the frame's pilot row.
+// Issues the tile's loads (lanes past q1 read q0 and are ignored).
+__device__ __forceinline__ void csi_load(const float2* __restrict__ y0, const float2* __restrict__ pf,
+                                         int K, int n_sc, int i0, CsiIn& in) {
+  const int tx = tid_x();
+  int q0, q1;
+  csi_range(K, n_sc, i0, q0, q1);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int q = q0 + tx + j * CSI_WG;
+    const int qc = q < q1 ? q : q0;
+    in.y[j] = y0[qc];
+    in.p[j] = pf[qc];
+  }
+}
+
+// hm: H[m][0][0] of the frame ([K][n_sc] rows follow).  The LS values go
+// through LDS (ls), then every user's row of the tile is written.
+__device__ __forceinline__ void csi_finish(float2* __restrict__ hm, int K, int n_sc, int i0,
+                                           const CsiIn& in, float2* ls) {
+  const int tx = tid_x();
+  int q0, q1;
+  csi_range(K, n_sc, i0, q0, q1);
+  const int G = n_sc / K;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int q = q0 + tx + j * CSI_WG;
+    if (q < q1) {
+      const float2 y = in.y[j], p = in.p[j];
+      const float pp = p.x * p.x + p.y * p.y;
+      // y conj(p) / |p|^2 ; a zero pilot gives 0/0 = NaN, flagged downstream
+      ls[q - q0] = make_float2((y.x * p.x + y.y * p.y) / pp, (y.y * p.x - y.x * p.y) / pp);
+    }
   }
   __syncthreads();
   int gq[2];
@@ -50,6 +80,14 @@ __device__ __forceinline__ void csi_tile(const float2* __restrict__ y0, const fl
     for (int e = 0; e < 2; ++e)
       if (ok[e]) hp[(int64_t)u * n_sc + e * CSI_WG] = ls[gq[e] + u];
   }
+}
+
+__device__ __forceinline__ void csi_tile(const float2* __restrict__ y0, const float2* __restrict__ pf,
+                                         float2* __restrict__ hm, int K, int n_sc, int i0,
+                                         float2* ls) {
+  CsiIn in;
+  csi_load(y0, pf, K, n_sc, i0, in);
+  csi_finish(hm, K, n_sc, i0, in, ls);
 }
 
 }  // namespace csik

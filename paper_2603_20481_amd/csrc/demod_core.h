@@ -75,17 +75,18 @@ __device__ __forceinline__ void demod_point(float2 x, float v, float* __restrict
 }
 
 // One (user, subcarrier) column: xc = &x_tilde[u][0][i], lc = &llr[u][0][i][0];
-// nu is read once and the D data symbols are demapped four loads at a time.
-template <int Q>
+// nu is read once and the D data symbols are demapped CH loads at a time
+// (more loads in flight per thread where fewer waves are resident).
+template <int Q, int CH = 4>
 __device__ __forceinline__ void demod_column(const float2* __restrict__ xc, float v,
                                              float* __restrict__ lc, int D, int n_sc) {
   int d = 0;
-  for (; d + 4 <= D; d += 4) {
-    float2 x[4];
+  for (; d + CH <= D; d += CH) {
+    float2 x[CH];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = xc[(uint32_t)(d + k) * n_sc];
+    for (int k = 0; k < CH; ++k) x[k] = xc[(uint32_t)(d + k) * n_sc];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) demod_point<Q>(x[k], v, lc + (uint32_t)(d + k) * n_sc * Q);
+    for (int k = 0; k < CH; ++k) demod_point<Q>(x[k], v, lc + (uint32_t)(d + k) * n_sc * Q);
   }
   for (; d < D; ++d) demod_point<Q>(xc[(uint32_t)d * n_sc], v, lc + (uint32_t)d * n_sc * Q);
 }
