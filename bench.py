@@ -391,7 +391,7 @@ def main():
         for prec in ("fp32", "bf16", "fp16"):
             ms, per = c3.time(fr3, prec, args.form_steps, 1)
             refined = int((c3.fl & rx.FLAG_REFINED).ne(0).sum().item())
-            out["forms"]["c3_" + prec] = form_summary(
+            out["forms"]["kronecker_64x16_n4096_64qam_" + prec] = form_summary(
                 s3, args.mixed_frames, ms, per,
                 {"refined_subcarriers": refined, "refined_fraction": refined / c3.fl.numel(),
                  "workload": "64x16 MIMO, N_FFT 4096, 3276 subcarriers, 64-QAM, Kronecker "
