@@ -209,31 +209,45 @@ detect_adjoint_kernel(const float2* __restrict__ H, const float2* __restrict__ Y
 }
 
 // C = X_hat V^H + V X_hat^H + 2 A^{-1} diag(e) A^{-1}, one thread per
-// (frame, subcarrier, column j).  Cw: [F][n_sc][K][K].
+// (frame, subcarrier, i, j) entry.  A workgroup stages the X_hat, V, A^{-1}
+// and e of NS = min(64, 256 / K^2) consecutive subcarriers in LDS (they are
+// contiguous in the workspace, so the loads coalesce).  Cw: [F][n_sc][K][K].
+constexpr int C_NS_MAX = 64;
 __global__ void __launch_bounds__(256)
 detect_adjoint_c_kernel(const float2* __restrict__ Xw, const float2* __restrict__ Vw,
                         const float2* __restrict__ Aw, const float* __restrict__ Ew,
                         float2* __restrict__ Cw, int64_t n_sub, int K, int D) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_sub * K) return;
-  const int64_t sub = t / K;
-  const int j = (int)(t - sub * K);
-  const float2* X = Xw + sub * K * D;
-  const float2* V = Vw + sub * K * D;
-  const float2* A = Aw + sub * K * K;
-  const float* E = Ew + sub * K;
-  for (int ii = 0; ii < K; ++ii) {
-    float2 acc = make_float2(0.f, 0.f);
-    for (int s = 0; s < D; ++s) {
-      acc = cms_bc(acc, X[ii * D + s], make_float2(-V[j * D + s].x, -V[j * D + s].y));  // + x[ii][s] conj(v[j][s])
-      acc = cms_bc(acc, V[ii * D + s], make_float2(-X[j * D + s].x, -X[j * D + s].y));  // + v[ii][s] conj(x[j][s])
-    }
-    for (int k = 0; k < K; ++k) {
-      const float2 a = A[k * K + ii];
-      acc = cms_ac(acc, make_float2(-a.x, -a.y), cscale(A[k * K + j], 2.f * E[k]));  // + conj(A[k][ii]) 2 e_k A[k][j]
-    }
-    Cw[(sub * K + ii) * K + j] = acc;
+  __shared__ float2 sx[2048], sv[2048], sa[256];
+  __shared__ float se[256];
+  const int KK = K * K;
+  const int NS = min(C_NS_MAX, 256 / KK);
+  const int64_t s0 = (int64_t)blockIdx.x * NS;
+  const int ns = (int)min((int64_t)NS, n_sub - s0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < ns * K * D; e += 256) {
+    sx[e] = Xw[s0 * K * D + e];
+    sv[e] = Vw[s0 * K * D + e];
   }
+  for (int e = tid; e < ns * KK; e += 256) sa[e] = Aw[s0 * KK + e];
+  for (int e = tid; e < ns * K; e += 256) se[e] = Ew[s0 * K + e];
+  __syncthreads();
+  if (tid >= ns * KK) return;
+  const int sl = tid / KK, r = tid - sl * KK;
+  const int ii = r / K, j = r - ii * K;
+  const float2* X = sx + sl * K * D;
+  const float2* V = sv + sl * K * D;
+  const float2* A = sa + sl * KK;
+  const float* E = se + sl * K;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int s = 0; s < D; ++s) {
+    acc = cms_bc(acc, X[ii * D + s], make_float2(-V[j * D + s].x, -V[j * D + s].y));  // + x[ii][s] conj(v[j][s])
+    acc = cms_bc(acc, V[ii * D + s], make_float2(-X[j * D + s].x, -X[j * D + s].y));  // + v[ii][s] conj(x[j][s])
+  }
+  for (int k = 0; k < K; ++k) {
+    const float2 a = A[k * K + ii];
+    acc = cms_ac(acc, make_float2(-a.x, -a.y), cscale(A[k * K + j], 2.f * E[k]));  // + conj(A[k][ii]) 2 e_k A[k][j]
+  }
+  Cw[(s0 + sl) * KK + r] = acc;
 }
 
 // dL/dY = H V into the data symbols of gyf, dL/dH = Y V^H - H C into gh.
@@ -245,8 +259,11 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
                             const float2* __restrict__ Vw, const float2* __restrict__ Cw,
                             float2* __restrict__ gyf, float2* __restrict__ gh, int M, int K,
                             int S, int n_sc) {
-  __shared__ float2 sv[16 * KP * 16];
-  __shared__ float2 sc[16 * KP * KP];
+  // per-subcarrier pitches padded by one float2: the 16 subcarrier lanes of a
+  // wave then read 16 different bank pairs
+  constexpr int VP = KP * 16 + 1, CP = KP * KP + 1;
+  __shared__ float2 sv[16 * VP];
+  __shared__ float2 sc[16 * CP];
   const int D = S - 1;
   const int f = blockIdx.z;
   const int i0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
@@ -255,12 +272,12 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
   for (int e = threadIdx.x; e < ntile * K * D; e += 256) {
     const int t = e / (K * D), r = e - t * (K * D);
     const int u = r / D, s = r - u * D;
-    sv[(t * KP + u) * 16 + s] = Vw[((int64_t)f * n_sc + i0 + t) * K * D + r];
+    sv[t * VP + u * 16 + s] = Vw[((int64_t)f * n_sc + i0 + t) * K * D + r];
   }
   for (int e = threadIdx.x; e < ntile * K * K; e += 256) {
     const int t = e / (K * K), r = e - t * (K * K);
     const int a = r / K, b = r - a * K;
-    sc[(t * KP + a) * KP + b] = Cw[((int64_t)f * n_sc + i0 + t) * K * K + r];
+    sc[t * CP + a * KP + b] = Cw[((int64_t)f * n_sc + i0 + t) * K * K + r];
   }
   __syncthreads();
   const int i = i0 + il, m = m0 + ml;
@@ -272,8 +289,8 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
 #pragma unroll
   for (int s = 0; s < 16; ++s)
     y[s] = s < D ? Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] : make_float2(0.f, 0.f);
-  const float2* V = sv + il * KP * 16;
-  const float2* C = sc + il * KP * KP;
+  const float2* V = sv + il * VP;
+  const float2* C = sc + il * CP;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     if (s < D) {
@@ -417,7 +434,8 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
   dim3 g1((fr.n_sc + TS - 1) / TS, n_frames);
   dim3 g2((fr.n_sc + 15) / 16, (fr.M + 15) / 16, n_frames);
   const int64_t n_sub = (int64_t)n_frames * fr.n_sc;
-  const unsigned gc = (unsigned)((n_sub * fr.K + 255) / 256);
+  const int c_ns = 256 / (fr.K * fr.K) < 64 ? 256 / (fr.K * fr.K) : 64;
+  const unsigned gc = (unsigned)((n_sub + c_ns - 1) / c_ns);
 #define RXPHY_ADJ(KP)                                                                               \
   hipLaunchKernelGGL(detect_adjoint_kernel<KP>, g1, dim3(256), 0, stream, h, yf, gxt, gnu, Xw, Vw,  \
                      Aw, Ew, fr.M, fr.K, fr.n_sym, fr.n_sc, fr.n0, mmse);                          \
