@@ -5,12 +5,14 @@ on one MI355X, in subcarrier-detections per second.
 Headline step = the whole receiver over one batch of 100 frames of the
 64-antenna, 16-user workload (N_FFT 2048, 1200 used subcarriers, 14 symbols,
 16-QAM, i.i.d. Rayleigh, per-user SNR uniform in [10, 30] dB), plain FP32 ZF,
-with the complex64 samples already resident in HBM.  One
+with the complex64 samples already resident in HBM: the FFT call, the fused
+CSI + detector call (the channel estimate is formed in the detector and never
+stored) and the demod call.  One
 subcarrier-detection is one (frame, data symbol, used subcarrier) turned into
 K*Q LLRs.
 
 Beside the headline the same line reports the other forms, each timed the same
-way: MMSE on the same frames; the BF16 / FP16 detector with FP64 refinement on
+way: the four separate stage calls on the same frames; MMSE; the BF16 / FP16 detector with FP64 refinement on
 the 64x16 N_FFT 4096 64-QAM correlated workload (and plain FP32 there); 256
 uneven frames in one persistent launch replayed from a hipGraph, with
 autotuned and default item sizes and against a loop of per-frame calls; and
@@ -36,7 +38,8 @@ import synth  # noqa: E402
 
 METRIC = "subcarrier-detections/s (64×16, FFT→ZF→LLR), mixed/batched vs plain FP32"
 HBM_PEAK_GBS = 8000.0
-NAMES = ["fft", "csi", "detect", "demod"]
+NAMES = ["fft", "csi", "detect", "demod"]            # the four stage calls
+FUSED_NAMES = ["fft", "csi_detect", "demod"]         # csi and detect fused
 
 
 def gen_frames(cfg, n, workers, shape=None):
@@ -45,13 +48,15 @@ def gen_frames(cfg, n, workers, shape=None):
 
 
 def stage_bytes(s):
-    """Compulsory HBM bytes of each stage's interface tensors for one frame."""
+    """Compulsory HBM bytes of each stage's interface tensors for one frame
+    (csi_detect: the fused csi + detect call, which never stores H)."""
     M, K, N, n_sc, S, cp, Q = s.M, s.K, s.n_fft, s.n_sc, s.n_sym, s.cp_len, s.qam_bits
     D = S - 1
     return {
         "fft": M * S * (cp + N) * 8 + M * S * n_sc * 8,
         "csi": M * n_sc * 8 + n_sc * 8 + M * K * n_sc * 8,
         "detect": M * K * n_sc * 8 + M * D * n_sc * 8 + K * D * n_sc * 8 + K * n_sc * 4 + n_sc,
+        "csi_detect": M * n_sc * 8 + n_sc * 8 + M * D * n_sc * 8 + K * D * n_sc * 8 + K * n_sc * 4 + n_sc,
         "demod": K * D * n_sc * 8 + K * n_sc * 4 + K * D * n_sc * Q * 4,
     }
 
@@ -115,36 +120,40 @@ class Chain:
         self.llr = torch.empty((F, shape.K, D, shape.n_sc, shape.qam_bits), dtype=f32, device=dev)
         self.ws = None
 
-    def step(self, fr, prec="fp32", ev=None):
+    def step(self, fr, prec="fp32", ev=None, fused=False):
         rx = self.rx
-        if ev: ev[0].record()
-        rx.fft(fr, self.x, self.yf)
-        if ev: ev[1].record()
-        rx.csi(fr, self.yf, self.p, self.h)
-        if ev: ev[2].record()
         need = rx.workspace_bytes(fr, self.F, rx.WS_DETECT, prec)
         if need and (self.ws is None or self.ws.numel() < need):
             self.ws = self.torch.empty((need,), dtype=self.torch.uint8, device="cuda")
-        rx.detect(fr, self.h, self.yf, prec, 1e3, self.xt, self.nu, self.fl,
-                  self.ws if need else None)
-        if ev: ev[3].record()
+        ws = self.ws if need else None
+        if ev: ev[0].record()
+        rx.fft(fr, self.x, self.yf)
+        if ev: ev[1].record()
+        if fused:
+            rx.csi_detect(fr, self.yf, self.p, prec, 1e3, self.xt, self.nu, self.fl, ws)
+        else:
+            rx.csi(fr, self.yf, self.p, self.h)
+            if ev: ev[2].record()
+            rx.detect(fr, self.h, self.yf, prec, 1e3, self.xt, self.nu, self.fl, ws)
+        if ev: ev[3 if not fused else 2].record()
         rx.demod(fr, self.xt, self.nu, self.llr)
-        if ev: ev[4].record()
+        if ev: ev[4 if not fused else 3].record()
 
-    def time(self, fr, prec, steps, warmup):
+    def time(self, fr, prec, steps, warmup, fused=False):
         torch = self.torch
+        names = FUSED_NAMES if fused else NAMES
         for _ in range(warmup):
-            self.step(fr, prec)
+            self.step(fr, prec, fused=fused)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
         t0 = time.perf_counter()
         for k in range(steps):
-            self.step(fr, prec, evs[k])
+            self.step(fr, prec, evs[k], fused=fused)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        per = {n: 0.0 for n in NAMES}
+        per = {n: 0.0 for n in names}
         for ev in evs:
-            for j, n in enumerate(NAMES):
+            for j, n in enumerate(names):
                 per[n] += ev[j].elapsed_time(ev[j + 1]) / steps   # ms
         return wall * 1e3 / steps, per
 
@@ -153,7 +162,7 @@ def stage_report(shape, F, per):
     sb = stage_bytes(shape)
     return {n: {"us": round(per[n] * 1e3, 2),
                 "GBps": round(sb[n] * F / (per[n] * 1e-3) / 1e9, 1),
-                "bytes_per_launch": sb[n] * F} for n in NAMES}
+                "bytes_per_launch": sb[n] * F} for n in per}
 
 
 def form_summary(shape, F, ms, per, extra=None):
@@ -161,7 +170,8 @@ def form_summary(shape, F, ms, per, extra=None):
     dets = F * shape.detections
     out = {"value": dets / (ms * 1e-3), "unit": "subcarrier-detections/s", "ms_per_step": round(ms, 4),
            "frames": F, "stages": stage_report(shape, F, per),
-           "hbm_frac": round(sum(sb.values()) * F / (sum(per.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+           "hbm_frac": round(sum(sb[n] for n in per) * F / (sum(per.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             4)}
     if extra:
         out.update(extra)
     return out
@@ -308,7 +318,7 @@ def main():
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
     ap.add_argument("--bwd-frames", type=int, default=50)
-    ap.add_argument("--forms", default="mmse,mixed,batched,fwd_bwd",
+    ap.add_argument("--forms", default="staged,mmse,mixed,batched,fwd_bwd",
                     help="comma list of extra forms to time ('' for the headline only)")
     ap.add_argument("--tile-cache", default=None)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -338,12 +348,12 @@ def main():
     chain = Chain(rx, torch, shape, x_h, p_h)
     del x_h, p_h
     fr = rx.Frame.of(shape, det, 1.0)
-    ms_per_step, per_stage = chain.time(fr, "fp32", args.steps, args.warmup)
+    ms_per_step, per_stage = chain.time(fr, "fp32", args.steps, args.warmup, fused=True)
     dets = F * shape.detections
     value = dets / (ms_per_step * 1e-3)
 
     sb = stage_bytes(shape)
-    dom = max(NAMES, key=lambda n: per_stage[n])
+    dom = max(per_stage, key=lambda n: per_stage[n])
     achieved = sb[dom] * F / (per_stage[dom] * 1e-3) / 1e9
 
     out = {
@@ -360,7 +370,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded generator: Rayleigh block channel, comb pilots, AWGN)",
         "config": {"workload": "64x16 MIMO, N_FFT 2048, 1200 used subcarriers, 14 symbols, 16-QAM, "
-                               "Rayleigh, SNR U[10,30] dB, 100 frames, ZF, FP32",
+                               "Rayleigh, SNR U[10,30] dB, 100 frames, ZF, FP32; fft, fused csi + "
+                               "detect (H never stored), demod",
                    "frames": F, "M": shape.M, "K": shape.K, "n_fft": shape.n_fft,
                    "n_sc": shape.n_sc, "n_sym": shape.n_sym, "qam_bits": shape.qam_bits,
                    "detector": "zf", "precision": "fp32"},
@@ -369,15 +380,21 @@ def main():
                      "traffic": measured_traffic(dom), "traffic_unit": "bytes/launch",
                      "algorithmic_bytes": sb[dom] * F},
         "stages": stage_report(shape, F, per_stage),
-        "staged_roofline_frac": round(sum(sb.values()) * F / (sum(per_stage.values()) * 1e-3) / 1e9
-                                      / HBM_PEAK_GBS, 4),
+        "staged_roofline_frac": round(sum(sb[n] for n in per_stage) * F / (sum(per_stage.values()) * 1e-3)
+                                      / 1e9 / HBM_PEAK_GBS, 4),
         "gen_seconds": round(gen_s, 1),
         "forms": {},
     }
     print("[bench] headline %.4g det/s (%.3f ms/step)" % (value, ms_per_step), file=sys.stderr, flush=True)
+    if "staged" in forms:
+        ms, per = chain.time(fr, "fp32", args.form_steps, 1)
+        out["forms"]["staged_fp32"] = form_summary(
+            shape, F, ms, per, {"workload": "as the headline, the four stage calls (H stored by csi, "
+                                            "read back by detect)"})
+        print("[bench] staged done", file=sys.stderr, flush=True)
     if "mmse" in forms:
         frm = rx.Frame.of(shape, rx.MMSE, 1.0)
-        ms, per = chain.time(frm, "fp32", args.form_steps, 1)
+        ms, per = chain.time(frm, "fp32", args.form_steps, 1, fused=True)
         out["forms"]["mmse_fp32"] = form_summary(shape, F, ms, per, {"workload": "as the headline, MMSE"})
         print("[bench] mmse done", file=sys.stderr, flush=True)
     del chain
@@ -389,7 +406,7 @@ def main():
         del x3, p3
         fr3 = rx.Frame.of(s3, rx.ZF, 1.0)
         for prec in ("fp32", "bf16", "fp16"):
-            ms, per = c3.time(fr3, prec, args.form_steps, 1)
+            ms, per = c3.time(fr3, prec, args.form_steps, 1, fused=True)
             refined = int((c3.fl & rx.FLAG_REFINED).ne(0).sum().item())
             out["forms"]["kronecker_64x16_n4096_64qam_" + prec] = form_summary(
                 s3, args.mixed_frames, ms, per,

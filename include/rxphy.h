@@ -120,6 +120,19 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames,
                           rxphy_precision precision, float cond_threshold,
                           void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* csi and equal stages fused: rxphy_csi followed by rxphy_detect on the same
+ * frames, with the channel estimate formed on the fly from symbol 0 of yf and
+ * the pilots instead of being written to and read back from an H tensor.
+ * Every output (xt, nu, flags, and the refinement of the low-precision
+ * forms) is bit-identical to the two-call sequence; the CSI stage's H is
+ * simply never stored.  Arguments as rxphy_csi and rxphy_detect; the
+ * workspace is rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT,
+ * precision) bytes.                                                            */
+rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
+                              const void* yf, const void* pilots, void* xt, float* nu,
+                              uint8_t* flags, rxphy_precision precision, float cond_threshold,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* demod stage (`demod` macro): max-log LLRs over the Gray square-QAM set
  * with unit average energy (bits b0 .. b_{Q-1}; b0, b2, b4 select the
  * in-phase level, b1, b3, b5 the quadrature level):

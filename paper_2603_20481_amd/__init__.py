@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_fft": [FR, I32, P, P, P],
         "rxphy_csi": [FR, I32, P, P, P, P],
         "rxphy_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
+        "rxphy_csi_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_demod": [FR, I32, P, P, P, P],
         "rxphy_backward": [FR, I32, P, P, ctypes.POINTER(_Saved), P, P, P, P, SZ, P],
     }
@@ -223,6 +224,29 @@ def detect(fr: Frame, h, yf, precision: str = "fp32", cond_threshold: float = 1e
     return xt, nu, flags
 
 
+def csi_detect(fr: Frame, yf, pilots, precision: str = "fp32", cond_threshold: float = 1e3,
+               xt=None, nu=None, flags=None, ws=None):
+    """csi and detect fused (H never stored); same outputs as detect(fr, csi(fr, yf, pilots), yf)."""
+    F = _nf(yf)
+    D = fr.n_data
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    xt = _empty((F, fr.K, D, fr.n_sc), torch.complex64, yf) if xt is None else xt
+    nu = _empty((F, fr.K, fr.n_sc), torch.float32, yf) if nu is None else nu
+    flags = _empty((F, fr.n_sc), torch.uint8, yf) if flags is None else flags
+    _need(xt, "xt", (F, fr.K, D, fr.n_sc), torch.complex64)
+    _need(nu, "nu", (F, fr.K, fr.n_sc), torch.float32)
+    _need(flags, "flags", (F, fr.n_sc), torch.uint8)
+    need = workspace_bytes(fr, F, WS_DETECT, precision)
+    if need and ws is None:
+        ws = _empty((need,), torch.uint8, yf)
+    _check(load().rxphy_csi_detect(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots), _ptr(xt), _ptr(nu),
+                                   _ptr(flags), PRECISIONS[precision], float(cond_threshold),
+                                   _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+           "rxphy_csi_detect")
+    return xt, nu, flags
+
+
 def demod(fr: Frame, xt, nu, llr=None):
     """-> llr f32 [F][K][D][n_sc][qam_bits]."""
     F = _nf(xt)
@@ -237,9 +261,15 @@ def demod(fr: Frame, xt, nu, llr=None):
     return llr
 
 
-def forward(fr: Frame, x, pilots, precision: str = "fp32", cond_threshold: float = 1e3):
-    """All four stages; returns a dict of every intermediate."""
+def forward(fr: Frame, x, pilots, precision: str = "fp32", cond_threshold: float = 1e3,
+            fused: bool = False):
+    """All four stages; returns a dict of every intermediate (no "h" when the
+    csi and detect stages run fused)."""
     yf = fft(fr, x)
+    if fused:
+        xt, nu, flags = csi_detect(fr, yf, pilots, precision, cond_threshold)
+        llr = demod(fr, xt, nu)
+        return dict(yf=yf, xt=xt, nu=nu, flags=flags, llr=llr)
     h = csi(fr, yf, pilots)
     xt, nu, flags = detect(fr, h, yf, precision, cond_threshold)
     llr = demod(fr, xt, nu)

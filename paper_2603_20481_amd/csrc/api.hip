@@ -142,8 +142,30 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames, const void
   if ((st = check_ptr(h, "h")) || (st = check_ptr(yf, "yf")) || (st = check_ptr(xt, "xt")) ||
       (st = check_ptr(nu, "nu")))
     return st;
-  return launch_detect(*frame, n_frames, (const float2*)h, (const float2*)yf, (float2*)xt, nu,
+  return launch_detect(*frame, n_frames, (const float2*)h, (const float2*)yf, nullptr, (float2*)xt, nu,
                        flags, precision, cond_threshold, ws, stream);
+}
+
+rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames, const void* yf,
+                              const void* pilots, void* xt, float* nu, uint8_t* flags,
+                              rxphy_precision precision, float cond_threshold, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
+    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
+    return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
+  size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT, precision);
+  if (need && (!ws || ws_bytes < need))
+    return fail(RXPHY_EWORKSPACE, "detect needs %zu workspace bytes, got %zu", need, ws_bytes);
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(xt, "xt")) ||
+      (st = check_ptr(nu, "nu")))
+    return st;
+  return launch_detect(*frame, n_frames, nullptr, (const float2*)yf, (const float2*)pilots, (float2*)xt,
+                       nu, flags, precision, cond_threshold, ws, stream);
 }
 
 rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames, const void* xt,

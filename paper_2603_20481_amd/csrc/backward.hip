@@ -141,9 +141,9 @@ detect_adjoint_kernel(const float2* __restrict__ H, const float2* __restrict__ Y
   __syncthreads();
 
   f32x4 gr[4], gi[4], zr[4], zi[4];
-  float2 hv[8], yv[8];
+  float2 hv[8], yv[8], pv;
   gram_mf(H + (int64_t)f * M * K * n_sc, Yf + (int64_t)f * M * S * n_sc, M, K, S, n_sc, i0, smem,
-          nonfin, gr, gi, zr, zi, hv, yv);
+          nonfin, gr, gi, zr, zi, hv, yv, pv);
   float2* P = smem + w * 4 * PMAT;
   const int col = l & 15, g4 = (l >> 4) * 4;
   const int scl = l >> 4, row = l & 15;
@@ -418,7 +418,8 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
     if ((st = launch_fft(fr, n_tr, (const float2*)x, (float2*)(w + L.yf), false, stream))) return st;
   if (!(saved && saved->h))
     if ((st = launch_csi(fr, n_frames, yf, (const float2*)pilots, (float2*)(w + L.h), stream))) return st;
-  if ((st = launch_detect(fr, n_frames, h, yf, xt, nu, flags, RXPHY_FP32, 0.f, nullptr, stream))) return st;
+  if ((st = launch_detect(fr, n_frames, h, yf, nullptr, xt, nu, flags, RXPHY_FP32, 0.f, nullptr, stream)))
+    return st;
 
   const int D = fr.n_sym - 1;
   const int64_t n_fu = (int64_t)n_frames * fr.K;

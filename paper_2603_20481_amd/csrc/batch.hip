@@ -92,14 +92,14 @@ __device__ __forceinline__ void run_detect(const BFrame& d, int tile, const floa
   const int nt = (d.n_sc + det::TS - 1) / det::TS;
   const int t0 = tile * d.det_tiles;
   const int t1 = min(t0 + d.det_tiles, nt);
-  float2 hv[8], yv[8];
+  float2 hv[8], yv[8], pv;
   bool have0 = false;
   for (int t = t0; t < t1; ++t) {
     if (t > t0) __syncthreads();
     det::detect_tile<KP, det::P_FP32>(h + d.h, yf + d.yf, xt + d.xt, nu + d.nu,
                                       flags ? flags + d.flags : nullptr, d.M, d.K, d.n_sym, d.n_sc,
                                       d.n0, d.mmse, 0.f, nullptr, 0u, t * det::TS, pool, nonfin, hv, yv,
-                                      have0, t + 1 < t1 ? (t + 1) * det::TS : -1);
+                                      pv, have0, t + 1 < t1 ? (t + 1) * det::TS : -1);
   }
 }
 

@@ -32,9 +32,11 @@ rxphy_status launch_fft(const rxphy_frame& fr, int64_t n_tr, const float2* x, fl
                         bool inverse, hipStream_t s);
 rxphy_status launch_csi(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
                         float2* h, hipStream_t s);
+// pil != nullptr: fused CSI (h unused; the channel is the LS estimate from
+// the pilot symbol of yf and the pilots, bit-identical to the CSI stage's).
 rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
-                           float2* xt, float* nu, uint8_t* flags, rxphy_precision prec,
-                           float thr, void* ws, hipStream_t s);
+                           const float2* pil, float2* xt, float* nu, uint8_t* flags,
+                           rxphy_precision prec, float thr, void* ws, hipStream_t s);
 size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec);
 rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, const float* nu,
                           float* llr, hipStream_t s);
@@ -60,5 +62,13 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Least-squares channel estimate from one pilot subcarrier: y conj(p) / |p|^2
+// (a zero pilot gives 0/0 = NaN, flagged downstream).  The CSI stage and the
+// fused CSI + detector path both call this one expression, so they round alike.
+__device__ __forceinline__ float2 ls_estimate(float2 y, float2 p) {
+  const float pp = p.x * p.x + p.y * p.y;
+  return make_float2((y.x * p.x + y.y * p.y) / pp, (y.y * p.x - y.x * p.y) / pp);
+}
 
 }  // namespace rxphy

@@ -58,12 +58,7 @@ __device__ __forceinline__ void csi_finish(float2* __restrict__ hm, int K, int n
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int q = q0 + tx + j * CSI_WG;
-    if (q < q1) {
-      const float2 y = in.y[j], p = in.p[j];
-      const float pp = p.x * p.x + p.y * p.y;
-      // y conj(p) / |p|^2 ; a zero pilot gives 0/0 = NaN, flagged downstream
-      ls[q - q0] = make_float2((y.x * p.x + y.y * p.y) / pp, (y.y * p.x - y.x * p.y) / pp);
-    }
+    if (q < q1) ls[q - q0] = ls_estimate(in.y[j], in.p[j]);
   }
   __syncthreads();
   int gq[2];

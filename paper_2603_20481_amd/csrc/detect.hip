@@ -13,11 +13,12 @@ using namespace det;
 
 constexpr int TPB = 1;   // tiles per workgroup
 
-template <int KP, int P>
+// FU: fused CSI (H formed from the pilot symbol of Yf and the pilots pil).
+template <int KP, int P, bool FU>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
-              float2* __restrict__ xt, float* __restrict__ nu, uint8_t* __restrict__ flags,
-              int M, int K, int S, int n_sc, float n0, int mmse, float thr,
+              const float2* __restrict__ pil, float2* __restrict__ xt, float* __restrict__ nu,
+              uint8_t* __restrict__ flags, int M, int K, int S, int n_sc, float n0, int mmse, float thr,
               uint32_t* __restrict__ rlist) {
   __shared__ float2 smem[SMEM_ALL];
   __shared__ int nonfin[TS];
@@ -27,14 +28,16 @@ detect_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   const int nt = (n_sc + TS - 1) / TS;
   const int t0 = blockIdx.x * TPB;
   const int t1 = min(t0 + TPB, nt);
-  float2 hv[8], yv[8];
+  float2 hv[8], yv[8], pv;
   bool have0 = false;
   for (int t = t0; t < t1; ++t) {
     if (t > t0) __syncthreads();
-    detect_tile<KP, P>(H + f * M * K * n_sc, Yf + f * M * S * n_sc, xt + f * K * (S - 1) * n_sc,
-                       nu + f * K * n_sc, flags ? flags + f * n_sc : nullptr, M, K, S, n_sc, n0, mmse,
-                       thr, rlist, (uint32_t)(f * n_sc), t * TS, smem, nonfin, hv, yv, have0,
-                       t + 1 < t1 ? (t + 1) * TS : -1);
+    detect_tile<KP, P, FU>(FU ? nullptr : H + f * M * K * n_sc, Yf + f * M * S * n_sc,
+                           xt + f * K * (S - 1) * n_sc, nu + f * K * n_sc,
+                           flags ? flags + f * n_sc : nullptr, M, K, S, n_sc, n0, mmse, thr, rlist,
+                           (uint32_t)(f * n_sc), t * TS, smem, nonfin, hv, yv, pv, have0,
+                           t + 1 < t1 ? (t + 1) * TS : -1, nullptr, nullptr,
+                           FU ? pil + f * n_sc : nullptr);
   }
 }
 
@@ -61,7 +64,8 @@ constexpr int RP = 17;   // row pitch (double2) of the 16 x 16 work matrices
 // refinement step x1 = x0 + A^{-1} (b - A x0) from the low-precision x0, and
 // d = diag(A^{-1}) from the FP64 factor; then the unbiasing, nu and flags.
 __global__ void __launch_bounds__(64)
-refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf, float2* __restrict__ xt,
+refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
+              const float2* __restrict__ pil, float2* __restrict__ xt,
               float* __restrict__ nu, uint8_t* __restrict__ flags, const uint32_t* __restrict__ rlist,
               int M, int K, int S, int n_sc, float n0f, int mmse) {
   __shared__ double2 Hs[64 * 16];
@@ -81,7 +85,14 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf, float
     const int f = (int)(sub / (uint32_t)n_sc), i = (int)(sub - (uint32_t)f * n_sc);
     for (int q = tid; q < M * K; q += 64) {
       const int m = q / K, u = q - m * K;
-      Hs[m * 16 + u] = d2(H[((int64_t)(f * M + m) * K + u) * n_sc + i]);
+      float2 hval;
+      if (pil) {                                  // fused CSI: the LS estimate, as the CSI stage forms it
+        const int G = n_sc / K, q = min(i / K, G - 1) * K + u;
+        hval = ls_estimate(Yf[((int64_t)(f * M + m) * S) * n_sc + q], pil[(int64_t)f * n_sc + q]);
+      } else {
+        hval = H[((int64_t)(f * M + m) * K + u) * n_sc + i];
+      }
+      Hs[m * 16 + u] = d2(hval);
     }
     for (int q = tid; q < M * D; q += 64) {
       const int m = q / D, s = q - m * D;
@@ -175,20 +186,27 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf, float
   }
 }
 
-template <int KP, int P>
-void launch_one(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, float2* xt,
-                float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
+template <int KP, int P, bool FU>
+void launch_one(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, const float2* pil,
+                float2* xt, float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
   dim3 grid(((fr.n_sc + TS - 1) / TS + TPB - 1) / TPB, nf);
-  hipLaunchKernelGGL((detect_kernel<KP, P>), grid, dim3(256), 0, s, h, yf, xt, nu, flags, fr.M, fr.K,
-                     fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0, thr, rl);
+  hipLaunchKernelGGL((detect_kernel<KP, P, FU>), grid, dim3(256), 0, s, h, yf, pil, xt, nu, flags, fr.M,
+                     fr.K, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0, thr, rl);
+}
+
+template <int P, bool FU>
+void launch_k(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, const float2* pil,
+              float2* xt, float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
+  if (fr.K <= 4) launch_one<4, P, FU>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
+  else if (fr.K <= 8) launch_one<8, P, FU>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
+  else launch_one<16, P, FU>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
 }
 
 template <int P>
-void launch_p(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, float2* xt,
-              float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
-  if (fr.K <= 4) launch_one<4, P>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
-  else if (fr.K <= 8) launch_one<8, P>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
-  else launch_one<16, P>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+void launch_p(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, const float2* pil,
+              float2* xt, float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
+  if (pil) launch_k<P, true>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
+  else launch_k<P, false>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
 }
 
 }  // namespace
@@ -199,23 +217,23 @@ size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision
 }
 
 rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
-                           float2* xt, float* nu, uint8_t* flags, rxphy_precision prec, float thr,
-                           void* ws, hipStream_t s) {
+                           const float2* pil, float2* xt, float* nu, uint8_t* flags, rxphy_precision prec,
+                           float thr, void* ws, hipStream_t s) {
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
   if (prec == RXPHY_FP32) {
-    launch_p<P_FP32>(fr, nf, h, yf, xt, nu, flags, thr, nullptr, s);
+    launch_p<P_FP32>(fr, nf, h, yf, pil, xt, nu, flags, thr, nullptr, s);
     return launch_status("detect kernel");
   }
   uint32_t* rl = (uint32_t*)ws;
   hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(64), 0, s, rl);
-  if (prec == RXPHY_BF16) launch_p<P_BF16>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
-  else launch_p<P_FP16>(fr, nf, h, yf, xt, nu, flags, thr, rl, s);
+  if (prec == RXPHY_BF16) launch_p<P_BF16>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
+  else launch_p<P_FP16>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
   rxphy_status st = launch_status("detect kernel");
   if (st) return st;
   const int64_t n_sub = (int64_t)nf * fr.n_sc;
   const unsigned blocks = (unsigned)(n_sub < 4096 ? n_sub : 4096);
-  hipLaunchKernelGGL(refine_kernel, dim3(blocks), dim3(64), 0, s, h, yf, xt, nu, flags, rl, fr.M, fr.K,
-                     fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  hipLaunchKernelGGL(refine_kernel, dim3(blocks), dim3(64), 0, s, h, yf, pil, xt, nu, flags, rl, fr.M,
+                     fr.K, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
   return launch_status("refine kernel");
 }
 

@@ -218,24 +218,59 @@ __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
 // H[m0 + it][rb][i0 + c16] and Y[m0 + it][1 + rb][i0 + c16]; absent slots,
 // antennas and subcarriers read zero.  The byte offsets are a lane constant
 // plus it times a uniform stride, and all 16 loads are issued back to back.
+// FU (fused CSI): instead of H, hv gets the pilot-symbol value Y[m][0][q] of
+// the lane's pilot subcarrier q = g(i) K + rb and pv its pilot p[q]; the LS
+// estimate is formed when the chunk is staged (stage_h), after the loads have
+// landed.
+template <bool FU>
 __device__ __forceinline__ void load_chunk(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
-                                           int M, int K, int S, int n_sc, int i0, int m0, float2* hv,
-                                           float2* yv) {
+                                           const float2* __restrict__ pil, int M, int K, int S, int n_sc,
+                                           int i0, int m0, float2* hv, float2* yv, float2& pv) {
   const int tid = tid_x();
   const int rb = tid >> 4, ic = i0 + (tid & 15);
   const int D = S - 1;
-  const __amdgpu_buffer_rsrc_t hrs = rsrc(Hf, (uint32_t)M * K * n_sc * 8u);
   const __amdgpu_buffer_rsrc_t yrs = rsrc(Yff, (uint32_t)M * S * n_sc * 8u);
   const bool in_range = ic < n_sc;
-  const uint32_t h_lane = in_range && rb < K ? (uint32_t)(rb * n_sc + ic) * 8u : OOB;
   const uint32_t y_lane = in_range && rb < D ? (uint32_t)((1 + rb) * n_sc + ic) * 8u : OOB;
-  const uint32_t h_ant = (uint32_t)K * n_sc * 8u, y_ant = (uint32_t)S * n_sc * 8u;
+  const uint32_t y_ant = (uint32_t)S * n_sc * 8u;
   const int mc = min(MC, M - m0);
+  if constexpr (!FU) {
+    const __amdgpu_buffer_rsrc_t hrs = rsrc(Hf, (uint32_t)M * K * n_sc * 8u);
+    const uint32_t h_lane = in_range && rb < K ? (uint32_t)(rb * n_sc + ic) * 8u : OOB;
+    const uint32_t h_ant = (uint32_t)K * n_sc * 8u;
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const uint32_t a = (uint32_t)(m0 + it);
-    hv[it] = ld2(hrs, it < mc ? h_lane + a * h_ant : OOB);
-    yv[it] = ld2(yrs, it < mc ? y_lane + a * y_ant : OOB);
+    for (int it = 0; it < 8; ++it) {
+      const uint32_t a = (uint32_t)(m0 + it);
+      hv[it] = ld2(hrs, it < mc ? h_lane + a * h_ant : OOB);
+      yv[it] = ld2(yrs, it < mc ? y_lane + a * y_ant : OOB);
+    }
+  } else {
+    const int G = n_sc / K;
+    const int q = min(ic / K, G - 1) * K + rb;
+    const bool hok = in_range && rb < K;
+    const uint32_t q_lane = hok ? (uint32_t)q * 8u : OOB;
+    if (m0 == 0) pv = ld2(rsrc(pil, (uint32_t)n_sc * 8u), q_lane);
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const uint32_t a = (uint32_t)(m0 + it);
+      hv[it] = ld2(yrs, it < mc ? q_lane + a * y_ant : OOB);
+      yv[it] = ld2(yrs, it < mc ? y_lane + a * y_ant : OOB);
+    }
+  }
+}
+
+// The channel value a lane stages for (antenna m0 + it, its user slot): the
+// loaded H, or with FU the LS estimate from the loaded pilot-symbol value
+// (zero for absent users, antennas and subcarriers).
+template <bool FU>
+__device__ __forceinline__ float2 stage_h(float2 h, float2 pv, int it, int M, int K, int n_sc, int i0,
+                                          int m0) {
+  if constexpr (!FU) {
+    return h;
+  } else {
+    const int tid = tid_x();
+    const bool ok = (tid >> 4) < K && i0 + (tid & 15) < n_sc && it < min(MC, M - m0);
+    return ok ? ls_estimate(h, pv) : make_float2(0.f, 0.f);
   }
 }
 
@@ -244,12 +279,13 @@ __device__ __forceinline__ void load_chunk(const float2* __restrict__ Hf, const 
 // rows (slot = user for H, data symbol for Y; absent slots, antennas and
 // subcarriers hold zero), so the MFMA loop reads them unmasked.  A
 // subcarrier with a non-finite input gets nonfin[c] = 1.
-template <int P = P_FP32>
+template <int P = P_FP32, bool FU = false>
 __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
                                         int M, int K, int S, int n_sc, int i0, float2* smem,
                                         int* nonfin, f32x4* gr, f32x4* gi, f32x4* zr, f32x4* zi,
-                                        float2* hv, float2* yv, bool have0 = false, int i0n = -1,
-                                        const float2* Hn = nullptr, const float2* Yn = nullptr) {
+                                        float2* hv, float2* yv, float2& pv, const float2* pil = nullptr,
+                                        bool have0 = false, int i0n = -1, const float2* Hn = nullptr,
+                                        const float2* Yn = nullptr, const float2* pn = nullptr) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) gr[t] = gi[t] = zr[t] = zi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -263,21 +299,23 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
   // next chunk is loaded while the current one feeds the MFMAs, and after
   // the last chunk the first chunk of tile i0n (if >= 0) is prefetched
   float probe = 0.f;
-  if (!have0) load_chunk(Hf, Yff, M, K, S, n_sc, i0, 0, hv, yv);
+  if (!have0) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, 0, hv, yv, pv);
   for (int m0 = 0; m0 < M; m0 += MC) {
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
       const int r = rb + 16 * it;
-      probe = __builtin_fmaf(hv[it].x, 0.f, probe);
-      probe = __builtin_fmaf(hv[it].y, 0.f, probe);
+      const float2 h = stage_h<FU>(hv[it], pv, it, M, K, n_sc, i0, m0);
+      probe = __builtin_fmaf(h.x, 0.f, probe);
+      probe = __builtin_fmaf(h.y, 0.f, probe);
       probe = __builtin_fmaf(yv[it].x, 0.f, probe);
       probe = __builtin_fmaf(yv[it].y, 0.f, probe);
-      Hs[r * PITCH + c16] = hv[it];
+      Hs[r * PITCH + c16] = h;
       Ys[r * PITCH + c16] = yv[it];
     }
     __syncthreads();
-    if (m0 + MC < M) load_chunk(Hf, Yff, M, K, S, n_sc, i0, m0 + MC, hv, yv);
-    else if (i0n >= 0) load_chunk(Hn ? Hn : Hf, Yn ? Yn : Yff, M, K, S, n_sc, i0n, 0, hv, yv);
+    if (m0 + MC < M) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, m0 + MC, hv, yv, pv);
+    else if (i0n >= 0)
+      load_chunk<FU>(Hn ? Hn : Hf, Yn ? Yn : Yff, pn ? pn : pil, M, K, S, n_sc, i0n, 0, hv, yv, pv);
     if constexpr (P == P_FP32) {
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
@@ -379,12 +417,13 @@ __device__ __forceinline__ void factor_solve(float2* P, float2* Pm, const f32x4*
 // tile's first subcarrier (DPP broadcast of lane 0 of each 16-lane row); any
 // difference, including a NaN, clears sf->uniform and the caller falls back
 // to the per-subcarrier path.
-template <int P = P_FP32>
+template <int P = P_FP32, bool FU = false>
 __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, const float2* __restrict__ Yff,
-                                               int M, int K, int S, int n_sc, int i0, float2* smem,
-                                               int* nonfin, SharedFactor* sf, f32x4* zr, f32x4* zi,
-                                               f32x4& g0r, f32x4& g0i, float2* hv, float2* yv, bool have0,
-                                               int i0n) {
+                                               const float2* __restrict__ pil, int M, int K, int S,
+                                               int n_sc, int i0, float2* smem, int* nonfin,
+                                               SharedFactor* sf, f32x4* zr, f32x4* zi, f32x4& g0r,
+                                               f32x4& g0i, float2* hv, float2* yv, float2& pv,
+                                               bool have0) {
   // matched filter with three real products per complex one: for h = a + jb,
   // y = c + jd, conj(h) y = (k1 + b (c + d)) + j (k1 + a (d - c)), k1 = (a - b) c
   f32x4 zk[4];
@@ -401,23 +440,23 @@ __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, co
   const bool in_range = ic < n_sc;
   float probe = 0.f;
   bool differ = false;
-  if (!have0) load_chunk(Hf, Yff, M, K, S, n_sc, i0, 0, hv, yv);
+  if (!have0) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, 0, hv, yv, pv);
   for (int m0 = 0; m0 < M; m0 += MC) {
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
       const int r = rb + 16 * it;
-      probe = __builtin_fmaf(hv[it].x, 0.f, probe);
-      probe = __builtin_fmaf(hv[it].y, 0.f, probe);
+      const float2 h = stage_h<FU>(hv[it], pv, it, M, K, n_sc, i0, m0);
+      probe = __builtin_fmaf(h.x, 0.f, probe);
+      probe = __builtin_fmaf(h.y, 0.f, probe);
       probe = __builtin_fmaf(yv[it].x, 0.f, probe);
       probe = __builtin_fmaf(yv[it].y, 0.f, probe);
-      const float fx = bc<0>(hv[it].x), fy = bc<0>(hv[it].y);
-      differ |= in_range && (hv[it].x != fx || hv[it].y != fy);
-      Hs[r * PITCH + c16] = hv[it];
+      const float fx = bc<0>(h.x), fy = bc<0>(h.y);
+      differ |= in_range && (h.x != fx || h.y != fy);
+      Hs[r * PITCH + c16] = h;
       Ys[r * PITCH + c16] = yv[it];
     }
     __syncthreads();
-    if (m0 + MC < M) load_chunk(Hf, Yff, M, K, S, n_sc, i0, m0 + MC, hv, yv);
-    else if (i0n >= 0) load_chunk(Hf, Yff, M, K, S, n_sc, i0n, 0, hv, yv);
+    if (m0 + MC < M) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, m0 + MC, hv, yv, pv);
     const bool gram_here = ((m0 / MC) & 3) == w;
     if constexpr (P == P_FP32) {
 #pragma unroll
@@ -536,18 +575,21 @@ constexpr int RL_OFF = 64;
 // One tile of TS subcarriers from i0 of one frame (H [M][K][n_sc], Yf
 // [M][S][n_sc], xt [K][D][n_sc], nu [K][n_sc], flags [n_sc] of that frame);
 // 256 threads; smem holds SMEM_ALL slots, nonfin TS.  A refined subcarrier i is
-// listed as sub_base + i.  hv/yv carry chunk 0 of this tile in when have0 is
+// listed as sub_base + i.  With FU the channel is not read from H: it is the
+// LS estimate from the pilot symbol of Yf and the pilots pil (exactly the CSI
+// stage's value).  hv/yv/pv carry chunk 0 of this tile in when have0 is
 // set; if i0n >= 0 they carry chunk 0 of the tile at i0n out (of the frame at
 // Hn/Yn, default this one), with have0 set, so that its loads fly during this
 // tile's phase 2.  The caller synchronises before reusing smem.
-template <int KP, int P>
+template <int KP, int P, bool FU = false>
 __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const float2* __restrict__ Yf,
                                             float2* __restrict__ xt, float* __restrict__ nu,
                                             uint8_t* __restrict__ flags, int M, int K, int S, int n_sc,
                                             float n0, int mmse, float thr, uint32_t* __restrict__ rlist,
                                             uint32_t sub_base, int i0, float2* smem, int* nonfin,
-                                            float2* hv, float2* yv, bool& have0, int i0n,
-                                            const float2* Hn = nullptr, const float2* Yn = nullptr) {
+                                            float2* hv, float2* yv, float2& pv, bool& have0, int i0n,
+                                            const float2* Hn = nullptr, const float2* Yn = nullptr,
+                                            const float2* pil = nullptr, const float2* pn = nullptr) {
   const int D = S - 1;
   const int tid = tid_x(), w = tid >> 6, l = tid & 63;
   SharedFactor* sf = reinterpret_cast<SharedFactor*>(smem + SMEM);
@@ -576,13 +618,16 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
     const int last = min(i0 + TS, n_sc) - 1;
     if (min(i0 / K, G - 1) == min(last / K, G - 1)) {
       f32x4 zr[4], zi[4], g0r, g0i;
-      gram_mf_shared<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, sf, zr, zi, g0r, g0i, hv, yv, have0, -1);
+      gram_mf_shared<P, FU>(H, Yf, pil, M, K, S, n_sc, i0, smem, nonfin, sf, zr, zi, g0r, g0i, hv, yv, pv,
+                            have0);
       have0 = false;
       shared = __builtin_amdgcn_readfirstlane(sf->uniform) != 0;
       if (shared) {
         factor_solve_shared<KP>(Pw, Pm, sf, w, (i0 / TS) & 3, g0r, g0i, zr, zi, K, n0, mmse, row, col, g4,
                                 z, inv, dl, ok, [&]() {
-                                  if (i0n >= 0) load_chunk(Hn ? Hn : H, Yn ? Yn : Yf, M, K, S, n_sc, i0n, 0, hv, yv);
+                                  if (i0n >= 0)
+                                    load_chunk<FU>(Hn ? Hn : H, Yn ? Yn : Yf, pn ? pn : pil, M, K, S, n_sc,
+                                                   i0n, 0, hv, yv, pv);
                                 });
         have0 = i0n >= 0;
       }
@@ -593,8 +638,8 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
     // prefetch across its phase 2 (registers)
     constexpr bool PREF = KP != 16;
     f32x4 gr[4], gi[4], zr[4], zi[4];
-    gram_mf<P>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi, hv, yv, have0, PREF ? i0n : -1, Hn,
-               Yn);
+    gram_mf<P, FU>(H, Yf, M, K, S, n_sc, i0, smem, nonfin, gr, gi, zr, zi, hv, yv, pv, pil, have0,
+                   PREF ? i0n : -1, Hn, Yn, pn);
     have0 = PREF && i0n >= 0;
     float2 v[16];
     factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);

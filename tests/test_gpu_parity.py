@@ -251,6 +251,36 @@ def test_headline_launch_sampled_frames(rx):
         assert e < 1e-4 and l < 1e-3 and mism == 0
 
 
+FUSED_CASES = [(synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.ZF, "fp32"),
+               (synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.MMSE, "bf16"),
+               (synth.Shape(32, 16, 1024, 601, 9, 16, 6), O.MMSE, "fp32"),
+               (synth.Shape(16, 5, 1024, 777, 14, 0, 2), O.ZF, "fp16"),
+               (synth.Shape(8, 1, 512, 300, 14, 0, 2), O.MMSE, "fp32"),
+               (synth.Shape(64, 12, 4096, 3276, 17, 0, 6), O.ZF, "fp32")]
+
+
+@pytest.mark.parametrize("sh,det,prec", FUSED_CASES)
+def test_fused_csi_detect_equals_two_calls(rx, sh, det, prec):
+    """rxphy_csi_detect is bit-identical to rxphy_csi followed by rxphy_detect
+    (every K padding, ragged tiles, both detectors, the refined forms, a zero
+    pilot, and a threshold that refines)."""
+    frs = [synth.make_frame(4, f, shape=sh) for f in range(2)]
+    x, p = frames_to_device(frs)
+    p[1, 7] = 0                                     # zero pilot: non-finite estimates, flagged
+    fr = rx.Frame.of(sh, det, 1.0)
+    yf = rx.fft(fr, x)
+    thr = 20.0 if prec != "fp32" else 1e3           # low threshold: some subcarriers refined
+    a = rx.detect(fr, rx.csi(fr, yf, p), yf, prec, thr)
+    b = rx.csi_detect(fr, yf, p, prec, thr)
+    torch.cuda.synchronize()
+    refined = int((a[2] & rx.FLAG_REFINED).ne(0).sum().item())
+    say("fused", sh, det, prec, "refined", refined, "flagged", int(a[2].ne(0).sum().item()))
+    for u, v, name in zip(a, b, ("xt", "nu", "flags")):
+        if u.is_complex():
+            u, v = torch.view_as_real(u), torch.view_as_real(v)
+        assert torch.equal(u, v), name
+
+
 def test_deterministic(rx):
     frs = synth.make_frames(2, 1)
     x, p = frames_to_device(frs)
