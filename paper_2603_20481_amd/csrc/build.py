@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "librxphy.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "demod.hip", "backward.hip", "batch.hip"]
+SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "detect_group.hip", "demod.hip", "backward.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

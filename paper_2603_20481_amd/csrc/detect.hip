@@ -221,6 +221,7 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
                            float thr, void* ws, hipStream_t s) {
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
   if (prec == RXPHY_FP32) {
+    if (pil && fr.K == 16) return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, s);
     launch_p<P_FP32>(fr, nf, h, yf, pil, xt, nu, flags, thr, nullptr, s);
     return launch_status("detect kernel");
   }

@@ -237,8 +237,11 @@ def test_headline_launch_sampled_frames(rx):
     x = dev(np.stack([r[0] for r in res]))
     p = dev(np.stack([r[1] for r in res]))
     fr = rx.Frame.of(sh, O.ZF, 1.0)
-    out = rx.forward(fr, x, p)
+    out = rx.forward(fr, x, p, fused=True)          # the benchmark's path
+    staged = rx.forward(fr, x, p)
     torch.cuda.synchronize()
+    for k in ("xt", "nu", "flags", "llr"):
+        assert torch.equal(out[k], staged[k]), k
     for f in (0, 41, 99):
         ref = O.forward(res[f][0], res[f][1], sh, 1.0, O.ZF, want_kappa=True)
         good = (ref["kappa"] <= 1e3) & (ref["flags"] == 0)
@@ -256,19 +259,27 @@ FUSED_CASES = [(synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.ZF, "fp32"),
                (synth.Shape(32, 16, 1024, 601, 9, 16, 6), O.MMSE, "fp32"),
                (synth.Shape(16, 5, 1024, 777, 14, 0, 2), O.ZF, "fp16"),
                (synth.Shape(8, 1, 512, 300, 14, 0, 2), O.MMSE, "fp32"),
-               (synth.Shape(64, 12, 4096, 3276, 17, 0, 6), O.ZF, "fp32")]
+               (synth.Shape(64, 12, 4096, 3276, 17, 0, 6), O.ZF, "fp32"),
+               # 16 users: one pilot group per tile (the group kernel): antennas
+               # not a multiple of 4, 16 and 1 data symbols, square M = K, ragged ends
+               (synth.Shape(21, 16, 512, 500, 17, 0, 4), O.MMSE, "fp32"),
+               (synth.Shape(64, 16, 1024, 1000, 2, 0, 2), O.ZF, "fp32"),
+               (synth.Shape(16, 16, 512, 200, 6, 8, 4), O.ZF, "fp32"),
+               (synth.Shape(64, 16, 4096, 3276, 17, 0, 6), O.MMSE, "fp32")]
 
 
 @pytest.mark.parametrize("sh,det,prec", FUSED_CASES)
 def test_fused_csi_detect_equals_two_calls(rx, sh, det, prec):
     """rxphy_csi_detect is bit-identical to rxphy_csi followed by rxphy_detect
     (every K padding, ragged tiles, both detectors, the refined forms, a zero
-    pilot, and a threshold that refines)."""
+    pilot, non-finite data values, and a threshold that refines)."""
     frs = [synth.make_frame(4, f, shape=sh) for f in range(2)]
     x, p = frames_to_device(frs)
     p[1, 7] = 0                                     # zero pilot: non-finite estimates, flagged
     fr = rx.Frame.of(sh, det, 1.0)
     yf = rx.fft(fr, x)
+    yf[0, 0, 1, 17] = float("nan")                  # non-finite data values: flagged subcarriers
+    yf[1, sh.M - 1, sh.n_sym - 1, 40] = float("inf")
     thr = 20.0 if prec != "fp32" else 1e3           # low threshold: some subcarriers refined
     a = rx.detect(fr, rx.csi(fr, yf, p), yf, prec, thr)
     b = rx.csi_detect(fr, yf, p, prec, thr)
