@@ -122,7 +122,7 @@ class Chain:
 
     def step(self, fr, prec="fp32", ev=None, fused=False):
         rx = self.rx
-        need = rx.workspace_bytes(fr, self.F, rx.WS_DETECT, prec)
+        need = rx.workspace_bytes(fr, self.F, rx.WS_CSI_DETECT if fused else rx.WS_DETECT, prec)
         if need and (self.ws is None or self.ws.numel() < need):
             self.ws = self.torch.empty((need,), dtype=self.torch.uint8, device="cuda")
         ws = self.ws if need else None

@@ -126,8 +126,11 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames,
  * Every output (xt, nu, flags, and the refinement of the low-precision
  * forms) is bit-identical to the two-call sequence; the CSI stage's H is
  * simply never stored.  Arguments as rxphy_csi and rxphy_detect; the
- * workspace is rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT,
- * precision) bytes.                                                            */
+ * workspace is rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT,
+ * precision) bytes (with 16 users in FP32, where each 16-subcarrier tile is
+ * one pilot group, it holds each tile's Cholesky factor: 2304 bytes per tile,
+ * 8-byte aligned, written and read back within the call; the caller owns it and may reuse it
+ * once the stream has passed the call).                                       */
 rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
                               const void* yf, const void* pilots, void* xt, float* nu,
                               uint8_t* flags, rxphy_precision precision, float cond_threshold,
@@ -172,10 +175,11 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames,
                             const float* dllr, void* dx, void* dh,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
-enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1 };
+enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1, RXPHY_WS_CSI_DETECT = 2 };
 
-/* Workspace bytes needed by rxphy_detect (which = RXPHY_WS_DETECT) or
- * rxphy_backward (RXPHY_WS_BACKWARD); 0 if none or if the shape is invalid. */
+/* Workspace bytes needed by rxphy_detect (which = RXPHY_WS_DETECT),
+ * rxphy_backward (RXPHY_WS_BACKWARD) or rxphy_csi_detect
+ * (RXPHY_WS_CSI_DETECT); 0 if none or if the shape is invalid.               */
 size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
                              rxphy_precision precision);
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librxphy.so")
 ZF, MMSE = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 FLAG_REFINED, FLAG_BREAKDOWN, FLAG_NONFINITE = 1, 2, 4
-WS_DETECT, WS_BACKWARD = 0, 1
+WS_DETECT, WS_BACKWARD, WS_CSI_DETECT = 0, 1, 2
 
 
 class RxphyError(RuntimeError):
@@ -237,7 +237,7 @@ def csi_detect(fr: Frame, yf, pilots, precision: str = "fp32", cond_threshold: f
     _need(xt, "xt", (F, fr.K, D, fr.n_sc), torch.complex64)
     _need(nu, "nu", (F, fr.K, fr.n_sc), torch.float32)
     _need(flags, "flags", (F, fr.n_sc), torch.uint8)
-    need = workspace_bytes(fr, F, WS_DETECT, precision)
+    need = workspace_bytes(fr, F, WS_CSI_DETECT, precision)
     if need and ws is None:
         ws = _empty((need,), torch.uint8, yf)
     _check(load().rxphy_csi_detect(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots), _ptr(xt), _ptr(nu),

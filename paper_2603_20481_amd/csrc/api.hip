@@ -157,9 +157,9 @@ rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames, const 
     return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
   if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
     return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
-  size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT, precision);
+  size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT, precision);
   if (need && (!ws || ws_bytes < need))
-    return fail(RXPHY_EWORKSPACE, "detect needs %zu workspace bytes, got %zu", need, ws_bytes);
+    return fail(RXPHY_EWORKSPACE, "csi_detect needs %zu workspace bytes, got %zu", need, ws_bytes);
   if (n_frames == 0) return RXPHY_OK;
   if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(xt, "xt")) ||
       (st = check_ptr(nu, "nu")))

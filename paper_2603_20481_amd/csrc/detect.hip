@@ -211,6 +211,11 @@ void launch_p(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* 
 
 }  // namespace
 
+size_t csi_detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
+  if (prec == RXPHY_FP32 && fr.K == 16) return group_workspace_bytes(fr, nf);
+  return detect_workspace_bytes(fr, nf, prec);
+}
+
 size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
   if (prec == RXPHY_FP32) return 0;
   return (size_t)RL_OFF * 4 + (size_t)nf * fr.n_sc * 4;
@@ -221,7 +226,7 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
                            float thr, void* ws, hipStream_t s) {
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
   if (prec == RXPHY_FP32) {
-    if (pil && fr.K == 16) return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, s);
+    if (pil && fr.K == 16) return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, ws, s);
     launch_p<P_FP32>(fr, nf, h, yf, pil, xt, nu, flags, thr, nullptr, s);
     return launch_status("detect kernel");
   }

@@ -6,20 +6,24 @@
 // same channel matrix H (64 x 16).  Per tile the work is
 //   G = H^H H (+ N0 I) once, its Cholesky factor once, and
 //   Z = H^H Y for 16 subcarriers x D data symbols, then L L^H X = Z.
-// This kernel is built around that shape instead of staging H per subcarrier:
+// Two kernels, so that the short serial factorisation never holds up the
+// streaming part:
 //
-//  * The data operands are loaded straight from HBM into the lanes that use
-//    them (lane (kq, u) of v_mfma_f32_16x16x4_f32: B = Y[4s + kq][1 + d][i0 + u],
-//    16 lanes per 128-byte row segment), all of a wave's loads issued at
-//    once, no LDS staging.  Wave w owns data symbols d = w, w + 4, w + 8,
-//    w + 12 and runs all 64 antennas for them (16 steps of 4 antennas).
-//  * H is formed once per tile (each wave 16 antennas: the pilot-symbol row
-//    and the pilots, LS) into LDS, read by every wave as the A operand.
-//  * The partial Gram matrices meet in LDS; one wave (rotating over the
-//    waves with the fewest symbols) factors A; each wave transposes its own
-//    Z through a wave-private LDS slab and solves its own right-hand sides
-//    (lane = (symbol, subcarrier)).  Two workgroups share a CU, so one's
-//    loads and products overlap the other's factorisation and solves.
+//  group_factor_kernel  four tiles per wavefront: loads each tile's
+//    pilot-symbol row and pilots, forms H (LS), the Gram matrix on MFMA, and
+//    factors A = G (+ N0 I) (Cholesky-Crout with L^-1, one tile per 16-lane
+//    row); writes L, 1 / L_kk, d_k = [A^-1]_kk and flags into a 2.25 KiB
+//    record per tile.  Many independent wavefronts per SIMD hide each one's
+//    serial latency.
+//  detect_group_kernel  one workgroup per tile: the data operands are loaded
+//    straight from HBM into the lanes that use them (lane (kq, u) of
+//    v_mfma_f32_16x16x4_f32: B = Y[4s + kq][1 + d][i0 + u], 16 lanes per
+//    128-byte row segment), all of a wave's loads issued at once, no LDS
+//    staging.  Wave w owns data symbols d = w, w + 4, w + 8, w + 12 and runs
+//    all 64 antennas for them (16 steps of 4 antennas); H is formed again
+//    (LS) into LDS as the A operand.  Each wave transposes its own Z through
+//    a wave-private LDS slab and solves its own right-hand sides (lane =
+//    (symbol, subcarrier)) with the record's factor.
 //
 // Every product, sum and factorisation step is the one the general detector
 // (detect_core.h, shared-factor path) performs on the same values in the
@@ -27,6 +31,17 @@
 #include "detect_core.h"
 
 namespace rxphy {
+
+// Per-tile factor record (workspace of the fused path).
+struct alignas(256) GroupRec {
+  float2 L[16 * 16];     // rows of L (strictly lower part used)
+  float inv[16];         // 1 / L_kk
+  float dl[16];          // d_k = [A^-1]_kk
+  int ok;                // factorisation succeeded
+  int hbad;              // a non-finite channel value
+};
+constexpr int REC_TAIL_WORDS = 34;   // inv, dl, ok, hbad
+
 namespace {
 
 using namespace det;
@@ -34,18 +49,6 @@ using namespace det;
 constexpr int GWAVES = 4;     // waves per workgroup
 constexpr int NJ = 4;         // symbol slots per wave: d = w + 4 j
 constexpr int ZP = 17;        // float2 pitch of a slab row (bank spread)
-
-struct GroupLds {
-  float2 h[64 * 16];                    // H of the tile: [antenna][user]
-  float2 part[GWAVES][16 * PP];         // per-wave partial Gram matrices
-  float2 L[16 * PP];                    // Cholesky factor, row by row
-  float inv[16];                        // 1 / L_kk
-  float dl[16];                         // d_k = [A^-1]_kk
-  int ok;
-  int hbad[GWAVES];                     // a non-finite H value (per storing wave)
-  uint32_t nfmask[GWAVES];              // subcarriers with a non-finite data value
-  float2 slab[GWAVES][NJ * 16 * ZP];    // per wave: Z as [slot j][user k][subcarrier]
-};
 
 __device__ __forceinline__ float2 ldg2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
@@ -62,14 +65,199 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// ------------------------------------------------------------- factorisation
+// H[4 s + kq][u] (s = 0..15) of tile tix for this lane (the MFMA A / B operand
+// layout): the pilot-symbol values and the user's pilot; a tile past the end
+// reads zero without touching memory.
+__device__ __forceinline__ void factor_loads(const float2* Yf, const float2* pil, int tix, int T, int nt, int M,
+                                             int S, int n_sc, int kq, int u, float2* hv, float2& pv) {
+  const bool in = tix < T;
+  const int f = in ? tix / nt : 0;
+  const int tt = tix - f * nt;
+  const int q = min(tt, n_sc / 16 - 1) * 16 + u;
+  const __amdgpu_buffer_rsrc_t yr = rsrc(Yf + (int64_t)f * M * S * n_sc, (uint32_t)M * S * n_sc * 8u);
+  const uint32_t ant = (uint32_t)S * n_sc * 32u;
+  uint32_t row = opaque(in ? (uint32_t)(kq * S * n_sc + q) * 8u : OOB);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    hv[s] = ldg2(yr, row);
+    row = opaque(row + ant);
+  }
+  pv = ldg2(rsrc(pil + (int64_t)f * n_sc, (uint32_t)n_sc * 8u), in ? (uint32_t)q * 8u : OOB);
+}
+
+// LS estimate, non-finite check and A = sum of the four partial Gram matrices
+// (8-antenna chunks c and c + 4, in order, summed in order) into t as rows
+// of pitch PP; returns whether a channel value is non-finite.
+__device__ __forceinline__ bool factor_gram(float2* hv, float2 pv, int M, int kq, int u, float2* t) {
+  float probe = 0.f;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    hv[s] = 4 * s + kq < M ? ls_estimate(hv[s], pv) : make_float2(0.f, 0.f);
+    probe = __builtin_fmaf(hv[s].x, 0.f, probe);
+    probe = __builtin_fmaf(hv[s].y, 0.f, probe);
+  }
+  f32x4 pr[4], pi[4];
+#pragma unroll
+  for (int wp = 0; wp < 4; ++wp) {
+    pr[wp] = pi[wp] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int c = wp + 4 * b;
+      if (c * MC < M) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const float2 h = hv[2 * c + a];
+          pr[wp] = mfma(h.x, h.x, pr[wp]);
+          pr[wp] = mfma(h.y, h.y, pr[wp]);
+          pi[wp] = mfma(h.x, h.y, pi[wp]);
+          pi[wp] = mfma(-h.y, h.x, pi[wp]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float2 g = make_float2(pr[0][r], pi[0][r]);
+    g = cadd(g, make_float2(pr[1][r], pi[1][r]));
+    g = cadd(g, make_float2(pr[2][r], pi[2][r]));
+    g = cadd(g, make_float2(pr[3][r], pi[3][r]));
+    t[(4 * kq + r) * PP + u] = g;
+  }
+  return __ballot(!(probe == 0.f)) != 0ull;
+}
+
+// Each wavefront factors four tiles: their Gram matrices one after the other
+// on MFMA (the next tile's loads in flight meanwhile), then one Crout pass in
+// which 16-lane row k works on tile k (the factorisation's broadcasts stay
+// within a row), so no lane repeats another's work.
+__global__ void __launch_bounds__(256)
+group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil, GroupRec* __restrict__ rec,
+                    int T, int nt, int M, int S, int n_sc, float n0, int mmse) {
+  __shared__ float2 tp[GWAVES][4][16 * PP];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int u = l & 15, kq = l >> 4;
+  const int base = (blockIdx.x * GWAVES + w) * 4;             // tiles base .. base + 3
+  if (base >= T) return;                                       // a whole wave; no barrier below
+
+  float2 ha[16], hb[16], pa, pb;
+  bool bad[4];
+  factor_loads(Yf, pil, base + 0, T, nt, M, S, n_sc, kq, u, ha, pa);
+  factor_loads(Yf, pil, base + 1, T, nt, M, S, n_sc, kq, u, hb, pb);
+  bad[0] = factor_gram(ha, pa, M, kq, u, tp[w][0]);
+  factor_loads(Yf, pil, base + 2, T, nt, M, S, n_sc, kq, u, ha, pa);
+  bad[1] = factor_gram(hb, pb, M, kq, u, tp[w][1]);
+  factor_loads(Yf, pil, base + 3, T, nt, M, S, n_sc, kq, u, hb, pb);
+  bad[2] = factor_gram(ha, pa, M, kq, u, tp[w][2]);
+  bad[3] = factor_gram(hb, pb, M, kq, u, tp[w][3]);
+
+  // row kq of the wave factors tile base + kq; lane `row` holds A[row][:]
+  const int row = u;
+  const float2* t = tp[w][kq];
+  float2 a[16], v[16];
+  float inv[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    float2 g = t[row * PP + c];
+    if (c == row) g.x = g.x + (mmse ? n0 : 0.f);
+    a[c] = g;
+  }
+  bool okw = true;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);
+  crout_all<16>(Seq16{}, a, v, inv, row, okw);
+  float d = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) d += v[k].x * v[k].x + v[k].y * v[k].y;
+  const int tix = base + kq;
+  if (tix < T) {
+    GroupRec& R = rec[tix];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) R.L[row * 16 + c] = a[c];
+    R.inv[row] = inv[row];
+    R.dl[row] = d;
+    if (row == 0) {
+      R.ok = okw ? 1 : 0;
+      R.hbad = (kq == 0 ? bad[0] : kq == 1 ? bad[1] : kq == 2 ? bad[2] : bad[3]) ? 1 : 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ detector
+struct GroupLds {
+  float2 h[64 * 16];                    // H of the tile: [antenna][user]
+  float2 L[16 * PP];                    // Cholesky factor, row by row
+  float tail[REC_TAIL_WORDS];           // inv[16], dl[16], ok, hbad as in GroupRec
+  uint32_t nfmask[GWAVES];              // subcarriers with a non-finite data value
+  float2 slab[GWAVES][NJ * 16 * ZP];    // per wave: Z as [slot j][user k][subcarrier]
+};
+
+// Forward and back substitution with the factor in LDS for the right-hand
+// side held by this lane: the arithmetic of fwd_all / bwd_all step for step,
+// with the L entries of the next step read while the current one computes
+// (each step is still pinned in place, as there).
+template <int I>
+__device__ __forceinline__ void fwd_row(const float2* Lm, float2* Lr) {
+#pragma unroll
+  for (int k = 0; k < I; ++k) Lr[k] = Lm[I * PP + k];          // L[I][k], k < I
+}
+template <int I>
+__device__ __forceinline__ void bwd_col(const float2* Lm, float2* Lc) {
+#pragma unroll
+  for (int k = I + 1; k < 16; ++k) Lc[k] = Lm[k * PP + I];     // L[k][I], k > I
+}
+
+template <int I>
+__device__ __forceinline__ void fwd_step2(const float2* Lm, const float* inv, float2* w, float2* Lcur,
+                                          float2* Lnext) {
+  if constexpr (I + 1 < 16) fwd_row<I + 1>(Lm, Lnext);
+  float2 sw = w[I];
+#pragma unroll
+  for (int k = 0; k < I; ++k) sw = cms(sw, Lcur[k], w[k]);
+  w[I] = cscale(sw, inv[I]);
+  asm volatile("" : "+v"(w[I].x), "+v"(w[I].y));
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int I>
+__device__ __forceinline__ void bwd_step2(const float2* Lm, const float* inv, float2* w, float2* Lcur,
+                                          float2* Lnext) {
+  if constexpr (I > 0) bwd_col<I - 1>(Lm, Lnext);
+  float2 sx = w[I];
+#pragma unroll
+  for (int k = I + 1; k < 16; ++k) sx = cms_ac(sx, Lcur[k], w[k]);
+  w[I] = cscale(sx, inv[I]);
+  asm volatile("" : "+v"(w[I].x), "+v"(w[I].y));
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int... Is>
+__device__ __forceinline__ void fwd_pipe(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
+  float2 A[16], B[16];
+  fwd_row<0>(Lm, A);
+  ((Is & 1 ? fwd_step2<Is>(Lm, inv, w, B, A) : fwd_step2<Is>(Lm, inv, w, A, B)), ...);
+}
+template <int... Is>
+__device__ __forceinline__ void bwd_pipe(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
+  float2 A[16], B[16];
+  bwd_col<15>(Lm, A);
+  (((15 - Is) & 1 ? bwd_step2<15 - Is>(Lm, inv, w, A, B) : bwd_step2<15 - Is>(Lm, inv, w, B, A)), ...);
+}
+
+__device__ __forceinline__ void solve16(const float2* Lm, const float* inv, float2* w) {
+  fwd_pipe(Seq16{}, Lm, inv, w);                // L W = Z
+  bwd_pipe(Seq16{}, Lm, inv, w);                // L^H X = W
+}
+
 // Z = H^H Y over the 16 antenna steps, in order, for symbol slot J, three
 // real products per complex one: for h = a + jb, y = c + jd,
-// conj(h) y = (k1 + b (c + d)) + j (k1 + a (d - c)), k1 = (a - b) c.
+// conj(h) y = (k1 + b (c + d)) + j (k1 + a (d - c)), k1 = (a - b) c; the
+// result goes to the wave's slab at once (rows 4 kq + r, column u).
 template <int J, bool FULLM>
-__device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[NJ], f32x4& zr, f32x4& zi,
-                                       float& probe, int kq, int u, int M) {
-  f32x4 zk = {0.f, 0.f, 0.f, 0.f};
-  zr = zi = zk;
+__device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[NJ], float2* slab, float& probe,
+                                       int kq, int u, int M) {
+  f32x4 zk = {0.f, 0.f, 0.f, 0.f}, zr = zk, zi = zk;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {                // antennas 4 s .. 4 s + 3
     if (FULLM || (s >> 1) * MC < M) {           // else an absent 8-antenna chunk
@@ -84,22 +272,24 @@ __device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[NJ], 
   }
   zr += zk;
   zi += zk;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) slab[(J * 16 + 4 * kq + r) * ZP + u] = make_float2(zr[r], zi[r]);
 }
 
 template <bool FULLM>
-__device__ __forceinline__ void z_all(const float2* hs, const float2 (*y)[NJ], f32x4* zr, f32x4* zi,
-                                      float& probe, int nj, int kq, int u, int M) {
-  if (nj > 0) z_slot<0, FULLM>(hs, y, zr[0], zi[0], probe, kq, u, M);
-  if (nj > 1) z_slot<1, FULLM>(hs, y, zr[1], zi[1], probe, kq, u, M);
-  if (nj > 2) z_slot<2, FULLM>(hs, y, zr[2], zi[2], probe, kq, u, M);
-  if (nj > 3) z_slot<3, FULLM>(hs, y, zr[3], zi[3], probe, kq, u, M);
+__device__ __forceinline__ void z_all(const float2* hs, const float2 (*y)[NJ], float2* slab, float& probe,
+                                      int nj, int kq, int u, int M) {
+  if (nj > 0) z_slot<0, FULLM>(hs, y, slab, probe, kq, u, M);
+  if (nj > 1) z_slot<1, FULLM>(hs, y, slab, probe, kq, u, M);
+  if (nj > 2) z_slot<2, FULLM>(hs, y, slab, probe, kq, u, M);
+  if (nj > 3) z_slot<3, FULLM>(hs, y, slab, probe, kq, u, M);
 }
 
 // One workgroup per (tile, frame): blockIdx.x = tile, blockIdx.y = frame.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil, float2* __restrict__ xt,
-                    float* __restrict__ nu, uint8_t* __restrict__ flags, int M, int S, int n_sc, float n0,
-                    int mmse) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil,
+                    const GroupRec* __restrict__ rec, float2* __restrict__ xt, float* __restrict__ nu,
+                    uint8_t* __restrict__ flags, int M, int S, int n_sc, float n0, int mmse) {
   __shared__ GroupLds sh;
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar branches
@@ -112,12 +302,19 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   // symbols of this wave: d = w + 4 j for j < nj
   const int nj = D > w ? (D - w + 3) >> 2 : 0;
 
+  // ---- loads, oldest first: the tile's factor record (one L entry per
+  // thread, the tail words on the first 34 lanes of each wave), this wave's
+  // 16 antennas of the pilot-symbol row and the pilots, then all of its data
+  // (a fixed count of loads per wave, so that each use waits for exactly its
+  // own; slots the wave does not own read zero without touching memory)
+  const GroupRec* R = rec + (f * gridDim.x + tt);
+  const __amdgpu_buffer_rsrc_t rr = rsrc(R, (uint32_t)(sizeof(float2) * 256 + 4 * REC_TAIL_WORDS));
+  const float2 lv = ldg2(rr, opaque((uint32_t)tid * 8u));
+  const float tv = __builtin_bit_cast(
+      float, __builtin_amdgcn_raw_buffer_load_b32(rr, (int)opaque(sizeof(float2) * 256 + 4u * l), 0, 0));
   const __amdgpu_buffer_rsrc_t yr = rsrc(Yf + f * M * S * n_sc, (uint32_t)M * S * n_sc * 8u);
   const uint32_t ant = (uint32_t)S * n_sc * 32u;             // 4 antennas
   const uint32_t sym = (uint32_t)n_sc * 32u;                 // 4 symbols
-
-  // ---- loads: this wave's 16 antennas of the pilot-symbol row and the
-  // pilots, then all of its data, symbol slot by symbol slot
   float2 hv[4], pv;
   {
     const int q = g * 16 + u;
@@ -132,8 +329,6 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   float2 y[16][NJ];
   {
     const uint32_t lane = i0 + u < n_sc ? (uint32_t)((kq * S + 1 + w) * n_sc + i0 + u) * 8u : OOB;
-    // (a fixed count of loads, so that each use waits for exactly its own:
-    // the slots this wave does not own read zero without touching memory)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       uint32_t row = opaque(j < nj ? lane + (uint32_t)j * sym : OOB);
@@ -145,103 +340,39 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     }
   }
 
-  // ---- H = LS estimate (absent antennas zero), non-finite check
-  {
-    float probe = 0.f;
+  // ---- the factor into LDS; H = LS estimate (absent antennas zero)
+  sh.L[(tid >> 4) * PP + (tid & 15)] = lv;
+  if (w == 0 && l < REC_TAIL_WORDS) sh.tail[l] = tv;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int m = 16 * w + 4 * a + kq;
-      const float2 h = m < M ? ls_estimate(hv[a], pv) : make_float2(0.f, 0.f);
-      probe = __builtin_fmaf(h.x, 0.f, probe);
-      probe = __builtin_fmaf(h.y, 0.f, probe);
-      sh.h[m * 16 + u] = h;
-    }
-    const bool bad = __ballot(!(probe == 0.f)) != 0ull;
-    if (l == 0) sh.hbad[w] = bad ? 1 : 0;
+  for (int a = 0; a < 4; ++a) {
+    const int m = 16 * w + 4 * a + kq;
+    sh.h[m * 16 + u] = m < M ? ls_estimate(hv[a], pv) : make_float2(0.f, 0.f);
   }
   __syncthreads();
 
-  // ---- phase 1: Z for this wave's symbols, the partial Gram matrix over
-  // the 8-antenna chunks w and w + 4
+  // ---- Z for this wave's symbols, into its slab
   {
-    f32x4 zr[NJ], zi[NJ];
     float probe = 0.f;
-    if (M == 64) z_all<true>(sh.h, y, zr, zi, probe, nj, kq, u, M);
-    else z_all<false>(sh.h, y, zr, zi, probe, nj, kq, u, M);
-    float2* slab = sh.slab[w];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      if (j < nj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) slab[(j * 16 + 4 * kq + r) * ZP + u] = make_float2(zr[j][r], zi[j][r]);
+    if (M == 64) z_all<true>(sh.h, y, sh.slab[w], probe, nj, kq, u, M);
+    else z_all<false>(sh.h, y, sh.slab[w], probe, nj, kq, u, M);
     const uint64_t bad = __ballot(!(probe == 0.f));
     const uint32_t m16 = (uint32_t)(bad | (bad >> 16) | (bad >> 32) | (bad >> 48)) & 0xffffu;
     if (l == 0) sh.nfmask[w] = m16;
   }
-  {
-    f32x4 g0r = {0.f, 0.f, 0.f, 0.f}, g0i = g0r;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int c = w + 4 * b;                  // chunk c: antennas 8 c .. 8 c + 7
-      if (c * MC < M) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const float2 h = sh.h[(8 * c + 4 * a + kq) * 16 + u];
-          g0r = mfma(h.x, h.x, g0r);
-          g0r = mfma(h.y, h.y, g0r);
-          g0i = mfma(h.x, h.y, g0i);
-          g0i = mfma(-h.y, h.x, g0i);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sh.part[w][(4 * kq + r) * PP + u] = make_float2(g0r[r], g0i[r]);
-  }
-  __syncthreads();
-
-  // ---- factorisation: one of the waves with the fewest symbols
-  const int e0 = D & 3;
-  const int wf = e0 ? e0 + (int)(tt % (4 - e0)) : (tt & 3);
-  if (w == wf) {
-    const int row = u;
-    float2 a[16], v[16];
-    float inv[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      float2 s = sh.part[0][row * PP + c];
-      s = cadd(s, sh.part[1][row * PP + c]);
-      s = cadd(s, sh.part[2][row * PP + c]);
-      s = cadd(s, sh.part[3][row * PP + c]);
-      if (c == row) s.x = s.x + (mmse ? n0 : 0.f);
-      a[c] = s;
-    }
-    bool okw = true;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);
-    crout_all<16>(Seq16{}, a, v, inv, row, okw);
-    float d = 0.f;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) d += v[k].x * v[k].x + v[k].y * v[k].y;
-    if (kq == 0) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) sh.L[row * PP + c] = a[c];
-      sh.dl[row] = d;
-      sh.inv[row] = inv[row];
-      if (row == 0) sh.ok = okw ? 1 : 0;
-    }
-  }
   __syncthreads();
 
   // ---- solves: lane (kq, u) = symbol slot kq, subcarrier u of this wave
+  const float* inv_s = sh.tail;
+  const float* dl_s = sh.tail + 16;
   const int d = w + 4 * kq;
   const int i = i0 + u;
   const uint32_t nfm = sh.nfmask[0] | sh.nfmask[1] | sh.nfmask[2] | sh.nfmask[3];
-  const bool hb = (sh.hbad[0] | sh.hbad[1] | sh.hbad[2] | sh.hbad[3]) != 0;
+  const bool hb = __builtin_bit_cast(int, sh.tail[33]) != 0;
   const bool nf_i = hb || ((nfm >> u) & 1u);
-  bool ok = sh.ok != 0;
+  bool ok = __builtin_bit_cast(int, sh.tail[32]) != 0;
   if (mmse) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) ok = ok && (1.0f - n0 * sh.dl[k] > 0.f);
+    for (int k = 0; k < 16; ++k) ok = ok && (1.0f - n0 * dl_s[k] > 0.f);
   }
   const bool erase = nf_i || !ok;
   if (d < D) {
@@ -251,12 +382,11 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
 #pragma unroll
     for (int k = 0; k < 16; ++k) z[k] = slab[(kq * 16 + k) * ZP + u];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) inv[k] = sh.inv[k];
-    fwd_all<16>(Seq16{}, sh.L, inv, z);          // L W = Z
-    bwd_all<16>(Seq16{}, sh.L, inv, z);          // L^H X = W
+    for (int k = 0; k < 16; ++k) inv[k] = inv_s[k];
+    solve16(sh.L, inv, z);                      // L L^H X = Z
     if (mmse) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) z[k] = cscale(z[k], __builtin_amdgcn_rcpf(1.0f - n0 * sh.dl[k]));
+      for (int k = 0; k < 16; ++k) z[k] = cscale(z[k], __builtin_amdgcn_rcpf(1.0f - n0 * dl_s[k]));
     }
     if (i < n_sc) {
       float2* xo = xt + f * 16 * D * n_sc;
@@ -266,7 +396,7 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   }
   if (i < n_sc) {
     const int k = 4 * w + kq;
-    const float dk = sh.dl[k];
+    const float dk = dl_s[k];
     const float nv = mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
     nu[(f * 16 + k) * n_sc + i] = erase ? INFINITY : nv;
     if (w == 0 && kq == 0 && flags)
@@ -276,12 +406,24 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
 
 }  // namespace
 
+size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf) {
+  return (size_t)nf * ((fr.n_sc + 15) / 16) * sizeof(GroupRec);
+}
+
 rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                 float2* xt, float* nu, uint8_t* flags, hipStream_t s) {
+                                 float2* xt, float* nu, uint8_t* flags, void* ws, hipStream_t s) {
   if (nf == 0) return RXPHY_OK;
-  const dim3 grid((fr.n_sc + 15) / 16, nf);
-  hipLaunchKernelGGL(detect_group_kernel, grid, dim3(256), 0, s, yf, pil, xt, nu, flags, fr.M, fr.n_sym,
-                     fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  if (!ws || ((uintptr_t)ws & 7u)) return fail(RXPHY_EWORKSPACE, "csi_detect workspace must be 8-byte aligned");
+  const int nt = (fr.n_sc + 15) / 16;
+  const int64_t T = (int64_t)nf * nt;
+  GroupRec* rec = (GroupRec*)ws;
+  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
+  hipLaunchKernelGGL(group_factor_kernel, dim3((unsigned)((T + 4 * GWAVES - 1) / (4 * GWAVES))), dim3(256), 0, s, yf, pil,
+                     rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse);
+  rxphy_status st = launch_status("group factor kernel");
+  if (st) return st;
+  hipLaunchKernelGGL(detect_group_kernel, dim3(nt, nf), dim3(256), 0, s, yf, pil, rec, xt, nu, flags, fr.M,
+                     fr.n_sym, fr.n_sc, fr.n0, mmse);
   return launch_status("detect group kernel");
 }
 
