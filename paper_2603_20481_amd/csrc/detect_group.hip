@@ -34,13 +34,11 @@ namespace rxphy {
 
 // Per-tile factor record (workspace of the fused path).
 struct alignas(256) GroupRec {
-  float2 L[16 * 16];     // rows of L (strictly lower part used)
-  float inv[16];         // 1 / L_kk
-  float dl[16];          // d_k = [A^-1]_kk
+  float2 B[16 * 16];     // A^-1 = V^H V (V = L^-1), row-major
+  float dl[16];          // d_k = [A^-1]_kk as the factorisation forms it
   int ok;                // factorisation succeeded
   int hbad;              // a non-finite channel value
 };
-constexpr int REC_TAIL_WORDS = 34;   // inv, dl, ok, hbad
 
 namespace {
 
@@ -48,7 +46,7 @@ using namespace det;
 
 constexpr int GWAVES = 4;     // waves per workgroup
 constexpr int NJ = 4;         // symbol slots per wave: d = w + 4 j
-constexpr int ZP = 17;        // float2 pitch of a slab row (bank spread)
+typedef float float4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float2 ldg2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
@@ -170,93 +168,51 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   float d = 0.f;
 #pragma unroll
   for (int k = 0; k < 16; ++k) d += v[k].x * v[k].x + v[k].y * v[k].y;
+  // V = L^-1 (lane `row` holds its column `row`) over A in LDS, then
+  // B = V^H V per tile: the Gram product again, V[4 s + kq][u] as both operands
+  float2* vt = tp[w][kq];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) vt[k * PP + row] = v[k];
   const int tix = base + kq;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    f32x4 br = {0.f, 0.f, 0.f, 0.f}, bi = br;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float2 x = tp[w][g][(4 * s + kq) * PP + u];
+      br = mfma(x.x, x.x, br);
+      br = mfma(x.y, x.y, br);
+      bi = mfma(x.x, x.y, bi);
+      bi = mfma(-x.y, x.x, bi);
+    }
+    const int tg = base + g;
+    if (tg < T) {
+      GroupRec& R = rec[tg];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) R.B[(4 * kq + r) * 16 + u] = make_float2(br[r], bi[r]);
+    }
+  }
   if (tix < T) {
     GroupRec& R = rec[tix];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) R.L[row * 16 + c] = a[c];
-    R.inv[row] = inv[row];
     R.dl[row] = d;
     if (row == 0) {
-      R.ok = okw ? 1 : 0;
+      R.ok = okw ? 1 : 0;                        // the same in every lane of the row
       R.hbad = (kq == 0 ? bad[0] : kq == 1 ? bad[1] : kq == 2 ? bad[2] : bad[3]) ? 1 : 0;
     }
   }
 }
 
 // ------------------------------------------------------------------ detector
-struct GroupLds {
-  float2 h[64 * 16];                    // H of the tile: [antenna][user]
-  float2 L[16 * PP];                    // Cholesky factor, row by row
-  float tail[REC_TAIL_WORDS];           // inv[16], dl[16], ok, hbad as in GroupRec
-  uint32_t nfmask[GWAVES];              // subcarriers with a non-finite data value
-  float2 slab[GWAVES][NJ * 16 * ZP];    // per wave: Z as [slot j][user k][subcarrier]
-};
-
-// Forward and back substitution with the factor in LDS for the right-hand
-// side held by this lane: the arithmetic of fwd_all / bwd_all step for step,
-// with the L entries of the next step read while the current one computes
-// (each step is still pinned in place, as there).
-template <int I>
-__device__ __forceinline__ void fwd_row(const float2* Lm, float2* Lr) {
-#pragma unroll
-  for (int k = 0; k < I; ++k) Lr[k] = Lm[I * PP + k];          // L[I][k], k < I
-}
-template <int I>
-__device__ __forceinline__ void bwd_col(const float2* Lm, float2* Lc) {
-#pragma unroll
-  for (int k = I + 1; k < 16; ++k) Lc[k] = Lm[k * PP + I];     // L[k][I], k > I
-}
-
-template <int I>
-__device__ __forceinline__ void fwd_step2(const float2* Lm, const float* inv, float2* w, float2* Lcur,
-                                          float2* Lnext) {
-  if constexpr (I + 1 < 16) fwd_row<I + 1>(Lm, Lnext);
-  float2 sw = w[I];
-#pragma unroll
-  for (int k = 0; k < I; ++k) sw = cms(sw, Lcur[k], w[k]);
-  w[I] = cscale(sw, inv[I]);
-  asm volatile("" : "+v"(w[I].x), "+v"(w[I].y));
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int I>
-__device__ __forceinline__ void bwd_step2(const float2* Lm, const float* inv, float2* w, float2* Lcur,
-                                          float2* Lnext) {
-  if constexpr (I > 0) bwd_col<I - 1>(Lm, Lnext);
-  float2 sx = w[I];
-#pragma unroll
-  for (int k = I + 1; k < 16; ++k) sx = cms_ac(sx, Lcur[k], w[k]);
-  w[I] = cscale(sx, inv[I]);
-  asm volatile("" : "+v"(w[I].x), "+v"(w[I].y));
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int... Is>
-__device__ __forceinline__ void fwd_pipe(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
-  float2 A[16], B[16];
-  fwd_row<0>(Lm, A);
-  ((Is & 1 ? fwd_step2<Is>(Lm, inv, w, B, A) : fwd_step2<Is>(Lm, inv, w, A, B)), ...);
-}
-template <int... Is>
-__device__ __forceinline__ void bwd_pipe(Seq<Is...>, const float2* Lm, const float* inv, float2* w) {
-  float2 A[16], B[16];
-  bwd_col<15>(Lm, A);
-  (((15 - Is) & 1 ? bwd_step2<15 - Is>(Lm, inv, w, A, B) : bwd_step2<15 - Is>(Lm, inv, w, B, A)), ...);
-}
-
-__device__ __forceinline__ void solve16(const float2* Lm, const float* inv, float2* w) {
-  fwd_pipe(Seq16{}, Lm, inv, w);                // L W = Z
-  bwd_pipe(Seq16{}, Lm, inv, w);                // L^H X = W
-}
-
 // Z = H^H Y over the 16 antenna steps, in order, for symbol slot J, three
 // real products per complex one: for h = a + jb, y = c + jd,
-// conj(h) y = (k1 + b (c + d)) + j (k1 + a (d - c)), k1 = (a - b) c; the
-// result goes to the wave's slab at once (rows 4 kq + r, column u).
+// conj(h) y = (k1 + b (c + d)) + j (k1 + a (d - c)), k1 = (a - b) c; then
+// X = A^-1 Z from the same lanes: step r of the product takes the users
+// 4 kq + r, which this lane already holds (Z rows 4 kq + r, column u), against
+// B[u][4 kq + r]; (a + jb)(c + jd) = (k1 - b (c + d)) + j (k1 + a (d - c)),
+// k1 = (a + b) c.  x gets X rows 4 kq + r, column u.
 template <int J, bool FULLM>
-__device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[NJ], float2* slab, float& probe,
-                                       int kq, int u, int M) {
+__device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[2], const float2* brow, float& probe,
+                                       int kq, int u, int M, f32x4& xr, f32x4& xi) {
   f32x4 zk = {0.f, 0.f, 0.f, 0.f}, zr = zk, zi = zk;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {                // antennas 4 s .. 4 s + 3
@@ -272,17 +228,31 @@ __device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[NJ], 
   }
   zr += zk;
   zi += zk;
+  f32x4 xk = {0.f, 0.f, 0.f, 0.f};
+  xr = xi = xk;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) slab[(J * 16 + 4 * kq + r) * ZP + u] = make_float2(zr[r], zi[r]);
+  for (int r = 0; r < 4; ++r) {
+    const float2 b = brow[r];
+    xk = mfma(b.x + b.y, zr[r], xk);
+    xr = mfma(b.y, zr[r] + zi[r], xr);
+    xi = mfma(b.x, zi[r] - zr[r], xi);
+  }
+  xr = xk - xr;
+  xi = xk + xi;
 }
 
-template <bool FULLM>
-__device__ __forceinline__ void z_all(const float2* hs, const float2 (*y)[NJ], float2* slab, float& probe,
-                                      int nj, int kq, int u, int M) {
-  if (nj > 0) z_slot<0, FULLM>(hs, y, slab, probe, kq, u, M);
-  if (nj > 1) z_slot<1, FULLM>(hs, y, slab, probe, kq, u, M);
-  if (nj > 2) z_slot<2, FULLM>(hs, y, slab, probe, kq, u, M);
-  if (nj > 3) z_slot<3, FULLM>(hs, y, slab, probe, kq, u, M);
+// Symbol slot j (d = w + 4 j) of this lane's data into register slot R:
+// y[s][R] = Y[4 s + kq][1 + d][i0 + u]; a slot the wave does not own reads
+// zero without touching memory, so every wave issues the same loads.
+template <int R>
+__device__ __forceinline__ void load_slot(float2 (*y)[2], __amdgpu_buffer_rsrc_t yr, uint32_t lane, int j, int nj,
+                                          uint32_t ant, uint32_t sym) {
+  uint32_t row = opaque(j < nj ? lane + (uint32_t)j * sym : OOB);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    y[s][R] = ldg2(yr, row);
+    row = opaque(row + ant);
+  }
 }
 
 // One workgroup per (tile, frame): blockIdx.x = tile, blockIdx.y = frame.
@@ -290,7 +260,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil,
                     const GroupRec* __restrict__ rec, float2* __restrict__ xt, float* __restrict__ nu,
                     uint8_t* __restrict__ flags, int M, int S, int n_sc, float n0, int mmse) {
-  __shared__ GroupLds sh;
+  __shared__ float2 hs[64 * 16];                // H of the tile: [antenna][user]
+  __shared__ uint32_t nfmask[GWAVES];           // subcarriers with a non-finite data value
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar branches
   const int u = l & 15, kq = l >> 4;
@@ -302,16 +273,26 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   // symbols of this wave: d = w + 4 j for j < nj
   const int nj = D > w ? (D - w + 3) >> 2 : 0;
 
-  // ---- loads, oldest first: the tile's factor record (one L entry per
-  // thread, the tail words on the first 34 lanes of each wave), this wave's
+  // ---- loads, oldest first: this lane's part of the tile's record (row u of
+  // A^-1, columns 4 kq .. 4 kq + 3; d_k of its users; the flags), this wave's
   // 16 antennas of the pilot-symbol row and the pilots, then all of its data
   // (a fixed count of loads per wave, so that each use waits for exactly its
   // own; slots the wave does not own read zero without touching memory)
   const GroupRec* R = rec + (f * gridDim.x + tt);
-  const __amdgpu_buffer_rsrc_t rr = rsrc(R, (uint32_t)(sizeof(float2) * 256 + 4 * REC_TAIL_WORDS));
-  const float2 lv = ldg2(rr, opaque((uint32_t)tid * 8u));
-  const float tv = __builtin_bit_cast(
-      float, __builtin_amdgcn_raw_buffer_load_b32(rr, (int)opaque(sizeof(float2) * 256 + 4u * l), 0, 0));
+  const __amdgpu_buffer_rsrc_t rr = rsrc(R, (uint32_t)sizeof(GroupRec));
+  float2 brow[4];
+  {
+    const uint32_t o = opaque((uint32_t)(u * 16 + 4 * kq) * 8u);
+    const float4v b01 = __builtin_bit_cast(float4v, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)o, 0, 0));
+    const float4v b23 = __builtin_bit_cast(float4v, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)(o + 16u), 0, 0));
+    brow[0] = make_float2(b01.x, b01.y);
+    brow[1] = make_float2(b01.z, b01.w);
+    brow[2] = make_float2(b23.x, b23.y);
+    brow[3] = make_float2(b23.z, b23.w);
+  }
+  const float4v dl4 = __builtin_bit_cast(
+      float4v, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)opaque(2048u + 16u * kq), 0, 0));
+  const float2 okh = ldg2(rr, opaque(2048u + 64u));
   const __amdgpu_buffer_rsrc_t yr = rsrc(Yf + f * M * S * n_sc, (uint32_t)M * S * n_sc * 8u);
   const uint32_t ant = (uint32_t)S * n_sc * 32u;             // 4 antennas
   const uint32_t sym = (uint32_t)n_sc * 32u;                 // 4 symbols
@@ -326,81 +307,90 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     }
     pv = ldg2(rsrc(pil + f * n_sc, (uint32_t)n_sc * 8u), opaque((uint32_t)q * 8u));
   }
-  float2 y[16][NJ];
-  {
-    const uint32_t lane = i0 + u < n_sc ? (uint32_t)((kq * S + 1 + w) * n_sc + i0 + u) * 8u : OOB;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      uint32_t row = opaque(j < nj ? lane + (uint32_t)j * sym : OOB);
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        y[s][j] = ldg2(yr, row);
-        row = opaque(row + ant);
-      }
-    }
-  }
+  // two symbol slots in registers at a time: slot j + 2 is loaded into slot
+  // j's registers as soon as slot j has been consumed
+  float2 y[16][2];
+  const uint32_t lane = i0 + u < n_sc ? (uint32_t)((kq * S + 1 + w) * n_sc + i0 + u) * 8u : OOB;
+  load_slot<0>(y, yr, lane, 0, nj, ant, sym);
+  load_slot<1>(y, yr, lane, 1, nj, ant, sym);
 
-  // ---- the factor into LDS; H = LS estimate (absent antennas zero)
-  sh.L[(tid >> 4) * PP + (tid & 15)] = lv;
-  if (w == 0 && l < REC_TAIL_WORDS) sh.tail[l] = tv;
+  // ---- H = LS estimate (absent antennas zero) into LDS
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int m = 16 * w + 4 * a + kq;
-    sh.h[m * 16 + u] = m < M ? ls_estimate(hv[a], pv) : make_float2(0.f, 0.f);
+    hs[m * 16 + u] = m < M ? ls_estimate(hv[a], pv) : make_float2(0.f, 0.f);
   }
   __syncthreads();
 
-  // ---- Z for this wave's symbols, into its slab
+  // ---- per-subcarrier factor state: every user's mu counts (the four rows
+  // of lanes with the same u hold the 16 users)
+  const int i = i0 + u;
+  bool ok = __builtin_bit_cast(int, okh.x) != 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ok = ok && (!mmse || 1.0f - n0 * dl4[r] > 0.f);
   {
-    float probe = 0.f;
-    if (M == 64) z_all<true>(sh.h, y, sh.slab[w], probe, nj, kq, u, M);
-    else z_all<false>(sh.h, y, sh.slab[w], probe, nj, kq, u, M);
+    const uint64_t okb = __ballot(ok);
+    ok = ((okb | (okb >> 16) | (okb >> 32) | (okb >> 48)) & 0xffffull) == 0xffffull;
+  }
+  float2* xo = xt + f * 16 * D * n_sc;
+  const bool col = i < n_sc;
+
+  // ---- X = A^-1 H^H Y for this wave's symbols, stored as each is done
+  // (a subcarrier found non-finite below is cleared afterwards)
+  float probe = 0.f;
+  auto emit = [&](int j, const f32x4& xr, const f32x4& xi) {
+    if (!col) return;
+    const int d = w + 4 * j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float2 x = make_float2(xr[r], xi[r]);
+      if (mmse) x = cscale(x, __builtin_amdgcn_rcpf(1.0f - n0 * dl4[r]));
+      xo[((int64_t)(4 * kq + r) * D + d) * n_sc + i] = ok ? x : make_float2(0.f, 0.f);
+    }
+  };
+  f32x4 xr, xi;
+  if (M == 64) {
+    if (nj > 0) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(0, xr, xi); }
+    load_slot<0>(y, yr, lane, 2, nj, ant, sym);
+    if (nj > 1) { z_slot<1, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(1, xr, xi); }
+    load_slot<1>(y, yr, lane, 3, nj, ant, sym);
+    if (nj > 2) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
+    if (nj > 3) { z_slot<1, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
+  } else {
+    if (nj > 0) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(0, xr, xi); }
+    load_slot<0>(y, yr, lane, 2, nj, ant, sym);
+    if (nj > 1) { z_slot<1, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(1, xr, xi); }
+    load_slot<1>(y, yr, lane, 3, nj, ant, sym);
+    if (nj > 2) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
+    if (nj > 3) { z_slot<1, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
+  }
+  {
     const uint64_t bad = __ballot(!(probe == 0.f));
     const uint32_t m16 = (uint32_t)(bad | (bad >> 16) | (bad >> 32) | (bad >> 48)) & 0xffffu;
-    if (l == 0) sh.nfmask[w] = m16;
+    if (l == 0) nfmask[w] = m16;
   }
   __syncthreads();
 
-  // ---- solves: lane (kq, u) = symbol slot kq, subcarrier u of this wave
-  const float* inv_s = sh.tail;
-  const float* dl_s = sh.tail + 16;
-  const int d = w + 4 * kq;
-  const int i = i0 + u;
-  const uint32_t nfm = sh.nfmask[0] | sh.nfmask[1] | sh.nfmask[2] | sh.nfmask[3];
-  const bool hb = __builtin_bit_cast(int, sh.tail[33]) != 0;
+  // ---- non-finite inputs: the subcarrier is erased (same lane, same
+  // addresses, so the zeros land after the values above); noise variances
+  // and flags
+  const uint32_t nfm = nfmask[0] | nfmask[1] | nfmask[2] | nfmask[3];
+  const bool hb = __builtin_bit_cast(int, okh.y) != 0;
   const bool nf_i = hb || ((nfm >> u) & 1u);
-  bool ok = __builtin_bit_cast(int, sh.tail[32]) != 0;
-  if (mmse) {
+  if (col && nf_i) {
+    for (int j = 0; j < nj; ++j)
 #pragma unroll
-    for (int k = 0; k < 16; ++k) ok = ok && (1.0f - n0 * dl_s[k] > 0.f);
+      for (int r = 0; r < 4; ++r) xo[((int64_t)(4 * kq + r) * D + w + 4 * j) * n_sc + i] = make_float2(0.f, 0.f);
   }
   const bool erase = nf_i || !ok;
-  if (d < D) {
-    float2 z[16];
-    float inv[16];
-    const float2* slab = sh.slab[w];
+  if (col && w == 0) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) z[k] = slab[(kq * 16 + k) * ZP + u];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) inv[k] = inv_s[k];
-    solve16(sh.L, inv, z);                      // L L^H X = Z
-    if (mmse) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) z[k] = cscale(z[k], __builtin_amdgcn_rcpf(1.0f - n0 * dl_s[k]));
+    for (int r = 0; r < 4; ++r) {
+      const float dk = dl4[r];
+      const float nv = mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
+      nu[(f * 16 + 4 * kq + r) * n_sc + i] = erase ? INFINITY : nv;
     }
-    if (i < n_sc) {
-      float2* xo = xt + f * 16 * D * n_sc;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) xo[((int64_t)k * D + d) * n_sc + i] = erase ? make_float2(0.f, 0.f) : z[k];
-    }
-  }
-  if (i < n_sc) {
-    const int k = 4 * w + kq;
-    const float dk = dl_s[k];
-    const float nv = mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
-    nu[(f * 16 + k) * n_sc + i] = erase ? INFINITY : nv;
-    if (w == 0 && kq == 0 && flags)
-      flags[f * n_sc + i] = nf_i ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
+    if (kq == 0 && flags) flags[f * n_sc + i] = nf_i ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
   }
 }
 
