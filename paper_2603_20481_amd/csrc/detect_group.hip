@@ -45,7 +45,6 @@ namespace {
 using namespace det;
 
 constexpr int GWAVES = 4;     // waves per workgroup
-constexpr int NJ = 4;         // symbol slots per wave: d = w + 4 j
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float2 ldg2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
@@ -211,7 +210,7 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
 // B[u][4 kq + r]; (a + jb)(c + jd) = (k1 - b (c + d)) + j (k1 + a (d - c)),
 // k1 = (a + b) c.  x gets X rows 4 kq + r, column u.
 template <int J, bool FULLM>
-__device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[2], const float2* brow, float& probe,
+__device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[3], const float2* brow, float& probe,
                                        int kq, int u, int M, f32x4& xr, f32x4& xi) {
   f32x4 zk = {0.f, 0.f, 0.f, 0.f}, zr = zk, zi = zk;
 #pragma unroll
@@ -245,7 +244,7 @@ __device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[2], c
 // y[s][R] = Y[4 s + kq][1 + d][i0 + u]; a slot the wave does not own reads
 // zero without touching memory, so every wave issues the same loads.
 template <int R>
-__device__ __forceinline__ void load_slot(float2 (*y)[2], __amdgpu_buffer_rsrc_t yr, uint32_t lane, int j, int nj,
+__device__ __forceinline__ void load_slot(float2 (*y)[3], __amdgpu_buffer_rsrc_t yr, uint32_t lane, int j, int nj,
                                           uint32_t ant, uint32_t sym) {
   uint32_t row = opaque(j < nj ? lane + (uint32_t)j * sym : OOB);
 #pragma unroll
@@ -307,12 +306,14 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     }
     pv = ldg2(rsrc(pil + f * n_sc, (uint32_t)n_sc * 8u), opaque((uint32_t)q * 8u));
   }
-  // two symbol slots in registers at a time: slot j + 2 is loaded into slot
-  // j's registers as soon as slot j has been consumed
-  float2 y[16][2];
+  // three symbol slots in registers at a time: the fourth (only wave 0 has
+  // one with 13 data symbols) is loaded into slot 0's registers as soon as
+  // slot 0 has been consumed
+  float2 y[16][3];
   const uint32_t lane = i0 + u < n_sc ? (uint32_t)((kq * S + 1 + w) * n_sc + i0 + u) * 8u : OOB;
   load_slot<0>(y, yr, lane, 0, nj, ant, sym);
   load_slot<1>(y, yr, lane, 1, nj, ant, sym);
+  load_slot<2>(y, yr, lane, 2, nj, ant, sym);
 
   // ---- H = LS estimate (absent antennas zero) into LDS
 #pragma unroll
@@ -351,18 +352,16 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   f32x4 xr, xi;
   if (M == 64) {
     if (nj > 0) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(0, xr, xi); }
-    load_slot<0>(y, yr, lane, 2, nj, ant, sym);
+    load_slot<0>(y, yr, lane, 3, nj, ant, sym);
     if (nj > 1) { z_slot<1, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(1, xr, xi); }
-    load_slot<1>(y, yr, lane, 3, nj, ant, sym);
-    if (nj > 2) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
-    if (nj > 3) { z_slot<1, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
+    if (nj > 2) { z_slot<2, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
+    if (nj > 3) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
   } else {
     if (nj > 0) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(0, xr, xi); }
-    load_slot<0>(y, yr, lane, 2, nj, ant, sym);
+    load_slot<0>(y, yr, lane, 3, nj, ant, sym);
     if (nj > 1) { z_slot<1, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(1, xr, xi); }
-    load_slot<1>(y, yr, lane, 3, nj, ant, sym);
-    if (nj > 2) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
-    if (nj > 3) { z_slot<1, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
+    if (nj > 2) { z_slot<2, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
+    if (nj > 3) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
   }
   {
     const uint64_t bad = __ballot(!(probe == 0.f));
