@@ -9,7 +9,7 @@
 // Two kernels, so that the short serial factorisation never holds up the
 // streaming part:
 //
-//  group_factor_kernel  four tiles per wavefront: loads each tile's
+//  group_factor_kernel  two tiles per wavefront: loads each tile's
 //    pilot-symbol row and pilots, forms H (LS), the Gram matrix on MFMA, and
 //    factors A = G (+ N0 I) (Cholesky-Crout with L^-1, one tile per 16-lane
 //    row); writes L, 1 / L_kk, d_k = [A^-1]_kk and flags into a 2.25 KiB
@@ -124,39 +124,36 @@ __device__ __forceinline__ bool factor_gram(float2* hv, float2 pv, int M, int kq
   return __ballot(!(probe == 0.f)) != 0ull;
 }
 
-// Each wavefront factors four tiles: their Gram matrices one after the other
-// on MFMA (the next tile's loads in flight meanwhile), then one Crout pass in
-// which 16-lane row k works on tile k (the factorisation's broadcasts stay
-// within a row), so no lane repeats another's work.
+// Each wavefront factors TPW tiles: all of their loads issued at once, their
+// Gram matrices one after the other on MFMA, then one Crout pass in which
+// 16-lane row k works on tile k % TPW (the factorisation's broadcasts stay
+// within a row).  Two tiles per wavefront keep four wavefronts per SIMD.
+template <int TPW>
 __global__ void __launch_bounds__(256)
 group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil, GroupRec* __restrict__ rec,
                     int T, int nt, int M, int S, int n_sc, float n0, int mmse) {
-  __shared__ float2 tp[GWAVES][4][16 * PP];
+  __shared__ float2 tp[GWAVES][TPW][16 * PP];
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int u = l & 15, kq = l >> 4;
-  const int base = (blockIdx.x * GWAVES + w) * 4;             // tiles base .. base + 3
+  const int base = (blockIdx.x * GWAVES + w) * TPW;           // tiles base .. base + TPW - 1
   if (base >= T) return;                                       // a whole wave; no barrier below
 
-  float2 ha[16], hb[16], pa, pb;
-  bool bad[4];
-  factor_loads(Yf, pil, base + 0, T, nt, M, S, n_sc, kq, u, ha, pa);
-  factor_loads(Yf, pil, base + 1, T, nt, M, S, n_sc, kq, u, hb, pb);
-  bad[0] = factor_gram(ha, pa, M, kq, u, tp[w][0]);
-  factor_loads(Yf, pil, base + 2, T, nt, M, S, n_sc, kq, u, ha, pa);
-  bad[1] = factor_gram(hb, pb, M, kq, u, tp[w][1]);
-  factor_loads(Yf, pil, base + 3, T, nt, M, S, n_sc, kq, u, hb, pb);
-  bad[2] = factor_gram(ha, pa, M, kq, u, tp[w][2]);
-  bad[3] = factor_gram(hb, pb, M, kq, u, tp[w][3]);
+  float2 hv[TPW][16], pv[TPW];
+  bool bad[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) factor_loads(Yf, pil, base + t, T, nt, M, S, n_sc, kq, u, hv[t], pv[t]);
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) bad[t] = factor_gram(hv[t], pv[t], M, kq, u, tp[w][t]);
 
-  // row kq of the wave factors tile base + kq; lane `row` holds A[row][:]
+  // row kq of the wave factors tile base + kq % TPW; lane `row` holds A[row][:]
+  const int tk = kq % TPW;
   const int row = u;
-  const float2* t = tp[w][kq];
   float2 a[16], v[16];
   float inv[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    float2 g = t[row * PP + c];
+    float2 g = tp[w][tk][row * PP + c];
     if (c == row) g.x = g.x + (mmse ? n0 : 0.f);
     a[c] = g;
   }
@@ -169,12 +166,12 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   for (int k = 0; k < 16; ++k) d += v[k].x * v[k].x + v[k].y * v[k].y;
   // V = L^-1 (lane `row` holds its column `row`) over A in LDS, then
   // B = V^H V per tile: the Gram product again, V[4 s + kq][u] as both operands
-  float2* vt = tp[w][kq];
+  if (kq < TPW) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) vt[k * PP + row] = v[k];
-  const int tix = base + kq;
+    for (int k = 0; k < 16; ++k) tp[w][tk][k * PP + row] = v[k];
+  }
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < TPW; ++g) {
     f32x4 br = {0.f, 0.f, 0.f, 0.f}, bi = br;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -184,19 +181,23 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
       bi = mfma(x.x, x.y, bi);
       bi = mfma(-x.y, x.x, bi);
     }
-    const int tg = base + g;
-    if (tg < T) {
-      GroupRec& R = rec[tg];
+    if (base + g < T) {
+      GroupRec& R = rec[base + g];
 #pragma unroll
       for (int r = 0; r < 4; ++r) R.B[(4 * kq + r) * 16 + u] = make_float2(br[r], bi[r]);
     }
   }
-  if (tix < T) {
+  const int tix = base + tk;
+  if (kq < TPW && tix < T) {
     GroupRec& R = rec[tix];
     R.dl[row] = d;
     if (row == 0) {
+      bool hb = bad[0];
+#pragma unroll
+      for (int t = 1; t < TPW; ++t)
+        if (tk == t) hb = bad[t];
       R.ok = okw ? 1 : 0;                        // the same in every lane of the row
-      R.hbad = (kq == 0 ? bad[0] : kq == 1 ? bad[1] : kq == 2 ? bad[2] : bad[3]) ? 1 : 0;
+      R.hbad = hb ? 1 : 0;
     }
   }
 }
@@ -407,7 +408,7 @@ rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2
   const int64_t T = (int64_t)nf * nt;
   GroupRec* rec = (GroupRec*)ws;
   const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
-  hipLaunchKernelGGL(group_factor_kernel, dim3((unsigned)((T + 4 * GWAVES - 1) / (4 * GWAVES))), dim3(256), 0, s, yf, pil,
+  hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s, yf, pil,
                      rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse);
   rxphy_status st = launch_status("group factor kernel");
   if (st) return st;
