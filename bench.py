@@ -5,14 +5,16 @@ on one MI355X, in subcarrier-detections per second.
 Headline step = the whole receiver over one batch of 100 frames of the
 64-antenna, 16-user workload (N_FFT 2048, 1200 used subcarriers, 14 symbols,
 16-QAM, i.i.d. Rayleigh, per-user SNR uniform in [10, 30] dB), plain FP32 ZF,
-with the complex64 samples already resident in HBM: the FFT call, the fused
-CSI + detector call (the channel estimate is formed in the detector and never
-stored) and the demod call.  One
+with the complex64 samples already resident in HBM: the FFT call and the
+fused CSI + detector + demod call (the channel estimate is formed in the
+detector and never stored, and each equalised symbol is demapped as it is
+formed, so neither H nor x_tilde goes through memory).  One
 subcarrier-detection is one (frame, data symbol, used subcarrier) turned into
 K*Q LLRs.
 
 Beside the headline the same line reports the other forms, each timed the same
-way: the four separate stage calls on the same frames; MMSE; the BF16 / FP16 detector with FP64 refinement on
+way: the four separate stage calls on the same frames; csi + detect fused with
+demod as its own call; MMSE; the BF16 / FP16 detector with FP64 refinement on
 the 64x16 N_FFT 4096 64-QAM correlated workload (and plain FP32 there); 256
 uneven frames in one persistent launch replayed from a hipGraph, with
 autotuned and default item sizes and against a loop of per-frame calls; and
@@ -38,8 +40,10 @@ import synth  # noqa: E402
 
 METRIC = "subcarrier-detections/s (64×16, FFT→ZF→LLR), mixed/batched vs plain FP32"
 HBM_PEAK_GBS = 8000.0
-NAMES = ["fft", "csi", "detect", "demod"]            # the four stage calls
-FUSED_NAMES = ["fft", "csi_detect", "demod"]         # csi and detect fused
+# the calls of each way of running the chain
+MODES = {"staged": ["fft", "csi", "detect", "demod"],          # the four stage calls
+         "csi_detect": ["fft", "csi_detect", "demod"],        # csi and detect fused
+         "full": ["fft", "csi_detect_demod"]}                 # csi, detect and demod fused
 
 
 def gen_frames(cfg, n, workers, shape=None):
@@ -49,7 +53,9 @@ def gen_frames(cfg, n, workers, shape=None):
 
 def stage_bytes(s):
     """Compulsory HBM bytes of each stage's interface tensors for one frame
-    (csi_detect: the fused csi + detect call, which never stores H)."""
+    (csi_detect: the fused csi + detect call, which never stores H;
+    csi_detect_demod: csi, detect and demod fused, which stores neither H nor
+    x_tilde)."""
     M, K, N, n_sc, S, cp, Q = s.M, s.K, s.n_fft, s.n_sc, s.n_sym, s.cp_len, s.qam_bits
     D = S - 1
     return {
@@ -57,6 +63,8 @@ def stage_bytes(s):
         "csi": M * n_sc * 8 + n_sc * 8 + M * K * n_sc * 8,
         "detect": M * K * n_sc * 8 + M * D * n_sc * 8 + K * D * n_sc * 8 + K * n_sc * 4 + n_sc,
         "csi_detect": M * n_sc * 8 + n_sc * 8 + M * D * n_sc * 8 + K * D * n_sc * 8 + K * n_sc * 4 + n_sc,
+        "csi_detect_demod": M * n_sc * 8 + n_sc * 8 + M * D * n_sc * 8 + K * n_sc * 4 + n_sc
+                            + K * D * n_sc * Q * 4,
         "demod": K * D * n_sc * 8 + K * n_sc * 4 + K * D * n_sc * Q * 4,
     }
 
@@ -120,35 +128,40 @@ class Chain:
         self.llr = torch.empty((F, shape.K, D, shape.n_sc, shape.qam_bits), dtype=f32, device=dev)
         self.ws = None
 
-    def step(self, fr, prec="fp32", ev=None, fused=False):
+    def step(self, fr, prec="fp32", ev=None, mode="full"):
         rx = self.rx
-        need = rx.workspace_bytes(fr, self.F, rx.WS_CSI_DETECT if fused else rx.WS_DETECT, prec)
+        kind = {"staged": rx.WS_DETECT, "csi_detect": rx.WS_CSI_DETECT, "full": rx.WS_CSI_DETECT_DEMOD}[mode]
+        need = rx.workspace_bytes(fr, self.F, kind, prec)
         if need and (self.ws is None or self.ws.numel() < need):
             self.ws = self.torch.empty((need,), dtype=self.torch.uint8, device="cuda")
         ws = self.ws if need else None
         if ev: ev[0].record()
         rx.fft(fr, self.x, self.yf)
         if ev: ev[1].record()
-        if fused:
+        if mode == "full":
+            rx.csi_detect_demod(fr, self.yf, self.p, prec, 1e3, llr=self.llr, nu=self.nu, flags=self.fl, ws=ws)
+            if ev: ev[2].record()
+            return
+        if mode == "csi_detect":
             rx.csi_detect(fr, self.yf, self.p, prec, 1e3, self.xt, self.nu, self.fl, ws)
         else:
             rx.csi(fr, self.yf, self.p, self.h)
             if ev: ev[2].record()
             rx.detect(fr, self.h, self.yf, prec, 1e3, self.xt, self.nu, self.fl, ws)
-        if ev: ev[3 if not fused else 2].record()
+        if ev: ev[len(MODES[mode]) - 1].record()
         rx.demod(fr, self.xt, self.nu, self.llr)
-        if ev: ev[4 if not fused else 3].record()
+        if ev: ev[len(MODES[mode])].record()
 
-    def time(self, fr, prec, steps, warmup, fused=False):
+    def time(self, fr, prec, steps, warmup, mode="full"):
         torch = self.torch
-        names = FUSED_NAMES if fused else NAMES
+        names = MODES[mode]
         for _ in range(warmup):
-            self.step(fr, prec, fused=fused)
+            self.step(fr, prec, mode=mode)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
         t0 = time.perf_counter()
         for k in range(steps):
-            self.step(fr, prec, evs[k], fused=fused)
+            self.step(fr, prec, evs[k], mode=mode)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         per = {n: 0.0 for n in names}
@@ -348,7 +361,7 @@ def main():
     chain = Chain(rx, torch, shape, x_h, p_h)
     del x_h, p_h
     fr = rx.Frame.of(shape, det, 1.0)
-    ms_per_step, per_stage = chain.time(fr, "fp32", args.steps, args.warmup, fused=True)
+    ms_per_step, per_stage = chain.time(fr, "fp32", args.steps, args.warmup, mode="full")
     dets = F * shape.detections
     value = dets / (ms_per_step * 1e-3)
 
@@ -370,8 +383,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded generator: Rayleigh block channel, comb pilots, AWGN)",
         "config": {"workload": "64x16 MIMO, N_FFT 2048, 1200 used subcarriers, 14 symbols, 16-QAM, "
-                               "Rayleigh, SNR U[10,30] dB, 100 frames, ZF, FP32; fft, fused csi + "
-                               "detect (H never stored), demod",
+                               "Rayleigh, SNR U[10,30] dB, 100 frames, ZF, FP32; fft, then csi + "
+                               "detect + demod fused (neither H nor x_tilde stored)",
                    "frames": F, "M": shape.M, "K": shape.K, "n_fft": shape.n_fft,
                    "n_sc": shape.n_sc, "n_sym": shape.n_sym, "qam_bits": shape.qam_bits,
                    "detector": "zf", "precision": "fp32"},
@@ -387,14 +400,19 @@ def main():
     }
     print("[bench] headline %.4g det/s (%.3f ms/step)" % (value, ms_per_step), file=sys.stderr, flush=True)
     if "staged" in forms:
-        ms, per = chain.time(fr, "fp32", args.form_steps, 1)
+        ms, per = chain.time(fr, "fp32", args.form_steps, 1, mode="staged")
         out["forms"]["staged_fp32"] = form_summary(
             shape, F, ms, per, {"workload": "as the headline, the four stage calls (H stored by csi, "
-                                            "read back by detect)"})
+                                            "read back by detect; x_tilde stored by detect, read back "
+                                            "by demod)"})
+        ms, per = chain.time(fr, "fp32", args.form_steps, 1, mode="csi_detect")
+        out["forms"]["csi_detect_fp32"] = form_summary(
+            shape, F, ms, per, {"workload": "as the headline, csi + detect fused, demod its own call "
+                                            "(x_tilde stored and read back)"})
         print("[bench] staged done", file=sys.stderr, flush=True)
     if "mmse" in forms:
         frm = rx.Frame.of(shape, rx.MMSE, 1.0)
-        ms, per = chain.time(frm, "fp32", args.form_steps, 1, fused=True)
+        ms, per = chain.time(frm, "fp32", args.form_steps, 1, mode="full")
         out["forms"]["mmse_fp32"] = form_summary(shape, F, ms, per, {"workload": "as the headline, MMSE"})
         print("[bench] mmse done", file=sys.stderr, flush=True)
     del chain
@@ -406,7 +424,7 @@ def main():
         del x3, p3
         fr3 = rx.Frame.of(s3, rx.ZF, 1.0)
         for prec in ("fp32", "bf16", "fp16"):
-            ms, per = c3.time(fr3, prec, args.form_steps, 1, fused=True)
+            ms, per = c3.time(fr3, prec, args.form_steps, 1, mode="full")
             refined = int((c3.fl & rx.FLAG_REFINED).ne(0).sum().item())
             out["forms"]["kronecker_64x16_n4096_64qam_" + prec] = form_summary(
                 s3, args.mixed_frames, ms, per,

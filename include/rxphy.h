@@ -136,6 +136,25 @@ rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
                               uint8_t* flags, rxphy_precision precision, float cond_threshold,
                               void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* csi, equal and demod stages fused: rxphy_csi_detect followed by
+ * rxphy_demod on its x_tilde and nu.  llr, nu and flags are bit-identical to
+ * that sequence; x_tilde is written only if xt is not NULL.  With 16 users in
+ * FP32 the whole chain after the FFT is two kernels (the per-tile
+ * factorisation, then the detector with the max-log demapping of each
+ * equalised symbol as it is formed, so x_tilde need not round-trip through
+ * memory); otherwise the stages run one after the other.
+ *   xt  : c64 [F][K][n_sym-1][n_sc] (written if not NULL)
+ *   llr : f32 [F][K][n_sym-1][n_sc][qam_bits] (written)
+ *   ws  : rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD,
+ *         precision) bytes, 8-byte aligned (caller-owned, reusable once the
+ *         stream has passed the call)
+ * Other arguments as rxphy_csi_detect.                                        */
+rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames,
+                                    const void* yf, const void* pilots, void* xt, float* nu,
+                                    uint8_t* flags, float* llr, rxphy_precision precision,
+                                    float cond_threshold, void* ws, size_t ws_bytes,
+                                    hipStream_t stream);
+
 /* demod stage (`demod` macro): max-log LLRs over the Gray square-QAM set
  * with unit average energy (bits b0 .. b_{Q-1}; b0, b2, b4 select the
  * in-phase level, b1, b3, b5 the quadrature level):
@@ -175,11 +194,12 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames,
                             const float* dllr, void* dx, void* dh,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
-enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1, RXPHY_WS_CSI_DETECT = 2 };
+enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1, RXPHY_WS_CSI_DETECT = 2, RXPHY_WS_CSI_DETECT_DEMOD = 3 };
 
 /* Workspace bytes needed by rxphy_detect (which = RXPHY_WS_DETECT),
- * rxphy_backward (RXPHY_WS_BACKWARD) or rxphy_csi_detect
- * (RXPHY_WS_CSI_DETECT); 0 if none or if the shape is invalid.               */
+ * rxphy_backward (RXPHY_WS_BACKWARD), rxphy_csi_detect (RXPHY_WS_CSI_DETECT)
+ * or rxphy_csi_detect_demod (RXPHY_WS_CSI_DETECT_DEMOD); 0 if none or if the
+ * shape is invalid.                                                          */
 size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
                              rxphy_precision precision);
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librxphy.so")
 ZF, MMSE = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 FLAG_REFINED, FLAG_BREAKDOWN, FLAG_NONFINITE = 1, 2, 4
-WS_DETECT, WS_BACKWARD, WS_CSI_DETECT = 0, 1, 2
+WS_DETECT, WS_BACKWARD, WS_CSI_DETECT, WS_CSI_DETECT_DEMOD = 0, 1, 2, 3
 
 
 class RxphyError(RuntimeError):
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_csi": [FR, I32, P, P, P, P],
         "rxphy_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
+        "rxphy_csi_detect_demod": [FR, I32, P, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_demod": [FR, I32, P, P, P, P],
         "rxphy_backward": [FR, I32, P, P, ctypes.POINTER(_Saved), P, P, P, P, SZ, P],
     }
@@ -247,6 +248,35 @@ def csi_detect(fr: Frame, yf, pilots, precision: str = "fp32", cond_threshold: f
     return xt, nu, flags
 
 
+def csi_detect_demod(fr: Frame, yf, pilots, precision: str = "fp32", cond_threshold: float = 1e3,
+                     want_xt: bool = False, llr=None, nu=None, flags=None, xt=None, ws=None):
+    """csi, detect and demod fused -> (llr, nu, flags, xt or None); the same
+    llr, nu and flags as demod(fr, *csi_detect(fr, yf, pilots)[:2])."""
+    F = _nf(yf)
+    D = fr.n_data
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    llr = _empty((F, fr.K, D, fr.n_sc, fr.qam_bits), torch.float32, yf) if llr is None else llr
+    nu = _empty((F, fr.K, fr.n_sc), torch.float32, yf) if nu is None else nu
+    flags = _empty((F, fr.n_sc), torch.uint8, yf) if flags is None else flags
+    if xt is None and want_xt:
+        xt = _empty((F, fr.K, D, fr.n_sc), torch.complex64, yf)
+    _need(llr, "llr", (F, fr.K, D, fr.n_sc, fr.qam_bits), torch.float32)
+    _need(nu, "nu", (F, fr.K, fr.n_sc), torch.float32)
+    _need(flags, "flags", (F, fr.n_sc), torch.uint8)
+    if xt is not None:
+        _need(xt, "xt", (F, fr.K, D, fr.n_sc), torch.complex64)
+    need = workspace_bytes(fr, F, WS_CSI_DETECT_DEMOD, precision)
+    if need and ws is None:
+        ws = _empty((need,), torch.uint8, yf)
+    _check(load().rxphy_csi_detect_demod(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots),
+                                         _ptr(xt) if xt is not None else None, _ptr(nu), _ptr(flags),
+                                         _ptr(llr), PRECISIONS[precision], float(cond_threshold),
+                                         _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+           "rxphy_csi_detect_demod")
+    return llr, nu, flags, xt
+
+
 def demod(fr: Frame, xt, nu, llr=None):
     """-> llr f32 [F][K][D][n_sc][qam_bits]."""
     F = _nf(xt)
@@ -264,11 +294,10 @@ def demod(fr: Frame, xt, nu, llr=None):
 def forward(fr: Frame, x, pilots, precision: str = "fp32", cond_threshold: float = 1e3,
             fused: bool = False):
     """All four stages; returns a dict of every intermediate (no "h" when the
-    csi and detect stages run fused)."""
+    csi, detect and demod stages run fused)."""
     yf = fft(fr, x)
     if fused:
-        xt, nu, flags = csi_detect(fr, yf, pilots, precision, cond_threshold)
-        llr = demod(fr, xt, nu)
+        llr, nu, flags, xt = csi_detect_demod(fr, yf, pilots, precision, cond_threshold, want_xt=True)
         return dict(yf=yf, xt=xt, nu=nu, flags=flags, llr=llr)
     h = csi(fr, yf, pilots)
     xt, nu, flags = detect(fr, h, yf, precision, cond_threshold)

@@ -168,6 +168,38 @@ rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames, const 
                        nu, flags, precision, cond_threshold, ws, stream);
 }
 
+rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames, const void* yf,
+                                    const void* pilots, void* xt, float* nu, uint8_t* flags, float* llr,
+                                    rxphy_precision precision, float cond_threshold, void* ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
+    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
+    return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
+  size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD, precision);
+  if (need && (!ws || ws_bytes < need))
+    return fail(RXPHY_EWORKSPACE, "csi_detect_demod needs %zu workspace bytes, got %zu", need, ws_bytes);
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(nu, "nu")) ||
+      (st = check_ptr(llr, "llr")))
+    return st;
+  const rxphy_frame& fr = *frame;
+  if (group_path(fr, precision))
+    return launch_detect_group(fr, n_frames, (const float2*)yf, (const float2*)pilots, (float2*)xt, nu, flags,
+                               llr, ws, stream);
+  // the stages one after the other; x_tilde in the caller's buffer or after
+  // the detector's part of the workspace
+  float2* x = (float2*)xt;
+  if (!x) x = (float2*)((char*)ws + ((detect_workspace_bytes(fr, n_frames, precision) + 255) & ~(size_t)255));
+  if ((st = launch_detect(fr, n_frames, nullptr, (const float2*)yf, (const float2*)pilots, x, nu, flags,
+                          precision, cond_threshold, ws, stream)))
+    return st;
+  return launch_demod(fr, n_frames, x, nu, llr, stream);
+}
+
 rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames, const void* xt,
                          const float* nu, float* llr, hipStream_t stream) {
   clear_error();

@@ -379,6 +379,7 @@ size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t
   if (check_frame(frame, n_frames) != RXPHY_OK) return 0;
   if (which == RXPHY_WS_DETECT) return detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT) return csi_detect_workspace_bytes(*frame, n_frames, precision);
+  if (which == RXPHY_WS_CSI_DETECT_DEMOD) return csi_detect_demod_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_BACKWARD) return layout(*frame, n_frames).total;
   return 0;
 }

@@ -39,11 +39,16 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
                            rxphy_precision prec, float thr, void* ws, hipStream_t s);
 // Fused CSI + detector for K = 16 in FP32 (one pilot group per tile); ws holds
 // group_workspace_bytes() of per-tile factor records.
+// llr != nullptr: the demod stage fused in (xt may then be nullptr).
 rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                 float2* xt, float* nu, uint8_t* flags, void* ws, hipStream_t s);
+                                 float2* xt, float* nu, uint8_t* flags, float* llr, void* ws, hipStream_t s);
 size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf);
 // Workspace of rxphy_csi_detect (the group path's records, else as detect).
 size_t csi_detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec);
+// Workspace of rxphy_csi_detect_demod: as rxphy_csi_detect, plus x_tilde
+// (for a caller that does not want it) where the demod runs as its own stage.
+size_t csi_detect_demod_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec);
+bool group_path(const rxphy_frame& fr, rxphy_precision prec);
 size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec);
 rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, const float* nu,
                           float* llr, hipStream_t s);

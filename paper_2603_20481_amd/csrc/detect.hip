@@ -211,9 +211,17 @@ void launch_p(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* 
 
 }  // namespace
 
+bool group_path(const rxphy_frame& fr, rxphy_precision prec) { return prec == RXPHY_FP32 && fr.K == 16; }
+
 size_t csi_detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
-  if (prec == RXPHY_FP32 && fr.K == 16) return group_workspace_bytes(fr, nf);
+  if (group_path(fr, prec)) return group_workspace_bytes(fr, nf);
   return detect_workspace_bytes(fr, nf, prec);
+}
+
+size_t csi_detect_demod_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
+  if (group_path(fr, prec)) return group_workspace_bytes(fr, nf);
+  const size_t a = (detect_workspace_bytes(fr, nf, prec) + 255) & ~(size_t)255;
+  return a + (size_t)nf * fr.K * (fr.n_sym - 1) * fr.n_sc * 8;
 }
 
 size_t detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
@@ -226,7 +234,7 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
                            float thr, void* ws, hipStream_t s) {
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
   if (prec == RXPHY_FP32) {
-    if (pil && fr.K == 16) return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, ws, s);
+    if (pil && group_path(fr, prec)) return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, nullptr, ws, s);
     launch_p<P_FP32>(fr, nf, h, yf, pil, xt, nu, flags, thr, nullptr, s);
     return launch_status("detect kernel");
   }

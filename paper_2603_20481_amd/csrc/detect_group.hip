@@ -28,6 +28,7 @@
 // Every product, sum and factorisation step is the one the general detector
 // (detect_core.h, shared-factor path) performs on the same values in the
 // same order, so the results are bit-identical to rxphy_csi + rxphy_detect.
+#include "demod_core.h"
 #include "detect_core.h"
 
 namespace rxphy {
@@ -256,10 +257,15 @@ __device__ __forceinline__ void load_slot(float2 (*y)[3], __amdgpu_buffer_rsrc_t
 }
 
 // One workgroup per (tile, frame): blockIdx.x = tile, blockIdx.y = frame.
+// Q > 0: the demod stage follows in the same kernel (max-log LLRs of every
+// equalised symbol into llr, as demod_kernel computes them from x_tilde and
+// nu); xt may then be null (not written).
+template <int Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil,
                     const GroupRec* __restrict__ rec, float2* __restrict__ xt, float* __restrict__ nu,
-                    uint8_t* __restrict__ flags, int M, int S, int n_sc, float n0, int mmse) {
+                    uint8_t* __restrict__ flags, float* __restrict__ llr, int M, int S, int n_sc, float n0,
+                    int mmse) {
   __shared__ float2 hs[64 * 16];                // H of the tile: [antenna][user]
   __shared__ uint32_t nfmask[GWAVES];           // subcarriers with a non-finite data value
   const int tid = threadIdx.x, l = tid & 63;
@@ -334,7 +340,8 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     const uint64_t okb = __ballot(ok);
     ok = ((okb | (okb >> 16) | (okb >> 32) | (okb >> 48)) & 0xffffull) == 0xffffull;
   }
-  float2* xo = xt + f * 16 * D * n_sc;
+  float2* xo = xt ? xt + f * 16 * D * n_sc : nullptr;
+  float* lo = llr + f * 16 * D * n_sc * Q;
   const bool col = i < n_sc;
 
   // ---- X = A^-1 H^H Y for this wave's symbols, stored as each is done
@@ -347,7 +354,15 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     for (int r = 0; r < 4; ++r) {
       float2 x = make_float2(xr[r], xi[r]);
       if (mmse) x = cscale(x, __builtin_amdgcn_rcpf(1.0f - n0 * dl4[r]));
-      xo[((int64_t)(4 * kq + r) * D + d) * n_sc + i] = ok ? x : make_float2(0.f, 0.f);
+      if (!ok) x = make_float2(0.f, 0.f);
+      const int64_t e = ((int64_t)(4 * kq + r) * D + d) * n_sc + i;
+      if (xo) xo[e] = x;
+      if constexpr (Q > 0) {
+        const float dk = dl4[r];
+        const float v = !ok ? INFINITY : mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
+        demk::demod_point<Q>(x, v, lo + e * Q);
+        __builtin_amdgcn_sched_barrier(0);       // one point at a time (registers)
+      }
     }
   };
   f32x4 xr, xi;
@@ -378,9 +393,14 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   const bool hb = __builtin_bit_cast(int, okh.y) != 0;
   const bool nf_i = hb || ((nfm >> u) & 1u);
   if (col && nf_i) {
-    for (int j = 0; j < nj; ++j)
+    for (int j = 0; j < nj; ++j) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) xo[((int64_t)(4 * kq + r) * D + w + 4 * j) * n_sc + i] = make_float2(0.f, 0.f);
+      for (int r = 0; r < 4; ++r) {
+        const int64_t e = ((int64_t)(4 * kq + r) * D + w + 4 * j) * n_sc + i;
+        if (xo) xo[e] = make_float2(0.f, 0.f);
+        if constexpr (Q > 0) demk::demod_point<Q>(make_float2(0.f, 0.f), INFINITY, lo + e * Q);
+      }
+    }
   }
   const bool erase = nf_i || !ok;
   if (col && w == 0) {
@@ -401,19 +421,30 @@ size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf) {
 }
 
 rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                 float2* xt, float* nu, uint8_t* flags, void* ws, hipStream_t s) {
+                                 float2* xt, float* nu, uint8_t* flags, float* llr, void* ws, hipStream_t s) {
   if (nf == 0) return RXPHY_OK;
   if (!ws || ((uintptr_t)ws & 7u)) return fail(RXPHY_EWORKSPACE, "csi_detect workspace must be 8-byte aligned");
   const int nt = (fr.n_sc + 15) / 16;
   const int64_t T = (int64_t)nf * nt;
   GroupRec* rec = (GroupRec*)ws;
   const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
-  hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s, yf, pil,
-                     rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse);
+  hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s, yf,
+                     pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse);
   rxphy_status st = launch_status("group factor kernel");
   if (st) return st;
-  hipLaunchKernelGGL(detect_group_kernel, dim3(nt, nf), dim3(256), 0, s, yf, pil, rec, xt, nu, flags, fr.M,
-                     fr.n_sym, fr.n_sc, fr.n0, mmse);
+  const dim3 grid(nt, nf);
+  const int q = llr ? fr.qam_bits : 0;
+#define RXPHY_GROUP_LAUNCH(QQ)                                                                              \
+  hipLaunchKernelGGL(detect_group_kernel<QQ>, grid, dim3(256), 0, s, yf, pil, rec, xt, nu, flags, llr, fr.M, \
+                     fr.n_sym, fr.n_sc, fr.n0, mmse)
+  switch (q) {
+    case 0: RXPHY_GROUP_LAUNCH(0); break;
+    case 2: RXPHY_GROUP_LAUNCH(2); break;
+    case 4: RXPHY_GROUP_LAUNCH(4); break;
+    case 6: RXPHY_GROUP_LAUNCH(6); break;
+    default: return fail(RXPHY_EINVAL, "qam_bits = %d", fr.qam_bits);
+  }
+#undef RXPHY_GROUP_LAUNCH
   return launch_status("detect group kernel");
 }
 

@@ -318,6 +318,32 @@ def test_fused_csi_detect_equals_two_calls(rx, sh, det, prec):
             assert e < 1e-4
 
 
+@pytest.mark.parametrize("sh,det,prec", FUSED_CASES)
+def test_fused_csi_detect_demod_equals_stages(rx, sh, det, prec):
+    """rxphy_csi_detect_demod gives the llr, nu and flags of rxphy_csi_detect
+    followed by rxphy_demod bit for bit (x_tilde too when asked for), with and
+    without x_tilde written, on the same zero pilot and non-finite values."""
+    frs = [synth.make_frame(4, f, shape=sh) for f in range(2)]
+    x, p = frames_to_device(frs)
+    p[1, 7] = 0
+    fr = rx.Frame.of(sh, det, 1.0)
+    yf = rx.fft(fr, x)
+    yf[0, 0, 1, 17] = float("nan")
+    yf[1, sh.M - 1, sh.n_sym - 1, 40] = float("inf")
+    thr = 20.0 if prec != "fp32" else 1e3
+    xt, nu, fl = rx.csi_detect(fr, yf, p, prec, thr)
+    llr = rx.demod(fr, xt, nu)
+    for want_xt in (False, True):
+        l2, nu2, fl2, xt2 = rx.csi_detect_demod(fr, yf, p, prec, thr, want_xt=want_xt)
+        torch.cuda.synchronize()
+        assert torch.equal(l2, llr) and torch.equal(nu2, nu) and torch.equal(fl2, fl)
+        if want_xt:
+            assert torch.equal(torch.view_as_real(xt2), torch.view_as_real(xt))
+        else:
+            assert xt2 is None
+    say("fused demod", sh, det, prec, "erased", int(fl.ne(0).sum().item()))
+
+
 def test_deterministic(rx):
     frs = synth.make_frames(2, 1)
     x, p = frames_to_device(frs)
