@@ -83,4 +83,12 @@ __device__ __forceinline__ float2 ls_estimate(float2 y, float2 p) {
   return make_float2((y.x * p.x + y.y * p.y) / pp, (y.y * p.x - y.x * p.y) / pp);
 }
 
+
+// Store that is not expected to be read again soon (global_store with the
+// non-temporal hint): for outputs streamed once, such as the LLRs.
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream2(float2* p, float2 v) {
+  __builtin_nontemporal_store(f32x2v{v.x, v.y}, reinterpret_cast<f32x2v*>(p));
+}
+
 }  // namespace rxphy

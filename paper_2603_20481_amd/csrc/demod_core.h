@@ -71,7 +71,7 @@ __device__ __forceinline__ void demod_point(float2 x, float v, float* __restrict
     for (int t = 0; t < Q / 2; ++t) { o[2 * t] = re[t]; o[2 * t + 1] = im[t]; }
   }
 #pragma unroll
-  for (int t = 0; t < Q / 2; ++t) reinterpret_cast<float2*>(dst)[t] = make_float2(o[2 * t], o[2 * t + 1]);
+  for (int t = 0; t < Q / 2; ++t) store_stream2(reinterpret_cast<float2*>(dst) + t, make_float2(o[2 * t], o[2 * t + 1]));
 }
 
 // One (user, subcarrier) column: xc = &x_tilde[u][0][i], lc = &llr[u][0][i][0];
