@@ -55,8 +55,10 @@ __device__ __forceinline__ void axis_llr(float x, float inv_nu, float* out) {
 
 
 // LLRs of one equalised symbol x with noise variance v (erased when v = inf)
-// into dst[0 .. Q-1].
-template <int Q>
+// into dst[0 .. Q-1]; STREAM: store with the non-temporal hint (measured: it
+// helps the fused detector, whose LLR stream competes with its data loads,
+// and slows the demod stage's own kernel).
+template <int Q, bool STREAM = false>
 __device__ __forceinline__ void demod_point(float2 x, float v, float* __restrict__ dst) {
   float o[Q];
   if (__builtin_isinf(v)) {
@@ -71,7 +73,11 @@ __device__ __forceinline__ void demod_point(float2 x, float v, float* __restrict
     for (int t = 0; t < Q / 2; ++t) { o[2 * t] = re[t]; o[2 * t + 1] = im[t]; }
   }
 #pragma unroll
-  for (int t = 0; t < Q / 2; ++t) store_stream2(reinterpret_cast<float2*>(dst) + t, make_float2(o[2 * t], o[2 * t + 1]));
+  for (int t = 0; t < Q / 2; ++t) {
+    const float2 pr = make_float2(o[2 * t], o[2 * t + 1]);
+    if constexpr (STREAM) store_stream2(reinterpret_cast<float2*>(dst) + t, pr);
+    else reinterpret_cast<float2*>(dst)[t] = pr;
+  }
 }
 
 // One (user, subcarrier) column: xc = &x_tilde[u][0][i], lc = &llr[u][0][i][0];

@@ -360,7 +360,7 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
       if constexpr (Q > 0) {
         const float dk = dl4[r];
         const float v = !ok ? INFINITY : mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
-        demk::demod_point<Q>(x, v, lo + e * Q);
+        demk::demod_point<Q, true>(x, v, lo + e * Q);
         __builtin_amdgcn_sched_barrier(0);       // one point at a time (registers)
       }
     }
@@ -398,7 +398,7 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
       for (int r = 0; r < 4; ++r) {
         const int64_t e = ((int64_t)(4 * kq + r) * D + w + 4 * j) * n_sc + i;
         if (xo) xo[e] = make_float2(0.f, 0.f);
-        if constexpr (Q > 0) demk::demod_point<Q>(make_float2(0.f, 0.f), INFINITY, lo + e * Q);
+        if constexpr (Q > 0) demk::demod_point<Q, true>(make_float2(0.f, 0.f), INFINITY, lo + e * Q);
       }
     }
   }
