@@ -423,6 +423,7 @@ size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf) {
 rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
                                  float2* xt, float* nu, uint8_t* flags, float* llr, void* ws, hipStream_t s) {
   if (nf == 0) return RXPHY_OK;
+  if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);   // grid y
   if (!ws || ((uintptr_t)ws & 7u)) return fail(RXPHY_EWORKSPACE, "csi_detect workspace must be 8-byte aligned");
   const int nt = (fr.n_sc + 15) / 16;
   const int64_t T = (int64_t)nf * nt;

@@ -96,6 +96,29 @@ def test_detect_argument_checks(lib):
     assert lib.rxphy_detect(ctypes.byref(fr), 0, None, None, None, None, None, 0, 1e3, None, 0, None) == 0
 
 
+def test_fused_call_checks(lib):
+    """rxphy_csi_detect_demod: argument, workspace, alignment and frame-count
+    errors come back before any HIP call (the pointers here are never
+    dereferenced)."""
+    fr = frame(M=64, K=16, n_fft=2048, n_sc=1200, n_sym=14, qam_bits=4)
+    p = ctypes.c_void_p(256)
+    f = lib.rxphy_csi_detect_demod
+    f.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32] + [ctypes.c_void_p] * 6 + \
+        [ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    lib.rxphy_workspace_bytes.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.rxphy_workspace_bytes.restype = ctypes.c_size_t
+    need = lib.rxphy_workspace_bytes(ctypes.byref(fr), 1, 3, 0)
+    assert need == 75 * 2304                         # one factor record per 16-subcarrier tile
+    big = 1 << 40
+    assert f(ctypes.byref(fr), 1, p, p, None, p, p, p, 0, 1e3, p, need - 1, None) == 3      # workspace
+    assert f(ctypes.byref(fr), 1, p, p, None, p, p, None, 0, 1e3, p, need, None) == 1       # llr NULL
+    assert f(ctypes.byref(fr), 1, p, p, None, p, p, p, 9, 1e3, p, need, None) == 1          # precision
+    assert f(ctypes.byref(fr), 1, p, p, None, p, p, p, 0, 1e3, ctypes.c_void_p(260), need, None) == 3
+    assert f(ctypes.byref(fr), 70000, p, p, None, p, p, p, 0, 1e3, p, big, None) == 2       # grid limit
+    assert f(ctypes.byref(fr), 0, None, None, None, None, None, None, 0, 1e3, None, 0, None) == 0
+
+
 def test_status_strings(lib):
     lib.rxphy_status_string.restype = ctypes.c_char_p
     assert lib.rxphy_status_string(0) == b"RXPHY_OK"
