@@ -19,6 +19,11 @@ the paper's preamble; the paper gives them no further definition):
   demod  max-log LLRs over the Gray square-QAM set, by brute force over every
          constellation point (definition of the max-log LLR).
 
+Downlink (the transmit-side macros modul, precode, ifft of the same preamble):
+  modulate_stage  bits -> Gray QAM points; precode_stage  zero-forcing
+  precoder from the uplink channel estimate; ifft_stage  inverse transform of
+  the used bins with a cyclic prefix.
+
 Every floating-point value is complex128 / float64.  Library primitives used
 as steps: numpy's FFT and matrix products.  The Cholesky factorisation and
 the triangular solves are written out.
@@ -416,6 +421,63 @@ def cascaded_theta_grad(gx, shape, theta, Gm, Fm, amp, symbols, pilots):
     # dH[m][u]/dtheta_k = (j/sqrt(n_el)) G[m][k] e^{j theta_k} F[k][u]
     t = np.einsum("mu,mk,ku->k", np.conj(gH), Gm, Fm)
     return np.real(t * 1j * ej) / math.sqrt(n_el)
+
+
+# ---------------------------------------------------------------------- downlink
+# The transmit direction the survey ranks next after the uplink path (the
+# `modul`, `precode` and `ifft` macros of the paper's preamble): QAM mapping,
+# a zero-forcing precoder built from the same Gram matrix and Cholesky factor
+# as the detector, and the inverse transform with a cyclic prefix.
+def modulate_stage(bits, q: int) -> np.ndarray:
+    """bits [..., q] (b0 first) -> the Gray square-QAM point with that label,
+    i.e. constellation(q)'s point index c = sum_j b_j 2^(q-1-j)."""
+    pts, _ = constellation(q)
+    b = np.asarray(bits).astype(np.int64)
+    if b.shape[-1] != q:
+        raise ValueError("last axis must hold the q bits")
+    idx = np.zeros(b.shape[:-1], dtype=np.int64)
+    for j in range(q):
+        idx = idx * 2 + b[..., j]
+    return pts[idx]
+
+
+def precode_stage(H, S, n0: float = 1.0, detector: int = ZF):
+    """Zero-forcing precoding with the uplink estimate (reciprocity): per
+    subcarrier X = H A^{-1} S with A = H^H H (ZF) or H^H H + N0 I (the
+    regularised form, detector = MMSE), so that a downlink channel H^H gives
+    H^H X = S for ZF.  A^{-1} S by the same Cholesky and two triangular solves
+    as detect_stage; no power normalisation.  A breakdown (pivot <= 0) or a
+    non-finite channel value transmits nothing on that subcarrier (X = 0) and
+    flags it.
+
+    H: [M, K, n_sc]; S: [K, D, n_sc]; returns dict(x [M, D, n_sc], flags [n_sc])."""
+    Hs = np.moveaxis(np.asarray(H, dtype=np.complex128), -1, 0)     # [n_sc, M, K]
+    Ss = np.moveaxis(np.asarray(S, dtype=np.complex128), -1, 0)     # [n_sc, K, D]
+    fin = np.isfinite(Hs).all(axis=(1, 2))
+    Hs = np.where(fin[:, None, None], Hs, 0.0)
+    A = regularised_gram(Hs, n0, detector)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        L, ok = cholesky_lower(A)
+        W = back_sub_h(L, forward_sub(L, Ss))                         # A^{-1} S
+        X = Hs @ W                                                    # [n_sc, M, D]
+    flags = np.zeros(Hs.shape[0], dtype=np.uint8)
+    flags[~ok & fin] |= FLAG_BREAKDOWN
+    flags[~fin] |= FLAG_NONFINITE
+    X[flags != 0] = 0.0
+    return dict(x=np.ascontiguousarray(np.moveaxis(X, 0, -1)), flags=flags)
+
+
+def ifft_stage(Xf, n_fft: int, n_sc: int, cp_len: int = 0) -> np.ndarray:
+    """Inverse of fft_stage's used-bin transform, unscaled, with a cyclic
+    prefix: x[n] = sum_i Xf[i] exp(+j 2 pi bin(i) n / N) for n = 0..N-1, then
+    the last cp_len samples are prepended (so fft_stage(ifft_stage(X)) = N X).
+
+    Xf: [..., n_sc]; returns [..., cp_len + n_fft] complex128."""
+    Xf = np.asarray(Xf, dtype=np.complex128)
+    grid = np.zeros(Xf.shape[:-1] + (n_fft,), dtype=np.complex128)
+    grid[..., used_bins(n_fft, n_sc)] = Xf
+    seg = np.fft.ifft(grid, axis=-1) * n_fft
+    return np.concatenate([seg[..., n_fft - cp_len:], seg], axis=-1)
 
 
 # ---------------------------------------------------------- pins: brute-force ML

@@ -488,3 +488,77 @@ def test_torch_cascade_synthesis_matches_frames_and_oracle_theta_grad():
     ref = O.cascaded_theta_grad(gx, sh, fr.extra["theta"], fr.extra["G"], fr.extra["F"],
                                 fr.extra["amp"], fr.symbols, fr.pilots)
     np.testing.assert_allclose(th.grad.numpy(), ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------- downlink
+@pytest.mark.parametrize("q", [2, 4, 6])
+def test_modulate_labels_generator_and_noiseless_round_trip(q):
+    """modulate_stage puts each label on its constellation point, agrees with
+    the generator's independent mapping, and noiseless max-log demapping of
+    its output returns the bits."""
+    rng = np.random.default_rng([7, q])
+    bits = rng.integers(0, 2, (3, 5, 11, q))
+    s = O.modulate_stage(bits, q)
+    assert np.allclose(s, synth.qam_map(bits, q), atol=1e-15, rtol=0)
+    pts, lab = O.constellation(q)
+    assert np.array_equal(O.modulate_stage(lab, q), pts)
+    llr = O.demod_stage(s.reshape(3, 55), np.ones((3, 55)), q)
+    assert np.array_equal(O.hard_bits(llr).reshape(bits.shape), bits)
+
+
+def _well_conditioned(rng, M, K, n_sc):
+    return (rng.standard_normal((M, K, n_sc)) + 1j * rng.standard_normal((M, K, n_sc))) / math.sqrt(2)
+
+
+@pytest.mark.parametrize("det", [O.ZF, O.MMSE])
+def test_precoder_matches_explicit_inverse_and_zf_loopback(det):
+    """X = H (H^H H [+ N0 I])^-1 S, checked against numpy's inverse of A
+    (a different method); for ZF the downlink channel H^H returns S."""
+    rng = np.random.default_rng(11)
+    M, K, D, n_sc, n0 = 8, 4, 3, 6, 0.7
+    H = _well_conditioned(rng, M, K, n_sc)
+    S = rng.standard_normal((K, D, n_sc)) + 1j * rng.standard_normal((K, D, n_sc))
+    out = O.precode_stage(H, S, n0, det)
+    assert not out["flags"].any()
+    for i in range(n_sc):
+        A = H[:, :, i].conj().T @ H[:, :, i] + (n0 * np.eye(K) if det == O.MMSE else 0)
+        ref = H[:, :, i] @ np.linalg.inv(A) @ S[:, :, i]
+        assert np.allclose(out["x"][:, :, i], ref, rtol=1e-12, atol=1e-12)
+        if det == O.ZF:
+            assert np.allclose(H[:, :, i].conj().T @ out["x"][:, :, i], S[:, :, i], rtol=1e-12, atol=1e-12)
+
+
+def test_precoder_single_user_closed_form():
+    """K = 1: x = h s / |h|^2 (maximum-ratio direction, unit gain back)."""
+    rng = np.random.default_rng(12)
+    h = rng.standard_normal((5, 1, 4)) + 1j * rng.standard_normal((5, 1, 4))
+    s = rng.standard_normal((1, 2, 4)) + 1j * rng.standard_normal((1, 2, 4))
+    x = O.precode_stage(h, s)["x"]
+    ref = h[:, 0, None, :] * s[0][None] / np.sum(np.abs(h[:, 0, :]) ** 2, axis=0)[None, None, :]
+    assert np.allclose(x, ref, rtol=1e-13, atol=1e-14)
+
+
+def test_precoder_breakdown_and_nonfinite():
+    rng = np.random.default_rng(13)
+    H = _well_conditioned(rng, 6, 3, 3)
+    H[:, 2, 1] = H[:, 0, 1]                         # rank deficient on subcarrier 1
+    H[4, 1, 2] = np.nan                             # non-finite on subcarrier 2
+    out = O.precode_stage(H, np.ones((3, 2, 3), dtype=np.complex128))
+    assert out["flags"][0] == 0
+    assert out["flags"][1] == O.FLAG_BREAKDOWN and out["flags"][2] == O.FLAG_NONFINITE
+    assert not out["x"][:, :, 1:].any()
+
+
+@pytest.mark.parametrize("N,n_sc,cp", [(8, 5, 2), (16, 16, 0), (64, 37, 9)])
+def test_ifft_stage_definition_cp_and_inverse(N, n_sc, cp):
+    """Term by term e^{+j 2 pi bin(i) n / N}; the prefix is the tail; and the
+    forward stage undoes it up to the factor N."""
+    rng = np.random.default_rng([14, N])
+    X = rng.standard_normal((2, n_sc)) + 1j * rng.standard_normal((2, n_sc))
+    x = O.ifft_stage(X, N, n_sc, cp)
+    bins = O.used_bins(N, n_sc)
+    for n in range(N):
+        ref = sum(X[:, i] * np.exp(2j * math.pi * bins[i] * n / N) for i in range(n_sc))
+        assert np.allclose(x[:, cp + n], ref, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(x[:, :cp], x[:, N:N + cp])
+    assert np.allclose(O.fft_stage(x, N, n_sc, cp), N * X, rtol=1e-12, atol=1e-11)
