@@ -167,6 +167,45 @@ rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames,
 rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames,
                          const void* xt, const float* nu, float* llr, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Downlink (the transmit direction: the preamble's `modul`, `precode` and
+ * `ifft` macros; the survey's first stage beyond the uplink path).
+ *
+ * rxphy_modulate: Gray square-QAM mapping, the inverse of rxphy_demod's
+ * labelling: bits b0 .. b_{Q-1} of each point (one byte per bit, b0 first,
+ * any non-zero byte is a one) -> the unit-energy point with that label.
+ *   bits : u8  [F][K][n_sym-1][n_sc][qam_bits]
+ *   sym  : c64 [F][K][n_sym-1][n_sc] (written)                                 */
+rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const uint8_t* bits, void* sym,
+                            hipStream_t stream);
+
+/* rxphy_precode: zero-forcing precoding with the uplink estimate
+ * (reciprocity): for every subcarrier X = H A^-1 S, A = H^H H (detector ZF)
+ * or H^H H + N0 I (MMSE: the regularised precoder), H the LS estimate of
+ * rxphy_csi from symbol 0 of yf and the pilots, so that a downlink channel
+ * H^H delivers S for ZF.  No power normalisation.  Built for K = 16 (each
+ * 16-subcarrier tile is one pilot group, factored once: the records of the
+ * fused detector); other K return RXPHY_EUNSUPPORTED.  A subcarrier whose
+ * factorisation breaks down or whose estimate is not finite transmits zeros
+ * and is flagged (RXPHY_FLAG_BREAKDOWN / _NONFINITE).
+ *   yf     : c64 [F][M][n_sym][n_sc] (symbol 0 read)   pilots: c64 [F][n_sc]
+ *   sym    : c64 [F][K][n_sym-1][n_sc]
+ *   xf     : c64 [F][M][n_sym-1][n_sc] (written)
+ *   flags  : u8  [F][n_sc] (written; may be NULL)
+ *   ws     : rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_PRECODE,
+ *            RXPHY_FP32) bytes, 8-byte aligned                                 */
+rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
+                           const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* rxphy_ifft: inverse of rxphy_fft's used-bin transform, unscaled, with a
+ * cyclic prefix: row r of xf (n_sc used subcarriers) becomes
+ * x[r][cp_len + n] = sum_i xf[r][i] exp(+j 2 pi bin(i) n / N), n = 0..N-1,
+ * and x[r][0 .. cp_len-1] repeats its last cp_len samples; so rxphy_fft of
+ * the result returns N xf.  Rows are independent (frame->n_sym is not used).
+ *   xf : c64 [n_rows][n_sc]     x : c64 [n_rows][cp_len + n_fft] (written)    */
+rxphy_status rxphy_ifft(const rxphy_frame* frame, int64_t n_rows, const void* xf, void* x, hipStream_t stream);
+
 /* Intermediate results of the forward stages that rxphy_backward may reuse;
  * any member may be NULL, in which case it is recomputed into the workspace. */
 typedef struct {
@@ -194,12 +233,18 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames,
                             const float* dllr, void* dx, void* dh,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
-enum { RXPHY_WS_DETECT = 0, RXPHY_WS_BACKWARD = 1, RXPHY_WS_CSI_DETECT = 2, RXPHY_WS_CSI_DETECT_DEMOD = 3 };
+enum {
+  RXPHY_WS_DETECT = 0,
+  RXPHY_WS_BACKWARD = 1,
+  RXPHY_WS_CSI_DETECT = 2,
+  RXPHY_WS_CSI_DETECT_DEMOD = 3,
+  RXPHY_WS_PRECODE = 4
+};
 
 /* Workspace bytes needed by rxphy_detect (which = RXPHY_WS_DETECT),
- * rxphy_backward (RXPHY_WS_BACKWARD), rxphy_csi_detect (RXPHY_WS_CSI_DETECT)
- * or rxphy_csi_detect_demod (RXPHY_WS_CSI_DETECT_DEMOD); 0 if none or if the
- * shape is invalid.                                                          */
+ * rxphy_backward (RXPHY_WS_BACKWARD), rxphy_csi_detect (RXPHY_WS_CSI_DETECT),
+ * rxphy_csi_detect_demod (RXPHY_WS_CSI_DETECT_DEMOD) or rxphy_precode
+ * (RXPHY_WS_PRECODE); 0 if none or if the shape is invalid.                  */
 size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
                              rxphy_precision precision);
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librxphy.so")
 ZF, MMSE = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 FLAG_REFINED, FLAG_BREAKDOWN, FLAG_NONFINITE = 1, 2, 4
-WS_DETECT, WS_BACKWARD, WS_CSI_DETECT, WS_CSI_DETECT_DEMOD = 0, 1, 2, 3
+WS_DETECT, WS_BACKWARD, WS_CSI_DETECT, WS_CSI_DETECT_DEMOD, WS_PRECODE = 0, 1, 2, 3, 4
 
 
 class RxphyError(RuntimeError):
@@ -104,6 +104,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect_demod": [FR, I32, P, P, P, P, P, P, I32, F32, P, SZ, P],
+        "rxphy_modulate": [FR, I32, P, P, P],
+        "rxphy_precode": [FR, I32, P, P, P, P, P, P, SZ, P],
+        "rxphy_ifft": [FR, ctypes.c_int64, P, P, P],
         "rxphy_demod": [FR, I32, P, P, P, P],
         "rxphy_backward": [FR, I32, P, P, ctypes.POINTER(_Saved), P, P, P, P, SZ, P],
     }
@@ -275,6 +278,52 @@ def csi_detect_demod(fr: Frame, yf, pilots, precision: str = "fp32", cond_thresh
                                          _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
            "rxphy_csi_detect_demod")
     return llr, nu, flags, xt
+
+
+# ------------------------------------------------------------------ downlink
+def modulate(fr: Frame, bits, sym=None):
+    """bits u8 [F][K][D][n_sc][qam_bits] (0/1, b0 first) -> QAM points c64 [F][K][D][n_sc]."""
+    F = _nf(bits)
+    D = fr.n_data
+    _need(bits, "bits", (F, fr.K, D, fr.n_sc, fr.qam_bits), torch.uint8)
+    sym = _empty((F, fr.K, D, fr.n_sc), torch.complex64, bits) if sym is None else sym
+    _need(sym, "sym", (F, fr.K, D, fr.n_sc), torch.complex64)
+    _check(load().rxphy_modulate(ctypes.byref(fr.c()), F, _ptr(bits), _ptr(sym), _stream()), "rxphy_modulate")
+    return sym
+
+
+def precode(fr: Frame, yf, pilots, sym, xf=None, flags=None, ws=None):
+    """ZF (or regularised, for MMSE) precoding with the uplink estimate from
+    symbol 0 of yf and the pilots -> (xf c64 [F][M][D][n_sc], flags); 16 users."""
+    F = _nf(yf)
+    D = fr.n_data
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    _need(sym, "sym", (F, fr.K, D, fr.n_sc), torch.complex64)
+    xf = _empty((F, fr.M, D, fr.n_sc), torch.complex64, yf) if xf is None else xf
+    flags = _empty((F, fr.n_sc), torch.uint8, yf) if flags is None else flags
+    _need(xf, "xf", (F, fr.M, D, fr.n_sc), torch.complex64)
+    _need(flags, "flags", (F, fr.n_sc), torch.uint8)
+    need = workspace_bytes(fr, F, WS_PRECODE, "fp32")
+    if need and ws is None:
+        ws = _empty((need,), torch.uint8, yf)
+    _check(load().rxphy_precode(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots), _ptr(sym), _ptr(xf),
+                                _ptr(flags), _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+           "rxphy_precode")
+    return xf, flags
+
+
+def ifft(fr: Frame, xf, x=None):
+    """Rows of n_sc used subcarriers [..., n_sc] -> time rows [..., cp_len + n_fft]
+    (unscaled inverse of fft(), cyclic prefix = the last cp_len samples)."""
+    if xf.device.type != "cuda" or xf.dtype != torch.complex64 or not xf.is_contiguous() or xf.shape[-1] != fr.n_sc:
+        raise RxphyError("xf: need a contiguous complex64 device tensor [..., %d]" % fr.n_sc)
+    rows = xf.numel() // fr.n_sc
+    shape = tuple(xf.shape[:-1]) + (fr.cp_len + fr.n_fft,)
+    x = _empty(shape, torch.complex64, xf) if x is None else x
+    _need(x, "x", shape, torch.complex64)
+    _check(load().rxphy_ifft(ctypes.byref(fr.c()), rows, _ptr(xf), _ptr(x), _stream()), "rxphy_ifft")
+    return x
 
 
 def demod(fr: Frame, xt, nu, llr=None):

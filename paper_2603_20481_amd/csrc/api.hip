@@ -200,6 +200,46 @@ rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames, 
   return launch_demod(fr, n_frames, x, nu, llr, stream);
 }
 
+rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const uint8_t* bits, void* sym,
+                            hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(bits, "bits")) || (st = check_ptr(sym, "sym"))) return st;
+  const int64_t n = (int64_t)n_frames * frame->K * (frame->n_sym - 1) * frame->n_sc;
+  return launch_modulate(*frame, n, bits, (float2*)sym, stream);
+}
+
+rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
+                           const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (frame->K != 16)
+    return fail(RXPHY_EUNSUPPORTED, "precode: K = %d (the precoder is built for 16 users)", frame->K);
+  size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_PRECODE, RXPHY_FP32);
+  if (need && (!ws || ws_bytes < need))
+    return fail(RXPHY_EWORKSPACE, "precode needs %zu workspace bytes, got %zu", need, ws_bytes);
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(sym, "sym")) ||
+      (st = check_ptr(xf, "xf")))
+    return st;
+  return launch_precode(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
+                        (float2*)xf, flags, ws, stream);
+}
+
+rxphy_status rxphy_ifft(const rxphy_frame* frame, int64_t n_rows, const void* xf, void* x, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, 0);
+  if (st) return st;
+  if (n_rows < 0) return fail(RXPHY_EINVAL, "n_rows = %lld < 0", (long long)n_rows);
+  if (n_rows == 0) return RXPHY_OK;
+  if ((st = check_ptr(xf, "xf")) || (st = check_ptr(x, "x"))) return st;
+  return launch_ifft_rows(*frame, n_rows, (const float2*)xf, (float2*)x, stream);
+}
+
 rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames, const void* xt,
                          const float* nu, float* llr, hipStream_t stream) {
   clear_error();

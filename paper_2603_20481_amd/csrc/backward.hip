@@ -380,6 +380,7 @@ size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t
   if (which == RXPHY_WS_DETECT) return detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT) return csi_detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT_DEMOD) return csi_detect_demod_workspace_bytes(*frame, n_frames, precision);
+  if (which == RXPHY_WS_PRECODE) return frame->K == 16 ? group_workspace_bytes(*frame, n_frames) : 0;
   if (which == RXPHY_WS_BACKWARD) return layout(*frame, n_frames).total;
   return 0;
 }

@@ -43,6 +43,14 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
 rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
                                  float2* xt, float* nu, uint8_t* flags, float* llr, void* ws, hipStream_t s);
 size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf);
+// Downlink: ZF precoder of 16 users from the uplink pilots (factor records in
+// ws, as the fused detector's); QAM mapping; inverse transform with a prefix.
+rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                            const float2* sym, float2* xf, uint8_t* flags, void* ws, hipStream_t s);
+rxphy_status launch_modulate(const rxphy_frame& fr, int64_t n_points, const uint8_t* bits, float2* sym,
+                             hipStream_t s);
+rxphy_status launch_ifft_rows(const rxphy_frame& fr, int64_t n_rows, const float2* in, float2* out,
+                              hipStream_t s);
 // Workspace of rxphy_csi_detect (the group path's records, else as detect).
 size_t csi_detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec);
 // Workspace of rxphy_csi_detect_demod: as rxphy_csi_detect, plus x_tilde

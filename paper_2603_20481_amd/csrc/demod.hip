@@ -19,7 +19,39 @@ demod_kernel(const float2* __restrict__ xt, const float* __restrict__ nu, float*
   demod_column<Q>(xt + fu * D * n_sc + i, nu[fu * n_sc + i], llr + (fu * D * n_sc + i) * Q, D, n_sc);
 }
 
+// Downlink QAM mapping, one thread per point: bits [n][Q] (one byte each,
+// b0 first; any non-zero byte is a one) -> the Gray point with that label,
+// each axis from the same level table as the demapper.
+template <int Q>
+__global__ void __launch_bounds__(256)
+modulate_kernel(const uint8_t* __restrict__ bits, float2* __restrict__ sym, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  const uint8_t* b = bits + p * Q;
+  int ci = 0, cq = 0;                             // axis codes: b0 b2 b4 / b1 b3 b5, MSB first
+#pragma unroll
+  for (int t = 0; t < Q / 2; ++t) {
+    ci = 2 * ci + (b[2 * t] != 0);
+    cq = 2 * cq + (b[2 * t + 1] != 0);
+  }
+  sym[p] = make_float2(axis_level<Q>(ci), axis_level<Q>(cq));
+}
+
 }  // namespace
+
+rxphy_status launch_modulate(const rxphy_frame& fr, int64_t n_points, const uint8_t* bits, float2* sym,
+                             hipStream_t s) {
+  if (n_points == 0) return RXPHY_OK;
+  const int64_t blocks = (n_points + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(RXPHY_EUNSUPPORTED, "too many points (%lld)", (long long)n_points);
+  switch (fr.qam_bits) {
+    case 2: hipLaunchKernelGGL(modulate_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, bits, sym, n_points); break;
+    case 4: hipLaunchKernelGGL(modulate_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, bits, sym, n_points); break;
+    case 6: hipLaunchKernelGGL(modulate_kernel<6>, dim3((unsigned)blocks), dim3(256), 0, s, bits, sym, n_points); break;
+    default: return fail(RXPHY_EINVAL, "qam_bits = %d", fr.qam_bits);
+  }
+  return launch_status("modulate kernel");
+}
 
 rxphy_status launch_demod(const rxphy_frame& fr, int32_t nf, const float2* xt, const float* nu,
                           float* llr, hipStream_t s) {

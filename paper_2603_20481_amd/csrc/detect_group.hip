@@ -414,7 +414,144 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   }
 }
 
+// ------------------------------------------------------------------ precoder
+// Downlink zero-forcing precoding with the uplink estimate (reciprocity):
+// per tile X = H A^-1 S for the 16 users' symbols S [F][16][D][n_sc], i.e.
+// W = A^-1 S from the factor record (step r of the product takes users
+// 4 kq + r of S, which this lane loads, against B[u][4 kq + r]), then
+// X = H W for each block of 16 antennas (step r takes H[16 b + u][4 kq + r]
+// from LDS against W[4 kq + r][u], which this lane holds); both with three
+// real products per complex one.  A tile whose factorisation broke down, or
+// whose channel is not finite, transmits nothing (X = 0) and is flagged.
+// One workgroup per (tile, frame); wave w owns the symbols d = w + 4 j.
+__global__ void __launch_bounds__(256)
+precode_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil,
+                     const GroupRec* __restrict__ rec, const float2* __restrict__ sym, float2* __restrict__ xf,
+                     uint8_t* __restrict__ flags, int M, int S, int n_sc) {
+  __shared__ float2 hs[64 * 16];                // H of the tile: [antenna][user]
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int u = l & 15, kq = l >> 4;
+  const int D = S - 1;
+  const int64_t f = blockIdx.y;
+  const int tt = blockIdx.x;
+  const int i0 = tt * 16;
+  const int g = min(tt, n_sc / 16 - 1);
+  const int nj = D > w ? (D - w + 3) >> 2 : 0;
+
+  const GroupRec* R = rec + (f * gridDim.x + tt);
+  const __amdgpu_buffer_rsrc_t rr = rsrc(R, (uint32_t)sizeof(GroupRec));
+  float2 brow[4];
+  {
+    const uint32_t o = opaque((uint32_t)(u * 16 + 4 * kq) * 8u);
+    const float4v b01 = __builtin_bit_cast(float4v, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)o, 0, 0));
+    const float4v b23 = __builtin_bit_cast(float4v, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)(o + 16u), 0, 0));
+    brow[0] = make_float2(b01.x, b01.y);
+    brow[1] = make_float2(b01.z, b01.w);
+    brow[2] = make_float2(b23.x, b23.y);
+    brow[3] = make_float2(b23.z, b23.w);
+  }
+  const float2 okh = ldg2(rr, opaque(2048u + 64u));
+  const __amdgpu_buffer_rsrc_t yr = rsrc(Yf + f * M * S * n_sc, (uint32_t)M * S * n_sc * 8u);
+  const uint32_t ant = (uint32_t)S * n_sc * 32u;
+  float2 hv[4], pv;
+  {
+    const int q = g * 16 + u;
+    uint32_t row = opaque((uint32_t)((16 * w + kq) * S * n_sc + q) * 8u);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      hv[a] = ldg2(yr, row);
+      row = opaque(row + ant);
+    }
+    pv = ldg2(rsrc(pil + f * n_sc, (uint32_t)n_sc * 8u), opaque((uint32_t)q * 8u));
+  }
+  // S[4 kq + r][d][i0 + u] for the wave's symbols (absent ones read zero)
+  float2 sv[4][4];
+  {
+    const __amdgpu_buffer_rsrc_t sr = rsrc(sym + f * 16 * D * n_sc, (uint32_t)16 * D * n_sc * 8u);
+    const uint32_t lane = i0 + u < n_sc ? (uint32_t)((4 * kq * D + w) * n_sc + i0 + u) * 8u : OOB;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t row = opaque(j < nj ? lane + (uint32_t)j * 4u * n_sc * 8u : OOB);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sv[j][r] = ldg2(sr, row);
+        row = opaque(row + (uint32_t)D * n_sc * 8u);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int m = 16 * w + 4 * a + kq;
+    hs[m * 16 + u] = m < M ? ls_estimate(hv[a], pv) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+
+  const bool hb = __builtin_bit_cast(int, okh.y) != 0;
+  const bool ok = __builtin_bit_cast(int, okh.x) != 0;
+  const bool erase = hb || !ok;
+  const int i = i0 + u;
+  float2* xo = xf + f * M * D * n_sc;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j >= nj) break;
+    const int d = w + 4 * j;
+    // W = A^-1 S
+    f32x4 wk = {0.f, 0.f, 0.f, 0.f}, wr = wk, wi = wk;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float2 b = brow[r], sr2 = sv[j][r];
+      wk = mfma(b.x + b.y, sr2.x, wk);
+      wr = mfma(b.y, sr2.x + sr2.y, wr);
+      wi = mfma(b.x, sr2.y - sr2.x, wi);
+    }
+    const f32x4 Wr = wk - wr, Wi = wk + wi;
+    // X = H W, 16 antennas at a time
+#pragma unroll
+    for (int bl = 0; bl < 4; ++bl) {
+      if (16 * bl >= M) break;
+      f32x4 xk = {0.f, 0.f, 0.f, 0.f}, xr = xk, xi = xk;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float2 h = hs[(16 * bl + u) * 16 + 4 * kq + r];
+        xk = mfma(h.x + h.y, Wr[r], xk);
+        xr = mfma(h.y, Wr[r] + Wi[r], xr);
+        xi = mfma(h.x, Wi[r] - Wr[r], xi);
+      }
+      if (i < n_sc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = 16 * bl + 4 * kq + r;
+          if (m < M)
+            xo[((int64_t)m * D + d) * n_sc + i] =
+                erase ? make_float2(0.f, 0.f) : make_float2(xk[r] - xr[r], xk[r] + xi[r]);
+        }
+      }
+    }
+  }
+  if (w == 0 && kq == 0 && i < n_sc && flags)
+    flags[f * n_sc + i] = hb ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
+}
+
 }  // namespace
+
+rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                            const float2* sym, float2* xf, uint8_t* flags, void* ws, hipStream_t s) {
+  if (nf == 0) return RXPHY_OK;
+  if (fr.K != 16) return fail(RXPHY_EUNSUPPORTED, "precode: K = %d (the precoder is built for 16 users)", fr.K);
+  if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
+  if (!ws || ((uintptr_t)ws & 7u)) return fail(RXPHY_EWORKSPACE, "precode workspace must be 8-byte aligned");
+  const int nt = (fr.n_sc + 15) / 16;
+  const int64_t T = (int64_t)nf * nt;
+  GroupRec* rec = (GroupRec*)ws;
+  hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s, yf,
+                     pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  rxphy_status st = launch_status("group factor kernel");
+  if (st) return st;
+  hipLaunchKernelGGL(precode_group_kernel, dim3(nt, nf), dim3(256), 0, s, yf, pil, rec, sym, xf, flags, fr.M,
+                     fr.n_sym, fr.n_sc);
+  return launch_status("precode kernel");
+}
 
 size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf) {
   return (size_t)nf * ((fr.n_sc + 15) / 16) * sizeof(GroupRec);

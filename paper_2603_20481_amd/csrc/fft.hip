@@ -13,36 +13,37 @@ constexpr int PER_WG = 8;
 template <int N, bool INV>
 __global__ void __launch_bounds__(WG)
 fft_kernel(const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
-           int64_t n_tr, int sym_len, int cp, int n_sc) {
+           int64_t n_tr, int sym_len, int cp, int n_sc, int cp_tail) {
   __shared__ float2 lds[Geom<N>::LDS];
   fft_tile<N, INV>(in, out, tw, n_tr, (int64_t)blockIdx.x * Geom<N>::TPW * PER_WG, PER_WG, sym_len,
-                   cp, n_sc, lds);
+                   cp, n_sc, lds, cp_tail != 0);
 }
 
 template <int N, bool INV>
 rxphy_status run(int64_t n_tr, const float2* in, float2* out, const float2* tw, int sym_len,
-                 int cp, int n_sc, hipStream_t s) {
+                 int cp, int n_sc, int cp_tail, hipStream_t s) {
   using G = Geom<N>;
   const int64_t per = (int64_t)G::TPW * PER_WG;
   int64_t blocks = (n_tr + per - 1) / per;
   if (blocks > 0x7fffffff) return fail(RXPHY_EUNSUPPORTED, "too many transforms (%lld)", (long long)n_tr);
+  if (blocks == 0) return RXPHY_OK;
   hipLaunchKernelGGL((fft_kernel<N, INV>), dim3((unsigned)blocks), dim3(WG), 0, s, in, out, tw,
-                     n_tr, sym_len, cp, n_sc);
+                     n_tr, sym_len, cp, n_sc, cp_tail);
   return launch_status("fft kernel");
 }
 
 }  // namespace
 
-rxphy_status launch_fft(const rxphy_frame& fr, int64_t n_tr, const float2* in, float2* out,
-                        bool inverse, hipStream_t s) {
+static rxphy_status dispatch(const rxphy_frame& fr, int64_t n_tr, const float2* in, float2* out, bool inverse,
+                             int cp_tail, hipStream_t s) {
   const float2* tw = nullptr;
   rxphy_status st = ensure_device_tables(&tw);
   if (st) return st;
   const int L = (int)sym_len(fr);
 #define RXPHY_FFT_CASE(NN)                                                                  \
   case NN:                                                                                  \
-    return inverse ? run<NN, true>(n_tr, in, out, tw, L, fr.cp_len, fr.n_sc, s)              \
-                   : run<NN, false>(n_tr, in, out, tw, L, fr.cp_len, fr.n_sc, s);
+    return inverse ? run<NN, true>(n_tr, in, out, tw, L, fr.cp_len, fr.n_sc, cp_tail, s)     \
+                   : run<NN, false>(n_tr, in, out, tw, L, fr.cp_len, fr.n_sc, cp_tail, s);
   switch (fr.n_fft) {
     RXPHY_FFT_CASE(512)
     RXPHY_FFT_CASE(1024)
@@ -51,6 +52,16 @@ rxphy_status launch_fft(const rxphy_frame& fr, int64_t n_tr, const float2* in, f
   }
 #undef RXPHY_FFT_CASE
   return fail(RXPHY_EUNSUPPORTED, "n_fft = %d", fr.n_fft);
+}
+
+rxphy_status launch_fft(const rxphy_frame& fr, int64_t n_tr, const float2* in, float2* out,
+                        bool inverse, hipStream_t s) {
+  return dispatch(fr, n_tr, in, out, inverse, 0, s);
+}
+
+rxphy_status launch_ifft_rows(const rxphy_frame& fr, int64_t n_rows, const float2* in, float2* out,
+                              hipStream_t s) {
+  return dispatch(fr, n_rows, in, out, true, 1, s);
 }
 
 }  // namespace rxphy

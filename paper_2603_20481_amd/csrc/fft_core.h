@@ -125,7 +125,8 @@ __device__ __forceinline__ void load_input(const float2* __restrict__ in, int64_
 template <int N, bool INV>
 __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* __restrict__ out,
                                          const float2* __restrict__ tw, int64_t n_tr, int64_t base,
-                                         int iters, int sym_len, int cp, int n_sc, float2* lds) {
+                                         int iters, int sym_len, int cp, int n_sc, float2* lds,
+                                         bool cp_tail = false) {
   using G = Geom<N>;
   constexpr int T = G::T;
   constexpr int VT = G::VT;
@@ -248,11 +249,16 @@ __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* 
           } else {
             float2* dst = out + tr * sym_len + cp;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[j + r * NS] = w[r];
+            for (int r = 0; r < R; ++r) {
+              const int n = j + r * NS;
+              dst[n] = w[r];
+              // transmitter: the cyclic prefix repeats the last cp samples
+              if (cp_tail && n >= N - cp) dst[n - N] = w[r];
+            }
           }
         }
       }
-    if (INV && active) {
+    if (INV && active && !cp_tail) {                // adjoint: the prefix carries no gradient
       float2* dst = out + tr * sym_len;
       for (int n = tid; n < cp; n += G::TT) dst[n] = make_float2(0.f, 0.f);
     }

@@ -1,0 +1,113 @@
+"""GPU parity of the downlink stages (QAM mapping, zero-forcing precoder with
+the uplink estimate, inverse transform with a cyclic prefix) against the FP64
+oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity_util import rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-downlink]", *a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("q", [2, 4, 6])
+def test_modulate_vs_oracle(rx, q):
+    sh = synth.Shape(8, 5, 512, 300, 6, 0, q)
+    fr = rx.Frame.of(sh, rx.ZF, 1.0)
+    rng = np.random.default_rng([21, q])
+    bits = rng.integers(0, 2, (2, sh.K, sh.n_data, sh.n_sc, q)).astype(np.uint8)
+    s = host(rx.modulate(fr, dev(bits)))
+    ref = O.modulate_stage(bits, q)
+    err = float(np.max(np.abs(s - ref)))
+    say("modulate", q, "max abs error", err)
+    # FP32 levels: a few units in the last place at magnitude <= 7/sqrt(42)
+    assert err < 4 * 2.0 ** -23
+
+
+@pytest.mark.parametrize("N,n_sc,cp", [(512, 300, 36), (2048, 1200, 0), (4096, 3276, 288), (1024, 601, 7)])
+def test_ifft_vs_oracle_prefix_and_round_trip(rx, N, n_sc, cp):
+    sh = synth.Shape(4, 2, N, n_sc, 3, cp, 2)
+    fr = rx.Frame.of(sh, rx.ZF, 1.0)
+    rng = np.random.default_rng([22, N])
+    X = (rng.standard_normal((2, 4, 3, n_sc)) + 1j * rng.standard_normal((2, 4, 3, n_sc))).astype(np.complex64)
+    x = rx.ifft(fr, dev(X))
+    xh = host(x)
+    ref = O.ifft_stage(X, N, n_sc, cp)
+    e = rel_rms(xh, ref)
+    say("ifft", N, n_sc, cp, "rel_rms", e)
+    assert e < 2e-6
+    assert np.array_equal(xh[..., :cp], xh[..., N:N + cp])          # prefix = tail, copied
+    back = host(rx.fft(fr, x.reshape(2, 4, 3, cp + N)))
+    e2 = rel_rms(back, N * X.astype(np.complex128))
+    say("  fft(ifft(X)) vs N X rel_rms", e2)
+    assert e2 < 2e-6
+
+
+PRECODE_CASES = [(synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.ZF),
+                 (synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.MMSE),
+                 (synth.Shape(21, 16, 512, 500, 17, 0, 2), O.ZF),
+                 (synth.Shape(16, 16, 512, 200, 6, 8, 6), O.MMSE),
+                 (synth.Shape(64, 16, 4096, 3276, 17, 0, 6), O.ZF)]
+
+
+@pytest.mark.parametrize("sh,det", PRECODE_CASES)
+def test_precode_vs_oracle_and_zf_loopback(rx, sh, det):
+    """X against the oracle's precoder on the GPU's own yf (relative RMS over
+    subcarriers with kappa_2(A) <= 1e3), identical flags (a zero pilot makes a
+    non-finite estimate), zeros where flagged, and for ZF H^H X = S."""
+    frs = [synth.make_frame(4, f, shape=sh) for f in range(2)]
+    x = dev(np.stack([f.x for f in frs]))
+    p = dev(np.stack([f.pilots for f in frs]))
+    p[1, 7] = 0
+    fr = rx.Frame.of(sh, det, 1.0)
+    yf = rx.fft(fr, x)
+    rng = np.random.default_rng([23, sh.M, sh.n_sc])
+    bits = rng.integers(0, 2, (2, sh.K, sh.n_data, sh.n_sc, sh.qam_bits)).astype(np.uint8)
+    s = rx.modulate(fr, dev(bits))
+    xf, fl = rx.precode(fr, yf, p, s)
+    torch.cuda.synchronize()
+    yh, ph, sh_, xh, flh = host(yf), host(p), host(s), host(xf), host(fl)
+    for f in range(2):
+        H = O.csi_stage(yh[f][:, 0, :], ph[f], sh.K)
+        ref = O.precode_stage(H, sh_[f], 1.0, det)
+        A = O.regularised_gram(np.moveaxis(np.where(np.isfinite(H), H, 0), -1, 0), 1.0, det)
+        ev = np.linalg.eigvalsh(A)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            kap = ev[:, -1] / ev[:, 0]
+        good = (kap <= 1e3) & (ref["flags"] == 0)
+        assert np.array_equal(flh[f], ref["flags"])
+        assert not xh[f][..., ref["flags"] != 0].any()
+        e = rel_rms(xh[f][..., good], ref["x"][..., good])
+        msg = ["frame", f, "rel_rms", e, "subcarriers", int(good.sum()), "flagged", int((ref["flags"] != 0).sum())]
+        assert e < 1e-4
+        if det == O.ZF:
+            back = np.einsum("mki,mdi->kdi", np.conj(H[..., good]), xh[f][..., good].astype(np.complex128))
+            el = rel_rms(back, sh_[f][..., good])
+            msg += ["loopback rel_rms", el]
+            assert el < 1e-4
+        say("precode", sh, "ZF" if det == O.ZF else "MMSE", *msg)
+
+
+def test_precode_is_built_for_sixteen_users(rx):
+    sh = synth.Shape(8, 4, 512, 300, 6, 0, 2)
+    fr = rx.Frame.of(sh, rx.ZF, 1.0)
+    yf = torch.zeros((1, 8, 6, 300), dtype=torch.complex64, device="cuda")
+    p = torch.ones((1, 300), dtype=torch.complex64, device="cuda")
+    s = torch.zeros((1, 4, 5, 300), dtype=torch.complex64, device="cuda")
+    with pytest.raises(rx.RxphyError):
+        rx.precode(fr, yf, p, s)
