@@ -18,7 +18,9 @@ demod as its own call; MMSE; the BF16 / FP16 detector with FP64 refinement on
 the 64x16 N_FFT 4096 64-QAM correlated workload (and plain FP32 there); 256
 uneven frames in one persistent launch replayed from a hipGraph, with
 autotuned and default item sizes and against a loop of per-frame calls; and
-forward + adjoint on the 64x8 cascaded-channel workload.
+forward + adjoint on the 64x8 cascaded-channel workload; and the downlink
+(QAM mapping, ZF precoder from the uplink estimate, inverse transform with
+prefix) over the headline frames.
 
 Before the W warm-up steps the headline runs untimed for --settle-s seconds
 (0.5 s by default; the count is reported as settle_steps): the first few
@@ -210,6 +212,67 @@ def form_summary(shape, F, ms, per, extra=None):
     return out
 
 
+def downlink_bytes(s):
+    """Compulsory HBM bytes of each downlink call for one frame (bits are one
+    byte each; precode reads symbol 0 of yf and the pilots, never stores H)."""
+    M, K, N, n_sc, cp, Q = s.M, s.K, s.n_fft, s.n_sc, s.cp_len, s.qam_bits
+    D = s.n_sym - 1
+    return {"modulate": K * D * n_sc * (Q + 8),
+            "precode": M * n_sc * 8 + n_sc * 8 + K * D * n_sc * 8 + M * D * n_sc * 8 + n_sc,
+            "ifft": M * D * n_sc * 8 + M * D * (cp + N) * 8}
+
+
+def run_downlink(rx, torch, chain, args):
+    """Modulate -> precode -> inverse transform over the headline frames, the
+    precoder built from the uplink estimate of the same frames' yf."""
+    shape, F = chain.shape, chain.F
+    D = shape.n_data
+    fr = rx.Frame.of(shape, rx.ZF, 1.0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    bits = torch.randint(0, 2, (F, shape.K, D, shape.n_sc, shape.qam_bits), generator=g,
+                         device="cuda", dtype=torch.uint8)
+    rx.fft(fr, chain.x, chain.yf)
+    sym = rx.modulate(fr, bits)
+    xf, fl = rx.precode(fr, chain.yf, chain.p, sym)
+    x = rx.ifft(fr, xf)
+    ws = torch.empty((rx.workspace_bytes(fr, F, rx.WS_PRECODE, "fp32"),), dtype=torch.uint8, device="cuda")
+    names = ("modulate", "precode", "ifft")
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        rx.modulate(fr, bits, sym)
+        if ev: ev[1].record()
+        rx.precode(fr, chain.yf, chain.p, sym, xf, fl, ws)
+        if ev: ev[2].record()
+        rx.ifft(fr, xf, x)
+        if ev: ev[3].record()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.form_steps)]
+    for ev in evs:
+        step(ev)
+    torch.cuda.synchronize()
+    per = {n: sum(ev[j].elapsed_time(ev[j + 1]) for ev in evs) / len(evs) for j, n in enumerate(names)}
+    ms = sum(per.values())
+    db = downlink_bytes(shape)
+    flagged = int(fl.ne(0).sum().item())
+    out = {"value": F * shape.detections / (ms * 1e-3), "unit": "subcarrier-precodings/s",
+           "ms_per_step": round(ms, 4), "frames": F,
+           "stages": {n: {"us": round(per[n] * 1e3, 2),
+                          "GBps": round(db[n] * F / (per[n] * 1e-3) / 1e9, 1),
+                          "bytes_per_launch": db[n] * F} for n in names},
+           "hbm_frac": round(sum(db.values()) * F / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "flagged_subcarriers": flagged,
+           "workload": "headline frames (64x16, N_FFT 2048, 1200 subcarriers, 13 data symbols, "
+                       "16-QAM): random bits -> QAM -> ZF precoder from the uplink LS estimate "
+                       "-> unscaled inverse transform with prefix, FP32"}
+    del bits, sym, xf, fl, x, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(rx, torch, args):
     """256 uneven frames: one persistent launch, replayed from a hipGraph."""
     from paper_2603_20481_amd.autotune import Tuner
@@ -353,7 +416,7 @@ def main():
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
     ap.add_argument("--bwd-frames", type=int, default=50)
-    ap.add_argument("--forms", default="staged,mmse,mixed,batched,fwd_bwd",
+    ap.add_argument("--forms", default="staged,mmse,downlink,mixed,batched,fwd_bwd",
                     help="comma list of extra forms to time ('' for the headline only)")
     ap.add_argument("--tile-cache", default=None)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -439,6 +502,9 @@ def main():
         ms, per = chain.time(frm, "fp32", args.form_steps, 1, mode="full")
         out["forms"]["mmse_fp32"] = form_summary(shape, F, ms, per, {"workload": "as the headline, MMSE"})
         print("[bench] mmse done", file=sys.stderr, flush=True)
+    if "downlink" in forms:
+        out["forms"]["downlink_zf_fp32"] = run_downlink(rx, torch, chain, args)
+        print("[bench] downlink done", file=sys.stderr, flush=True)
     del chain
     torch.cuda.empty_cache()
     if "mixed" in forms:

@@ -39,6 +39,31 @@ def test_modulate_vs_oracle(rx, q):
     assert err < 4 * 2.0 ** -23
 
 
+@pytest.mark.parametrize("q", [2, 4, 6])
+@pytest.mark.parametrize("boff,soff", [(0, 0), (1, 0), (0, 1), (2, 3)])
+def test_modulate_ragged_and_misaligned(rx, q, boff, soff):
+    """A point count that is not a multiple of four (the ragged tail) and bits
+    or symbols that start off their word / 16-byte boundary (the byte path)
+    give the same points as the oracle."""
+    sh = synth.Shape(4, 3, 512, 301, 2, 0, q)
+    fr = rx.Frame.of(sh, rx.ZF, 1.0)
+    rng = np.random.default_rng([23, q, boff, soff])
+    bits = rng.integers(0, 2, (1, sh.K, sh.n_data, sh.n_sc, q)).astype(np.uint8)
+    bits[0, 0, 0, :5] *= 7                                   # non-zero bytes other than 1 are ones
+    n = bits.size
+    bbuf = torch.zeros(n + 8, dtype=torch.uint8, device="cuda")
+    bbuf[boff:boff + n] = dev(bits.reshape(-1))
+    sbuf = torch.full((sh.K * sh.n_sc + 8,), complex(9.0, 9.0), dtype=torch.complex64, device="cuda")
+    sym = sbuf[soff:soff + sh.K * sh.n_sc].view(1, sh.K, 1, sh.n_sc)
+    rx.modulate(fr, bbuf[boff:boff + n].view(bits.shape), sym)
+    ref = O.modulate_stage((bits != 0).astype(np.uint8), q)
+    err = float(np.max(np.abs(host(sym) - ref)))
+    say("modulate ragged", q, boff, soff, "points", sh.K * sh.n_sc, "max abs error", err)
+    assert err < 4 * 2.0 ** -23
+    rest = host(sbuf)
+    assert np.all(rest[:soff] == 9 + 9j) and np.all(rest[soff + sh.K * sh.n_sc:] == 9 + 9j)
+
+
 @pytest.mark.parametrize("N,n_sc,cp", [(512, 300, 36), (2048, 1200, 0), (4096, 3276, 288), (1024, 601, 7)])
 def test_ifft_vs_oracle_prefix_and_round_trip(rx, N, n_sc, cp):
     sh = synth.Shape(4, 2, N, n_sc, 3, cp, 2)
