@@ -20,7 +20,9 @@ uneven frames in one persistent launch replayed from a hipGraph, with
 autotuned and default item sizes and against a loop of per-frame calls; and
 forward + adjoint on the 64x8 cascaded-channel workload; and the downlink
 (QAM mapping, ZF precoder from the uplink estimate, inverse transform with
-prefix) over the headline frames.
+prefix) over the headline frames; and the real-time form: one task of C
+frames released per frame period into a ping-pong stream, with the p99
+latency against the period, for host-memory and device-resident samples.
 
 Before the W warm-up steps the headline runs untimed for --settle-s seconds
 (0.5 s by default; the count is reported as settle_steps): the first few
@@ -273,6 +275,86 @@ def run_downlink(rx, torch, chain, args):
     return out
 
 
+SCS_HZ = 15e3      # subcarrier spacing of the streaming form: f_s = N_FFT x 15 kHz
+
+
+def run_streaming(rx, torch, chain, args):
+    """Real-time form: one task (C frames of the headline shape) becomes
+    available every frame period P = n_sym (cp + N) / f_s; a producer thread
+    releases task k at t0 + k P into a ping-pong stream (2 slots) and the
+    runtime stamps its completion.  A configuration is real-time when at
+    least 99 % of tasks finish within P (nearest-rank p99 <= P)."""
+    shape, F = chain.shape, chain.F
+    fs = shape.n_fft * SCS_HZ
+    period_us = shape.n_sym * (shape.cp_len + shape.n_fft) / fs * 1e6
+    fr = rx.Frame.of(shape, rx.ZF, 1.0)
+    runs = []
+    for host_io, counts in ((True, (1, 2, 3, 4)), (False, (1, 25, 50, 100))):
+        for C in counts:
+            if C > F:
+                continue
+            st = rx.Stream(fr, C, depth=2, host_io=host_io)
+            outs = None
+            if host_io:
+                xh = chain.x[:C].cpu().numpy()
+                ph = chain.p[:C].cpu().numpy()
+                for slot in range(2):
+                    h = st.host(slot)
+                    h["x"][...] = xh
+                    h["pilots"][...] = ph
+            else:
+                outs = [(torch.empty((C, fr.K, fr.n_data, fr.n_sc, fr.qam_bits), device="cuda"),
+                         torch.empty((C, fr.K, fr.n_sc), device="cuda"),
+                         torch.empty((C, fr.n_sc), dtype=torch.uint8, device="cuda")) for _ in range(2)]
+                xs, ps = chain.x[:C], chain.p[:C]
+                torch.cuda.synchronize()
+
+            def produce(n):
+                t0 = rx.clock_ns() + 1_000_000
+                step = int(round(period_us * 1e3))
+                for k in range(n):
+                    t = t0 + k * step
+                    while rx.clock_ns() < t:
+                        pass
+                    slot = st.acquire()
+                    if host_io:
+                        st.submit(slot, t)
+                    else:
+                        st.submit(slot, t, xs, ps, *outs[slot])
+                st.drain()
+            produce(args.stream_warmup)
+            st.reset_latencies()
+            produce(args.stream_tasks)
+            lat = st.latencies()
+            st.close()
+            summ = rx.latency_summary(lat, period_us)
+            runs.append({"io": "host (PCIe in and out)" if host_io else "device-resident",
+                         "frames_per_task": C, "tasks": int(summ["count"]),
+                         "p50_us": round(summ["p50_us"], 1), "p99_us": round(summ["p99_us"], 1),
+                         "max_us": round(summ["max_us"], 1), "mean_us": round(summ["mean_us"], 1),
+                         "on_time": int(summ["on_time"]), "real_time": bool(summ["meets_99"]),
+                         "detections_per_s": C * shape.detections / (period_us * 1e-6)})
+            print("[bench] streaming %s C=%d p99 %.1f us (period %.1f)" %
+                  ("host" if host_io else "device", C, summ["p99_us"], period_us), file=sys.stderr, flush=True)
+            del st, outs
+    best = {}
+    for r in runs:
+        if r["real_time"]:
+            k = r["io"]
+            if k not in best or r["frames_per_task"] > best[k]["frames_per_task"]:
+                best[k] = {"frames_per_task": r["frames_per_task"], "detections_per_s": r["detections_per_s"],
+                           "p99_us": r["p99_us"]}
+    torch.cuda.empty_cache()
+    return {"period_us": round(period_us, 2), "sample_rate_msps": fs / 1e6, "depth": 2, "runs": runs,
+            "largest_real_time": best,
+            "workload": "tasks of C headline frames (64x16, N_FFT 2048, 1200 subcarriers, 14 symbols, "
+                        "16-QAM, ZF, FP32), one task released per frame period (14 symbols at 15 kHz "
+                        "subcarrier spacing, f_s = 30.72 MS/s); task = fft + fused csi/detect/demod, with "
+                        "the samples copied in from and the LLRs, noise variances and flags copied back "
+                        "to pinned host memory (host) or read and written in HBM (device-resident); "
+                        "latency = completion - release; real time = at least 99 % within the period"}
+
+
 def run_batched(rx, torch, args):
     """256 uneven frames: one persistent launch, replayed from a hipGraph."""
     from paper_2603_20481_amd.autotune import Tuner
@@ -416,8 +498,10 @@ def main():
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
     ap.add_argument("--bwd-frames", type=int, default=50)
-    ap.add_argument("--forms", default="staged,mmse,downlink,mixed,batched,fwd_bwd",
+    ap.add_argument("--forms", default="staged,mmse,streaming,downlink,mixed,batched,fwd_bwd",
                     help="comma list of extra forms to time ('' for the headline only)")
+    ap.add_argument("--stream-tasks", type=int, default=400)
+    ap.add_argument("--stream-warmup", type=int, default=20)
     ap.add_argument("--tile-cache", default=None)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -502,6 +586,9 @@ def main():
         ms, per = chain.time(frm, "fp32", args.form_steps, 1, mode="full")
         out["forms"]["mmse_fp32"] = form_summary(shape, F, ms, per, {"workload": "as the headline, MMSE"})
         print("[bench] mmse done", file=sys.stderr, flush=True)
+    if "streaming" in forms:
+        out["forms"]["streaming_fp32"] = run_streaming(rx, torch, chain, args)
+        print("[bench] streaming done", file=sys.stderr, flush=True)
     if "downlink" in forms:
         out["forms"]["downlink_zf_fp32"] = run_downlink(rx, torch, chain, args)
         print("[bench] downlink done", file=sys.stderr, flush=True)

@@ -337,6 +337,84 @@ rxphy_status rxphy_plan_replay(rxphy_plan* plan, hipStream_t stream);
 rxphy_status rxphy_plan_device_status(rxphy_plan* plan, uint32_t* status);
 void rxphy_plan_destroy(rxphy_plan* plan);
 
+/* ---------------------------------------------------------------------------
+ * Real-time streaming (Section III-B: a task must finish before the next one
+ * becomes available, for at least 99 % of tasks; Section IV-D: a ping-pong
+ * buffer between the arriving samples and their processing, whose depth sets
+ * the latency budget).  A stream holds `depth` slots (2 = ping-pong); each
+ * slot owns a HIP stream (default priority), a completion event and the
+ * device buffers of one task of n_frames frames.  A task is rxphy_fft
+ * followed by rxphy_csi_detect_demod (FP32) on its frames.
+ *
+ * Host I/O streams (host_io = 1) also own pinned host buffers per slot: the
+ * producer writes the task's samples and pilots there, submit copies them in,
+ * runs the task and copies llr, nu and flags back into the slot's pinned
+ * outputs.  Device-resident streams (host_io = 0) take the task's input and
+ * output device pointers at submit (samples already in HBM).
+ *
+ * The slots are handed out in turn: acquire waits until the next slot's
+ * previous task has completed (back-pressure), the producer fills it and
+ * submits it.  A completion thread owned by the stream polls the slots'
+ * events and records each task's latency = completion time - arrival time
+ * (steady clock, rxphy_clock_ns), in submission order.  The outputs of a host
+ * I/O slot stay valid until that slot is submitted again.  One producer
+ * thread per stream.
+ * ------------------------------------------------------------------------- */
+
+typedef struct rxphy_stream rxphy_stream;   /* opaque */
+
+/* Pinned host buffers of one slot of a host I/O stream (layouts as in the
+ * single-frame calls, F = n_frames). */
+typedef struct {
+  void* x;          /* c64 [F][M][n_sym][cp_len + n_fft]  input  */
+  void* pilots;     /* c64 [F][n_sc]                      input  */
+  float* llr;       /* f32 [F][K][n_sym-1][n_sc][qam_bits] output */
+  float* nu;        /* f32 [F][K][n_sc]                   output */
+  uint8_t* flags;   /* u8  [F][n_sc]                      output */
+} rxphy_stream_host;
+
+/* Latency summary.  Percentiles are nearest-rank: p-th = the ceil(p n / 100)-th
+ * smallest value, so p99_us <= bound_us exactly when at least 99 % of the
+ * tasks met the bound (meets_99 = 1). */
+typedef struct {
+  int64_t count;      /* tasks summarised                                 */
+  int64_t on_time;    /* tasks with latency <= bound_us                   */
+  int32_t meets_99;   /* 100 * on_time >= 99 * count (and count > 0)      */
+  double p50_us, p99_us, max_us, mean_us;
+} rxphy_latency_summary;
+
+/* Creates a stream on the current device: 1 <= n_frames <= 65535,
+ * 1 <= depth <= 8, host_io 0 or 1.  Arguments are validated before any HIP
+ * call; allocation failures return RXPHY_EHIP with nothing left allocated. */
+rxphy_status rxphy_stream_create(const rxphy_frame* frame, int32_t n_frames, int32_t depth, int32_t host_io,
+                                 rxphy_stream** stream);
+/* Pinned host buffers of `slot` (host I/O streams only). */
+rxphy_status rxphy_stream_host_buffers(rxphy_stream* stream, int32_t slot, rxphy_stream_host* host);
+/* Waits until the next slot in turn is free and hands it to the caller. */
+rxphy_status rxphy_stream_acquire(rxphy_stream* stream, int32_t* slot);
+/* Enqueues the task of an acquired slot.  arrival_ns: the time the task's
+ * samples became available (rxphy_clock_ns; 0 = now).  Device-resident
+ * streams pass x, pilots, llr and nu (flags may be NULL) as device pointers
+ * in the single-frame layouts; host I/O streams pass NULL for all five.  A
+ * rejected submit leaves the slot acquired. */
+rxphy_status rxphy_stream_submit(rxphy_stream* stream, int32_t slot, int64_t arrival_ns, const void* x,
+                                 const void* pilots, float* llr, float* nu, uint8_t* flags);
+/* Waits for every submitted task; returns RXPHY_EHIP if a task failed on
+ * the device. */
+rxphy_status rxphy_stream_drain(rxphy_stream* stream);
+/* Latencies (microseconds) of the submitted tasks in submission order, NaN
+ * for tasks not yet completed: copies min(cap, n) values, *n = tasks so far. */
+rxphy_status rxphy_stream_latencies(rxphy_stream* stream, double* lat_us, int64_t cap, int64_t* n);
+/* Forgets the recorded latencies (no task may be outstanding). */
+rxphy_status rxphy_stream_reset_latencies(rxphy_stream* stream);
+/* Drains, stops the completion thread and frees every buffer. */
+void rxphy_stream_destroy(rxphy_stream* stream);
+/* The steady clock the stream stamps completions with, in nanoseconds. */
+int64_t rxphy_clock_ns(void);
+/* Summary of n latencies against bound_us (host only; NaN entries are
+ * rejected with RXPHY_EINVAL; n = 0 gives a zero summary). */
+rxphy_status rxphy_latency_summarize(const double* lat_us, int64_t n, double bound_us, rxphy_latency_summary* out);
+
 /* Human-readable name of a status, and thread-local detail of the last
  * non-OK status returned on the calling thread (empty string if none). */
 const char* rxphy_status_string(rxphy_status status);

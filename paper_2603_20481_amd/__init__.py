@@ -11,6 +11,7 @@ import ctypes
 import dataclasses
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,6 +86,17 @@ class Frame:
                      shape.qam_bits, int(detector), float(n0))
 
 
+class _StreamHost(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("pilots", ctypes.c_void_p), ("llr", ctypes.c_void_p),
+                ("nu", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class _LatencySummary(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("on_time", ctypes.c_int64), ("meets_99", ctypes.c_int32),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -129,6 +141,27 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    ST = ctypes.c_void_p
+    stream_sigs = {
+        "rxphy_stream_create": [FR, I32, I32, I32, ctypes.POINTER(ST)],
+        "rxphy_stream_host_buffers": [ST, I32, ctypes.POINTER(_StreamHost)],
+        "rxphy_stream_acquire": [ST, ctypes.POINTER(I32)],
+        "rxphy_stream_submit": [ST, I32, ctypes.c_int64, P, P, P, P, P],
+        "rxphy_stream_drain": [ST],
+        "rxphy_stream_latencies": [ST, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)],
+        "rxphy_stream_reset_latencies": [ST],
+        "rxphy_latency_summarize": [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_double,
+                                    ctypes.POINTER(_LatencySummary)],
+    }
+    for name, args in stream_sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rxphy_stream_destroy.argtypes = [ST]
+    lib.rxphy_stream_destroy.restype = None
+    lib.rxphy_clock_ns.argtypes = []
+    lib.rxphy_clock_ns.restype = ctypes.c_int64
     lib.rxphy_plan_destroy.argtypes = [PL]
     lib.rxphy_plan_destroy.restype = None
     lib.rxphy_workspace_bytes.argtypes = [FR, I32, I32, I32]
@@ -506,3 +539,103 @@ class Plan:
         v = ctypes.c_uint32()
         _check(load().rxphy_plan_device_status(self._h, ctypes.byref(v)), "rxphy_plan_device_status")
         return int(v.value)
+
+
+# ------------------------------------------------------------------ streaming
+def clock_ns() -> int:
+    """The steady clock the streaming runtime stamps completions with."""
+    return int(load().rxphy_clock_ns())
+
+
+def latency_summary(lat_us, bound_us: float) -> dict:
+    """Nearest-rank p50 / p99 / max / mean of latencies (microseconds), the
+    count within bound_us, and whether at least 99 % met it."""
+    a = np.ascontiguousarray(np.asarray(lat_us, dtype=np.float64))
+    out = _LatencySummary()
+    _check(load().rxphy_latency_summarize(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size,
+                                          float(bound_us), ctypes.byref(out)), "rxphy_latency_summarize")
+    return {k: getattr(out, k) for k, _ in _LatencySummary._fields_}
+
+
+def _host_array(addr: int, shape, dtype):
+    n = int(np.prod(shape)) * np.dtype(dtype).itemsize
+    buf = (ctypes.c_uint8 * n).from_address(addr)
+    return np.frombuffer(buf, dtype=dtype).reshape(shape)
+
+
+class Stream:
+    """Real-time task stream (rxphy_stream_*): ``depth`` slots handed out in
+    turn, a task = fft + fused csi/detect/demod over ``n_frames`` frames.
+
+    host_io=True: ``host(slot)`` gives numpy views of the slot's pinned host
+    buffers (x, pilots in; llr, nu, flags out), valid until ``close()``.
+    host_io=False: ``submit`` takes device tensors for the task's inputs and
+    outputs; the task runs on the slot's own HIP stream, so the inputs must
+    already be complete (synchronise their producer first), and the outputs
+    are complete after ``drain()``."""
+
+    def __init__(self, fr: Frame, n_frames: int, depth: int = 2, host_io: bool = True):
+        lib = load()
+        self.fr, self.nf, self.depth, self.host_io = fr, int(n_frames), int(depth), bool(host_io)
+        h = ctypes.c_void_p()
+        _check(lib.rxphy_stream_create(ctypes.byref(fr.c()), self.nf, self.depth, int(self.host_io),
+                                       ctypes.byref(h)), "rxphy_stream_create")
+        self._h = h
+        self._keep = {}
+
+    def shapes(self):
+        fr, F = self.fr, self.nf
+        return {"x": ((F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft), np.complex64),
+                "pilots": ((F, fr.n_sc), np.complex64),
+                "llr": ((F, fr.K, fr.n_data, fr.n_sc, fr.qam_bits), np.float32),
+                "nu": ((F, fr.K, fr.n_sc), np.float32), "flags": ((F, fr.n_sc), np.uint8)}
+
+    def host(self, slot: int) -> dict:
+        hb = _StreamHost()
+        _check(load().rxphy_stream_host_buffers(self._h, int(slot), ctypes.byref(hb)),
+               "rxphy_stream_host_buffers")
+        return {k: _host_array(getattr(hb, k), shp, dt) for k, (shp, dt) in self.shapes().items()}
+
+    def acquire(self) -> int:
+        v = ctypes.c_int32()
+        _check(load().rxphy_stream_acquire(self._h, ctypes.byref(v)), "rxphy_stream_acquire")
+        return int(v.value)
+
+    def submit(self, slot: int, arrival_ns: int = 0, x=None, pilots=None, llr=None, nu=None, flags=None):
+        if not self.host_io:
+            shp = self.shapes()
+            for name, t, dt in (("x", x, torch.complex64), ("pilots", pilots, torch.complex64),
+                                ("llr", llr, torch.float32), ("nu", nu, torch.float32)):
+                if t is None:
+                    raise RxphyError("device-resident stream: %s is required" % name)
+                _need(t, name, shp[name][0], dt)
+            if flags is not None:
+                _need(flags, "flags", shp["flags"][0], torch.uint8)
+            self._keep[int(slot)] = (x, pilots, llr, nu, flags)
+        _check(load().rxphy_stream_submit(self._h, int(slot), int(arrival_ns), _ptr(x), _ptr(pilots),
+                                          _ptr(llr), _ptr(nu), _ptr(flags)), "rxphy_stream_submit")
+
+    def drain(self):
+        _check(load().rxphy_stream_drain(self._h), "rxphy_stream_drain")
+
+    def latencies(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        lib = load()
+        _check(lib.rxphy_stream_latencies(self._h, None, 0, ctypes.byref(n)), "rxphy_stream_latencies")
+        out = np.empty(n.value, dtype=np.float64)
+        _check(lib.rxphy_stream_latencies(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          out.size, ctypes.byref(n)), "rxphy_stream_latencies")
+        return out
+
+    def reset_latencies(self):
+        _check(load().rxphy_stream_reset_latencies(self._h), "rxphy_stream_reset_latencies")
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rxphy_stream_destroy(h)
+        self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        self.close()

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "librxphy.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "detect_group.hip", "demod.hip", "backward.hip", "batch.hip"]
+SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "detect_group.hip", "demod.hip", "backward.hip", "batch.hip",
+           "stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
@@ -18,7 +19,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # the same tile body then rounds the same way in every kernel that
          # inlines it (the batched kernel reproduces the per-stage kernels)
          "-ffp-contract=on",
-         "-Wall", "-Wno-unused-function"]
+         "-Wall", "-Wno-unused-function", "-pthread"]
 
 
 # Per-source extra flags.  The persistent batched kernel holds every stage body
@@ -45,7 +46,7 @@ def build(verbose: bool = False) -> str:
         if msg and verbose:
             print(msg, file=sys.stderr)
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [o for o, _ in results]
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-o", tmp] + [o for o, _ in results]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
