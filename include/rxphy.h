@@ -415,6 +415,74 @@ int64_t rxphy_clock_ns(void);
  * rejected with RXPHY_EINVAL; n = 0 gives a zero summary). */
 rxphy_status rxphy_latency_summarize(const double* lat_us, int64_t n, double bound_us, rxphy_latency_summary* out);
 
+/* ---------------------------------------------------------------------------
+ * Spectrum sensing (the paper's own pipeline, Sections III-A1 and IV-B):
+ * a capture of T consecutive non-overlapping F-sample segments becomes a TF
+ * plot of FFT magnitudes (row = segment, column c = bin (c - F/2) mod F, no
+ * normalisation); its column sums are the PSD, smoothed by a Savitzky-Golay
+ * filter (mirror-reflected edges); the lowest local minimum of the smoothed
+ * PSD (interior points no larger than both neighbours; the global minimum if
+ * there is none) is the noise floor N0 and theta_PSD = psd_factor * N0;
+ * columns whose PSD is below theta_PSD are pruned; each retained column is
+ * binarised at Otsu's threshold (the bin that maximises the between-class
+ * variance of a `bins`-bin histogram over the column's [min, max], ties to
+ * the lower bin, decided exactly in integers; a value's bin is
+ * min(bins-1, floor((v - min) * (bins / (max - min)))) in FP32); the mask
+ * then gets one 3x3 closing, one 3x3 opening and one 1x3 opening along
+ * frequency (all-ones elements, neighbours inside the plot only); its
+ * 4-connected components give one inclusive box (t0, f0, t1, f1) each,
+ * listed in raster order of each component's first pixel.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t n_fft;       /* F: plot width, 512, 1024, 2048 or 4096             */
+  int32_t n_rows;      /* T: segments per plot, 3 .. 4096                    */
+  int32_t sg_window;   /* Savitzky-Golay window: odd, 3 .. 63, <= F           */
+  int32_t sg_order;    /* polynomial order: 0 .. min(6, sg_window - 1)        */
+  float psd_factor;    /* theta_PSD = psd_factor * N0, > 0                    */
+  int32_t bins;        /* Otsu histogram bins, 2 .. 256                       */
+} rxphy_sense_config;
+
+/* Intermediate results, each optional (NULL = kept in the workspace). */
+typedef struct {
+  float* tf;           /* f32 [P][T][F] magnitudes                            */
+  float* psd;          /* f32 [P][F] column sums                              */
+  float* psd_smooth;   /* f32 [P][F]                                          */
+  float* floor;        /* f32 [P][2]: N0, theta_PSD                           */
+  int32_t* otsu_bin;   /* i32 [P][F]: the threshold bin; -1 for a pruned column
+                          or one whose values all fall into one bin          */
+  uint8_t* mask;       /* u8 [P][T][F] after binarisation (0 / 1)             */
+  uint8_t* mask_mo;    /* u8 [P][T][F] after the morphological operations    */
+} rxphy_sense_outputs;
+
+/* Workspace bytes of rxphy_sense for n_plots plots (0 if cfg is invalid). */
+size_t rxphy_sense_workspace_bytes(const rxphy_sense_config* cfg, int32_t n_plots);
+
+/* The whole pipeline over n_plots captures (1 .. 65535).
+ *   x        : c64 [P][T][F] samples (device)
+ *   out      : optional intermediates (may be NULL)
+ *   n_boxes  : i32 [P] number of components of each plot (device; may exceed
+ *              max_boxes, in which case only the first max_boxes are written)
+ *   boxes    : i32 [P][max_boxes][4] (t0, f0, t1, f1) (device)
+ *   ws       : rxphy_sense_workspace_bytes bytes, 256-byte aligned (device)
+ * Asynchronous on `stream`; no allocation, no synchronisation. */
+rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const void* x,
+                         const rxphy_sense_outputs* out, int32_t* n_boxes, int32_t* boxes, int32_t max_boxes,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Detection metrics of Section III-A on the host: the IoU matrix of ground
+ * truth boxes against detections (inclusive pixel boxes), N_t = ground
+ * truths whose best IoU exceeds theta_iou, N_f = detections whose best IoU
+ * is below it, P_d = N_t / N_gt and P_fa = N_f / N_d (NaN when the
+ * denominator is 0), mean_iou = mean over ground truths of their best IoU
+ * (0 when either list is empty).  iou may be NULL (else n_gt x n_det). */
+typedef struct {
+  int32_t n_t, n_f;
+  double p_d, p_fa, mean_iou;
+} rxphy_detection_metrics;
+rxphy_status rxphy_box_metrics(const int32_t* gt, int32_t n_gt, const int32_t* det, int32_t n_det,
+                               double theta_iou, double* iou, rxphy_detection_metrics* out);
+
 /* Human-readable name of a status, and thread-local detail of the last
  * non-OK status returned on the calling thread (empty string if none). */
 const char* rxphy_status_string(rxphy_status status);

@@ -86,6 +86,23 @@ class Frame:
                      shape.qam_bits, int(detector), float(n0))
 
 
+class _SenseConfig(ctypes.Structure):
+    _fields_ = [("n_fft", ctypes.c_int32), ("n_rows", ctypes.c_int32), ("sg_window", ctypes.c_int32),
+                ("sg_order", ctypes.c_int32), ("psd_factor", ctypes.c_float), ("bins", ctypes.c_int32)]
+
+
+_SENSE_OUT = ("tf", "psd", "psd_smooth", "floor", "otsu_bin", "mask", "mask_mo")
+
+
+class _SenseOutputs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in _SENSE_OUT]
+
+
+class _Metrics(ctypes.Structure):
+    _fields_ = [("n_t", ctypes.c_int32), ("n_f", ctypes.c_int32), ("p_d", ctypes.c_double),
+                ("p_fa", ctypes.c_double), ("mean_iou", ctypes.c_double)]
+
+
 class _StreamHost(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("pilots", ctypes.c_void_p), ("llr", ctypes.c_void_p),
                 ("nu", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
@@ -158,6 +175,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    SC = ctypes.POINTER(_SenseConfig)
+    lib.rxphy_sense_workspace_bytes.argtypes = [SC, I32]
+    lib.rxphy_sense_workspace_bytes.restype = SZ
+    lib.rxphy_sense.argtypes = [SC, I32, P, ctypes.POINTER(_SenseOutputs), P, P, I32, P, SZ, P]
+    lib.rxphy_sense.restype = ctypes.c_int
+    lib.rxphy_box_metrics.argtypes = [P, I32, P, I32, ctypes.c_double, P, ctypes.POINTER(_Metrics)]
+    lib.rxphy_box_metrics.restype = ctypes.c_int
     lib.rxphy_stream_destroy.argtypes = [ST]
     lib.rxphy_stream_destroy.restype = None
     lib.rxphy_clock_ns.argtypes = []
@@ -639,3 +663,73 @@ class Stream:
 
     def __del__(self):
         self.close()
+
+
+# ------------------------------------------------------------------- sensing
+@dataclasses.dataclass(frozen=True)
+class SenseConfig:
+    """Spectrum-sensing configuration (mirrors ``rxphy_sense_config``)."""
+    n_fft: int = 1024
+    n_rows: int = 2000
+    sg_window: int = 21
+    sg_order: int = 1
+    psd_factor: float = 1.1
+    bins: int = 256
+
+    def c(self) -> _SenseConfig:
+        return _SenseConfig(self.n_fft, self.n_rows, self.sg_window, self.sg_order, self.psd_factor, self.bins)
+
+
+def sense_workspace_bytes(cfg: SenseConfig, n_plots: int) -> int:
+    return int(load().rxphy_sense_workspace_bytes(ctypes.byref(cfg.c()), int(n_plots)))
+
+
+def sense(cfg: SenseConfig, x, max_boxes: int = 1024, intermediates: bool = False, ws=None, boxes=None,
+          n_boxes=None) -> dict:
+    """x c64 [P][T][F] -> dict(n_boxes i32 [P], boxes i32 [P][max_boxes][4]
+    (t0, f0, t1, f1); with intermediates: tf, psd, psd_smooth, floor,
+    otsu_bin, mask, mask_mo)."""
+    P = _nf(x)
+    T, F = cfg.n_rows, cfg.n_fft
+    _need(x, "x", (P, T, F), torch.complex64)
+    dev = x.device
+    out = {}
+    if intermediates:
+        out = {"tf": torch.empty((P, T, F), dtype=torch.float32, device=dev),
+               "psd": torch.empty((P, F), dtype=torch.float32, device=dev),
+               "psd_smooth": torch.empty((P, F), dtype=torch.float32, device=dev),
+               "floor": torch.empty((P, 2), dtype=torch.float32, device=dev),
+               "otsu_bin": torch.empty((P, F), dtype=torch.int32, device=dev),
+               "mask": torch.empty((P, T, F), dtype=torch.uint8, device=dev),
+               "mask_mo": torch.empty((P, T, F), dtype=torch.uint8, device=dev)}
+    o = _SenseOutputs(*[out[k].data_ptr() if k in out else None for k in _SENSE_OUT])
+    n_boxes = torch.empty((P,), dtype=torch.int32, device=dev) if n_boxes is None else n_boxes
+    _need(n_boxes, "n_boxes", (P,), torch.int32)
+    if boxes is None:
+        boxes = torch.empty((P, max(max_boxes, 0), 4), dtype=torch.int32, device=dev)
+    _need(boxes, "boxes", (P, max_boxes, 4), torch.int32)
+    need = sense_workspace_bytes(cfg, P)
+    if need == 0:
+        raise RxphyError("invalid sense config %s" % (cfg,))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty((need,), dtype=torch.uint8, device=dev)
+    _check(load().rxphy_sense(ctypes.byref(cfg.c()), P, _ptr(x), ctypes.byref(o), _ptr(n_boxes),
+                              _ptr(boxes) if max_boxes > 0 else None, int(max_boxes), _ptr(ws), ws.numel(),
+                              _stream()), "rxphy_sense")
+    out.update(n_boxes=n_boxes, boxes=boxes)
+    return out
+
+
+def box_metrics(gt, det, theta_iou: float, want_iou: bool = False) -> dict:
+    """Section III-A detection metrics of inclusive (t0, f0, t1, f1) boxes."""
+    g = np.ascontiguousarray(np.asarray(gt, dtype=np.int32).reshape(-1, 4))
+    d = np.ascontiguousarray(np.asarray(det, dtype=np.int32).reshape(-1, 4))
+    iou = np.zeros((len(g), len(d)), dtype=np.float64) if want_iou else None
+    m = _Metrics()
+    _check(load().rxphy_box_metrics(g.ctypes.data if len(g) else None, len(g), d.ctypes.data if len(d) else None,
+                                    len(d), float(theta_iou), iou.ctypes.data if want_iou and iou.size else None,
+                                    ctypes.byref(m)), "rxphy_box_metrics")
+    r = {k: getattr(m, k) for k, _ in _Metrics._fields_}
+    if want_iou:
+        r["iou"] = iou
+    return r

@@ -10,16 +10,16 @@ using namespace fftk;
 // Each workgroup runs PER_WG transforms per transform slot.
 constexpr int PER_WG = 8;
 
-template <int N, bool INV>
+template <int N, bool INV, bool MAG = false>
 __global__ void __launch_bounds__(WG)
 fft_kernel(const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
            int64_t n_tr, int sym_len, int cp, int n_sc, int cp_tail) {
   __shared__ float2 lds[Geom<N>::LDS];
-  fft_tile<N, INV>(in, out, tw, n_tr, (int64_t)blockIdx.x * Geom<N>::TPW * PER_WG, PER_WG, sym_len,
-                   cp, n_sc, lds, cp_tail != 0);
+  fft_tile<N, INV, MAG>(in, out, tw, n_tr, (int64_t)blockIdx.x * Geom<N>::TPW * PER_WG, PER_WG, sym_len,
+                        cp, n_sc, lds, cp_tail != 0);
 }
 
-template <int N, bool INV>
+template <int N, bool INV, bool MAG = false>
 rxphy_status run(int64_t n_tr, const float2* in, float2* out, const float2* tw, int sym_len,
                  int cp, int n_sc, int cp_tail, hipStream_t s) {
   using G = Geom<N>;
@@ -27,7 +27,7 @@ rxphy_status run(int64_t n_tr, const float2* in, float2* out, const float2* tw, 
   int64_t blocks = (n_tr + per - 1) / per;
   if (blocks > 0x7fffffff) return fail(RXPHY_EUNSUPPORTED, "too many transforms (%lld)", (long long)n_tr);
   if (blocks == 0) return RXPHY_OK;
-  hipLaunchKernelGGL((fft_kernel<N, INV>), dim3((unsigned)blocks), dim3(WG), 0, s, in, out, tw,
+  hipLaunchKernelGGL((fft_kernel<N, INV, MAG>), dim3((unsigned)blocks), dim3(WG), 0, s, in, out, tw,
                      n_tr, sym_len, cp, n_sc, cp_tail);
   return launch_status("fft kernel");
 }
@@ -57,6 +57,20 @@ static rxphy_status dispatch(const rxphy_frame& fr, int64_t n_tr, const float2* 
 rxphy_status launch_fft(const rxphy_frame& fr, int64_t n_tr, const float2* in, float2* out,
                         bool inverse, hipStream_t s) {
   return dispatch(fr, n_tr, in, out, inverse, 0, s);
+}
+
+rxphy_status launch_fft_mag(int n_fft, int64_t n_rows, const float2* in, float* out, hipStream_t s) {
+  const float2* tw = nullptr;
+  rxphy_status st = ensure_device_tables(&tw);
+  if (st) return st;
+  float2* o = reinterpret_cast<float2*>(out);
+  switch (n_fft) {
+    case 512: return run<512, false, true>(n_rows, in, o, tw, 512, 0, 512, 0, s);
+    case 1024: return run<1024, false, true>(n_rows, in, o, tw, 1024, 0, 1024, 0, s);
+    case 2048: return run<2048, false, true>(n_rows, in, o, tw, 2048, 0, 2048, 0, s);
+    case 4096: return run<4096, false, true>(n_rows, in, o, tw, 4096, 0, 4096, 0, s);
+  }
+  return fail(RXPHY_EUNSUPPORTED, "n_fft = %d", n_fft);
 }
 
 rxphy_status launch_ifft_rows(const rxphy_frame& fr, int64_t n_rows, const float2* in, float2* out,

@@ -122,7 +122,7 @@ __device__ __forceinline__ void load_input(const float2* __restrict__ in, int64_
 // skipped.  The twiddles a thread needs are the same for every transform, so
 // they are loaded into registers once.  `lds` holds Geom<N>::LDS
 // slots; the caller synchronises before reusing it.
-template <int N, bool INV>
+template <int N, bool INV, bool MAG = false>
 __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* __restrict__ out,
                                          const float2* __restrict__ tw, int64_t n_tr, int64_t base,
                                          int iters, int sym_len, int cp, int n_sc, float2* lds,
@@ -239,7 +239,15 @@ __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* 
         for (int r = 1; r < R; ++r) w[r] = twid<INV>(w[r], twl[q][b][r - 1]);
         dftR<R, INV>(w);
         if (active) {
-          if (!INV) {
+          if constexpr (MAG) {
+            // magnitudes of the used bins (a float row of n_sc per transform)
+            float* dst = reinterpret_cast<float*>(out) + tr * n_sc;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const int i = (j + r * NS + half) & (N - 1);
+              if (i < n_sc) dst[i] = sqrtf(w[r].x * w[r].x + w[r].y * w[r].y);
+            }
+          } else if (!INV) {
             float2* dst = out + tr * n_sc;
 #pragma unroll
             for (int r = 0; r < R; ++r) {

@@ -1,0 +1,629 @@
+// Spectrum-sensing pipeline (Section III-A1: TF plot of segment FFT
+// magnitudes; Section IV-B: PSD, Savitzky-Golay, noise floor, PSD pruning,
+// column Otsu, morphological operations, 4-connected components and boxes;
+// Section III-A: detection metrics on the host).
+//
+// Kernels, all batched over plots (grid y / z = plot):
+//   fft_kernel<F, false, MAG>  magnitudes of the centred bins (fft.hip)
+//   colstat_kernel   column sum (PSD), min and max; 64 columns per workgroup
+//   floor_kernel     Savitzky-Golay smoothing, lowest local minimum, theta
+//   otsu_kernel      per retained column: LDS histogram, exact integer Otsu,
+//                    mask written in a second pass over the column strip
+//   morph_kernel     64x64 tile + halo in LDS, the six erosions / dilations,
+//                    mask and the union-find labels written
+//   merge_kernel     lock-free union of 4-neighbours (smaller index wins)
+//   flatten_kernel   every label to its root; roots counted per 1024 pixels
+//   scan_kernel      per-plot exclusive scan of the counts; box records reset
+//   assign_kernel    each root gets its ordinal (raster order of roots)
+//   boxes_kernel     row runs of one component reduced per thread, then
+//                    atomic min / max into the component's box
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace rxphy {
+namespace {
+
+constexpr int SG_MAX = 63;
+constexpr int PIX_BLK = 1024;                  // pixels per flatten / assign workgroup
+
+struct SgCoef {
+  float c[SG_MAX];
+  int h;
+};
+
+__device__ __forceinline__ int ld_agent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ------------------------------------------------------------ column stats
+__global__ void __launch_bounds__(256)
+colstat_kernel(const float* __restrict__ tf, float* __restrict__ psd, float* __restrict__ lo,
+               float* __restrict__ hi, int T, int F) {
+  __shared__ float ss[4][64], smn[4][64], smx[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const int64_t p = blockIdx.y;
+  const float* col = tf + p * T * F + c;
+  float s = 0.f, mn = INFINITY, mx = -INFINITY;
+  for (int t = w; t < T; t += 4) {
+    const float v = col[(int64_t)t * F];
+    s += v;
+    mn = fminf(mn, v);
+    mx = fmaxf(mx, v);
+  }
+  ss[w][lane] = s;
+  smn[w][lane] = mn;
+  smx[w][lane] = mx;
+  __syncthreads();
+  if (w == 0) {
+    const float a = ((ss[0][lane] + ss[1][lane]) + ss[2][lane]) + ss[3][lane];
+    psd[p * F + c] = a;
+    lo[p * F + c] = fminf(fminf(smn[0][lane], smn[1][lane]), fminf(smn[2][lane], smn[3][lane]));
+    hi[p * F + c] = fmaxf(fmaxf(smx[0][lane], smx[1][lane]), fmaxf(smx[2][lane], smx[3][lane]));
+  }
+}
+
+// ------------------------------------------------------ noise floor, theta
+__global__ void __launch_bounds__(1024)
+floor_kernel(const float* __restrict__ psd, float* __restrict__ psd_s, float* __restrict__ flo, SgCoef sg,
+             float factor, int F) {
+  __shared__ float sp[4096], sm[4096];
+  __shared__ float red[2][16];
+  const int tid = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  for (int j = tid; j < F; j += 1024) sp[j] = psd[p * F + j];
+  __syncthreads();
+  const int h = sg.h;
+  for (int j = tid; j < F; j += 1024) {
+    float acc = 0.f;
+    for (int k = -h; k <= h; ++k) {
+      int q = j + k;
+      q = q < 0 ? -q : (q >= F ? 2 * (F - 1) - q : q);      // mirror about the end samples
+      acc += sg.c[k + h] * sp[q];
+    }
+    sm[j] = acc;
+    psd_s[p * F + j] = acc;
+  }
+  __syncthreads();
+  float best = INFINITY, all = INFINITY;                   // lowest local minimum, lowest value
+  for (int j = tid; j < F; j += 1024) {
+    const float v = sm[j];
+    all = fminf(all, v);
+    if (j > 0 && j < F - 1 && v <= sm[j - 1] && v <= sm[j + 1]) best = fminf(best, v);
+  }
+  best = wave_min(best);
+  all = wave_min(all);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = best;
+    red[1][tid >> 6] = all;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float b = INFINITY, a = INFINITY;
+    for (int i = 0; i < 16; ++i) {
+      b = fminf(b, red[0][i]);
+      a = fminf(a, red[1][i]);
+    }
+    const float n0 = b < INFINITY ? b : a;       // no interior local minimum: the lowest value
+    flo[2 * p] = n0;
+    flo[2 * p + 1] = factor * n0;
+  }
+}
+
+// ------------------------------------------------------------------ Otsu
+__device__ __forceinline__ int value_bin(float v, float lo, float scale, int bins) {
+  const int b = (int)((v - lo) * scale);         // truncation = floor for v >= lo
+  return b < 0 ? 0 : (b < bins - 1 ? b : bins - 1);
+}
+
+// The threshold bin k (class 0 = bins <= k) maximising
+// (N m0 - M w0)^2 / (w0 w1), ties to the smallest k, -1 if none; exact: the
+// square fits 64 bits for N <= 4096 and bins <= 256, the cross products 128.
+__device__ int otsu_bin(const uint32_t* h, int bins, int N) {
+  int64_t M = 0;
+  for (int i = 1; i < bins; ++i) M += (int64_t)i * h[i];
+  int best = -1;
+  uint64_t bnum = 0, bden = 1;
+  int64_t w0 = 0, m0 = 0;
+  for (int k = 0; k < bins - 1; ++k) {
+    w0 += h[k];
+    m0 += (int64_t)k * h[k];
+    const int64_t w1 = N - w0;
+    if (w0 == 0 || w1 == 0) continue;
+    const int64_t d = (int64_t)N * m0 - M * w0;
+    const uint64_t a = (uint64_t)(d < 0 ? -d : d);
+    const uint64_t num = a * a;
+    const uint64_t den = (uint64_t)(w0 * w1);
+    if (best < 0 || (unsigned __int128)num * bden > (unsigned __int128)bnum * den) {
+      best = k;
+      bnum = num;
+      bden = den;
+    }
+  }
+  return best;
+}
+
+__global__ void __launch_bounds__(256)
+otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const float* __restrict__ lo_,
+            const float* __restrict__ hi_, const float* __restrict__ flo, int32_t* __restrict__ kbin,
+            uint8_t* __restrict__ mask, int T, int F, int bins) {
+  __shared__ uint32_t hist[64 * 257];
+  __shared__ int kk[64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const int64_t p = blockIdx.y;
+  const int stride = bins + 1;                  // odd stride: the 64 columns hit different banks
+  for (int i = tid; i < 64 * stride; i += 256) hist[i] = 0u;
+  const bool keep = psd[p * F + c] >= flo[2 * p + 1];
+  const float lo = lo_[p * F + c], hi = hi_[p * F + c];
+  const bool spread = hi > lo;
+  const float scale = spread ? __fdiv_rn((float)bins, hi - lo) : 0.f;
+  const float* col = tf + p * T * F + c;
+  __syncthreads();
+  if (keep) {
+    uint32_t* hc = hist + lane * stride;
+    for (int t = w; t < T; t += 4) atomicAdd(hc + value_bin(col[(int64_t)t * F], lo, scale, bins), 1u);
+  }
+  __syncthreads();
+  if (w == 0) {
+    const int k = keep ? otsu_bin(hist + lane * stride, bins, T) : -1;
+    kk[lane] = k;
+    kbin[p * F + c] = k;
+  }
+  __syncthreads();
+  const int k = kk[lane];
+  uint8_t* mc = mask + p * T * F + c;
+  for (int t = w; t < T; t += 4)
+    mc[(int64_t)t * F] = (k >= 0 && value_bin(col[(int64_t)t * F], lo, scale, bins) > k) ? 1 : 0;
+}
+
+// ------------------------------------------------------------ morphology
+// A 64x64 core with a halo of 4 rows (four 3x3 operations) and 6 columns
+// (six operations 3 wide).  Pixels outside the plot hold 2 and are skipped by
+// both operations (dilation: max over in-plot 1s; erosion: min over in-plot
+// values).  Values near the region edge use clamped neighbours; the error
+// moves one pixel per operation and never reaches the core.
+constexpr int MR = 64 + 8, MC = 64 + 12;
+
+template <bool DIL, int DR>
+__device__ __forceinline__ void morph_op(const uint8_t* a, uint8_t* b) {
+  for (int idx = threadIdx.x; idx < MR * MC; idx += 256) {
+    const int r = idx / MC, c = idx - r * MC;
+    const uint8_t self = a[idx];
+    uint8_t o = self;
+    if (self != 2) {
+      bool hit = false;                          // dilation: a 1 nearby; erosion: a 0 nearby
+#pragma unroll
+      for (int i = -DR; i <= DR; ++i)
+#pragma unroll
+        for (int j = -1; j <= 1; ++j) {
+          const int rr = min(max(r + i, 0), MR - 1), cc = min(max(c + j, 0), MC - 1);
+          hit |= a[rr * MC + cc] == (DIL ? 1 : 0);
+        }
+      o = DIL ? (hit ? 1 : 0) : (hit ? 0 : 1);
+    }
+    b[idx] = o;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256)
+morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab, int T,
+             int F) {
+  __shared__ uint8_t A[MR * MC], B[MR * MC];
+  const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
+  const int64_t p = blockIdx.z;
+  const uint8_t* m = mask + p * T * F;
+  for (int idx = threadIdx.x; idx < MR * MC; idx += 256) {
+    const int r = idx / MC, c = idx - r * MC;
+    const int t = t0 - 4 + r, f = f0 - 6 + c;
+    A[idx] = (t >= 0 && t < T && f >= 0 && f < F) ? m[(int64_t)t * F + f] : 2;
+  }
+  __syncthreads();
+  morph_op<true, 1>(A, B);                       // closing 3x3
+  morph_op<false, 1>(B, A);
+  morph_op<false, 1>(A, B);                      // opening 3x3
+  morph_op<true, 1>(B, A);
+  morph_op<false, 0>(A, B);                      // opening 1x3 along frequency
+  morph_op<true, 0>(B, A);
+  uint8_t* o = out + p * T * F;
+  int32_t* L = lab + p * T * F;
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int r = idx >> 6, c = idx & 63;
+    const int t = t0 + r, f = f0 + c;
+    if (t < T) {
+      const uint8_t v = A[(r + 4) * MC + c + 6];
+      o[(int64_t)t * F + f] = v;
+      L[(int64_t)t * F + f] = v ? t * F + f : -1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ CCL
+__device__ __forceinline__ int find_root(const int* L, int x) {
+  int y = ld_agent(L + x);
+  while (y != x) {
+    x = y;
+    y = ld_agent(L + x);
+  }
+  return x;
+}
+
+// Links the sets of a and b: the larger root is pointed at the smaller one
+// with an atomic min; if that root gained another parent meanwhile, the
+// union continues from that parent.
+__device__ void unite(int* L, int a, int b) {
+  for (;;) {
+    a = find_root(L, a);
+    b = find_root(L, b);
+    if (a == b) return;
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin(L + b, a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+merge_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int T, int F) {
+  const int64_t p = blockIdx.y;
+  const int n = T * F;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const uint8_t* m = mask + p * n;
+  if (!m[q]) return;
+  int* L = lab + p * n;
+  const int f = q % F;
+  if (f > 0 && m[q - 1]) unite(L, q, q - 1);
+  if (q >= F && m[q - F]) unite(L, q, q - F);
+}
+
+__device__ __forceinline__ int block_count(int v, int* red) {
+  // sum of v over the 256 threads (every thread gets it)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+__global__ void __launch_bounds__(256)
+flatten_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int32_t* __restrict__ cnt, int T,
+               int F, int nblk) {
+  __shared__ int red[4];
+  const int64_t p = blockIdx.y;
+  const int n = T * F;
+  const uint8_t* m = mask + p * n;
+  int* L = lab + p * n;
+  int roots = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = blockIdx.x * PIX_BLK + threadIdx.x * 4 + i;
+    if (q < n && m[q]) {
+      const int r = find_root(L, q);
+      L[q] = r;
+      roots += r == q;
+    }
+  }
+  roots = block_count(roots, red);
+  if (threadIdx.x == 0) cnt[p * nblk + blockIdx.x] = roots;
+}
+
+__global__ void __launch_bounds__(1024)
+scan_kernel(const int32_t* __restrict__ cnt, int32_t* __restrict__ off, int32_t* __restrict__ n_boxes,
+            int32_t* __restrict__ boxes, int max_boxes, int nblk) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  const int b0 = tid * per, b1 = min(nblk, b0 + per);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += cnt[p * nblk + b];
+  part[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {          // inclusive Hillis-Steele scan
+    const int v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;
+  for (int b = b0; b < b1; ++b) {
+    off[p * nblk + b] = run;
+    run += cnt[p * nblk + b];
+  }
+  if (tid == 1023) n_boxes[p] = part[1023];
+  for (int i = tid; i < max_boxes; i += 1024) {
+    int32_t* bx = boxes + (p * max_boxes + i) * 4;
+    bx[0] = INT_MAX;
+    bx[1] = INT_MAX;
+    bx[2] = -1;
+    bx[3] = -1;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+assign_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, const int32_t* __restrict__ off,
+              int T, int F, int nblk) {
+  __shared__ int wsum[4];
+  const int64_t p = blockIdx.y;
+  const int n = T * F;
+  const uint8_t* m = mask + p * n;
+  int* L = lab + p * n;
+  bool root[4];
+  int mine = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = blockIdx.x * PIX_BLK + threadIdx.x * 4 + i;
+    root[i] = q < n && m[q] && L[q] == q;
+    mine += root[i];
+  }
+  // exclusive prefix of `mine` over the workgroup (thread order = raster order)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int base = off[p * nblk + blockIdx.x];
+  for (int i = 0; i < w; ++i) base += wsum[i];
+  int ord = base + inc - mine;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (root[i]) {
+      L[blockIdx.x * PIX_BLK + threadIdx.x * 4 + i] = -2 - ord;   // a root holds -2 - its ordinal
+      ++ord;
+    }
+  }
+}
+
+__device__ __forceinline__ void flush_run(int32_t* boxes, int max_boxes, int ord, int t, int fa, int fb) {
+  if (ord < 0 || ord >= max_boxes) return;
+  int32_t* bx = boxes + (int64_t)ord * 4;
+  atomicMin(bx + 0, t);
+  atomicMin(bx + 1, fa);
+  atomicMax(bx + 2, t);
+  atomicMax(bx + 3, fb);
+}
+
+__global__ void __launch_bounds__(256)
+boxes_kernel(const uint8_t* __restrict__ mask, const int32_t* __restrict__ lab, int32_t* __restrict__ boxes,
+             int max_boxes, int T, int F) {
+  const int64_t p = blockIdx.y;
+  const int segs = F / 32;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= T * segs) return;
+  const int t = g / segs, fs = (g - t * segs) * 32;
+  const int n = T * F;
+  const uint8_t* m = mask + p * n + (int64_t)t * F;
+  const int* L = lab + p * n;
+  int32_t* bx = boxes + p * max_boxes * 4;
+  int cur = -1, fa = 0, fb = 0;
+  for (int f = fs; f < fs + 32; ++f) {
+    int ord = -1;
+    if (m[f]) {
+      const int l = L[t * F + f];
+      ord = l < -1 ? -2 - l : -2 - L[l];
+    }
+    if (ord != cur) {
+      flush_run(bx, max_boxes, cur, t, fa, fb);
+      cur = ord;
+      fa = f;
+    }
+    fb = f;
+  }
+  flush_run(bx, max_boxes, cur, t, fa, fb);
+}
+
+// ------------------------------------------------------------------ host
+bool config_ok(const rxphy_sense_config* c) {
+  if (!c) return false;
+  const int F = c->n_fft;
+  return (F == 512 || F == 1024 || F == 2048 || F == 4096) && c->n_rows >= 3 && c->n_rows <= 4096 &&
+         c->sg_window >= 3 && c->sg_window <= SG_MAX && (c->sg_window & 1) && c->sg_window <= F &&
+         c->sg_order >= 0 && c->sg_order <= 6 && c->sg_order < c->sg_window && std::isfinite(c->psd_factor) &&
+         c->psd_factor > 0.f && c->bins >= 2 && c->bins <= 256;
+}
+
+// Savitzky-Golay smoothing weights: the value at 0 of the least-squares
+// polynomial of degree `order` over offsets -h..h, c = V (V^T V)^-1 e0 with
+// V[k][q] = (k/h)^q (scaled for conditioning; same column space), by Gaussian
+// elimination with partial pivoting in double.
+SgCoef sg_coeffs(int window, int order) {
+  const int h = window / 2, n = order + 1;
+  double G[7][8] = {};
+  for (int k = -h; k <= h; ++k) {
+    double pw[7];
+    pw[0] = 1.0;
+    for (int q = 1; q < n; ++q) pw[q] = pw[q - 1] * ((double)k / h);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) G[a][b] += pw[a] * pw[b];
+  }
+  for (int a = 0; a < n; ++a) G[a][n] = a == 0 ? 1.0 : 0.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(G[r][col]) > std::fabs(G[piv][col])) piv = r;
+    for (int j = 0; j <= n; ++j) std::swap(G[col][j], G[piv][j]);
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double fct = G[r][col] / G[col][col];
+      for (int j = col; j <= n; ++j) G[r][j] -= fct * G[col][j];
+    }
+  }
+  double z[7];
+  for (int a = 0; a < n; ++a) z[a] = G[a][n] / G[a][a];
+  SgCoef s;
+  std::memset(&s, 0, sizeof(s));
+  s.h = h;
+  for (int k = -h; k <= h; ++k) {
+    double v = 0.0, pw = 1.0;
+    for (int q = 0; q < n; ++q) {
+      v += pw * z[q];
+      pw *= (double)k / h;
+    }
+    s.c[k + h] = (float)v;
+  }
+  return s;
+}
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct SenseLayout {
+  size_t tf, psd, psd_s, flo, kbin, lo, hi, mask, mask_mo, lab, cnt, off, total;
+};
+
+SenseLayout layout(const rxphy_sense_config& c, int32_t P) {
+  const size_t TF = (size_t)c.n_rows * c.n_fft, F = c.n_fft;
+  const size_t nblk = (TF + PIX_BLK - 1) / PIX_BLK;
+  SenseLayout L{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t at = o;
+    o += al(bytes);
+    return at;
+  };
+  L.tf = put(P * TF * 4);
+  L.psd = put(P * F * 4);
+  L.psd_s = put(P * F * 4);
+  L.flo = put(P * 2 * 4);
+  L.kbin = put(P * F * 4);
+  L.lo = put(P * F * 4);
+  L.hi = put(P * F * 4);
+  L.mask = put(P * TF);
+  L.mask_mo = put(P * TF);
+  L.lab = put(P * TF * 4);
+  L.cnt = put(P * nblk * 4);
+  L.off = put(P * nblk * 4);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+}  // namespace rxphy
+
+extern "C" {
+
+size_t rxphy_sense_workspace_bytes(const rxphy_sense_config* cfg, int32_t n_plots) {
+  if (!rxphy::config_ok(cfg) || n_plots < 1) return 0;
+  return rxphy::layout(*cfg, n_plots).total;
+}
+
+rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const void* x,
+                         const rxphy_sense_outputs* out, int32_t* n_boxes, int32_t* boxes, int32_t max_boxes,
+                         void* ws, size_t ws_bytes, hipStream_t stream) {
+  using namespace rxphy;
+  clear_error();
+  if (!config_ok(cfg))
+    return fail(RXPHY_EINVAL, "sense config: n_fft in {512..4096}, 3 <= n_rows <= 4096, odd sg_window 3..63, "
+                              "sg_order 0..6 below the window, psd_factor > 0, bins 2..256");
+  if (n_plots < 1 || n_plots > 65535) return fail(RXPHY_EINVAL, "n_plots = %d (1 .. 65535)", n_plots);
+  if (max_boxes < 0) return fail(RXPHY_EINVAL, "max_boxes = %d", max_boxes);
+  if (!x || !n_boxes || (max_boxes > 0 && !boxes)) return fail(RXPHY_EINVAL, "x, n_boxes or boxes is NULL");
+  const SenseLayout Lo = layout(*cfg, n_plots);
+  if (!ws || ws_bytes < Lo.total) return fail(RXPHY_EWORKSPACE, "sense needs %zu workspace bytes, got %zu", Lo.total, ws_bytes);
+  if ((uintptr_t)ws & 255u) return fail(RXPHY_EWORKSPACE, "sense workspace must be 256-byte aligned");
+  const rxphy_sense_config& c = *cfg;
+  const int T = c.n_rows, F = c.n_fft, P = n_plots;
+  const int64_t TF = (int64_t)T * F;
+  const int nblk = (int)((TF + PIX_BLK - 1) / PIX_BLK);
+  char* w = (char*)ws;
+  rxphy_sense_outputs o{};
+  if (out) o = *out;
+  float* tf = o.tf ? o.tf : (float*)(w + Lo.tf);
+  float* psd = o.psd ? o.psd : (float*)(w + Lo.psd);
+  float* psd_s = o.psd_smooth ? o.psd_smooth : (float*)(w + Lo.psd_s);
+  float* flo = o.floor ? o.floor : (float*)(w + Lo.flo);
+  int32_t* kbin = o.otsu_bin ? o.otsu_bin : (int32_t*)(w + Lo.kbin);
+  uint8_t* mask = o.mask ? o.mask : (uint8_t*)(w + Lo.mask);
+  uint8_t* mask_mo = o.mask_mo ? o.mask_mo : (uint8_t*)(w + Lo.mask_mo);
+  float* lo = (float*)(w + Lo.lo);
+  float* hi = (float*)(w + Lo.hi);
+  int32_t* lab = (int32_t*)(w + Lo.lab);
+  int32_t* cnt = (int32_t*)(w + Lo.cnt);
+  int32_t* off = (int32_t*)(w + Lo.off);
+  const SgCoef sg = sg_coeffs(c.sg_window, c.sg_order);
+
+  rxphy_status st = launch_fft_mag(F, (int64_t)P * T, (const float2*)x, tf, stream);
+  if (st) return st;
+  const unsigned strips = (unsigned)(F / 64);
+  hipLaunchKernelGGL(colstat_kernel, dim3(strips, P), dim3(256), 0, stream, tf, psd, lo, hi, T, F);
+  if ((st = launch_status("colstat kernel"))) return st;
+  hipLaunchKernelGGL(floor_kernel, dim3(P), dim3(1024), 0, stream, psd, psd_s, flo, sg, c.psd_factor, F);
+  if ((st = launch_status("floor kernel"))) return st;
+  hipLaunchKernelGGL(otsu_kernel, dim3(strips, P), dim3(256), 0, stream, tf, psd, lo, hi, flo, kbin, mask, T, F,
+                     c.bins);
+  if ((st = launch_status("otsu kernel"))) return st;
+  hipLaunchKernelGGL(morph_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask, mask_mo, lab, T, F);
+  if ((st = launch_status("morph kernel"))) return st;
+  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((TF + 255) / 256), P), dim3(256), 0, stream, mask_mo, lab, T, F);
+  if ((st = launch_status("merge kernel"))) return st;
+  hipLaunchKernelGGL(flatten_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, cnt, T, F, nblk);
+  if ((st = launch_status("flatten kernel"))) return st;
+  hipLaunchKernelGGL(scan_kernel, dim3(P), dim3(1024), 0, stream, cnt, off, n_boxes, boxes, max_boxes, nblk);
+  if ((st = launch_status("scan kernel"))) return st;
+  hipLaunchKernelGGL(assign_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, off, T, F, nblk);
+  if ((st = launch_status("assign kernel"))) return st;
+  if (max_boxes > 0) {
+    const int64_t runs = (int64_t)T * (F / 32);
+    hipLaunchKernelGGL(boxes_kernel, dim3((unsigned)((runs + 255) / 256), P), dim3(256), 0, stream, mask_mo, lab,
+                       boxes, max_boxes, T, F);
+    if ((st = launch_status("boxes kernel"))) return st;
+  }
+  return RXPHY_OK;
+}
+
+rxphy_status rxphy_box_metrics(const int32_t* gt, int32_t n_gt, const int32_t* det, int32_t n_det,
+                               double theta_iou, double* iou, rxphy_detection_metrics* out) {
+  using namespace rxphy;
+  clear_error();
+  if (!out || n_gt < 0 || n_det < 0 || (n_gt && !gt) || (n_det && !det)) return fail(RXPHY_EINVAL, "bad arguments");
+  auto area = [](const int32_t* b) { return (double)(b[2] - b[0] + 1) * (double)(b[3] - b[1] + 1); };
+  std::vector<double> best_gt(n_gt, 0.0), best_det(n_det, 0.0);
+  for (int i = 0; i < n_gt; ++i)
+    for (int j = 0; j < n_det; ++j) {
+      const int32_t *a = gt + 4 * i, *b = det + 4 * j;
+      const int it = std::min(a[2], b[2]) - std::max(a[0], b[0]) + 1;
+      const int jf = std::min(a[3], b[3]) - std::max(a[1], b[1]) + 1;
+      const double inter = (double)std::max(it, 0) * (double)std::max(jf, 0);
+      const double v = inter / (area(a) + area(b) - inter);
+      if (iou) iou[(int64_t)i * n_det + j] = v;
+      best_gt[i] = std::max(best_gt[i], v);
+      best_det[j] = std::max(best_det[j], v);
+    }
+  int nt = 0, nf = 0;
+  double sum = 0.0;
+  for (int i = 0; i < n_gt; ++i) {
+    nt += n_det > 0 && best_gt[i] > theta_iou;
+    sum += best_gt[i];
+  }
+  for (int j = 0; j < n_det; ++j) nf += n_gt == 0 || best_det[j] < theta_iou;
+  out->n_t = nt;
+  out->n_f = nf;
+  out->p_d = n_gt ? (double)nt / n_gt : NAN;
+  out->p_fa = n_det ? (double)nf / n_det : NAN;
+  out->mean_iou = n_gt && n_det ? sum / n_gt : 0.0;
+  return RXPHY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+"""GPU parity of the sensing pipeline (rxphy_sense) against the oracle, stage
+by stage on the GPU's own upstream results: the TF plot against the FP64
+transform; the PSD and its smoothing within FP32 summation error; the noise
+floor as the exact lowest local minimum of the GPU's smoothed PSD; theta in
+FP32; the Otsu bins, the mask, the morphology and the boxes bit for bit
+(integer work, with every floating-point decision taken in FP32 on both
+sides)."""
+import numpy as np
+import pytest
+
+from oracle import sensing_oracle as S
+from synth import sensing as SS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-sense]", *a, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.sqrt(np.sum((a - b) ** 2) / max(np.sum(b ** 2), 1e-300)))
+
+
+def check_plot(cfg, ocfg, x, g, i, max_boxes):
+    tf = g["tf"][i]
+    assert rel(tf, S.tf_plot(x, cfg.n_fft)) < 2e-6
+    psd = g["psd"][i]
+    assert rel(psd, S.psd(tf)) < 2e-6
+    ps = g["psd_smooth"][i]
+    assert rel(ps, S.sg_smooth(psd, cfg.sg_window, cfg.sg_order)) < 2e-6
+    n0, theta = g["floor"][i]
+    assert n0 == S.noise_floor(ps.astype(np.float64))          # a selection: exact
+    assert theta == np.float32(cfg.psd_factor) * n0            # FP32 product
+    retained = psd >= theta                                    # FP32 comparison
+    mask, ks = S.binarize(tf, retained, cfg.bins)
+    assert np.array_equal(g["otsu_bin"][i], ks)
+    assert np.array_equal(g["mask"][i], mask)
+    mo = S.morph(g["mask"][i])
+    assert np.array_equal(g["mask_mo"][i], mo)
+    bx = S.boxes(g["mask_mo"][i])
+    assert g["n_boxes"][i] == len(bx)
+    k = min(len(bx), max_boxes)
+    assert np.array_equal(g["boxes"][i][:k], bx[:k])
+    return retained, bx
+
+
+CASES = [  # (F, T, scenario, plots, max_boxes)
+    (512, 400, "sparse_wifi", 2, 64),
+    (1024, 2000, "mixed", 2, 256),
+    (1024, 333, "dense_ble", 3, 256),                         # T not a multiple of 64
+    (2048, 150, "dense_wifi", 1, 256),
+    (1024, 2000, "dense_ble", 1, 5),                          # more components than box slots
+]
+
+
+@pytest.mark.parametrize("F,T,scen,P,max_boxes", CASES)
+def test_sense_stages_vs_oracle(rx, F, T, scen, P, max_boxes):
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ocfg = S.SenseConfig(F=F, T=T)
+    scenes = [SS.make_scene(100 + s, scen, T=T, F=F) for s in range(P)]
+    x = torch.from_numpy(np.stack([s.x for s in scenes])).cuda()
+    out = rx.sense(cfg, x, max_boxes=max_boxes, intermediates=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    for i, sc in enumerate(scenes):
+        retained, bx = check_plot(cfg, ocfg, sc.x, g, i, max_boxes)
+        m = S.metrics(sc.boxes, bx, 0.4)
+        say(F, T, scen, "plot", i, "retained", int(retained.sum()), "boxes", len(bx), "gt", len(sc.boxes),
+            "P_d %.2f P_fa %.2f mean IoU %.2f" % (m["p_d"], m["p_fa"], m["mean_iou"]))
+
+
+def test_sense_configs_and_degenerate_plots(rx):
+    """Other Savitzky-Golay orders, bin counts and factors; an all-zero plot
+    (no threshold anywhere, no boxes); a plot whose every column is retained."""
+    T, F = 256, 512
+    sc = SS.make_scene(7, "dense_wifi", T=T, F=F)
+    zero = np.zeros((T, F), np.complex64)
+    rng = np.random.default_rng(3)
+    loud = (rng.standard_normal((T, F)) + 1j * rng.standard_normal((T, F))).astype(np.complex64)
+    loud[T // 3: T // 2] *= 30                                # a wideband burst: every column retained
+    x = torch.from_numpy(np.stack([sc.x, zero, loud])).cuda()
+    for cfg in (rx.SenseConfig(n_fft=F, n_rows=T, sg_order=3, psd_factor=1.05, bins=64),
+                rx.SenseConfig(n_fft=F, n_rows=T, sg_window=3, sg_order=0, psd_factor=1.2, bins=2),
+                rx.SenseConfig(n_fft=F, n_rows=T, sg_window=63, sg_order=6, psd_factor=1.1, bins=256)):
+        out = rx.sense(cfg, x, max_boxes=128, intermediates=True)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        ocfg = S.SenseConfig(F=F, T=T, sg_window=cfg.sg_window, sg_order=cfg.sg_order,
+                             psd_factor=cfg.psd_factor, bins=cfg.bins)
+        for i, xi in enumerate((sc.x, zero, loud)):
+            retained, bx = check_plot(cfg, ocfg, xi, g, i, 128)
+            say("cfg", cfg.sg_window, cfg.sg_order, cfg.psd_factor, cfg.bins, "plot", i,
+                "retained", int(retained.sum()), "boxes", len(bx))
+        assert g["n_boxes"][1] == 0 and not g["mask"][1].any()
+        assert (g["otsu_bin"][1] == -1).all()
+
+
+def test_sense_is_deterministic_and_reuses_workspace(rx):
+    T, F = 2000, 1024
+    scenes = [SS.make_scene(50 + s, "mixed", T=T, F=F) for s in range(2)]
+    x = torch.from_numpy(np.stack([s.x for s in scenes])).cuda()
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ws = torch.empty((rx.sense_workspace_bytes(cfg, 2),), dtype=torch.uint8, device="cuda")
+    a = rx.sense(cfg, x, max_boxes=256, ws=ws)
+    b = rx.sense(cfg, x, max_boxes=256, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(a["n_boxes"], b["n_boxes"]) and torch.equal(a["boxes"], b["boxes"])
