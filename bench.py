@@ -22,7 +22,10 @@ forward + adjoint on the 64x8 cascaded-channel workload; and the downlink
 (QAM mapping, ZF precoder from the uplink estimate, inverse transform with
 prefix) over the headline frames; and the real-time form: one task of C
 frames released per frame period into a ping-pong stream, with the p99
-latency against the period, for host-memory and device-resident samples.
+latency against the period, for host-memory and device-resident samples;
+and the paper's own sensing pipeline on (2000, 1024) TF plots: a batch of
+plots per call, single-plot latency against the 20.48 ms window, detection
+quality and the oracle on one core.
 
 Before the W warm-up steps the headline runs untimed for --settle-s seconds
 (0.5 s by default; the count is reported as settle_steps): the first few
@@ -355,6 +358,93 @@ def run_streaming(rx, torch, chain, args):
                         "latency = completion - release; real time = at least 99 % within the period"}
 
 
+SENSE_DEADLINE_US = 20480.0   # (T, F) = (2000, 1024) at 100 MS/s: T * F / f_s
+
+
+def sense_bytes(T, F):
+    """Compulsory HBM bytes of one plot per kernel of rxphy_sense (the label
+    array is 4 bytes per pixel; the union-find's own label traffic on
+    foreground pixels is not counted)."""
+    px = T * F
+    return {"fft_mag": px * 12, "colstat": px * 4 + F * 12, "otsu": px * 5 + F * 4,
+            "morph": px * 6, "ccl": px * (1 + 1 + 1 + 4 + 1 + 4)}
+
+
+def run_sensing(rx, torch, args):
+    """The paper's sensing pipeline on (T, F) = (2000, 1024) plots: a batch
+    of plots in one call (throughput), single plots (latency against the
+    20.48 ms window) and the oracle on one host core."""
+    from synth import sensing as SS
+    T, F, P = 2000, 1024, args.sense_plots
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    distinct = min(P, 16)
+    t0 = time.time()
+    scenes = [SS.make_scene(900 + i, "mixed", T=T, F=F) for i in range(distinct)]
+    gen_s = time.time() - t0
+    xh = np.stack([scenes[i % distinct].x for i in range(P)])
+    x = torch.from_numpy(xh).cuda()
+    ws = torch.empty((rx.sense_workspace_bytes(cfg, P),), dtype=torch.uint8, device="cuda")
+    nb = torch.empty((P,), dtype=torch.int32, device="cuda")
+    bx = torch.empty((P, 1024, 4), dtype=torch.int32, device="cuda")
+
+    def call(xx, n, b):
+        rx.sense(cfg, xx, max_boxes=1024, ws=ws, boxes=b, n_boxes=n)
+    for _ in range(args.warmup):
+        call(x, nb, bx)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.form_steps):
+        call(x, nb, bx)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.form_steps
+    sb = sense_bytes(T, F)
+    byts = sum(sb.values()) * P
+    # quality of the batch's boxes against the scenes' ground truth
+    n_h, b_h = nb.cpu().numpy(), bx.cpu().numpy()
+    pd, pfa, miou = [], [], []
+    for i in range(distinct):
+        m = rx.box_metrics(scenes[i].boxes, b_h[i][:min(int(n_h[i]), 1024)], 0.4)
+        pd.append(m["p_d"])
+        pfa.append(m["p_fa"])
+        miou.append(m["mean_iou"])
+    # single plots, each call synchronised: latency of one plot
+    x1, n1, b1 = x[:1], nb[:1], bx[:1]
+    lat = []
+    for k in range(args.sense_latency_calls + 5):
+        t1 = time.perf_counter()
+        call(x1, n1, b1)
+        torch.cuda.synchronize()
+        if k >= 5:
+            lat.append((time.perf_counter() - t1) * 1e6)
+    summ = rx.latency_summary(lat, SENSE_DEADLINE_US)
+    out = {"value": P / (ms * 1e-3), "unit": "TF plots/s", "ms_per_step": round(ms, 4), "plots": P,
+           "algorithmic_bytes": byts, "GBps": round(byts / (ms * 1e-3) / 1e9, 1),
+           "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "bytes_per_plot": sb,
+           "single_plot_latency_us": {"p50": round(summ["p50_us"], 1), "p99": round(summ["p99_us"], 1),
+                                      "max": round(summ["max_us"], 1), "calls": int(summ["count"]),
+                                      "deadline_us": SENSE_DEADLINE_US, "real_time": bool(summ["meets_99"])},
+           "detection": {"p_d": round(float(np.mean(pd)), 4), "p_fa": round(float(np.mean(pfa)), 4),
+                         "mean_iou": round(float(np.mean(miou)), 4), "theta_iou": 0.4,
+                         "scenes": distinct},
+           "gen_seconds": round(gen_s, 1),
+           "workload": "(T, F) = (2000, 1024) TF plots of synthetic captures (noise + BLE / OFDM / DSSS "
+                       "energy blocks, mixed scenario, 16 distinct scenes), Savitzky-Golay 21/1, theta_PSD "
+                       "1.1 N0, 256 Otsu bins; %d plots per call, FP32" % P}
+    if not args.no_cpu_baseline:
+        from oracle import sensing_oracle as SO
+        t1 = time.perf_counter()
+        SO.sense(scenes[0].x, SO.SenseConfig(F=F, T=T))
+        dt = time.perf_counter() - t1
+        out["cpu_oracle"] = {"value": 1.0 / dt, "unit": "TF plots/s", "cores": 1,
+                             "sample": "one (2000, 1024) plot through the sensing oracle, %.2f s" % dt}
+    del x, ws, nb, bx
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(rx, torch, args):
     """256 uneven frames: one persistent launch, replayed from a hipGraph."""
     from paper_2603_20481_amd.autotune import Tuner
@@ -498,8 +588,10 @@ def main():
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
     ap.add_argument("--bwd-frames", type=int, default=50)
-    ap.add_argument("--forms", default="staged,mmse,streaming,downlink,mixed,batched,fwd_bwd",
+    ap.add_argument("--forms", default="staged,mmse,streaming,downlink,mixed,batched,fwd_bwd,sensing",
                     help="comma list of extra forms to time ('' for the headline only)")
+    ap.add_argument("--sense-plots", type=int, default=64)
+    ap.add_argument("--sense-latency-calls", type=int, default=200)
     ap.add_argument("--stream-tasks", type=int, default=400)
     ap.add_argument("--stream-warmup", type=int, default=20)
     ap.add_argument("--tile-cache", default=None)
@@ -618,6 +710,9 @@ def main():
     if "fwd_bwd" in forms:
         out["forms"]["fwd_bwd_fp32"] = run_fwd_bwd(rx, torch, args)
         print("[bench] fwd+bwd done", file=sys.stderr, flush=True)
+    if "sensing" in forms:
+        out["forms"]["sensing_fp32"] = run_sensing(rx, torch, args)
+        print("[bench] sensing done", file=sys.stderr, flush=True)
     if args.copy_mib > 0:
         # plain device-to-device copy of a known size: the achievable-bandwidth
         # reference, and the calibration kernel for the HBM byte counters

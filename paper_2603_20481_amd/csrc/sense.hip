@@ -10,8 +10,9 @@
 //   otsu_kernel      per retained column: LDS histogram, exact integer Otsu,
 //                    mask written in a second pass over the column strip
 //   morph_kernel     64x64 tile + halo in LDS, the six erosions / dilations,
-//                    mask and the union-find labels written
-//   merge_kernel     lock-free union of 4-neighbours (smaller index wins)
+//                    then the tile's components labelled in LDS; mask and
+//                    labels (each pixel's local root) written
+//   merge_kernel     lock-free unions across tile borders (smaller index wins)
 //   flatten_kernel   every label to its root; roots counted per 1024 pixels
 //   scan_kernel      per-plot exclusive scan of the counts; box records reset
 //   assign_kernel    each root gets its ordinal (raster order of roots)
@@ -127,59 +128,104 @@ __device__ __forceinline__ int value_bin(float v, float lo, float scale, int bin
   return b < 0 ? 0 : (b < bins - 1 ? b : bins - 1);
 }
 
-// The threshold bin k (class 0 = bins <= k) maximising
-// (N m0 - M w0)^2 / (w0 w1), ties to the smallest k, -1 if none; exact: the
-// square fits 64 bits for N <= 4096 and bins <= 256, the cross products 128.
-__device__ int otsu_bin(const uint32_t* h, int bins, int N) {
-  int64_t M = 0;
-  for (int i = 1; i < bins; ++i) M += (int64_t)i * h[i];
-  int best = -1;
-  uint64_t bnum = 0, bden = 1;
-  int64_t w0 = 0, m0 = 0;
-  for (int k = 0; k < bins - 1; ++k) {
-    w0 += h[k];
-    m0 += (int64_t)k * h[k];
-    const int64_t w1 = N - w0;
-    if (w0 == 0 || w1 == 0) continue;
-    const int64_t d = (int64_t)N * m0 - M * w0;
-    const uint64_t a = (uint64_t)(d < 0 ? -d : d);
-    const uint64_t num = a * a;
-    const uint64_t den = (uint64_t)(w0 * w1);
-    if (best < 0 || (unsigned __int128)num * bden > (unsigned __int128)bnum * den) {
-      best = k;
-      bnum = num;
-      bden = den;
-    }
-  }
-  return best;
+// Otsu's threshold: the bin k (class 0 = bins <= k) maximising
+// (N m0 - M w0)^2 / (w0 w1) (between-class variance times N^2), ties to the
+// smallest k, -1 if no k leaves both classes non-empty.  Exact: |N m0 - M w0|
+// <= N * N * (bins - 1), whose square fits 64 bits for N <= 4096 and
+// bins <= 256; the cross products are compared in 128 bits.
+struct OtsuBest {
+  uint64_t num, den;
+  int k;
+};
+
+__device__ __forceinline__ bool better(uint64_t num, uint64_t den, const OtsuBest& b) {
+  return b.k < 0 || (unsigned __int128)num * b.den > (unsigned __int128)b.num * den;
+}
+
+// Histogram counts are 16-bit halves of LDS words: bin b of a column is half
+// (b & 1) of word (b >> 1).  A column has at most 4096 values, so a half never
+// carries into the other.
+__device__ __forceinline__ uint32_t hcount(const uint32_t* h, int b) {
+  return (h[b >> 1] >> ((b & 1) * 16)) & 0xffffu;
 }
 
 __global__ void __launch_bounds__(256)
 otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const float* __restrict__ lo_,
             const float* __restrict__ hi_, const float* __restrict__ flo, int32_t* __restrict__ kbin,
             uint8_t* __restrict__ mask, int T, int F, int bins) {
-  __shared__ uint32_t hist[64 * 257];
+  __shared__ uint32_t hist[64 * 129];
+  __shared__ int64_t qw[4][64], qm[4][64];
+  __shared__ OtsuBest qb[4][64];
   __shared__ int kk[64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = blockIdx.x * 64 + lane;
   const int64_t p = blockIdx.y;
-  const int stride = bins + 1;                  // odd stride: the 64 columns hit different banks
+  const int stride = (bins + 1) / 2 + 1;        // words per column, odd: the 64 columns hit different banks
   for (int i = tid; i < 64 * stride; i += 256) hist[i] = 0u;
   const bool keep = psd[p * F + c] >= flo[2 * p + 1];
   const float lo = lo_[p * F + c], hi = hi_[p * F + c];
   const bool spread = hi > lo;
   const float scale = spread ? __fdiv_rn((float)bins, hi - lo) : 0.f;
   const float* col = tf + p * T * F + c;
+  const uint32_t* hc = hist + lane * stride;
   __syncthreads();
   if (keep) {
-    uint32_t* hc = hist + lane * stride;
-    for (int t = w; t < T; t += 4) atomicAdd(hc + value_bin(col[(int64_t)t * F], lo, scale, bins), 1u);
+    for (int t = w; t < T; t += 4) {
+      const int b = value_bin(col[(int64_t)t * F], lo, scale, bins);
+      atomicAdd(hist + lane * stride + (b >> 1), 1u << ((b & 1) * 16));
+    }
+  }
+  __syncthreads();
+  // wave w scans candidate thresholds k in [w q, (w + 1) q), q = ceil((bins - 1) / 4)
+  const int q = (bins - 1 + 3) / 4;
+  const int k0 = w * q, k1 = min(bins - 1, k0 + q);
+  {
+    int64_t sw = 0, sm = 0;
+    for (int b = k0; b < k1; ++b) {
+      const uint32_t v = hcount(hc, b);
+      sw += v;
+      sm += (int64_t)b * v;
+    }
+    qw[w][lane] = sw;
+    qm[w][lane] = sm;
+  }
+  __syncthreads();
+  {
+    int64_t w0 = 0, m0 = 0, M = 0;
+    for (int i = 0; i < 4; ++i) {
+      if (i < w) {
+        w0 += qw[i][lane];
+        m0 += qm[i][lane];
+      }
+      M += qm[i][lane];
+    }
+    M += (int64_t)(bins - 1) * hcount(hc, bins - 1);    // the last bin is never in class 0
+    const int64_t N = T;
+    OtsuBest best{0, 1, -1};
+    if (keep) {
+      for (int k = k0; k < k1; ++k) {
+        const uint32_t v = hcount(hc, k);
+        w0 += v;
+        m0 += (int64_t)k * v;
+        const int64_t w1 = N - w0;
+        if (w0 == 0 || w1 == 0) continue;
+        const int64_t d = N * m0 - M * w0;
+        const uint64_t a = (uint64_t)(d < 0 ? -d : d);
+        const uint64_t num = a * a, den = (uint64_t)(w0 * w1);
+        if (better(num, den, best)) best = OtsuBest{num, den, k};
+      }
+    }
+    qb[w][lane] = best;
   }
   __syncthreads();
   if (w == 0) {
-    const int k = keep ? otsu_bin(hist + lane * stride, bins, T) : -1;
-    kk[lane] = k;
-    kbin[p * F + c] = k;
+    OtsuBest best = qb[0][lane];
+    for (int i = 1; i < 4; ++i) {                  // strictly better only: ties keep the smaller k
+      const OtsuBest& o = qb[i][lane];
+      if (o.k >= 0 && better(o.num, o.den, best)) best = o;
+    }
+    kk[lane] = best.k;
+    kbin[p * F + c] = best.k;
   }
   __syncthreads();
   const int k = kk[lane];
@@ -218,10 +264,47 @@ __device__ __forceinline__ void morph_op(const uint8_t* a, uint8_t* b) {
   __syncthreads();
 }
 
+// Union-find inside one 64x64 tile in LDS (same rule as the global one: the
+// larger root is linked under the smaller, so a local root is the smallest
+// pixel of its local component, which is also its smallest global index).
+// Path splitting: every node passed is pointed at its grandparent.  Parents
+// only ever move to smaller indices of the same set, so the plain stores never
+// undo a link that a concurrent atomic min made.
+__device__ __forceinline__ int lfind(volatile int* lab, int x) {
+  for (;;) {
+    const int y = lab[x];
+    if (y == x) return x;
+    const int z = lab[y];
+    if (z == y) return y;
+    lab[x] = z;
+    x = y;
+  }
+}
+
+__device__ void lunite(volatile int* lab, int a, int b) {
+  for (;;) {
+    a = lfind(lab, a);
+    b = lfind(lab, b);
+    if (a == b) return;
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin((int*)lab + b, a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+// After the morphology the tile's components are labelled in LDS and every
+// pixel's global label is its local root's global index (-1: background);
+// only unions across tile borders are left for the global pass.
 __global__ void __launch_bounds__(256)
 morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab, int T,
              int F) {
   __shared__ uint8_t A[MR * MC], B[MR * MC];
+  __shared__ int loc[64 * 64];
   const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
   const int64_t p = blockIdx.z;
   const uint8_t* m = mask + p * T * F;
@@ -237,15 +320,33 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
   morph_op<true, 1>(B, A);
   morph_op<false, 0>(A, B);                      // opening 1x3 along frequency
   morph_op<true, 0>(B, A);
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int r = idx >> 6, c = idx & 63;
+    loc[idx] = (t0 + r < T && A[(r + 4) * MC + c + 6] == 1) ? idx : -1;
+  }
+  __syncthreads();
+  volatile int* vl = loc;
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    if (vl[idx] < 0) continue;                   // foreground labels stay >= 0 throughout
+    const int r = idx >> 6, c = idx & 63;
+    if (c > 0 && vl[idx - 1] >= 0) lunite(vl, idx, idx - 1);
+    if (r > 0 && vl[idx - 64] >= 0) lunite(vl, idx, idx - 64);
+  }
+  __syncthreads();
   uint8_t* o = out + p * T * F;
   int32_t* L = lab + p * T * F;
   for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
     const int r = idx >> 6, c = idx & 63;
     const int t = t0 + r, f = f0 + c;
     if (t < T) {
-      const uint8_t v = A[(r + 4) * MC + c + 6];
-      o[(int64_t)t * F + f] = v;
-      L[(int64_t)t * F + f] = v ? t * F + f : -1;
+      const bool fg = vl[idx] >= 0;
+      o[(int64_t)t * F + f] = fg ? 1 : 0;
+      int g = -1;
+      if (fg) {
+        const int root = lfind(vl, idx);
+        g = (t0 + (root >> 6)) * F + f0 + (root & 63);
+      }
+      L[(int64_t)t * F + f] = g;
     }
   }
 }
@@ -279,18 +380,25 @@ __device__ void unite(int* L, int a, int b) {
   }
 }
 
-__global__ void __launch_bounds__(256)
+// Unions across tile borders: thread i < 64 takes the tile's top row pixel i
+// and the pixel above it, thread 64 + i the left column pixel i and the pixel
+// to its left.
+__global__ void __launch_bounds__(128)
 merge_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int T, int F) {
-  const int64_t p = blockIdx.y;
+  const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
+  const int64_t p = blockIdx.z;
   const int n = T * F;
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= n) return;
   const uint8_t* m = mask + p * n;
-  if (!m[q]) return;
   int* L = lab + p * n;
-  const int f = q % F;
-  if (f > 0 && m[q - 1]) unite(L, q, q - 1);
-  if (q >= F && m[q - F]) unite(L, q, q - F);
+  const int i = threadIdx.x & 63;
+  if (threadIdx.x < 64) {
+    const int q = t0 * F + f0 + i;
+    if (t0 > 0 && m[q] && m[q - F]) unite(L, q, q - F);
+  } else {
+    const int t = t0 + i;
+    const int q = t * F + f0;
+    if (f0 > 0 && t < T && m[q] && m[q - 1]) unite(L, q, q - 1);
+  }
 }
 
 __device__ __forceinline__ int block_count(int v, int* red) {
@@ -576,7 +684,7 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   if ((st = launch_status("otsu kernel"))) return st;
   hipLaunchKernelGGL(morph_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask, mask_mo, lab, T, F);
   if ((st = launch_status("morph kernel"))) return st;
-  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((TF + 255) / 256), P), dim3(256), 0, stream, mask_mo, lab, T, F);
+  hipLaunchKernelGGL(merge_kernel, dim3(strips, (T + 63) / 64, P), dim3(128), 0, stream, mask_mo, lab, T, F);
   if ((st = launch_status("merge kernel"))) return st;
   hipLaunchKernelGGL(flatten_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, cnt, T, F, nblk);
   if ((st = launch_status("flatten kernel"))) return st;
