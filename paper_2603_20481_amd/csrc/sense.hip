@@ -5,19 +5,22 @@
 //
 // Kernels, all batched over plots (grid y / z = plot):
 //   fft_kernel<F, false, MAG>  magnitudes of the centred bins (fft.hip)
-//   colstat_kernel   column sum (PSD), min and max; 64 columns per workgroup
+//   colstat_kernel   column sum (PSD), min and max; 64 columns per workgroup,
+//                    16 waves over the rows
 //   floor_kernel     Savitzky-Golay smoothing, lowest local minimum, theta
 //   otsu_kernel      per retained column: LDS histogram, exact integer Otsu,
 //                    mask written in a second pass over the column strip
-//   morph_kernel     64x64 tile + halo in LDS, the six erosions / dilations,
+//   morph_kernel     64x64 tile + halo as 128-bit row masks, the six
+//                    erosions / dilations as shifts and ANDs / ORs,
 //                    then the tile's components labelled in LDS; mask and
 //                    labels (each pixel's local root) written
 //   merge_kernel     lock-free unions across tile borders (smaller index wins)
 //   flatten_kernel   every label to its root; roots counted per 1024 pixels
 //   scan_kernel      per-plot exclusive scan of the counts; box records reset
 //   assign_kernel    each root gets its ordinal (raster order of roots)
-//   boxes_kernel     row runs of one component reduced per thread, then
-//                    atomic min / max into the component's box
+//   boxes_kernel     one wave per 64-pixel row segment: runs of one
+//                    component found by ballot, then atomic min / max into
+//                    the component's box
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -48,16 +51,20 @@ __device__ __forceinline__ float wave_min(float v) {
 }
 
 // ------------------------------------------------------------ column stats
-__global__ void __launch_bounds__(256)
+// Column kernels: 64 columns per workgroup (lane = column, 256-byte row
+// loads), CW waves over the rows.
+constexpr int CW = 16;
+
+__global__ void __launch_bounds__(64 * CW)
 colstat_kernel(const float* __restrict__ tf, float* __restrict__ psd, float* __restrict__ lo,
                float* __restrict__ hi, int T, int F) {
-  __shared__ float ss[4][64], smn[4][64], smx[4][64];
+  __shared__ float ss[CW][64], smn[CW][64], smx[CW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
   const int64_t p = blockIdx.y;
   const float* col = tf + p * T * F + c;
   float s = 0.f, mn = INFINITY, mx = -INFINITY;
-  for (int t = w; t < T; t += 4) {
+  for (int t = w; t < T; t += CW) {
     const float v = col[(int64_t)t * F];
     s += v;
     mn = fminf(mn, v);
@@ -68,10 +75,15 @@ colstat_kernel(const float* __restrict__ tf, float* __restrict__ psd, float* __r
   smx[w][lane] = mx;
   __syncthreads();
   if (w == 0) {
-    const float a = ((ss[0][lane] + ss[1][lane]) + ss[2][lane]) + ss[3][lane];
+    float a = ss[0][lane], l = smn[0][lane], h = smx[0][lane];
+    for (int i = 1; i < CW; ++i) {               // fixed order: the same sum on every run
+      a += ss[i][lane];
+      l = fminf(l, smn[i][lane]);
+      h = fmaxf(h, smx[i][lane]);
+    }
     psd[p * F + c] = a;
-    lo[p * F + c] = fminf(fminf(smn[0][lane], smn[1][lane]), fminf(smn[2][lane], smn[3][lane]));
-    hi[p * F + c] = fmaxf(fmaxf(smx[0][lane], smx[1][lane]), fmaxf(smx[2][lane], smx[3][lane]));
+    lo[p * F + c] = l;
+    hi[p * F + c] = h;
   }
 }
 
@@ -149,19 +161,19 @@ __device__ __forceinline__ uint32_t hcount(const uint32_t* h, int b) {
   return (h[b >> 1] >> ((b & 1) * 16)) & 0xffffu;
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * CW)
 otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const float* __restrict__ lo_,
             const float* __restrict__ hi_, const float* __restrict__ flo, int32_t* __restrict__ kbin,
             uint8_t* __restrict__ mask, int T, int F, int bins) {
   __shared__ uint32_t hist[64 * 129];
-  __shared__ int64_t qw[4][64], qm[4][64];
-  __shared__ OtsuBest qb[4][64];
+  __shared__ int64_t qw[CW][64], qm[CW][64];
+  __shared__ OtsuBest qb[CW][64];
   __shared__ int kk[64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = blockIdx.x * 64 + lane;
   const int64_t p = blockIdx.y;
   const int stride = (bins + 1) / 2 + 1;        // words per column, odd: the 64 columns hit different banks
-  for (int i = tid; i < 64 * stride; i += 256) hist[i] = 0u;
+  for (int i = tid; i < 64 * stride; i += 64 * CW) hist[i] = 0u;
   const bool keep = psd[p * F + c] >= flo[2 * p + 1];
   const float lo = lo_[p * F + c], hi = hi_[p * F + c];
   const bool spread = hi > lo;
@@ -170,14 +182,14 @@ otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const f
   const uint32_t* hc = hist + lane * stride;
   __syncthreads();
   if (keep) {
-    for (int t = w; t < T; t += 4) {
+    for (int t = w; t < T; t += CW) {
       const int b = value_bin(col[(int64_t)t * F], lo, scale, bins);
       atomicAdd(hist + lane * stride + (b >> 1), 1u << ((b & 1) * 16));
     }
   }
   __syncthreads();
-  // wave w scans candidate thresholds k in [w q, (w + 1) q), q = ceil((bins - 1) / 4)
-  const int q = (bins - 1 + 3) / 4;
+  // wave w scans candidate thresholds k in [w q, (w + 1) q), q = ceil((bins - 1) / CW)
+  const int q = (bins - 1 + CW - 1) / CW;
   const int k0 = w * q, k1 = min(bins - 1, k0 + q);
   {
     int64_t sw = 0, sm = 0;
@@ -192,7 +204,7 @@ otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const f
   __syncthreads();
   {
     int64_t w0 = 0, m0 = 0, M = 0;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < CW; ++i) {
       if (i < w) {
         w0 += qw[i][lane];
         m0 += qm[i][lane];
@@ -220,7 +232,7 @@ otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const f
   __syncthreads();
   if (w == 0) {
     OtsuBest best = qb[0][lane];
-    for (int i = 1; i < 4; ++i) {                  // strictly better only: ties keep the smaller k
+    for (int i = 1; i < CW; ++i) {                 // strictly better only: ties keep the smaller k
       const OtsuBest& o = qb[i][lane];
       if (o.k >= 0 && better(o.num, o.den, best)) best = o;
     }
@@ -230,36 +242,58 @@ otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const f
   __syncthreads();
   const int k = kk[lane];
   uint8_t* mc = mask + p * T * F + c;
-  for (int t = w; t < T; t += 4)
+  for (int t = w; t < T; t += CW)
     mc[(int64_t)t * F] = (k >= 0 && value_bin(col[(int64_t)t * F], lo, scale, bins) > k) ? 1 : 0;
 }
 
 // ------------------------------------------------------------ morphology
 // A 64x64 core with a halo of 4 rows (four 3x3 operations) and 6 columns
-// (six operations 3 wide).  Pixels outside the plot hold 2 and are skipped by
-// both operations (dilation: max over in-plot 1s; erosion: min over in-plot
-// values).  Values near the region edge use clamped neighbours; the error
-// moves one pixel per operation and never reaches the core.
+// (six operations 3 wide): MR x MC region rows held as 128-bit masks (bit c =
+// region column c), with a second mask of the pixels inside the plot.
+// Dilation ORs the shifted rows of the foreground (outside = 0); erosion ANDs
+// them with the outside set to 1; both clear the outside again.  Rows and
+// columns beyond the region use neutral values; the error this makes moves
+// one pixel per operation and never reaches the core.
 constexpr int MR = 64 + 8, MC = 64 + 12;
+constexpr uint64_t HI_VALID = (1ull << (MC - 64)) - 1;   // region columns 64 .. MC-1
 
-template <bool DIL, int DR>
-__device__ __forceinline__ void morph_op(const uint8_t* a, uint8_t* b) {
-  for (int idx = threadIdx.x; idx < MR * MC; idx += 256) {
-    const int r = idx / MC, c = idx - r * MC;
-    const uint8_t self = a[idx];
-    uint8_t o = self;
-    if (self != 2) {
-      bool hit = false;                          // dilation: a 1 nearby; erosion: a 0 nearby
-#pragma unroll
-      for (int i = -DR; i <= DR; ++i)
-#pragma unroll
-        for (int j = -1; j <= 1; ++j) {
-          const int rr = min(max(r + i, 0), MR - 1), cc = min(max(c + j, 0), MC - 1);
-          hit |= a[rr * MC + cc] == (DIL ? 1 : 0);
-        }
-      o = DIL ? (hit ? 1 : 0) : (hit ? 0 : 1);
+struct Row {
+  uint64_t lo, hi;
+};
+
+__device__ __forceinline__ Row shl1(Row x, uint64_t fill) {   // column c -> c + 1
+  return Row{(x.lo << 1) | fill, ((x.hi << 1) | (x.lo >> 63)) & HI_VALID};
+}
+__device__ __forceinline__ Row shr1(Row x, uint64_t fill) {   // column c -> c - 1
+  return Row{(x.lo >> 1) | (x.hi << 63), (x.hi >> 1) | (fill << (MC - 65))};
+}
+
+template <bool DIL, bool VERT>
+__device__ __forceinline__ void row_op(Row (*cur)[MR], Row (*nxt)[MR], Row* hb, const Row* inm) {
+  const int r = threadIdx.x;
+  Row h{0, 0};
+  if (r < MR) {
+    const Row x = (*cur)[r], in = inm[r];
+    if (DIL) {
+      const Row a = shl1(x, 0), b = shr1(x, 0);
+      h = Row{x.lo | a.lo | b.lo, x.hi | a.hi | b.hi};
+    } else {
+      const Row y{x.lo | ~in.lo, (x.hi | ~in.hi) & HI_VALID};
+      const Row a = shl1(y, 1), b = shr1(y, 1);
+      h = Row{y.lo & a.lo & b.lo, y.hi & a.hi & b.hi};
     }
-    b[idx] = o;
+    if (VERT) hb[r] = h;
+  }
+  if (VERT) __syncthreads();
+  if (r < MR) {
+    Row v = h;
+    if (VERT) {
+      const Row n0 = DIL ? Row{0, 0} : Row{~0ull, HI_VALID};
+      const Row u = r > 0 ? hb[r - 1] : n0, d = r < MR - 1 ? hb[r + 1] : n0;
+      v = DIL ? Row{u.lo | h.lo | d.lo, u.hi | h.hi | d.hi} : Row{u.lo & h.lo & d.lo, u.hi & h.hi & d.hi};
+    }
+    const Row in = inm[r];
+    (*nxt)[r] = Row{v.lo & in.lo, v.hi & in.hi};
   }
   __syncthreads();
 }
@@ -303,26 +337,41 @@ __device__ void lunite(volatile int* lab, int a, int b) {
 __global__ void __launch_bounds__(256)
 morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab, int T,
              int F) {
-  __shared__ uint8_t A[MR * MC], B[MR * MC];
+  __shared__ Row bufA[MR], bufB[MR], hb[MR], inm[MR];
   __shared__ int loc[64 * 64];
   const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
   const int64_t p = blockIdx.z;
   const uint8_t* m = mask + p * T * F;
-  for (int idx = threadIdx.x; idx < MR * MC; idx += 256) {
-    const int r = idx / MC, c = idx - r * MC;
-    const int t = t0 - 4 + r, f = f0 - 6 + c;
-    A[idx] = (t >= 0 && t < T && f >= 0 && f < F) ? m[(int64_t)t * F + f] : 2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = w; r < MR; r += 4) {               // one region row per wave step: two ballots each
+    const int t = t0 - 4 + r;
+    const bool trow = t >= 0 && t < T;
+    const int fa = f0 - 6 + lane, fb = f0 - 6 + 64 + lane;
+    const bool ina = trow && fa >= 0 && fa < F;
+    const bool inb = trow && lane < MC - 64 && fb >= 0 && fb < F;
+    const bool va = ina && m[(int64_t)t * F + fa];
+    const bool vb = inb && m[(int64_t)t * F + fb];
+    const uint64_t ba = __ballot(va), bb = __ballot(vb), ia = __ballot(ina), ib = __ballot(inb);
+    if (lane == 0) {
+      bufA[r] = Row{ba, bb};
+      inm[r] = Row{ia, ib};
+    }
   }
   __syncthreads();
-  morph_op<true, 1>(A, B);                       // closing 3x3
-  morph_op<false, 1>(B, A);
-  morph_op<false, 1>(A, B);                      // opening 3x3
-  morph_op<true, 1>(B, A);
-  morph_op<false, 0>(A, B);                      // opening 1x3 along frequency
-  morph_op<true, 0>(B, A);
+  Row(*A)[MR] = &bufA;
+  Row(*B)[MR] = &bufB;
+  row_op<true, true>(A, B, hb, inm);               // closing 3x3
+  row_op<false, true>(B, A, hb, inm);
+  row_op<false, true>(A, B, hb, inm);              // opening 3x3
+  row_op<true, true>(B, A, hb, inm);
+  row_op<false, false>(A, B, hb, inm);             // opening 1x3 along frequency
+  row_op<true, false>(B, A, hb, inm);
   for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
     const int r = idx >> 6, c = idx & 63;
-    loc[idx] = (t0 + r < T && A[(r + 4) * MC + c + 6] == 1) ? idx : -1;
+    const Row x = (*A)[r + 4];
+    const int col = c + 6;
+    const bool fg = ((col < 64 ? x.lo >> col : x.hi >> (col - 64)) & 1ull) != 0;
+    loc[idx] = (t0 + r < T && fg) ? idx : -1;
   }
   __syncthreads();
   volatile int* vl = loc;
@@ -514,33 +563,65 @@ __device__ __forceinline__ void flush_run(int32_t* boxes, int max_boxes, int ord
   atomicMax(bx + 3, fb);
 }
 
+// One wave per BSEG consecutive 64-pixel segments of one row (F / 64 is a
+// multiple of BSEG, so they never cross a row): the lanes load every
+// segment's mask bytes, then labels, then root labels (three round trips in
+// all), find where each component's run starts with a shuffle and a ballot,
+// and fold each run into its component's box with atomic min / max.  A run
+// that reaches the end of a segment is carried into the next one and folded
+// once.
+constexpr int BSEG = 8;
+
 __global__ void __launch_bounds__(256)
 boxes_kernel(const uint8_t* __restrict__ mask, const int32_t* __restrict__ lab, int32_t* __restrict__ boxes,
              int max_boxes, int T, int F) {
   const int64_t p = blockIdx.y;
-  const int segs = F / 32;
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= T * segs) return;
-  const int t = g / segs, fs = (g - t * segs) * 32;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int spr = F / 64;
   const int n = T * F;
-  const uint8_t* m = mask + p * n + (int64_t)t * F;
+  const uint8_t* m = mask + p * n;
   const int* L = lab + p * n;
   int32_t* bx = boxes + p * max_boxes * 4;
-  int cur = -1, fa = 0, fb = 0;
-  for (int f = fs; f < fs + 32; ++f) {
-    int ord = -1;
-    if (m[f]) {
-      const int l = L[t * F + f];
-      ord = l < -1 ? -2 - l : -2 - L[l];
+  const int s0 = (blockIdx.x * 4 + w) * BSEG;
+  const int t = s0 / spr;
+  if (t >= T) return;                            // wave-uniform
+  const int f0 = (s0 - t * spr) * 64;
+  const int q0 = t * F + f0 + lane;
+  uint8_t fg[BSEG];
+  int l[BSEG], ord[BSEG];
+#pragma unroll
+  for (int k = 0; k < BSEG; ++k) fg[k] = m[q0 + 64 * k];
+#pragma unroll
+  for (int k = 0; k < BSEG; ++k) l[k] = fg[k] ? L[q0 + 64 * k] : -1;
+#pragma unroll
+  for (int k = 0; k < BSEG; ++k) ord[k] = l[k] >= 0 ? -2 - L[l[k]] : (l[k] < -1 ? -2 - l[k] : -1);
+  int carry = -1, carry_fa = 0;                  // wave-uniform: the run open at the previous segment's end
+#pragma unroll
+  for (int k = 0; k < BSEG; ++k) {
+    const int fs = f0 + 64 * k;
+    const int o = ord[k];
+    const int prev = __shfl_up(o, 1, 64);
+    const bool start = lane == 0 || o != prev;
+    const uint64_t starts = __ballot(start);
+    const int first = __shfl(o, 0, 64);
+    const int lastlane_start = 63 - __builtin_clzll(starts);  // start of the run that ends at lane 63
+    const int last_ord = __shfl(o, 63, 64);
+    // the carried run continues into lane 0 of this segment if the component matches
+    const bool cont = carry >= 0 && first == carry;
+    if (!cont && carry >= 0 && lane == 0) flush_run(bx, max_boxes, carry, t, carry_fa, fs - 1);
+    if (start && o >= 0) {
+      const uint64_t nxt = lane == 63 ? 0ull : starts >> (lane + 1);
+      const int last = nxt ? lane + __builtin_ctzll(nxt) : 63;
+      const bool open = last == 63 && k < BSEG - 1;           // carried into the next segment
+      const bool joined = lane == 0 && cont;
+      const int fa = joined ? carry_fa : fs + lane;
+      if (!open) flush_run(bx, max_boxes, o, t, fa, fs + last);
     }
-    if (ord != cur) {
-      flush_run(bx, max_boxes, cur, t, fa, fb);
-      cur = ord;
-      fa = f;
-    }
-    fb = f;
+    // the run that ends at lane 63 becomes the carry (its start: carried or in this segment)
+    const int new_fa = (lastlane_start == 0 && cont) ? carry_fa : fs + lastlane_start;
+    carry = (k < BSEG - 1 && last_ord >= 0) ? last_ord : -1;
+    carry_fa = new_fa;
   }
-  flush_run(bx, max_boxes, cur, t, fa, fb);
 }
 
 // ------------------------------------------------------------------ host
@@ -675,11 +756,11 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   rxphy_status st = launch_fft_mag(F, (int64_t)P * T, (const float2*)x, tf, stream);
   if (st) return st;
   const unsigned strips = (unsigned)(F / 64);
-  hipLaunchKernelGGL(colstat_kernel, dim3(strips, P), dim3(256), 0, stream, tf, psd, lo, hi, T, F);
+  hipLaunchKernelGGL(colstat_kernel, dim3(strips, P), dim3(64 * CW), 0, stream, tf, psd, lo, hi, T, F);
   if ((st = launch_status("colstat kernel"))) return st;
   hipLaunchKernelGGL(floor_kernel, dim3(P), dim3(1024), 0, stream, psd, psd_s, flo, sg, c.psd_factor, F);
   if ((st = launch_status("floor kernel"))) return st;
-  hipLaunchKernelGGL(otsu_kernel, dim3(strips, P), dim3(256), 0, stream, tf, psd, lo, hi, flo, kbin, mask, T, F,
+  hipLaunchKernelGGL(otsu_kernel, dim3(strips, P), dim3(64 * CW), 0, stream, tf, psd, lo, hi, flo, kbin, mask, T, F,
                      c.bins);
   if ((st = launch_status("otsu kernel"))) return st;
   hipLaunchKernelGGL(morph_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask, mask_mo, lab, T, F);
@@ -693,8 +774,8 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   hipLaunchKernelGGL(assign_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, off, T, F, nblk);
   if ((st = launch_status("assign kernel"))) return st;
   if (max_boxes > 0) {
-    const int64_t runs = (int64_t)T * (F / 32);
-    hipLaunchKernelGGL(boxes_kernel, dim3((unsigned)((runs + 255) / 256), P), dim3(256), 0, stream, mask_mo, lab,
+    const int64_t waves = ((int64_t)T * (F / 64) + BSEG - 1) / BSEG;
+    hipLaunchKernelGGL(boxes_kernel, dim3((unsigned)((waves + 3) / 4), P), dim3(256), 0, stream, mask_mo, lab,
                        boxes, max_boxes, T, F);
     if ((st = launch_status("boxes kernel"))) return st;
   }
