@@ -23,7 +23,8 @@ forward + adjoint on the 64x8 cascaded-channel workload; and the downlink
 prefix) over the headline frames; and the real-time form: one task of C
 frames released per frame period into a ping-pong stream, with the p99
 latency against the period, for host-memory and device-resident samples;
-and the paper's own sensing pipeline on (2000, 1024) TF plots: a batch of
+the headline step with 16-bit I/Q samples (the fronthaul format); and the
+paper's own sensing pipeline on (2000, 1024) TF plots: a batch of
 plots per call, single-plot latency against the 20.48 ms window, detection
 quality and the oracle on one core.
 
@@ -292,18 +293,20 @@ def run_streaming(rx, torch, chain, args):
     period_us = shape.n_sym * (shape.cp_len + shape.n_fft) / fs * 1e6
     fr = rx.Frame.of(shape, rx.ZF, 1.0)
     runs = []
-    for host_io, counts in ((True, (1, 2, 3, 4)), (False, (1, 25, 50, 100))):
+    for host_io, sc16, counts in ((True, False, (1, 2, 3, 4)), (True, True, (2, 3, 4, 5)),
+                                  (False, False, (1, 25, 50, 100))):
         for C in counts:
             if C > F:
                 continue
-            st = rx.Stream(fr, C, depth=2, host_io=host_io)
+            xh = chain.x[:C].cpu().numpy() if host_io else None
+            q, scale = synth.quantize_sc16(xh) if sc16 else (None, 0.0)
+            st = rx.Stream(fr, C, depth=2, host_io=host_io, sc16_scale=scale)
             outs = None
             if host_io:
-                xh = chain.x[:C].cpu().numpy()
                 ph = chain.p[:C].cpu().numpy()
                 for slot in range(2):
                     h = st.host(slot)
-                    h["x"][...] = xh
+                    h["x"][...] = q if sc16 else xh
                     h["pilots"][...] = ph
             else:
                 outs = [(torch.empty((C, fr.K, fr.n_data, fr.n_sc, fr.qam_bits), device="cuda"),
@@ -331,14 +334,16 @@ def run_streaming(rx, torch, chain, args):
             lat = st.latencies()
             st.close()
             summ = rx.latency_summary(lat, period_us)
-            runs.append({"io": "host (PCIe in and out)" if host_io else "device-resident",
+            io = "device-resident" if not host_io else \
+                ("host, 16-bit I/Q in" if sc16 else "host (PCIe in and out)")
+            runs.append({"io": io,
                          "frames_per_task": C, "tasks": int(summ["count"]),
                          "p50_us": round(summ["p50_us"], 1), "p99_us": round(summ["p99_us"], 1),
                          "max_us": round(summ["max_us"], 1), "mean_us": round(summ["mean_us"], 1),
                          "on_time": int(summ["on_time"]), "real_time": bool(summ["meets_99"]),
                          "detections_per_s": C * shape.detections / (period_us * 1e-6)})
             print("[bench] streaming %s C=%d p99 %.1f us (period %.1f)" %
-                  ("host" if host_io else "device", C, summ["p99_us"], period_us), file=sys.stderr, flush=True)
+                  (io, C, summ["p99_us"], period_us), file=sys.stderr, flush=True)
             del st, outs
     best = {}
     for r in runs:
@@ -355,7 +360,8 @@ def run_streaming(rx, torch, chain, args):
                         "subcarrier spacing, f_s = 30.72 MS/s); task = fft + fused csi/detect/demod, with "
                         "the samples copied in from and the LLRs, noise variances and flags copied back "
                         "to pinned host memory (host) or read and written in HBM (device-resident); "
-                        "latency = completion - release; real time = at least 99 % within the period"}
+                        "latency = completion - release; real time = at least 99 % within the period; the "
+                        "16-bit runs carry the samples as quantised I/Q pairs (power-of-two scale)"}
 
 
 SENSE_DEADLINE_US = 20480.0   # (T, F) = (2000, 1024) at 100 MS/s: T * F / f_s
@@ -441,6 +447,49 @@ def run_sensing(rx, torch, args):
         out["cpu_oracle"] = {"value": 1.0 / dt, "unit": "TF plots/s", "cores": 1,
                              "sample": "one (2000, 1024) plot through the sensing oracle, %.2f s" % dt}
     del x, ws, nb, bx
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_sc16(rx, torch, chain, args):
+    """The headline step with the samples as 16-bit I/Q (the fronthaul format
+    of Section IV-D): the headline frames quantised with a power-of-two
+    scale, then fft_sc16 and the fused csi + detect + demod call."""
+    shape, F = chain.shape, chain.F
+    fr = rx.Frame.of(shape, rx.ZF, 1.0)
+    xh = chain.x.cpu().numpy()
+    q_h, scale = synth.quantize_sc16(xh)
+    q = torch.from_numpy(q_h).cuda()
+    del q_h
+    ws = torch.empty((rx.workspace_bytes(fr, F, rx.WS_CSI_DETECT_DEMOD, "fp32"),), dtype=torch.uint8,
+                     device="cuda")
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        rx.fft_sc16(fr, q, scale, chain.yf)
+        if ev: ev[1].record()
+        rx.csi_detect_demod(fr, chain.yf, chain.p, "fp32", 1e3, llr=chain.llr, nu=chain.nu, flags=chain.fl, ws=ws)
+        if ev: ev[2].record()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.form_steps)]
+    for ev in evs:
+        step(ev)
+    torch.cuda.synchronize()
+    per = {n: sum(ev[j].elapsed_time(ev[j + 1]) for ev in evs) / len(evs)
+           for j, n in enumerate(("fft_sc16", "csi_detect_demod"))}
+    ms = sum(per.values())
+    sb = stage_bytes(shape)
+    M, S, N, n_sc, cp = shape.M, shape.n_sym, shape.n_fft, shape.n_sc, shape.cp_len
+    byts = {"fft_sc16": M * S * (cp + N) * 4 + M * S * n_sc * 8, "csi_detect_demod": sb["csi_detect_demod"]}
+    out = {"value": F * shape.detections / (ms * 1e-3), "unit": "subcarrier-detections/s",
+           "ms_per_step": round(ms, 4), "frames": F, "scale": scale,
+           "stages": {n: {"us": round(per[n] * 1e3, 2), "GBps": round(byts[n] * F / (per[n] * 1e-3) / 1e9, 1),
+                          "bytes_per_launch": byts[n] * F} for n in per},
+           "workload": "as the headline, with the samples as 16-bit I/Q pairs (power-of-two scale, "
+                       "converted to FP32 in the FFT's loads)"}
+    del q, ws
     torch.cuda.empty_cache()
     return out
 
@@ -588,7 +637,7 @@ def main():
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
     ap.add_argument("--bwd-frames", type=int, default=50)
-    ap.add_argument("--forms", default="staged,mmse,streaming,downlink,mixed,batched,fwd_bwd,sensing",
+    ap.add_argument("--forms", default="staged,mmse,sc16,streaming,downlink,mixed,batched,fwd_bwd,sensing",
                     help="comma list of extra forms to time ('' for the headline only)")
     ap.add_argument("--sense-plots", type=int, default=64)
     ap.add_argument("--sense-latency-calls", type=int, default=200)
@@ -678,6 +727,9 @@ def main():
         ms, per = chain.time(frm, "fp32", args.form_steps, 1, mode="full")
         out["forms"]["mmse_fp32"] = form_summary(shape, F, ms, per, {"workload": "as the headline, MMSE"})
         print("[bench] mmse done", file=sys.stderr, flush=True)
+    if "sc16" in forms:
+        out["forms"]["sc16_ingest_fp32"] = run_sc16(rx, torch, chain, args)
+        print("[bench] sc16 done", file=sys.stderr, flush=True)
     if "streaming" in forms:
         out["forms"]["streaming_fp32"] = run_streaming(rx, torch, chain, args)
         print("[bench] streaming done", file=sys.stderr, flush=True)

@@ -83,6 +83,16 @@ typedef struct {
 rxphy_status rxphy_fft(const rxphy_frame* frame, int32_t n_frames,
                        const void* x, void* yf, hipStream_t stream);
 
+/* rxphy_fft from 16-bit fixed-point I/Q samples, the fronthaul format of
+ * Section IV-D (processing stays FP32): sample = (x[..][0] + j x[..][1]) *
+ * scale, converted exactly to FP32 when scale is a power of two (then the
+ * result equals rxphy_fft of the converted samples bit for bit).
+ *   x     : i16 [F][M][n_sym][cp_len + n_fft][2] (I, Q interleaved; read)
+ *   scale : finite, > 0
+ *   yf    : c64 [F][M][n_sym][n_sc] (written)                                */
+rxphy_status rxphy_fft_sc16(const rxphy_frame* frame, int32_t n_frames, const int16_t* x, float scale,
+                            void* yf, hipStream_t stream);
+
 /* csi stage (`csi` macro): least-squares channel estimate from the comb
  * pilots of symbol 0, held over each pilot group.  G = n_sc / K groups;
  * subcarrier i belongs to group g(i) = min(i / K, G - 1) and
@@ -366,7 +376,7 @@ typedef struct rxphy_stream rxphy_stream;   /* opaque */
 /* Pinned host buffers of one slot of a host I/O stream (layouts as in the
  * single-frame calls, F = n_frames). */
 typedef struct {
-  void* x;          /* c64 [F][M][n_sym][cp_len + n_fft]  input  */
+  void* x;          /* c64 (or i16 pairs) [F][M][n_sym][cp_len + n_fft]  input */
   void* pilots;     /* c64 [F][n_sc]                      input  */
   float* llr;       /* f32 [F][K][n_sym-1][n_sc][qam_bits] output */
   float* nu;        /* f32 [F][K][n_sc]                   output */
@@ -384,10 +394,13 @@ typedef struct {
 } rxphy_latency_summary;
 
 /* Creates a stream on the current device: 1 <= n_frames <= 65535,
- * 1 <= depth <= 8, host_io 0 or 1.  Arguments are validated before any HIP
- * call; allocation failures return RXPHY_EHIP with nothing left allocated. */
+ * 1 <= depth <= 8, host_io 0 or 1.  sc16_scale = 0: the samples x are
+ * complex64; sc16_scale > 0: they are 16-bit I/Q pairs (rxphy_fft_sc16's
+ * layout and scale), half the bytes to move.  Arguments are validated before
+ * any HIP call; allocation failures return RXPHY_EHIP with nothing left
+ * allocated. */
 rxphy_status rxphy_stream_create(const rxphy_frame* frame, int32_t n_frames, int32_t depth, int32_t host_io,
-                                 rxphy_stream** stream);
+                                 float sc16_scale, rxphy_stream** stream);
 /* Pinned host buffers of `slot` (host I/O streams only). */
 rxphy_status rxphy_stream_host_buffers(rxphy_stream* stream, int32_t slot, rxphy_stream_host* host);
 /* Waits until the next slot in turn is free and hands it to the caller. */

@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     FR = ctypes.POINTER(_Frame)
     sigs = {
         "rxphy_fft": [FR, I32, P, P, P],
+        "rxphy_fft_sc16": [FR, I32, P, F32, P, P],
         "rxphy_csi": [FR, I32, P, P, P, P],
         "rxphy_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
@@ -160,7 +161,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     ST = ctypes.c_void_p
     stream_sigs = {
-        "rxphy_stream_create": [FR, I32, I32, I32, ctypes.POINTER(ST)],
+        "rxphy_stream_create": [FR, I32, I32, I32, F32, ctypes.POINTER(ST)],
         "rxphy_stream_host_buffers": [ST, I32, ctypes.POINTER(_StreamHost)],
         "rxphy_stream_acquire": [ST, ctypes.POINTER(I32)],
         "rxphy_stream_submit": [ST, I32, ctypes.c_int64, P, P, P, P, P],
@@ -241,6 +242,20 @@ def fft(fr: Frame, x, yf=None):
         yf = _empty((F, fr.M, fr.n_sym, fr.n_sc), torch.complex64, x)
     _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
     _check(load().rxphy_fft(ctypes.byref(fr.c()), F, _ptr(x), _ptr(yf), _stream()), "rxphy_fft")
+    return yf
+
+
+
+def fft_sc16(fr: Frame, x, scale: float, yf=None):
+    """x i16 [F][M][n_sym][cp+N][2] (I, Q) with value = integer * scale ->
+    yf c64 [F][M][n_sym][n_sc]."""
+    F = _nf(x)
+    _need(x, "x", (F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft, 2), torch.int16)
+    if yf is None:
+        yf = _empty((F, fr.M, fr.n_sym, fr.n_sc), torch.complex64, x)
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _check(load().rxphy_fft_sc16(ctypes.byref(fr.c()), F, _ptr(x), float(scale), _ptr(yf), _stream()),
+           "rxphy_fft_sc16")
     return yf
 
 
@@ -593,23 +608,27 @@ class Stream:
 
     host_io=True: ``host(slot)`` gives numpy views of the slot's pinned host
     buffers (x, pilots in; llr, nu, flags out), valid until ``close()``.
+    sc16_scale > 0: the samples are 16-bit I/Q pairs (as ``fft_sc16``).
     host_io=False: ``submit`` takes device tensors for the task's inputs and
     outputs; the task runs on the slot's own HIP stream, so the inputs must
     already be complete (synchronise their producer first), and the outputs
     are complete after ``drain()``."""
 
-    def __init__(self, fr: Frame, n_frames: int, depth: int = 2, host_io: bool = True):
+    def __init__(self, fr: Frame, n_frames: int, depth: int = 2, host_io: bool = True, sc16_scale: float = 0.0):
         lib = load()
         self.fr, self.nf, self.depth, self.host_io = fr, int(n_frames), int(depth), bool(host_io)
+        self.sc16 = float(sc16_scale)
         h = ctypes.c_void_p()
         _check(lib.rxphy_stream_create(ctypes.byref(fr.c()), self.nf, self.depth, int(self.host_io),
-                                       ctypes.byref(h)), "rxphy_stream_create")
+                                       self.sc16, ctypes.byref(h)), "rxphy_stream_create")
         self._h = h
         self._keep = {}
 
     def shapes(self):
         fr, F = self.fr, self.nf
-        return {"x": ((F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft), np.complex64),
+        xs = ((F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft, 2), np.int16) if self.sc16 > 0 else \
+            ((F, fr.M, fr.n_sym, fr.cp_len + fr.n_fft), np.complex64)
+        return {"x": xs,
                 "pilots": ((F, fr.n_sc), np.complex64),
                 "llr": ((F, fr.K, fr.n_data, fr.n_sc, fr.qam_bits), np.float32),
                 "nu": ((F, fr.K, fr.n_sc), np.float32), "flags": ((F, fr.n_sc), np.uint8)}
@@ -628,7 +647,8 @@ class Stream:
     def submit(self, slot: int, arrival_ns: int = 0, x=None, pilots=None, llr=None, nu=None, flags=None):
         if not self.host_io:
             shp = self.shapes()
-            for name, t, dt in (("x", x, torch.complex64), ("pilots", pilots, torch.complex64),
+            for name, t, dt in (("x", x, torch.int16 if self.sc16 > 0 else torch.complex64),
+                                ("pilots", pilots, torch.complex64),
                                 ("llr", llr, torch.float32), ("nu", nu, torch.float32)):
                 if t is None:
                     raise RxphyError("device-resident stream: %s is required" % name)

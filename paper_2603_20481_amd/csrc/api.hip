@@ -168,6 +168,18 @@ rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames, const 
                        nu, flags, precision, cond_threshold, ws, stream);
 }
 
+rxphy_status rxphy_fft_sc16(const rxphy_frame* frame, int32_t n_frames, const int16_t* x, float scale,
+                            void* yf, hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (!(scale > 0.0f) || !std::isfinite(scale)) return fail(RXPHY_EINVAL, "scale = %g must be finite and > 0", scale);
+  if (n_frames == 0) return RXPHY_OK;
+  if ((st = check_ptr(x, "x")) || (st = check_ptr(yf, "yf"))) return st;
+  int64_t n_tr = (int64_t)n_frames * frame->M * frame->n_sym;
+  return launch_fft_sc16(*frame, n_tr, (const short2*)x, scale, (float2*)yf, stream);
+}
+
 rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames, const void* yf,
                                     const void* pilots, void* xt, float* nu, uint8_t* flags, float* llr,
                                     rxphy_precision precision, float cond_threshold, void* ws,

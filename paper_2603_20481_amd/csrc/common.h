@@ -49,6 +49,9 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
                             const float2* sym, float2* xf, uint8_t* flags, void* ws, hipStream_t s);
 rxphy_status launch_modulate(const rxphy_frame& fr, int64_t n_points, const uint8_t* bits, float2* sym,
                              hipStream_t s);
+// the forward FFT of 16-bit I/Q samples (value = integer * scale)
+rxphy_status launch_fft_sc16(const rxphy_frame& fr, int64_t n_tr, const short2* in, float scale, float2* out,
+                             hipStream_t s);
 // |FFT| of n_rows F-point rows into float rows of F centred bins (TF plot)
 rxphy_status launch_fft_mag(int n_fft, int64_t n_rows, const float2* in, float* out, hipStream_t s);
 rxphy_status launch_ifft_rows(const rxphy_frame& fr, int64_t n_rows, const float2* in, float2* out,

@@ -14,6 +14,8 @@
 // the way in and writes every time sample (zeros over the cyclic prefix).
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace rxphy {
@@ -98,15 +100,36 @@ struct Geom {
 
 constexpr int LDS_MAX = Geom<4096>::LDS;             // largest LDS need of any size
 
-template <int N, bool INV>
-__device__ __forceinline__ void load_input(const float2* __restrict__ in, int64_t tr, bool active,
-                                           int vt, int sym_len, int cp, int n_sc, float2* v) {
+// Samples are complex64, or 16-bit fixed-point I/Q pairs (short2): value =
+// integer * scale.  A 16-bit pair is loaded as one raw 32-bit word (kept in
+// the .x slot) and converted only where the transform first uses it, so the
+// eight loads of a transform stay in flight together.
+__device__ __forceinline__ float2 to_f2(float2 v, float) { return v; }
+__device__ __forceinline__ float2 to_f2(short2 v, float) {
+  return make_float2(__builtin_bit_cast(float, v), 0.f);
+}
+
+template <typename IN_T>
+__device__ __forceinline__ void finish_input(float2* v, float scale) {
+  if constexpr (!std::is_same<IN_T, float2>::value) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const short2 s = __builtin_bit_cast(short2, v[r].x);
+      v[r] = make_float2((float)s.x * scale, (float)s.y * scale);
+    }
+  }
+}
+
+template <int N, bool INV, typename IN_T = float2>
+__device__ __forceinline__ void load_input(const IN_T* __restrict__ in, int64_t tr, bool active,
+                                           int vt, int sym_len, int cp, int n_sc, float2* v,
+                                           float scale = 1.f) {
   constexpr int T = N / 8;
   const int half = n_sc >> 1;
-  if (!INV) {
-    const float2* src = in + (active ? tr : 0) * sym_len + cp;
+  if constexpr (!INV) {
+    const IN_T* src = in + (active ? tr : 0) * sym_len + cp;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = active ? src[vt + r * T] : make_float2(0.f, 0.f);
+    for (int r = 0; r < 8; ++r) v[r] = active ? to_f2(src[vt + r * T], scale) : make_float2(0.f, 0.f);
   } else {
     const float2* src = in + (active ? tr : 0) * n_sc;
 #pragma unroll
@@ -122,11 +145,11 @@ __device__ __forceinline__ void load_input(const float2* __restrict__ in, int64_
 // skipped.  The twiddles a thread needs are the same for every transform, so
 // they are loaded into registers once.  `lds` holds Geom<N>::LDS
 // slots; the caller synchronises before reusing it.
-template <int N, bool INV, bool MAG = false>
-__device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* __restrict__ out,
+template <int N, bool INV, bool MAG = false, typename IN_T = float2>
+__device__ __forceinline__ void fft_tile(const IN_T* __restrict__ in, float2* __restrict__ out,
                                          const float2* __restrict__ tw, int64_t n_tr, int64_t base,
                                          int iters, int sym_len, int cp, int n_sc, float2* lds,
-                                         bool cp_tail = false) {
+                                         bool cp_tail = false, float in_scale = 1.f) {
   using G = Geom<N>;
   constexpr int T = G::T;
   constexpr int VT = G::VT;
@@ -173,7 +196,7 @@ __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* 
   if (PREFETCH) {
 #pragma unroll
     for (int q = 0; q < VT; ++q)
-      load_input<N, INV>(in, base, base < n_tr, tid + q * G::TT, sym_len, cp, n_sc, v[q]);
+      load_input<N, INV, IN_T>(in, base, base < n_tr, tid + q * G::TT, sym_len, cp, n_sc, v[q], in_scale);
   }
   for (int it = 0; it < iters; ++it) {
     const int64_t tr = base + (int64_t)it * G::TPW;
@@ -181,12 +204,13 @@ __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* 
     if (!PREFETCH) {
 #pragma unroll
       for (int q = 0; q < VT; ++q)
-        load_input<N, INV>(in, tr, active, tid + q * G::TT, sym_len, cp, n_sc, v[q]);
+        load_input<N, INV, IN_T>(in, tr, active, tid + q * G::TT, sym_len, cp, n_sc, v[q], in_scale);
     }
     // pass 0: radix 8, Ns = 1 (no twiddles); input element vt + r T
 #pragma unroll
     for (int q = 0; q < VT; ++q) {
       const int vt = tid + q * G::TT;
+      finish_input<IN_T>(v[q], in_scale);
       dft8<INV>(v[q]);
 #pragma unroll
       for (int r = 0; r < 8; ++r) buf[vt * 9 + r] = v[q][r];   // padi(8 vt + r)
@@ -196,7 +220,7 @@ __device__ __forceinline__ void fft_tile(const float2* __restrict__ in, float2* 
       const int64_t tn = tr + G::TPW;
 #pragma unroll
       for (int q = 0; q < VT; ++q)
-        load_input<N, INV>(in, tn, tn < n_tr, tid + q * G::TT, sym_len, cp, n_sc, vn[q]);
+        load_input<N, INV, IN_T>(in, tn, tn < n_tr, tid + q * G::TT, sym_len, cp, n_sc, vn[q], in_scale);
     }
     // middle radix-8 passes, Ns = 8, 64, ...
     int Ns = 8;

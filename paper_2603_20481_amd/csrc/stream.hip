@@ -49,6 +49,7 @@ int64_t steady_ns() {
 struct rxphy_stream {
   rxphy_frame fr{};
   int32_t nf = 0, depth = 0, host_io = 0, device = 0;
+  float sc16 = 0.f;                             // > 0: 16-bit I/Q samples with this scale
   size_t bx = 0, bp = 0, byf = 0, bws = 0, bllr = 0, bnu = 0, bfl = 0;
   std::vector<Slot> slots;
   std::mutex mu;
@@ -154,7 +155,7 @@ extern "C" {
 int64_t rxphy_clock_ns(void) { return steady_ns(); }
 
 rxphy_status rxphy_stream_create(const rxphy_frame* frame, int32_t n_frames, int32_t depth, int32_t host_io,
-                                 rxphy_stream** stream) {
+                                 float sc16_scale, rxphy_stream** stream) {
   rxphy::clear_error();
   if (!stream) return fail(RXPHY_EINVAL, "stream is NULL");
   *stream = nullptr;
@@ -163,6 +164,8 @@ rxphy_status rxphy_stream_create(const rxphy_frame* frame, int32_t n_frames, int
   if (n_frames < 1 || n_frames > 65535) return fail(RXPHY_EINVAL, "n_frames = %d (1 .. 65535)", n_frames);
   if (depth < 1 || depth > 8) return fail(RXPHY_EINVAL, "depth = %d (1 .. 8)", depth);
   if (host_io != 0 && host_io != 1) return fail(RXPHY_EINVAL, "host_io = %d (0 or 1)", host_io);
+  if (!(sc16_scale >= 0.0f) || !std::isfinite(sc16_scale))
+    return fail(RXPHY_EINVAL, "sc16_scale = %g (0 or finite > 0)", sc16_scale);
   const rxphy_frame& fr = *frame;
   const size_t F = (size_t)n_frames, D = (size_t)fr.n_sym - 1;
   rxphy_stream* s = new rxphy_stream();
@@ -170,7 +173,8 @@ rxphy_status rxphy_stream_create(const rxphy_frame* frame, int32_t n_frames, int
   s->nf = n_frames;
   s->depth = depth;
   s->host_io = host_io;
-  s->bx = F * fr.M * fr.n_sym * (size_t)(fr.cp_len + fr.n_fft) * 8;
+  s->sc16 = sc16_scale;
+  s->bx = F * fr.M * fr.n_sym * (size_t)(fr.cp_len + fr.n_fft) * (sc16_scale > 0.f ? 4 : 8);
   s->bp = F * fr.n_sc * 8;
   s->byf = F * fr.M * fr.n_sym * (size_t)fr.n_sc * 8;
   s->bws = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD, RXPHY_FP32);
@@ -246,7 +250,8 @@ rxphy_status rxphy_stream_submit(rxphy_stream* s, int32_t slot, int64_t arrival_
     if (e == hipSuccess) e = hipMemcpyAsync(sl.d_p, sl.h_p, s->bp, hipMemcpyHostToDevice, sl.st);
     if (e != hipSuccess) return fail(RXPHY_EHIP, "input copy: %s", hipGetErrorString(e));
   }
-  rxphy_status st = rxphy_fft(&s->fr, s->nf, x, sl.d_yf, sl.st);
+  rxphy_status st = s->sc16 > 0.f ? rxphy_fft_sc16(&s->fr, s->nf, (const int16_t*)x, s->sc16, sl.d_yf, sl.st)
+                                  : rxphy_fft(&s->fr, s->nf, x, sl.d_yf, sl.st);
   if (!st)
     st = rxphy_csi_detect_demod(&s->fr, s->nf, sl.d_yf, pilots, nullptr, nu, flags, llr, RXPHY_FP32, 0.0f, sl.d_ws,
                                 s->bws, sl.st);

@@ -9,5 +9,5 @@ the HIP package; both consume what it produces.
 """
 from .frames import (  # noqa: F401
     Shape, Frame, CONFIGS, STREAMS, config_shape, make_frame, make_frames,
-    qam_map, used_bins, pilot_user, fft_framing, draw_batch_shapes, draw_inputs,
+    qam_map, used_bins, pilot_user, fft_framing, draw_batch_shapes, draw_inputs, quantize_sc16,
 )

@@ -289,3 +289,15 @@ def fft_framing(n_fft: int, fs: float, sample_bits: int):
     dt = n_fft / fs
     df = fs / n_fft
     return dt, df, n_fft * sample_bits / dt
+
+
+def quantize_sc16(x, headroom: float = 2.0):
+    """The radio's 16-bit fixed-point I/Q: a power-of-two scale chosen so that
+    the largest component times `headroom` fits in int16, each component
+    rounded to the nearest integer.  Returns (int16 [..., 2], scale); the
+    samples are q * scale."""
+    x = np.asarray(x)
+    peak = float(max(np.abs(x.real).max(), np.abs(x.imag).max(), 1e-30))
+    scale = 2.0 ** np.ceil(np.log2(peak * headroom / 32767.0))
+    q = np.stack([np.rint(x.real / scale), np.rint(x.imag / scale)], axis=-1)
+    return np.clip(q, -32768, 32767).astype(np.int16), float(scale)

@@ -46,14 +46,15 @@ def test_summary_edges():
 
 
 @pytest.mark.parametrize("kw", [dict(n_frames=0), dict(n_frames=65536), dict(depth=0), dict(depth=9),
-                                dict(host_io=2)])
+                                dict(host_io=2), dict(sc16=-1.0), dict(sc16=float("nan")),
+                                dict(sc16=float("inf"))])
 def test_create_rejects_bad_arguments_before_the_gpu(kw):
-    a = dict(n_frames=1, depth=2, host_io=1)
+    a = dict(n_frames=1, depth=2, host_io=1, sc16=0.0)
     a.update(kw)
     fr = rx.Frame(8, 2, 512, 300, 14, 0, 2)
     h = ctypes.c_void_p(1)
     st = rx.load().rxphy_stream_create(ctypes.byref(fr.c()), a["n_frames"], a["depth"], a["host_io"],
-                                       ctypes.byref(h))
+                                       a["sc16"], ctypes.byref(h))
     assert st == 1 and not h.value
 
 
@@ -74,3 +75,24 @@ def test_null_stream_calls_fail_cleanly():
     assert lib.rxphy_stream_latencies(None, None, 0, ctypes.byref(n)) == 1
     lib.rxphy_stream_destroy(None)
     assert rx.clock_ns() > 0
+
+
+def test_fft_sc16_argument_checks():
+    lib = rx.load()
+    fr = rx.Frame(8, 2, 512, 300, 14, 0, 2)
+    p = ctypes.c_void_p(256)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.rxphy_fft_sc16(ctypes.byref(fr.c()), 1, p, bad, p, None) == 1
+    assert lib.rxphy_fft_sc16(ctypes.byref(fr.c()), 1, None, 1.0, p, None) == 1
+    assert lib.rxphy_fft_sc16(ctypes.byref(fr.c()), 0, None, 1.0, None, None) == 0   # nothing to do
+
+
+def test_quantizer_is_a_power_of_two_scale():
+    import synth
+    rng = np.random.default_rng(2)
+    x = (rng.standard_normal(1000) + 1j * rng.standard_normal(1000)) * 37.0
+    q, scale = synth.quantize_sc16(x)
+    assert np.log2(scale) == int(np.log2(scale))
+    assert np.abs(q).max() <= 32767 // 2 + 1
+    back = q[..., 0] * scale + 1j * q[..., 1] * scale
+    assert np.max(np.abs(back - x)) <= scale * 0.5 * np.sqrt(2) + 1e-12
