@@ -109,3 +109,28 @@ def test_sense_is_deterministic_and_reuses_workspace(rx):
     b = rx.sense(cfg, x, max_boxes=256, ws=ws)
     torch.cuda.synchronize()
     assert torch.equal(a["n_boxes"], b["n_boxes"]) and torch.equal(a["boxes"], b["boxes"])
+
+
+@pytest.mark.parametrize("F,T", [(4096, 70), (512, 3), (1024, 65)])
+def test_sense_edge_shapes_and_no_box_array(rx, F, T):
+    """The widest plot, the fewest rows (3) and a single row past one tile,
+    on noise with a strong block; then the same call with max_boxes = 0 (no
+    box array), which still counts the components."""
+    rng = np.random.default_rng([41, F, T])
+    x = ((rng.standard_normal((2, T, F)) + 1j * rng.standard_normal((2, T, F))) / np.sqrt(2)).astype(np.complex64)
+    blk = np.zeros((T, F), np.complex128)
+    cols = (np.arange(F // 8, F // 4) - F // 2) % F
+    blk[:, cols] = (rng.standard_normal((T, len(cols))) + 1j * rng.standard_normal((T, len(cols)))) * np.sqrt(F * 50)
+    x[1] += np.fft.ifft(blk, axis=1).astype(np.complex64)
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ocfg = S.SenseConfig(F=F, T=T)
+    xd = torch.from_numpy(x).cuda()
+    out = rx.sense(cfg, xd, max_boxes=64, intermediates=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    for i in range(2):
+        retained, bx = check_plot(cfg, ocfg, x[i], g, i, 64)
+        say("edge", F, T, "plot", i, "retained", int(retained.sum()), "boxes", len(bx))
+    none = rx.sense(cfg, xd, max_boxes=0)
+    torch.cuda.synchronize()
+    assert np.array_equal(none["n_boxes"].cpu().numpy(), g["n_boxes"])
