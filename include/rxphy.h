@@ -193,9 +193,10 @@ rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const ui
  * (reciprocity): for every subcarrier X = H A^-1 S, A = H^H H (detector ZF)
  * or H^H H + N0 I (MMSE: the regularised precoder), H the LS estimate of
  * rxphy_csi from symbol 0 of yf and the pilots, so that a downlink channel
- * H^H delivers S for ZF.  No power normalisation.  Built for K = 16 (each
- * 16-subcarrier tile is one pilot group, factored once: the records of the
- * fused detector); other K return RXPHY_EUNSUPPORTED.  A subcarrier whose
+ * H^H delivers S for ZF.  No power normalisation.  Every pilot group of K
+ * subcarriers shares one H and one A, factored once: for K = 16 by the fused
+ * detector's factor kernel (its records, in the workspace), for K < 16 by a
+ * wave per group (no workspace).  A subcarrier whose
  * factorisation breaks down or whose estimate is not finite transmits zeros
  * and is flagged (RXPHY_FLAG_BREAKDOWN / _NONFINITE).
  *   yf     : c64 [F][M][n_sym][n_sc] (symbol 0 read)   pilots: c64 [F][n_sc]
@@ -203,7 +204,8 @@ rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const ui
  *   xf     : c64 [F][M][n_sym-1][n_sc] (written)
  *   flags  : u8  [F][n_sc] (written; may be NULL)
  *   ws     : rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_PRECODE,
- *            RXPHY_FP32) bytes, 8-byte aligned                                 */
+ *            RXPHY_FP32) bytes, 8-byte aligned (0 bytes, may be NULL, for
+ *            K < 16)                                                          */
 rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
                            const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
                            hipStream_t stream);

@@ -11,6 +11,10 @@
 
 namespace rxphy {
 
+// precode.hip: the precoder for K < 16 (one wave per pilot group)
+rxphy_status launch_precode_general(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                                    const float2* sym, float2* xf, uint8_t* flags, hipStream_t s);
+
 static thread_local char g_err[512];
 
 rxphy_status fail(rxphy_status st, const char* fmt, ...) {
@@ -229,8 +233,6 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
-  if (frame->K != 16)
-    return fail(RXPHY_EUNSUPPORTED, "precode: K = %d (the precoder is built for 16 users)", frame->K);
   size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_PRECODE, RXPHY_FP32);
   if (need && (!ws || ws_bytes < need))
     return fail(RXPHY_EWORKSPACE, "precode needs %zu workspace bytes, got %zu", need, ws_bytes);
@@ -238,8 +240,11 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
   if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(sym, "sym")) ||
       (st = check_ptr(xf, "xf")))
     return st;
-  return launch_precode(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
-                        (float2*)xf, flags, ws, stream);
+  if (frame->K == 16)
+    return launch_precode(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
+                          (float2*)xf, flags, ws, stream);
+  return launch_precode_general(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
+                                (float2*)xf, flags, stream);
 }
 
 rxphy_status rxphy_ifft(const rxphy_frame* frame, int64_t n_rows, const void* xf, void* x, hipStream_t stream) {

@@ -87,7 +87,13 @@ PRECODE_CASES = [(synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.ZF),
                  (synth.Shape(64, 16, 2048, 1200, 14, 0, 4), O.MMSE),
                  (synth.Shape(21, 16, 512, 500, 17, 0, 2), O.ZF),
                  (synth.Shape(16, 16, 512, 200, 6, 8, 6), O.MMSE),
-                 (synth.Shape(64, 16, 4096, 3276, 17, 0, 6), O.ZF)]
+                 (synth.Shape(64, 16, 4096, 3276, 17, 0, 6), O.ZF),
+                 # fewer than 16 users: one wave per pilot group of K subcarriers
+                 (synth.Shape(32, 8, 1024, 600, 14, 0, 4), O.ZF),
+                 (synth.Shape(32, 8, 1024, 600, 14, 0, 4), O.MMSE),
+                 (synth.Shape(13, 5, 512, 301, 6, 0, 2), O.ZF),            # ragged last group
+                 (synth.Shape(8, 1, 512, 64, 3, 0, 6), O.MMSE),            # one user
+                 (synth.Shape(64, 15, 2048, 1200, 14, 0, 4), O.ZF)]
 
 
 @pytest.mark.parametrize("sh,det", PRECODE_CASES)
@@ -128,11 +134,9 @@ def test_precode_vs_oracle_and_zf_loopback(rx, sh, det):
         say("precode", sh, "ZF" if det == O.ZF else "MMSE", *msg)
 
 
-def test_precode_is_built_for_sixteen_users(rx):
-    sh = synth.Shape(8, 4, 512, 300, 6, 0, 2)
-    fr = rx.Frame.of(sh, rx.ZF, 1.0)
-    yf = torch.zeros((1, 8, 6, 300), dtype=torch.complex64, device="cuda")
-    p = torch.ones((1, 300), dtype=torch.complex64, device="cuda")
-    s = torch.zeros((1, 4, 5, 300), dtype=torch.complex64, device="cuda")
-    with pytest.raises(rx.RxphyError):
-        rx.precode(fr, yf, p, s)
+def test_precode_workspace_only_for_sixteen_users(rx):
+    """16 users use the factor records in the workspace; fewer need none."""
+    for K, need in ((16, True), (8, False), (1, False)):
+        sh = synth.Shape(32, K, 512, 300, 6, 0, 2)
+        fr = rx.Frame.of(sh, rx.ZF, 1.0)
+        assert (rx.workspace_bytes(fr, 2, rx.WS_PRECODE, "fp32") > 0) == need
