@@ -507,7 +507,7 @@ def run_batched(rx, torch, args):
     tuner.save()
     res = {}
     dets = sum(s.detections for s in shapes)
-    byts = sum(sum(stage_bytes(s).values()) for s in shapes)
+    byts = sum(stage_bytes(s)[k] for s in shapes for k in MODES["staged"])   # the four stages the plan runs
     bufs = None
     for label, tiles in (("tuned", tuner.tiles_for(frames)), ("default", None)):
         plan = rx.Plan(frames, tiles=tiles)
