@@ -652,7 +652,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: frames are independent, so more GPUs would each "
-              "run this same single-GPU path on their own share of frames (see DESIGN.md)",
+              "run this same single-GPU path on their own share of frames",
               file=sys.stderr)
         sys.exit(2)
     forms = [f for f in args.forms.split(",") if f]

@@ -179,7 +179,7 @@ rxphy_status rxphy_demod(const rxphy_frame* frame, int32_t n_frames,
 
 /* ---------------------------------------------------------------------------
  * Downlink (the transmit direction: the preamble's `modul`, `precode` and
- * `ifft` macros; the survey's first stage beyond the uplink path).
+ * `ifft` macros, beside the uplink stages).
  *
  * rxphy_modulate: Gray square-QAM mapping, the inverse of rxphy_demod's
  * labelling: bits b0 .. b_{Q-1} of each point (one byte per bit, b0 first,

@@ -424,8 +424,8 @@ def cascaded_theta_grad(gx, shape, theta, Gm, Fm, amp, symbols, pilots):
 
 
 # ---------------------------------------------------------------------- downlink
-# The transmit direction the survey ranks next after the uplink path (the
-# `modul`, `precode` and `ifft` macros of the paper's preamble): QAM mapping,
+# The transmit direction beside the uplink path (the `modul`, `precode` and
+# `ifft` macros of the paper's preamble): QAM mapping,
 # a zero-forcing precoder built from the same Gram matrix and Cholesky factor
 # as the detector, and the inverse transform with a cyclic prefix.
 def modulate_stage(bits, q: int) -> np.ndarray:
