@@ -140,3 +140,35 @@ def test_precode_workspace_only_for_sixteen_users(rx):
         sh = synth.Shape(32, K, 512, 300, 6, 0, 2)
         fr = rx.Frame.of(sh, rx.ZF, 1.0)
         assert (rx.workspace_bytes(fr, 2, rx.WS_PRECODE, "fp32") > 0) == need
+
+
+def test_downlink_bench_launch_sampled_frames(rx):
+    """The 100-frame 64x16 downlink exactly as the benchmark launches it (one
+    modulate, one precode and one inverse-transform call over all frames);
+    sampled frames checked against the oracle."""
+    sh = synth.config_shape(2)
+    res = synth.draw_inputs(2, range(100), workers=8)
+    x = dev(np.stack([r[0] for r in res]))
+    p = dev(np.stack([r[1] for r in res]))
+    fr = rx.Frame.of(sh, rx.ZF, 1.0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    bits = torch.randint(0, 2, (100, sh.K, sh.n_data, sh.n_sc, sh.qam_bits), generator=g, device="cuda",
+                         dtype=torch.uint8)
+    yf = rx.fft(fr, x)
+    del x
+    s = rx.modulate(fr, bits)
+    xf, fl = rx.precode(fr, yf, p, s)
+    xt = rx.ifft(fr, xf)
+    torch.cuda.synchronize()
+    for f in (0, 57, 99):
+        bh, sh_, yh, ph = host(bits[f]), host(s[f]), host(yf[f]), host(p[f])
+        assert np.max(np.abs(sh_ - O.modulate_stage(bh, sh.qam_bits))) < 4 * 2.0 ** -23
+        H = O.csi_stage(yh[:, 0, :], ph, sh.K)
+        ref = O.precode_stage(H, sh_, 1.0, O.ZF)
+        assert np.array_equal(host(fl[f]), ref["flags"])
+        e = rel_rms(host(xf[f]), ref["x"])
+        t = O.ifft_stage(host(xf[f]), sh.n_fft, sh.n_sc, sh.cp_len)
+        e2 = rel_rms(host(xt[f]), t)
+        say("100-frame downlink, frame", f, "precode rel_rms", e, "ifft rel_rms", e2)
+        assert e < 1e-4 and e2 < 2e-6

@@ -134,3 +134,24 @@ def test_sense_edge_shapes_and_no_box_array(rx, F, T):
     none = rx.sense(cfg, xd, max_boxes=0)
     torch.cuda.synchronize()
     assert np.array_equal(none["n_boxes"].cpu().numpy(), g["n_boxes"])
+
+
+def test_sense_bench_launch_sampled_plots(rx):
+    """64 plots of (2000, 1024) in one call, as the benchmark launches them
+    (16 distinct scenes repeated); sampled plots checked stage by stage, and
+    every repeat of a scene gives the same boxes."""
+    T, F, P = 2000, 1024, 64
+    scenes = [SS.make_scene(900 + i, "mixed", T=T, F=F) for i in range(16)]
+    x = torch.from_numpy(np.stack([scenes[i % 16].x for i in range(P)])).cuda()
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ocfg = S.SenseConfig(F=F, T=T)
+    out = rx.sense(cfg, x, max_boxes=1024, intermediates=True)
+    torch.cuda.synchronize()
+    nb = out["n_boxes"].cpu().numpy()
+    bx = out["boxes"].cpu().numpy()
+    for i in range(16, P):
+        assert nb[i] == nb[i % 16] and np.array_equal(bx[i], bx[i % 16])
+    for i in (0, 37, 63):
+        g = {k: v[i:i + 1].cpu().numpy() for k, v in out.items()}
+        retained, b = check_plot(cfg, ocfg, scenes[i % 16].x, g, 0, 1024)
+        say("64-plot launch, plot", i, "retained", int(retained.sum()), "boxes", len(b))
