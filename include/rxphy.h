@@ -205,10 +205,16 @@ rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const ui
  *   flags  : u8  [F][n_sc] (written; may be NULL)
  *   ws     : rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_PRECODE,
  *            RXPHY_FP32) bytes, 8-byte aligned (0 bytes, may be NULL, for
- *            K < 16)                                                          */
+ *            K < 16)
+ *   options: RXPHY_PRECODE_REUSE_FACTORS (K = 16): ws already holds the
+ *            factor records that rxphy_csi_detect or rxphy_csi_detect_demod
+ *            (FP32) left in its workspace for the same frames, yf, pilots and
+ *            detector, the same Gram and Cholesky as the uplink (reciprocity);
+ *            the factorisation is then skipped.  0: factor here.            */
+enum { RXPHY_PRECODE_REUSE_FACTORS = 1u };   /* options of rxphy_precode */
 rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
                            const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
-                           hipStream_t stream);
+                           uint32_t options, hipStream_t stream);
 
 /* rxphy_ifft: inverse of rxphy_fft's used-bin transform, unscaled, with a
  * cyclic prefix: row r of xf (n_sc used subcarriers) becomes

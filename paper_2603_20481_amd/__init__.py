@@ -135,7 +135,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_csi_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect_demod": [FR, I32, P, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_modulate": [FR, I32, P, P, P],
-        "rxphy_precode": [FR, I32, P, P, P, P, P, P, SZ, P],
+        "rxphy_precode": [FR, I32, P, P, P, P, P, P, SZ, ctypes.c_uint32, P],
         "rxphy_ifft": [FR, ctypes.c_int64, P, P, P],
         "rxphy_demod": [FR, I32, P, P, P, P],
         "rxphy_backward": [FR, I32, P, P, ctypes.POINTER(_Saved), P, P, P, P, SZ, P],
@@ -364,9 +364,15 @@ def modulate(fr: Frame, bits, sym=None):
     return sym
 
 
-def precode(fr: Frame, yf, pilots, sym, xf=None, flags=None, ws=None):
+PRECODE_REUSE_FACTORS = 1
+
+
+def precode(fr: Frame, yf, pilots, sym, xf=None, flags=None, ws=None, reuse_factors: bool = False):
     """ZF (or regularised, for MMSE) precoding with the uplink estimate from
-    symbol 0 of yf and the pilots -> (xf c64 [F][M][D][n_sc], flags); 16 users."""
+    symbol 0 of yf and the pilots -> (xf c64 [F][M][D][n_sc], flags).  With
+    reuse_factors (16 users), ws is the workspace that csi_detect or
+    csi_detect_demod (FP32) just used on the same frames: its factor records
+    are reused and the factorisation is skipped."""
     F = _nf(yf)
     D = fr.n_data
     _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
@@ -377,10 +383,13 @@ def precode(fr: Frame, yf, pilots, sym, xf=None, flags=None, ws=None):
     _need(xf, "xf", (F, fr.M, D, fr.n_sc), torch.complex64)
     _need(flags, "flags", (F, fr.n_sc), torch.uint8)
     need = workspace_bytes(fr, F, WS_PRECODE, "fp32")
+    if reuse_factors and ws is None:
+        raise RxphyError("reuse_factors needs the workspace that holds the uplink's factor records")
     if need and ws is None:
         ws = _empty((need,), torch.uint8, yf)
     _check(load().rxphy_precode(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots), _ptr(sym), _ptr(xf),
-                                _ptr(flags), _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
+                                _ptr(flags), _ptr(ws), ws.numel() if ws is not None else 0,
+                                PRECODE_REUSE_FACTORS if reuse_factors else 0, _stream()),
            "rxphy_precode")
     return xf, flags
 

@@ -229,10 +229,14 @@ rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const ui
 
 rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
                            const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
-                           hipStream_t stream) {
+                           uint32_t options, hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
+  if (options & ~(uint32_t)RXPHY_PRECODE_REUSE_FACTORS) return fail(RXPHY_EINVAL, "precode options = %#x", options);
+  const bool reuse = (options & RXPHY_PRECODE_REUSE_FACTORS) != 0;
+  if (reuse && frame->K != 16)
+    return fail(RXPHY_EINVAL, "precode: reusing the uplink factors needs K = 16 (the group records), K = %d", frame->K);
   size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_PRECODE, RXPHY_FP32);
   if (need && (!ws || ws_bytes < need))
     return fail(RXPHY_EWORKSPACE, "precode needs %zu workspace bytes, got %zu", need, ws_bytes);
@@ -242,7 +246,7 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
     return st;
   if (frame->K == 16)
     return launch_precode(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
-                          (float2*)xf, flags, ws, stream);
+                          (float2*)xf, flags, ws, reuse, stream);
   return launch_precode_general(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
                                 (float2*)xf, flags, stream);
 }

@@ -536,7 +536,7 @@ precode_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ p
 }  // namespace
 
 rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                            const float2* sym, float2* xf, uint8_t* flags, void* ws, hipStream_t s) {
+                            const float2* sym, float2* xf, uint8_t* flags, void* ws, bool reuse, hipStream_t s) {
   if (nf == 0) return RXPHY_OK;
   if (fr.K != 16) return fail(RXPHY_EUNSUPPORTED, "precode: K = %d (the precoder is built for 16 users)", fr.K);
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
@@ -544,10 +544,12 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
   const int nt = (fr.n_sc + 15) / 16;
   const int64_t T = (int64_t)nf * nt;
   GroupRec* rec = (GroupRec*)ws;
-  hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s, yf,
-                     pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
-  rxphy_status st = launch_status("group factor kernel");
-  if (st) return st;
+  if (!reuse) {                                  // else: the uplink's records for these frames are in ws
+    hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s,
+                       yf, pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+    rxphy_status st = launch_status("group factor kernel");
+    if (st) return st;
+  }
   hipLaunchKernelGGL(precode_group_kernel, dim3(nt, nf), dim3(256), 0, s, yf, pil, rec, sym, xf, flags, fr.M,
                      fr.n_sym, fr.n_sc);
   return launch_status("precode kernel");

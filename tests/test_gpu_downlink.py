@@ -172,3 +172,29 @@ def test_downlink_bench_launch_sampled_frames(rx):
         e2 = rel_rms(host(xt[f]), t)
         say("100-frame downlink, frame", f, "precode rel_rms", e, "ifft rel_rms", e2)
         assert e < 1e-4 and e2 < 2e-6
+
+
+@pytest.mark.parametrize("det", [0, 1])
+def test_precode_reuses_the_uplink_factors(rx, det):
+    """After the fused uplink call (csi_detect_demod, and csi_detect) on the
+    same frames, precoding with its workspace's factor records gives exactly
+    what refactoring gives."""
+    sh = synth.Shape(64, 16, 2048, 1200, 14, 0, 4)
+    frs = [synth.make_frame(4, 20 + f, shape=sh) for f in range(3)]
+    x = dev(np.stack([f.x for f in frs]))
+    p = dev(np.stack([f.pilots for f in frs]))
+    p[2, 30] = 0
+    fr = rx.Frame.of(sh, det, 1.0)
+    yf = rx.fft(fr, x)
+    rng = np.random.default_rng([24, det])
+    s = rx.modulate(fr, dev(rng.integers(0, 2, (3, sh.K, sh.n_data, sh.n_sc, sh.qam_bits)).astype(np.uint8)))
+    ref_x, ref_f = rx.precode(fr, yf, p, s)
+    for kind in (rx.WS_CSI_DETECT_DEMOD, rx.WS_CSI_DETECT):
+        ws = torch.empty((rx.workspace_bytes(fr, 3, kind, "fp32"),), dtype=torch.uint8, device="cuda")
+        if kind == rx.WS_CSI_DETECT_DEMOD:
+            rx.csi_detect_demod(fr, yf, p, ws=ws)
+        else:
+            rx.csi_detect(fr, yf, p, ws=ws)
+        xf, fl = rx.precode(fr, yf, p, s, ws=ws, reuse_factors=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xf, ref_x) and torch.equal(fl, ref_f), kind

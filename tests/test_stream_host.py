@@ -96,3 +96,12 @@ def test_quantizer_is_a_power_of_two_scale():
     assert np.abs(q).max() <= 32767 // 2 + 1
     back = q[..., 0] * scale + 1j * q[..., 1] * scale
     assert np.max(np.abs(back - x)) <= scale * 0.5 * np.sqrt(2) + 1e-12
+
+
+def test_precode_option_checks():
+    lib = rx.load()
+    p = ctypes.c_void_p(256)
+    fr16 = rx.Frame(32, 16, 512, 300, 6, 0, 2)
+    fr8 = rx.Frame(32, 8, 512, 300, 6, 0, 2)
+    assert lib.rxphy_precode(ctypes.byref(fr16.c()), 1, p, p, p, p, None, p, 1 << 20, 2, None) == 1   # unknown option
+    assert lib.rxphy_precode(ctypes.byref(fr8.c()), 1, p, p, p, p, None, None, 0, 1, None) == 1       # reuse needs K = 16
