@@ -563,15 +563,14 @@ __device__ __forceinline__ void flush_run(int32_t* boxes, int max_boxes, int ord
   atomicMax(bx + 3, fb);
 }
 
-// One wave per BSEG consecutive 64-pixel segments of one row (F / 64 is a
-// multiple of BSEG, so they never cross a row): the lanes load every
+// One wave per BSEG consecutive 64-pixel segments of one row (8, or 16 when
+// F >= 1024; F / 64 is a multiple of BSEG, so they never cross a row): the lanes load every
 // segment's mask bytes, then labels, then root labels (three round trips in
 // all), find where each component's run starts with a shuffle and a ballot,
 // and fold each run into its component's box with atomic min / max.  A run
 // that reaches the end of a segment is carried into the next one and folded
 // once.
-constexpr int BSEG = 8;
-
+template <int BSEG>
 __global__ void __launch_bounds__(256)
 boxes_kernel(const uint8_t* __restrict__ mask, const int32_t* __restrict__ lab, int32_t* __restrict__ boxes,
              int max_boxes, int T, int F) {
@@ -774,9 +773,13 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   hipLaunchKernelGGL(assign_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, off, T, F, nblk);
   if ((st = launch_status("assign kernel"))) return st;
   if (max_boxes > 0) {
-    const int64_t waves = ((int64_t)T * (F / 64) + BSEG - 1) / BSEG;
-    hipLaunchKernelGGL(boxes_kernel, dim3((unsigned)((waves + 3) / 4), P), dim3(256), 0, stream, mask_mo, lab,
-                       boxes, max_boxes, T, F);
+    const int bseg = F >= 1024 ? 16 : 8;
+    const int64_t waves = ((int64_t)T * (F / 64) + bseg - 1) / bseg;
+    const dim3 bgrid((unsigned)((waves + 3) / 4), P);
+    if (bseg == 16)
+      hipLaunchKernelGGL(boxes_kernel<16>, bgrid, dim3(256), 0, stream, mask_mo, lab, boxes, max_boxes, T, F);
+    else
+      hipLaunchKernelGGL(boxes_kernel<8>, bgrid, dim3(256), 0, stream, mask_mo, lab, boxes, max_boxes, T, F);
     if ((st = launch_status("boxes kernel"))) return st;
   }
   return RXPHY_OK;
