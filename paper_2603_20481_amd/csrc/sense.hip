@@ -12,7 +12,8 @@
 //                    mask written in a second pass over the column strip
 //   morph_kernel     64x64 tile + halo as 128-bit row masks, the six
 //                    erosions / dilations as shifts and ANDs / ORs,
-//                    then the tile's components labelled in LDS; mask and
+//                    then the tile's components labelled in LDS from row
+//                    runs (bit operations on the row masks); mask and
 //                    labels (each pixel's local root) written
 //   merge_kernel     lock-free unions across tile borders (smaller index wins)
 //   flatten_kernel   every label to its root; roots counted per 1024 pixels
@@ -315,6 +316,8 @@ __device__ __forceinline__ int lfind(volatile int* lab, int x) {
   }
 }
 
+__device__ __forceinline__ uint64_t lowmask(int n) { return n >= 64 ? ~0ull : (1ull << n) - 1; }
+
 __device__ void lunite(volatile int* lab, int a, int b) {
   for (;;) {
     a = lfind(lab, a);
@@ -331,13 +334,15 @@ __device__ void lunite(volatile int* lab, int a, int b) {
   }
 }
 
-// After the morphology the tile's components are labelled in LDS and every
-// pixel's global label is its local root's global index (-1: background);
-// only unions across tile borders are left for the global pass.
+// After the morphology the tile's components are labelled in LDS (union-find
+// over row runs) and every pixel's global label is its local root's global
+// index (-1: background); only unions across tile borders are left for the
+// global pass.
 __global__ void __launch_bounds__(256)
 morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab, int T,
              int F) {
   __shared__ Row bufA[MR], bufB[MR], hb[MR], inm[MR];
+  __shared__ uint64_t crow[64];
   __shared__ int loc[64 * 64];
   const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
   const int64_t p = blockIdx.z;
@@ -366,20 +371,50 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
   row_op<true, true>(B, A, hb, inm);
   row_op<false, false>(A, B, hb, inm);             // opening 1x3 along frequency
   row_op<true, false>(B, A, hb, inm);
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    const int r = idx >> 6, c = idx & 63;
+  // The tile's components from its row runs: a run's first pixel stands for
+  // it; lane r (one wave) unites each run of core row r with every run of row
+  // r - 1 it overlaps, found with bit operations on the row masks.
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
     const Row x = (*A)[r + 4];
-    const int col = c + 6;
-    const bool fg = ((col < 64 ? x.lo >> col : x.hi >> (col - 64)) & 1ull) != 0;
-    loc[idx] = (t0 + r < T && fg) ? idx : -1;
+    crow[r] = t0 + r < T ? ((x.lo >> 6) | (x.hi << 58)) : 0ull;   // core columns 0..63
   }
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) loc[idx] = -1;
   __syncthreads();
   volatile int* vl = loc;
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    if (vl[idx] < 0) continue;                   // foreground labels stay >= 0 throughout
-    const int r = idx >> 6, c = idx & 63;
-    if (c > 0 && vl[idx - 1] >= 0) lunite(vl, idx, idx - 1);
-    if (r > 0 && vl[idx - 64] >= 0) lunite(vl, idx, idx - 64);
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    uint64_t st = crow[r] & ~(crow[r] << 1);     // run starts
+    while (st) {
+      const int c = __builtin_ctzll(st);
+      st &= st - 1;
+      vl[r * 64 + c] = r * 64 + c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x > 0 && threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    const uint64_t row = crow[r], prow = crow[r - 1];
+    const uint64_t pst = prow & ~(prow << 1);
+    uint64_t st = row & ~(row << 1);
+    while (st) {
+      const int c0 = __builtin_ctzll(st);
+      st &= st - 1;
+      const uint64_t inv = ~(row >> c0);
+      const int len = inv ? __builtin_ctzll(inv) : 64 - c0;
+      const uint64_t span = lowmask(len) << c0;
+      const uint64_t ov = prow & span;
+      if (!ov) continue;
+      const int b = __builtin_ctzll(ov);
+      const int ps = 63 - __builtin_clzll(pst & lowmask(b + 1));   // start of the run holding bit b
+      lunite(vl, r * 64 + c0, (r - 1) * 64 + ps);
+      uint64_t more = pst & span & ~lowmask(b + 1);                // further runs that start in the span
+      while (more) {
+        const int q = __builtin_ctzll(more);
+        more &= more - 1;
+        lunite(vl, r * 64 + c0, (r - 1) * 64 + q);
+      }
+    }
   }
   __syncthreads();
   uint8_t* o = out + p * T * F;
@@ -388,11 +423,13 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
     const int r = idx >> 6, c = idx & 63;
     const int t = t0 + r, f = f0 + c;
     if (t < T) {
-      const bool fg = vl[idx] >= 0;
+      const uint64_t row = crow[r];
+      const bool fg = ((row >> c) & 1ull) != 0;
       o[(int64_t)t * F + f] = fg ? 1 : 0;
       int g = -1;
       if (fg) {
-        const int root = lfind(vl, idx);
+        const uint64_t st = row & ~(row << 1) & lowmask(c + 1);
+        const int root = lfind(vl, r * 64 + 63 - __builtin_clzll(st));
         g = (t0 + (root >> 6)) * F + f0 + (root & 63);
       }
       L[(int64_t)t * F + f] = g;
