@@ -19,9 +19,9 @@
 //   flatten_kernel   every label to its root; roots counted per 1024 pixels
 //   scan_kernel      per-plot exclusive scan of the counts; box records reset
 //   assign_kernel    each root gets its ordinal (raster order of roots)
-//   boxes_kernel     one wave per 64-pixel row segment: runs of one
-//                    component found by ballot, then atomic min / max into
-//                    the component's box
+//   boxes_kernel     per tile: each local component's box (from the tile
+//                    list the morphology kernel wrote) folded into its
+//                    component's box; overflowed tiles read pixel by pixel
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -35,6 +35,20 @@ namespace {
 
 constexpr int SG_MAX = 63;
 constexpr int PIX_BLK = 1024;                  // pixels per flatten / assign workgroup
+
+// Per 64x64 tile: its local components (after the morphology), each with its
+// root (the component's first pixel, a plot-local index) and its bounding box
+// inside the tile, in plot coordinates.  n = -1: more than TL_CAP components,
+// the box kernel then reads the tile's pixels instead.
+constexpr int TL_CAP = 64;
+struct TileEntry {
+  int32_t root;
+  int16_t t0, f0, t1, f1;
+};
+struct TileList {
+  int32_t n, pad[3];
+  TileEntry e[TL_CAP];
+};
 
 struct SgCoef {
   float c[SG_MAX];
@@ -339,11 +353,15 @@ __device__ void lunite(volatile int* lab, int a, int b) {
 // index (-1: background); only unions across tile borders are left for the
 // global pass.
 __global__ void __launch_bounds__(256)
-morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab, int T,
-             int F) {
+morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab,
+             TileList* __restrict__ tl, int T, int F) {
   __shared__ Row bufA[MR], bufB[MR], hb[MR], inm[MR];
   __shared__ uint64_t crow[64];
   __shared__ int loc[64 * 64];
+  __shared__ uint8_t idof[64 * 64];             // list position of a local root (255: past the list)
+  __shared__ int bb[TL_CAP][4];                 // local box: min row, min column, max row, max column
+  __shared__ int16_t rootof[TL_CAP];
+  __shared__ int nroots;
   const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
   const int64_t p = blockIdx.z;
   const uint8_t* m = mask + p * T * F;
@@ -433,6 +451,65 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
         g = (t0 + (root >> 6)) * F + f0 + (root & 63);
       }
       L[(int64_t)t * F + f] = g;
+    }
+  }
+  // the tile's component list: roots numbered in any order, boxes reduced per
+  // row run with LDS atomics
+  if (threadIdx.x == 0) nroots = 0;
+  for (int i = threadIdx.x; i < TL_CAP; i += 256) {
+    bb[i][0] = INT_MAX;
+    bb[i][1] = INT_MAX;
+    bb[i][2] = -1;
+    bb[i][3] = -1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    uint64_t st = crow[r] & ~(crow[r] << 1);
+    while (st) {
+      const int c = __builtin_ctzll(st);
+      st &= st - 1;
+      const int x = r * 64 + c;
+      if (lfind(vl, x) == x) {
+        const int id = atomicAdd(&nroots, 1);
+        idof[x] = id < TL_CAP ? (uint8_t)id : 255;
+        if (id < TL_CAP) rootof[id] = (int16_t)x;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    const uint64_t row = crow[r];
+    uint64_t st = row & ~(row << 1);
+    while (st) {
+      const int c0 = __builtin_ctzll(st);
+      st &= st - 1;
+      const uint64_t inv = ~(row >> c0);
+      const int c1 = c0 + (inv ? __builtin_ctzll(inv) : 64 - c0) - 1;
+      const int id = idof[lfind(vl, r * 64 + c0)];
+      if (id != 255) {
+        atomicMin(&bb[id][0], r);
+        atomicMin(&bb[id][1], c0);
+        atomicMax(&bb[id][2], r);
+        atomicMax(&bb[id][3], c1);
+      }
+    }
+  }
+  __syncthreads();
+  TileList& out_l = tl[(p * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  const int n = nroots;
+  if (threadIdx.x == 0) out_l.n = n <= TL_CAP ? n : -1;
+  if (n <= TL_CAP) {
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int x = rootof[e];
+      TileEntry te;
+      te.root = (t0 + (x >> 6)) * F + f0 + (x & 63);
+      te.t0 = (int16_t)(t0 + bb[e][0]);
+      te.f0 = (int16_t)(f0 + bb[e][1]);
+      te.t1 = (int16_t)(t0 + bb[e][2]);
+      te.f1 = (int16_t)(f0 + bb[e][3]);
+      out_l.e[e] = te;
     }
   }
 }
@@ -600,63 +677,54 @@ __device__ __forceinline__ void flush_run(int32_t* boxes, int max_boxes, int ord
   atomicMax(bx + 3, fb);
 }
 
-// One wave per BSEG consecutive 64-pixel segments of one row (8, or 16 when
-// F >= 1024; F / 64 is a multiple of BSEG, so they never cross a row): the lanes load every
-// segment's mask bytes, then labels, then root labels (three round trips in
-// all), find where each component's run starts with a shuffle and a ballot,
-// and fold each run into its component's box with atomic min / max.  A run
-// that reaches the end of a segment is carried into the next one and folded
-// once.
-template <int BSEG>
+// One workgroup per 64x64 tile.  A tile with a component list folds each
+// local component's box into its component's box (four atomic min / max per
+// local component); a tile whose list overflowed is read pixel by pixel: each
+// wave takes rows of the tile, finds the runs of one component with a shuffle
+// and a ballot, and folds each run.
 __global__ void __launch_bounds__(256)
-boxes_kernel(const uint8_t* __restrict__ mask, const int32_t* __restrict__ lab, int32_t* __restrict__ boxes,
-             int max_boxes, int T, int F) {
-  const int64_t p = blockIdx.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int spr = F / 64;
-  const int n = T * F;
-  const uint8_t* m = mask + p * n;
-  const int* L = lab + p * n;
+boxes_kernel(const uint8_t* __restrict__ mask, const int32_t* __restrict__ lab, const TileList* __restrict__ tl,
+             int32_t* __restrict__ boxes, int max_boxes, int T, int F) {
+  const int64_t p = blockIdx.z;
+  const int t0 = blockIdx.y * 64, f0 = blockIdx.x * 64;
+  const int n_px = T * F;
+  const int* L = lab + p * n_px;
   int32_t* bx = boxes + p * max_boxes * 4;
-  const int s0 = (blockIdx.x * 4 + w) * BSEG;
-  const int t = s0 / spr;
-  if (t >= T) return;                            // wave-uniform
-  const int f0 = (s0 - t * spr) * 64;
-  const int q0 = t * F + f0 + lane;
-  uint8_t fg[BSEG];
-  int l[BSEG], ord[BSEG];
-#pragma unroll
-  for (int k = 0; k < BSEG; ++k) fg[k] = m[q0 + 64 * k];
-#pragma unroll
-  for (int k = 0; k < BSEG; ++k) l[k] = fg[k] ? L[q0 + 64 * k] : -1;
-#pragma unroll
-  for (int k = 0; k < BSEG; ++k) ord[k] = l[k] >= 0 ? -2 - L[l[k]] : (l[k] < -1 ? -2 - l[k] : -1);
-  int carry = -1, carry_fa = 0;                  // wave-uniform: the run open at the previous segment's end
-#pragma unroll
-  for (int k = 0; k < BSEG; ++k) {
-    const int fs = f0 + 64 * k;
-    const int o = ord[k];
-    const int prev = __shfl_up(o, 1, 64);
-    const bool start = lane == 0 || o != prev;
+  const TileList& tlst = tl[(p * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  const int n = tlst.n;
+  if (n >= 0) {
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const TileEntry te = tlst.e[e];
+      const int l = L[te.root];
+      const int ord = l < -1 ? -2 - l : -2 - L[l];
+      if (ord < max_boxes) {
+        int32_t* b = bx + (int64_t)ord * 4;
+        atomicMin(b + 0, (int)te.t0);
+        atomicMin(b + 1, (int)te.f0);
+        atomicMax(b + 2, (int)te.t1);
+        atomicMax(b + 3, (int)te.f1);
+      }
+    }
+    return;
+  }
+  const uint8_t* m = mask + p * n_px;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = w; r < 64 && t0 + r < T; r += 4) {
+    const int t = t0 + r;
+    const int q = t * F + f0 + lane;
+    int ord = -1;
+    if (m[q]) {
+      const int l = L[q];
+      ord = l < -1 ? -2 - l : -2 - L[l];
+    }
+    const int prev = __shfl_up(ord, 1, 64);
+    const bool start = lane == 0 || ord != prev;
     const uint64_t starts = __ballot(start);
-    const int first = __shfl(o, 0, 64);
-    const int lastlane_start = 63 - __builtin_clzll(starts);  // start of the run that ends at lane 63
-    const int last_ord = __shfl(o, 63, 64);
-    // the carried run continues into lane 0 of this segment if the component matches
-    const bool cont = carry >= 0 && first == carry;
-    if (!cont && carry >= 0 && lane == 0) flush_run(bx, max_boxes, carry, t, carry_fa, fs - 1);
-    if (start && o >= 0) {
+    if (start && ord >= 0) {
       const uint64_t nxt = lane == 63 ? 0ull : starts >> (lane + 1);
       const int last = nxt ? lane + __builtin_ctzll(nxt) : 63;
-      const bool open = last == 63 && k < BSEG - 1;           // carried into the next segment
-      const bool joined = lane == 0 && cont;
-      const int fa = joined ? carry_fa : fs + lane;
-      if (!open) flush_run(bx, max_boxes, o, t, fa, fs + last);
+      flush_run(bx, max_boxes, ord, t, f0 + lane, f0 + last);
     }
-    // the run that ends at lane 63 becomes the carry (its start: carried or in this segment)
-    const int new_fa = (lastlane_start == 0 && cont) ? carry_fa : fs + lastlane_start;
-    carry = (k < BSEG - 1 && last_ord >= 0) ? last_ord : -1;
-    carry_fa = new_fa;
   }
 }
 
@@ -715,7 +783,7 @@ SgCoef sg_coeffs(int window, int order) {
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct SenseLayout {
-  size_t tf, psd, psd_s, flo, kbin, lo, hi, mask, mask_mo, lab, cnt, off, total;
+  size_t tf, psd, psd_s, flo, kbin, lo, hi, mask, mask_mo, lab, cnt, off, tl, total;
 };
 
 SenseLayout layout(const rxphy_sense_config& c, int32_t P) {
@@ -740,6 +808,7 @@ SenseLayout layout(const rxphy_sense_config& c, int32_t P) {
   L.lab = put(P * TF * 4);
   L.cnt = put(P * nblk * 4);
   L.off = put(P * nblk * 4);
+  L.tl = put(P * (size_t)(c.n_fft / 64) * ((c.n_rows + 63) / 64) * sizeof(TileList));
   L.total = o;
   return L;
 }
@@ -799,7 +868,9 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   hipLaunchKernelGGL(otsu_kernel, dim3(strips, P), dim3(64 * CW), 0, stream, tf, psd, lo, hi, flo, kbin, mask, T, F,
                      c.bins);
   if ((st = launch_status("otsu kernel"))) return st;
-  hipLaunchKernelGGL(morph_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask, mask_mo, lab, T, F);
+  TileList* tl = (TileList*)(w + Lo.tl);
+  hipLaunchKernelGGL(morph_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask, mask_mo, lab, tl, T,
+                     F);
   if ((st = launch_status("morph kernel"))) return st;
   hipLaunchKernelGGL(merge_kernel, dim3(strips, (T + 63) / 64, P), dim3(128), 0, stream, mask_mo, lab, T, F);
   if ((st = launch_status("merge kernel"))) return st;
@@ -810,13 +881,8 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   hipLaunchKernelGGL(assign_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, off, T, F, nblk);
   if ((st = launch_status("assign kernel"))) return st;
   if (max_boxes > 0) {
-    const int bseg = F >= 1024 ? 16 : 8;
-    const int64_t waves = ((int64_t)T * (F / 64) + bseg - 1) / bseg;
-    const dim3 bgrid((unsigned)((waves + 3) / 4), P);
-    if (bseg == 16)
-      hipLaunchKernelGGL(boxes_kernel<16>, bgrid, dim3(256), 0, stream, mask_mo, lab, boxes, max_boxes, T, F);
-    else
-      hipLaunchKernelGGL(boxes_kernel<8>, bgrid, dim3(256), 0, stream, mask_mo, lab, boxes, max_boxes, T, F);
+    hipLaunchKernelGGL(boxes_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask_mo, lab, tl, boxes,
+                       max_boxes, T, F);
     if ((st = launch_status("boxes kernel"))) return st;
   }
   return RXPHY_OK;

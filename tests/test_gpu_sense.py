@@ -155,3 +155,32 @@ def test_sense_bench_launch_sampled_plots(rx):
         g = {k: v[i:i + 1].cpu().numpy() for k, v in out.items()}
         retained, b = check_plot(cfg, ocfg, scenes[i % 16].x, g, 0, 1024)
         say("64-plot launch, plot", i, "retained", int(retained.sum()), "boxes", len(b))
+
+
+def lattice_capture(T, F, period=6, size=3, offset=2, big=100.0, small=1.0):
+    """Samples whose TF plot is a lattice of size x size blocks (gaps of
+    period - size, which the 3x3 closing does not bridge): every 64x64 tile
+    then holds up to 121 components."""
+    cols = (np.arange(F) - F // 2) % F
+    on_t = ((np.arange(T) - offset) % period) < size
+    on_f = ((np.arange(F) - offset) % period) < size
+    X = np.where(on_t[:, None] & on_f[None, :], big, small).astype(np.complex128)
+    Xb = np.zeros((T, F), np.complex128)
+    Xb[:, cols] = X
+    return np.fft.ifft(Xb, axis=1).astype(np.complex64), on_t[:, None] & on_f[None, :]
+
+
+def test_sense_dense_lattice_overflows_the_tile_lists(rx):
+    """More components per tile than a tile's list holds: the box kernel reads
+    those tiles pixel by pixel and still returns the oracle's boxes."""
+    T, F = 200, 512
+    x, lat = lattice_capture(T, F)
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ocfg = S.SenseConfig(F=F, T=T)
+    out = rx.sense(cfg, torch.from_numpy(x[None]).cuda(), max_boxes=4096, intermediates=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    retained, bx = check_plot(cfg, ocfg, x, g, 0, 4096)
+    say("lattice", T, F, "boxes", len(bx), "mask equals lattice", bool(np.array_equal(g["mask_mo"][0], lat)))
+    assert np.array_equal(g["mask_mo"][0], lat.astype(np.uint8))
+    assert len(bx) > 64 * (T // 64) * (F // 64) // 4
