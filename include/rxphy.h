@@ -450,7 +450,8 @@ rxphy_status rxphy_latency_summarize(const double* lat_us, int64_t n, double bou
  * the lower bin, decided exactly in integers; a value's bin is
  * min(bins-1, floor((v - min) * (bins / (max - min)))) in FP32); the mask
  * then gets one 3x3 closing, one 3x3 opening and one 1x3 opening along
- * frequency (all-ones elements, neighbours inside the plot only); its
+ * frequency, in that order (all-ones elements, neighbours inside the plot
+ * only; the last one leaves a 3x3 opening unchanged); its
  * 4-connected components give one inclusive box (t0, f0, t1, f1) each,
  * listed in raster order of each component's first pixel.
  * ------------------------------------------------------------------------- */

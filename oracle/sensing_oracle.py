@@ -27,9 +27,10 @@ Steps (Section IV-B unless noted):
                  the paper processes samples in (Section IV-D); the argmax is
                  exact (integer arithmetic).
   morph          one 3x3 closing, one 3x3 opening, one 1x3 opening along
-                 frequency, all-ones structuring elements; erosion and
-                 dilation take the structuring element's pixels inside the
-                 plot only.
+                 frequency, in the order listed (the last one never changes
+                 the mask after a 3x3 opening), all-ones structuring
+                 elements; erosion and dilation take the structuring
+                 element's pixels inside the plot only.
   boxes          4-connected components found by one raster scan, each
                  component's inclusive (t0, f0, t1, f1), in the order the
                  scan meets them.
@@ -197,7 +198,10 @@ def erode(a, dt: int, df: int):
 
 
 def morph(mask):
-    """3x3 closing, then 3x3 opening, then 1x3 opening along frequency."""
+    """3x3 closing, then 3x3 opening, then 1x3 opening along frequency, the
+    order the paper lists them in.  The last step never changes the mask: a
+    3x3 opening leaves a union of 3x3 squares, which every 1x3 opening
+    keeps; it is applied all the same."""
     a = erode(dilate(mask, 1, 1), 1, 1)         # closing
     a = dilate(erode(a, 1, 1), 1, 1)            # opening
     a = dilate(erode(a, 0, 1), 0, 1)            # horizontal opening

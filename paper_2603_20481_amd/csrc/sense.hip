@@ -387,7 +387,7 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
   row_op<false, true>(B, A, hb, inm);
   row_op<false, true>(A, B, hb, inm);              // opening 3x3
   row_op<true, true>(B, A, hb, inm);
-  row_op<false, false>(A, B, hb, inm);             // opening 1x3 along frequency
+  row_op<false, false>(A, B, hb, inm);             // opening 1x3 along frequency (leaves a 3x3 opening unchanged)
   row_op<true, false>(B, A, hb, inm);
   // The tile's components from its row runs: a run's first pixel stands for
   // it; lane r (one wave) unites each run of core row r with every run of row

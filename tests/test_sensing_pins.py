@@ -147,6 +147,9 @@ def test_morphology_matches_scipy():
         ref = ndi.binary_dilation(ndi.binary_erosion(ref, se, border_value=1), se, border_value=0)
         ref = ndi.binary_dilation(ndi.binary_erosion(ref, sh, border_value=1), sh, border_value=0)
         assert np.array_equal(S.morph(a), ref)
+        # a 1x3 opening after the 3x3 opening is the identity
+        o3 = ndi.binary_dilation(ndi.binary_erosion(a, se, border_value=1), se, border_value=0)
+        assert np.array_equal(ndi.binary_dilation(ndi.binary_erosion(o3, sh, border_value=1), sh, border_value=0), o3)
 
 
 def test_morphology_effects():
@@ -160,6 +163,14 @@ def test_morphology_effects():
     assert m[10:15, 2:12].all()
     full = np.ones((6, 6), np.uint8)
     assert S.morph(full).all()                               # the plot edge erodes nothing
+    # two blocks with a one-bin line in the three-bin gap between them: the
+    # closing bridges the one-bin gaps on both sides, one block results
+    b = np.zeros((12, 15), np.uint8)
+    b[2:10, 0:5] = 1
+    b[2:10, 8:13] = 1
+    b[2:10, 6] = 1
+    m = S.morph(b)
+    assert m[3:9, 0:13].all() and len(S.boxes(m)) == 1
 
 
 def test_boxes_match_scipy_label():
