@@ -277,6 +277,20 @@ def run_downlink(rx, torch, chain, args):
     e1.record()
     torch.cuda.synchronize()
     reuse_us = e0.elapsed_time(e1) / args.form_steps * 1e3
+    # the time samples as 16-bit I/Q for the radio (power-of-two step with
+    # one bit of headroom over the peak sample)
+    peak = float(torch.max(torch.abs(torch.view_as_real(x))).item())
+    q_scale = 2.0 ** np.ceil(np.log2(peak * 2.0 / 32767.0))
+    x16 = rx.ifft_sc16(fr, xf, q_scale)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.form_steps):
+        rx.ifft_sc16(fr, xf, q_scale, x16)
+    e1.record()
+    torch.cuda.synchronize()
+    ifft16_us = e0.elapsed_time(e1) / args.form_steps * 1e3
+    ifft16_bytes = F * shape.M * D * (shape.n_sc * 8 + (shape.cp_len + shape.n_fft) * 4)
     out = {"value": F * shape.detections / (ms * 1e-3), "unit": "subcarrier-precodings/s",
            "ms_per_step": round(ms, 4), "frames": F,
            "stages": {n: {"us": round(per[n] * 1e3, 2),
@@ -288,10 +302,14 @@ def run_downlink(rx, torch, chain, args):
                             "ms_per_step": round(per["modulate"] + reuse_us * 1e-3 + per["ifft"], 4),
                             "note": "precode reusing the uplink fused call's factor records "
                                     "(same frames, ZF): the factorisation is skipped"},
+           "sc16_out": {"ifft_us": round(ifft16_us, 2), "scale": q_scale,
+                        "GBps": round(ifft16_bytes / (ifft16_us * 1e-6) / 1e9, 1), "bytes_per_launch": ifft16_bytes,
+                        "ms_per_step_after_uplink": round(per["modulate"] + (reuse_us + ifft16_us) * 1e-3, 4),
+                        "note": "time samples written as 16-bit I/Q (round to nearest, saturating)"},
            "workload": "headline frames (64x16, N_FFT 2048, 1200 subcarriers, 13 data symbols, "
                        "16-QAM): random bits -> QAM -> ZF precoder from the uplink LS estimate "
                        "-> unscaled inverse transform with prefix, FP32"}
-    del bits, sym, xf, fl, x, ws, wsu
+    del bits, sym, xf, fl, x, ws, wsu, x16
     torch.cuda.empty_cache()
     return out
 

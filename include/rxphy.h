@@ -224,6 +224,15 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
  *   xf : c64 [n_rows][n_sc]     x : c64 [n_rows][cp_len + n_fft] (written)    */
 rxphy_status rxphy_ifft(const rxphy_frame* frame, int64_t n_rows, const void* xf, void* x, hipStream_t stream);
 
+/* rxphy_ifft with the time samples as 16-bit I/Q for the radio (the
+ * fronthaul format of Section IV-D): each component of a sample becomes
+ * round(value * (1 / scale)) to nearest even in FP32, saturated to
+ * [-32768, 32767]; that is the FP32 sample rxphy_ifft writes, quantised.
+ *   xf : c64 [n_rows][n_sc]   x : i16 [n_rows][cp_len + n_fft][2] (written)
+ *   scale : finite, > 0 (the value of one integer step)                      */
+rxphy_status rxphy_ifft_sc16(const rxphy_frame* frame, int64_t n_rows, const void* xf, float scale, int16_t* x,
+                            hipStream_t stream);
+
 /* Intermediate results of the forward stages that rxphy_backward may reuse;
  * any member may be NULL, in which case it is recomputed into the workspace. */
 typedef struct {

@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_modulate": [FR, I32, P, P, P],
         "rxphy_precode": [FR, I32, P, P, P, P, P, P, SZ, ctypes.c_uint32, P],
         "rxphy_ifft": [FR, ctypes.c_int64, P, P, P],
+        "rxphy_ifft_sc16": [FR, ctypes.c_int64, P, F32, P, P],
         "rxphy_demod": [FR, I32, P, P, P, P],
         "rxphy_backward": [FR, I32, P, P, ctypes.POINTER(_Saved), P, P, P, P, SZ, P],
     }
@@ -406,6 +407,19 @@ def ifft(fr: Frame, xf, x=None):
     _check(load().rxphy_ifft(ctypes.byref(fr.c()), rows, _ptr(xf), _ptr(x), _stream()), "rxphy_ifft")
     return x
 
+
+
+def ifft_sc16(fr: Frame, xf, scale: float, x=None):
+    """Rows of n_sc used subcarriers [..., n_sc] -> 16-bit I/Q time rows
+    [..., cp_len + n_fft, 2] (round(value / scale), saturated)."""
+    if xf.device.type != "cuda" or xf.dtype != torch.complex64 or not xf.is_contiguous() or xf.shape[-1] != fr.n_sc:
+        raise RxphyError("xf must be a contiguous complex64 device tensor [..., n_sc]")
+    shape = tuple(xf.shape[:-1]) + (fr.cp_len + fr.n_fft, 2)
+    x = _empty(shape, torch.int16, xf) if x is None else x
+    _need(x, "x", shape, torch.int16)
+    _check(load().rxphy_ifft_sc16(ctypes.byref(fr.c()), xf.numel() // fr.n_sc, _ptr(xf), float(scale), _ptr(x),
+                                  _stream()), "rxphy_ifft_sc16")
+    return x
 
 def demod(fr: Frame, xt, nu, llr=None):
     """-> llr f32 [F][K][D][n_sc][qam_bits]."""

@@ -251,6 +251,18 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
                                 (float2*)xf, flags, stream);
 }
 
+rxphy_status rxphy_ifft_sc16(const rxphy_frame* frame, int64_t n_rows, const void* xf, float scale, int16_t* x,
+                            hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, 0);
+  if (st) return st;
+  if (!(scale > 0.0f) || !std::isfinite(scale)) return fail(RXPHY_EINVAL, "scale = %g must be finite and > 0", scale);
+  if (n_rows < 0) return fail(RXPHY_EINVAL, "n_rows = %lld < 0", (long long)n_rows);
+  if (n_rows == 0) return RXPHY_OK;
+  if ((st = check_ptr(xf, "xf")) || (st = check_ptr(x, "x"))) return st;
+  return launch_ifft_rows_sc16(*frame, n_rows, (const float2*)xf, 1.0f / scale, (short2*)x, stream);
+}
+
 rxphy_status rxphy_ifft(const rxphy_frame* frame, int64_t n_rows, const void* xf, void* x, hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, 0);

@@ -52,6 +52,9 @@ rxphy_status launch_modulate(const rxphy_frame& fr, int64_t n_points, const uint
 // the forward FFT of 16-bit I/Q samples (value = integer * scale)
 rxphy_status launch_fft_sc16(const rxphy_frame& fr, int64_t n_tr, const short2* in, float scale, float2* out,
                              hipStream_t s);
+// the inverse rows with prefix as 16-bit I/Q: round(sample * out_scale), saturated
+rxphy_status launch_ifft_rows_sc16(const rxphy_frame& fr, int64_t n_rows, const float2* in, float out_scale,
+                                   short2* out, hipStream_t s);
 // |FFT| of n_rows F-point rows into float rows of F centred bins (TF plot)
 rxphy_status launch_fft_mag(int n_fft, int64_t n_rows, const float2* in, float* out, hipStream_t s);
 rxphy_status launch_ifft_rows(const rxphy_frame& fr, int64_t n_rows, const float2* in, float2* out,

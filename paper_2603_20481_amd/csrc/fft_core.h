@@ -145,11 +145,19 @@ __device__ __forceinline__ void load_input(const IN_T* __restrict__ in, int64_t 
 // skipped.  The twiddles a thread needs are the same for every transform, so
 // they are loaded into registers once.  `lds` holds Geom<N>::LDS
 // slots; the caller synchronises before reusing it.
-template <int N, bool INV, bool MAG = false, typename IN_T = float2>
+// Inverse output as 16-bit I/Q (the transmit fronthaul format): each
+// component times out_scale, rounded to nearest even and saturated.
+__device__ __forceinline__ short2 to_sc16(float2 v, float s) {
+  const int a = min(max(__float2int_rn(v.x * s), -32768), 32767);
+  const int b = min(max(__float2int_rn(v.y * s), -32768), 32767);
+  return make_short2((short)a, (short)b);
+}
+
+template <int N, bool INV, bool MAG = false, typename IN_T = float2, bool OUT16 = false>
 __device__ __forceinline__ void fft_tile(const IN_T* __restrict__ in, float2* __restrict__ out,
                                          const float2* __restrict__ tw, int64_t n_tr, int64_t base,
                                          int iters, int sym_len, int cp, int n_sc, float2* lds,
-                                         bool cp_tail = false, float in_scale = 1.f) {
+                                         bool cp_tail = false, float in_scale = 1.f, float out_scale = 1.f) {
   using G = Geom<N>;
   constexpr int T = G::T;
   constexpr int VT = G::VT;
@@ -278,6 +286,15 @@ __device__ __forceinline__ void fft_tile(const IN_T* __restrict__ in, float2* __
               const int i = (j + r * NS + half) & (N - 1);
               if (i < n_sc) dst[i] = w[r];
             }
+          } else if constexpr (OUT16) {
+            short2* dst = reinterpret_cast<short2*>(out) + tr * sym_len + cp;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const int n = j + r * NS;
+              const short2 q = to_sc16(w[r], out_scale);
+              dst[n] = q;
+              if (n >= N - cp) dst[n - N] = q;       // the cyclic prefix repeats the last cp samples
+            }
           } else {
             float2* dst = out + tr * sym_len + cp;
 #pragma unroll
@@ -290,7 +307,7 @@ __device__ __forceinline__ void fft_tile(const IN_T* __restrict__ in, float2* __
           }
         }
       }
-    if (INV && active && !cp_tail) {                // adjoint: the prefix carries no gradient
+    if (INV && !OUT16 && active && !cp_tail) {      // adjoint: the prefix carries no gradient
       float2* dst = out + tr * sym_len;
       for (int n = tid; n < cp; n += G::TT) dst[n] = make_float2(0.f, 0.f);
     }

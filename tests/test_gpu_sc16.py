@@ -94,3 +94,25 @@ def test_sc16_stream_equals_direct_calls(rx):
             assert np.array_equal(h["llr"], l) and np.array_equal(h["nu"], n) and np.array_equal(h["flags"], f)
     finally:
         st.close()
+
+
+@pytest.mark.parametrize("N,n_sc,cp", [(2048, 1200, 0), (1024, 601, 72), (512, 300, 36)])
+def test_ifft_sc16_is_the_quantised_ifft(rx, N, n_sc, cp):
+    """The 16-bit inverse output equals the FP32 inverse output multiplied by
+    1/scale in FP32, rounded to nearest even and saturated, bit for bit,
+    prefix included; a scale that overdrives the range saturates."""
+    sh = synth.Shape(4, 2, N, n_sc, 3, cp, 2)
+    fr = rx.Frame.of(sh, rx.ZF, 1.0)
+    rng = np.random.default_rng([33, N])
+    X = ((rng.standard_normal((2, 4, 3, n_sc)) + 1j * rng.standard_normal((2, 4, 3, n_sc))) * 3.0).astype(np.complex64)
+    xf = torch.from_numpy(X).cuda()
+    x32 = rx.ifft(fr, xf).cpu().numpy()
+    for scale in (2.0 ** -8, 0.0173, 2.0 ** -14):
+        q = rx.ifft_sc16(fr, xf, scale).cpu().numpy()
+        s = np.float32(1.0) / np.float32(scale)
+        ref = np.stack([np.rint(x32.real.astype(np.float32) * s), np.rint(x32.imag.astype(np.float32) * s)], -1)
+        ref = np.clip(ref, -32768, 32767).astype(np.int16)
+        sat = int(np.sum(np.abs(ref.astype(np.int32)) >= 32767))
+        say("ifft_sc16", N, n_sc, cp, "scale", scale, "saturated", sat)
+        assert np.array_equal(q, ref)
+        assert np.array_equal(q[..., :cp, :], q[..., N:N + cp, :])
