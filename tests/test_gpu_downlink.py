@@ -198,3 +198,24 @@ def test_precode_reuses_the_uplink_factors(rx, det):
         xf, fl = rx.precode(fr, yf, p, s, ws=ws, reuse_factors=True)
         torch.cuda.synchronize()
         assert torch.equal(xf, ref_x) and torch.equal(fl, ref_f), kind
+
+
+def test_empty_calls_are_no_ops(rx):
+    """Zero frames or rows: every downlink and 16-bit call returns OK and
+    touches nothing."""
+    import ctypes
+    lib = rx.load()
+    for K in (16, 4):
+        sh = synth.Shape(16, K, 512, 300, 6, 0, 2)
+        fr = rx.Frame.of(sh, rx.ZF, 1.0)
+        c = ctypes.byref(fr.c())
+        sentinel = torch.full((64,), 7, dtype=torch.uint8, device="cuda")
+        p = ctypes.c_void_p(sentinel.data_ptr())
+        assert lib.rxphy_modulate(c, 0, None, None, None) == 0
+        assert lib.rxphy_precode(c, 0, None, None, None, None, None, None, 0, 0, None) == 0
+        assert lib.rxphy_ifft(c, 0, None, None, None) == 0
+        assert lib.rxphy_ifft_sc16(c, 0, None, 1.0, None, None) == 0
+        assert lib.rxphy_fft_sc16(c, 0, None, 1.0, None, None) == 0
+        assert lib.rxphy_ifft(c, -1, p, p, None) == 1
+        torch.cuda.synchronize()
+        assert (sentinel == 7).all()
