@@ -277,6 +277,15 @@ def run_downlink(rx, torch, chain, args):
     e1.record()
     torch.cuda.synchronize()
     reuse_us = e0.elapsed_time(e1) / args.form_steps * 1e3
+    # modulation fused into the precoder (the symbols never stored), factors reused
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rx.modulate_precode(fr, chain.yf, chain.p, bits, xf, fl, wsu, reuse_factors=True)
+    e0.record()
+    for _ in range(args.form_steps):
+        rx.modulate_precode(fr, chain.yf, chain.p, bits, xf, fl, wsu, reuse_factors=True)
+    e1.record()
+    torch.cuda.synchronize()
+    fused_us = e0.elapsed_time(e1) / args.form_steps * 1e3
     # the time samples as 16-bit I/Q for the radio (power-of-two step with
     # one bit of headroom over the peak sample)
     peak = float(torch.max(torch.abs(torch.view_as_real(x))).item())
@@ -302,6 +311,11 @@ def run_downlink(rx, torch, chain, args):
                             "ms_per_step": round(per["modulate"] + reuse_us * 1e-3 + per["ifft"], 4),
                             "note": "precode reusing the uplink fused call's factor records "
                                     "(same frames, ZF): the factorisation is skipped"},
+           "modulate_precode": {"us": round(fused_us, 2),
+                                "ms_per_step_after_uplink": round((fused_us + per["ifft"] * 1e3) * 1e-3, 4),
+                                "ms_per_step_after_uplink_sc16_out": round((fused_us + ifft16_us) * 1e-3, 4),
+                                "note": "modulation fused into the precoder (the symbols never stored), "
+                                        "the uplink's factor records reused"},
            "sc16_out": {"ifft_us": round(ifft16_us, 2), "scale": q_scale,
                         "GBps": round(ifft16_bytes / (ifft16_us * 1e-6) / 1e9, 1), "bytes_per_launch": ifft16_bytes,
                         "ms_per_step_after_uplink": round(per["modulate"] + (reuse_us + ifft16_us) * 1e-3, 4),

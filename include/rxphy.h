@@ -216,6 +216,15 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
                            const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
                            uint32_t options, hipStream_t stream);
 
+/* rxphy_modulate_precode: rxphy_modulate then rxphy_precode in one call,
+ * the symbols never stored: each point is mapped from its bit bytes where
+ * the precoder reads it, so xf and flags equal those of the two calls bit
+ * for bit.  Arguments as rxphy_precode, with
+ *   bits : u8 [F][K][n_sym-1][n_sc][qam_bits] in place of sym               */
+rxphy_status rxphy_modulate_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
+                                    const uint8_t* bits, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
+                                    uint32_t options, hipStream_t stream);
+
 /* rxphy_ifft: inverse of rxphy_fft's used-bin transform, unscaled, with a
  * cyclic prefix: row r of xf (n_sc used subcarriers) becomes
  * x[r][cp_len + n] = sum_i xf[r][i] exp(+j 2 pi bin(i) n / N), n = 0..N-1,

@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_csi_detect_demod": [FR, I32, P, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_modulate": [FR, I32, P, P, P],
         "rxphy_precode": [FR, I32, P, P, P, P, P, P, SZ, ctypes.c_uint32, P],
+        "rxphy_modulate_precode": [FR, I32, P, P, P, P, P, P, SZ, ctypes.c_uint32, P],
         "rxphy_ifft": [FR, ctypes.c_int64, P, P, P],
         "rxphy_ifft_sc16": [FR, ctypes.c_int64, P, F32, P, P],
         "rxphy_demod": [FR, I32, P, P, P, P],
@@ -392,6 +393,30 @@ def precode(fr: Frame, yf, pilots, sym, xf=None, flags=None, ws=None, reuse_fact
                                 _ptr(flags), _ptr(ws), ws.numel() if ws is not None else 0,
                                 PRECODE_REUSE_FACTORS if reuse_factors else 0, _stream()),
            "rxphy_precode")
+    return xf, flags
+
+
+def modulate_precode(fr: Frame, yf, pilots, bits, xf=None, flags=None, ws=None, reuse_factors: bool = False):
+    """modulate then precode in one call (the symbols never stored) ->
+    (xf, flags), the same as precode(fr, yf, pilots, modulate(fr, bits))."""
+    F = _nf(yf)
+    D = fr.n_data
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    _need(bits, "bits", (F, fr.K, D, fr.n_sc, fr.qam_bits), torch.uint8)
+    xf = _empty((F, fr.M, D, fr.n_sc), torch.complex64, yf) if xf is None else xf
+    flags = _empty((F, fr.n_sc), torch.uint8, yf) if flags is None else flags
+    _need(xf, "xf", (F, fr.M, D, fr.n_sc), torch.complex64)
+    _need(flags, "flags", (F, fr.n_sc), torch.uint8)
+    need = workspace_bytes(fr, F, WS_PRECODE, "fp32")
+    if reuse_factors and ws is None:
+        raise RxphyError("reuse_factors needs the workspace that holds the uplink's factor records")
+    if need and ws is None:
+        ws = _empty((need,), torch.uint8, yf)
+    _check(load().rxphy_modulate_precode(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots), _ptr(bits), _ptr(xf),
+                                         _ptr(flags), _ptr(ws), ws.numel() if ws is not None else 0,
+                                         PRECODE_REUSE_FACTORS if reuse_factors else 0, _stream()),
+           "rxphy_modulate_precode")
     return xf, flags
 
 

@@ -13,7 +13,7 @@ namespace rxphy {
 
 // precode.hip: the precoder for K < 16 (one wave per pilot group)
 rxphy_status launch_precode_general(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                    const float2* sym, float2* xf, uint8_t* flags, hipStream_t s);
+                                    const void* src, int src_bits, float2* xf, uint8_t* flags, hipStream_t s);
 
 static thread_local char g_err[512];
 
@@ -227,9 +227,11 @@ rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const ui
   return launch_modulate(*frame, n, bits, (float2*)sym, stream);
 }
 
-rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
-                           const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
-                           uint32_t options, hipStream_t stream) {
+// rxphy_precode and rxphy_modulate_precode: the points come as complex64
+// symbols (src_bits = 0) or as bit bytes mapped on the fly (src_bits = Q).
+static rxphy_status precode_common(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
+                                   const void* src, int src_bits, void* xf, uint8_t* flags, void* ws,
+                                   size_t ws_bytes, uint32_t options, hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
@@ -241,14 +243,31 @@ rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const voi
   if (need && (!ws || ws_bytes < need))
     return fail(RXPHY_EWORKSPACE, "precode needs %zu workspace bytes, got %zu", need, ws_bytes);
   if (n_frames == 0) return RXPHY_OK;
-  if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) || (st = check_ptr(sym, "sym")) ||
-      (st = check_ptr(xf, "xf")))
+  if ((st = check_ptr(yf, "yf")) || (st = check_ptr(pilots, "pilots")) ||
+      (st = check_ptr(src, src_bits ? "bits" : "sym")) || (st = check_ptr(xf, "xf")))
     return st;
   if (frame->K == 16)
-    return launch_precode(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
-                          (float2*)xf, flags, ws, reuse, stream);
-  return launch_precode_general(*frame, n_frames, (const float2*)yf, (const float2*)pilots, (const float2*)sym,
+    return launch_precode(*frame, n_frames, (const float2*)yf, (const float2*)pilots, src, src_bits, (float2*)xf,
+                          flags, ws, reuse, stream);
+  return launch_precode_general(*frame, n_frames, (const float2*)yf, (const float2*)pilots, src, src_bits,
                                 (float2*)xf, flags, stream);
+}
+
+rxphy_status rxphy_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
+                           const void* sym, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
+                           uint32_t options, hipStream_t stream) {
+  return precode_common(frame, n_frames, yf, pilots, sym, 0, xf, flags, ws, ws_bytes, options, stream);
+}
+
+rxphy_status rxphy_modulate_precode(const rxphy_frame* frame, int32_t n_frames, const void* yf, const void* pilots,
+                                    const uint8_t* bits, void* xf, uint8_t* flags, void* ws, size_t ws_bytes,
+                                    uint32_t options, hipStream_t stream) {
+  if (frame && (frame->qam_bits != 2 && frame->qam_bits != 4 && frame->qam_bits != 6)) {
+    clear_error();
+    return fail(RXPHY_EINVAL, "qam_bits = %d", frame->qam_bits);
+  }
+  return precode_common(frame, n_frames, yf, pilots, bits, frame ? frame->qam_bits : 0, xf, flags, ws, ws_bytes,
+                        options, stream);
 }
 
 rxphy_status rxphy_ifft_sc16(const rxphy_frame* frame, int64_t n_rows, const void* xf, float scale, int16_t* x,

@@ -46,7 +46,8 @@ size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf);
 // Downlink: ZF precoder of 16 users from the uplink pilots (factor records in
 // ws, as the fused detector's); QAM mapping; inverse transform with a prefix.
 rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                            const float2* sym, float2* xf, uint8_t* flags, void* ws, bool reuse, hipStream_t s);
+                            const void* src, int src_bits, float2* xf, uint8_t* flags, void* ws, bool reuse,
+                            hipStream_t s);
 rxphy_status launch_modulate(const rxphy_frame& fr, int64_t n_points, const uint8_t* bits, float2* sym,
                              hipStream_t s);
 // the forward FFT of 16-bit I/Q samples (value = integer * scale)

@@ -52,6 +52,43 @@ __device__ __forceinline__ float2 ldg2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
+// One transmit point: Q = 0 reads a complex64 symbol; Q = 2, 4, 6 reads the
+// point's Q bit bytes (b0 first, non-zero = one) and maps them as
+// rxphy_modulate does (axis codes b0 b2 b4 / b1 b3 b5, most significant
+// first).  `e` is the point's element index (or past the range).
+template <int Q>
+__device__ __forceinline__ float2 load_point(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+  if constexpr (Q == 0) {
+    return ldg2(r, e * 8u);
+  } else {
+    uint32_t b = 0;                              // byte t of the point at bits 8t .. 8t+7
+    if constexpr (Q == 2) {
+      b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(e * 2u), 0, 0);
+    } else if constexpr (Q == 4) {
+      b = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e * 4u), 0, 0);
+    }
+    int ci = 0, cq = 0;
+    if constexpr (Q == 6) {
+      const uint32_t h0 = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(e * 6u), 0, 0);
+      const uint32_t h1 = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(e * 6u + 2u), 0, 0);
+      const uint32_t h2 = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(e * 6u + 4u), 0, 0);
+      const uint32_t by[6] = {h0 & 255u, h0 >> 8, h1 & 255u, h1 >> 8, h2 & 255u, h2 >> 8};
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        ci = 2 * ci + (by[2 * t] != 0);
+        cq = 2 * cq + (by[2 * t + 1] != 0);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < Q / 2; ++t) {
+        ci = 2 * ci + (((b >> (16 * t)) & 255u) != 0);
+        cq = 2 * cq + (((b >> (16 * t + 8)) & 255u) != 0);
+      }
+    }
+    return make_float2(demk::axis_level<Q>(ci), demk::axis_level<Q>(cq));
+  }
+}
+
 // Byte offsets are a lane part plus a wave-uniform part, formed next to each
 // load (the empty asm keeps the compiler from precomputing all of them into
 // registers).  The frame's buffer resource ends after antenna M - 1, so
@@ -424,9 +461,10 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
 // real products per complex one.  A tile whose factorisation broke down, or
 // whose channel is not finite, transmits nothing (X = 0) and is flagged.
 // One workgroup per (tile, frame); wave w owns the symbols d = w + 4 j.
+template <int Q>
 __global__ void __launch_bounds__(256)
 precode_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil,
-                     const GroupRec* __restrict__ rec, const float2* __restrict__ sym, float2* __restrict__ xf,
+                     const GroupRec* __restrict__ rec, const void* __restrict__ src, float2* __restrict__ xf,
                      uint8_t* __restrict__ flags, int M, int S, int n_sc) {
   __shared__ float2 hs[64 * 16];                // H of the tile: [antenna][user]
   const int tid = threadIdx.x, l = tid & 63;
@@ -468,15 +506,18 @@ precode_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ p
   // S[4 kq + r][d][i0 + u] for the wave's symbols (absent ones read zero)
   float2 sv[4][4];
   {
-    const __amdgpu_buffer_rsrc_t sr = rsrc(sym + f * 16 * D * n_sc, (uint32_t)16 * D * n_sc * 8u);
-    const uint32_t lane = i0 + u < n_sc ? (uint32_t)((4 * kq * D + w) * n_sc + i0 + u) * 8u : OOB;
+    constexpr uint32_t PB = Q ? Q : 8;           // bytes per point
+    const __amdgpu_buffer_rsrc_t sr =
+        rsrc((const uint8_t*)src + f * 16 * D * n_sc * PB, (uint32_t)16 * D * n_sc * PB);
+    const uint32_t OOBE = OOB / 8u;              // an element index whose byte offset is past any range
+    const uint32_t lane = i0 + u < n_sc ? (uint32_t)((4 * kq * D + w) * n_sc + i0 + u) : OOBE;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      uint32_t row = opaque(j < nj ? lane + (uint32_t)j * 4u * n_sc * 8u : OOB);
+      uint32_t row = opaque(j < nj ? lane + (uint32_t)j * 4u * n_sc : OOBE);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        sv[j][r] = ldg2(sr, row);
-        row = opaque(row + (uint32_t)D * n_sc * 8u);
+        sv[j][r] = load_point<Q>(sr, row);
+        row = opaque(row + (uint32_t)D * n_sc);
       }
     }
   }
@@ -536,7 +577,8 @@ precode_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ p
 }  // namespace
 
 rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                            const float2* sym, float2* xf, uint8_t* flags, void* ws, bool reuse, hipStream_t s) {
+                            const void* src, int src_bits, float2* xf, uint8_t* flags, void* ws, bool reuse,
+                            hipStream_t s) {
   if (nf == 0) return RXPHY_OK;
   if (fr.K != 16) return fail(RXPHY_EUNSUPPORTED, "precode: K = %d (the precoder is built for 16 users)", fr.K);
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
@@ -550,8 +592,14 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
     rxphy_status st = launch_status("group factor kernel");
     if (st) return st;
   }
-  hipLaunchKernelGGL(precode_group_kernel, dim3(nt, nf), dim3(256), 0, s, yf, pil, rec, sym, xf, flags, fr.M,
-                     fr.n_sym, fr.n_sc);
+  const dim3 grid(nt, nf);
+  switch (src_bits) {
+    case 0: hipLaunchKernelGGL(precode_group_kernel<0>, grid, dim3(256), 0, s, yf, pil, rec, src, xf, flags, fr.M, fr.n_sym, fr.n_sc); break;
+    case 2: hipLaunchKernelGGL(precode_group_kernel<2>, grid, dim3(256), 0, s, yf, pil, rec, src, xf, flags, fr.M, fr.n_sym, fr.n_sc); break;
+    case 4: hipLaunchKernelGGL(precode_group_kernel<4>, grid, dim3(256), 0, s, yf, pil, rec, src, xf, flags, fr.M, fr.n_sym, fr.n_sc); break;
+    case 6: hipLaunchKernelGGL(precode_group_kernel<6>, grid, dim3(256), 0, s, yf, pil, rec, src, xf, flags, fr.M, fr.n_sym, fr.n_sc); break;
+    default: return fail(RXPHY_EINVAL, "qam_bits = %d", src_bits);
+  }
   return launch_status("precode kernel");
 }
 

@@ -11,6 +11,7 @@
 // A pivot <= 0 or not finite erases the group and flags BREAKDOWN; a
 // non-finite estimate erases it and flags NONFINITE.
 #include "common.h"
+#include "demod_core.h"
 
 namespace rxphy {
 namespace {
@@ -25,8 +26,27 @@ __device__ __forceinline__ float2 cmc(float2 a, float2 b) {         // conj(a) b
   return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// One transmit point: a complex64 symbol (Q = 0), or Q bit bytes mapped as
+// rxphy_modulate maps them (axis codes b0 b2 b4 / b1 b3 b5).
+template <int Q>
+__device__ __forceinline__ float2 point_at(const void* src, int64_t e) {
+  if constexpr (Q == 0) {
+    return static_cast<const float2*>(src)[e];
+  } else {
+    const uint8_t* b = static_cast<const uint8_t*>(src) + e * Q;
+    int ci = 0, cq = 0;
+#pragma unroll
+    for (int t = 0; t < Q / 2; ++t) {
+      ci = 2 * ci + (b[2 * t] != 0);
+      cq = 2 * cq + (b[2 * t + 1] != 0);
+    }
+    return make_float2(demk::axis_level<Q>(ci), demk::axis_level<Q>(cq));
+  }
+}
+
+template <int Q>
 __global__ void __launch_bounds__(64)
-precode_general_kernel(const float2* __restrict__ yf, const float2* __restrict__ pil, const float2* __restrict__ sym,
+precode_general_kernel(const float2* __restrict__ yf, const float2* __restrict__ pil, const void* __restrict__ sym,
                        float2* __restrict__ xf, uint8_t* __restrict__ flags, int M, int K, int S, int n_sc,
                        float n0, int mmse) {
   __shared__ float2 H[PM * PK];               // [m][u]
@@ -93,7 +113,7 @@ precode_general_kernel(const float2* __restrict__ yf, const float2* __restrict__
   const int w = i1 - i0;                      // <= 2K - 1 < 64
   if (flags && tid < w) flags[f * n_sc + i0 + tid] = st == 2 ? RXPHY_FLAG_NONFINITE : (st ? RXPHY_FLAG_BREAKDOWN : 0);
   float2* xo = xf + f * M * D * n_sc;
-  const float2* so = sym + f * K * D * n_sc;
+  const int64_t so = f * K * D * n_sc;          // first point of the frame
   for (int r = tid; r < D * w; r += 64) {
     const int d = r / w, i = i0 + (r - d * w);
     if (st) {
@@ -101,7 +121,7 @@ precode_general_kernel(const float2* __restrict__ yf, const float2* __restrict__
       continue;
     }
     float2* v = vb + tid * (PK + 1);               // this lane's right-hand side (odd stride: no bank clash)
-    for (int u = 0; u < K; ++u) v[u] = so[((int64_t)u * D + d) * n_sc + i];
+    for (int u = 0; u < K; ++u) v[u] = point_at<Q>(sym, so + ((int64_t)u * D + d) * n_sc + i);
     for (int a = 0; a < K; ++a) {                  // L y = s
       float2 t = v[a];
       for (int b = 0; b < a; ++b) {
@@ -135,12 +155,22 @@ precode_general_kernel(const float2* __restrict__ yf, const float2* __restrict__
 }  // namespace
 
 rxphy_status launch_precode_general(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                    const float2* sym, float2* xf, uint8_t* flags, hipStream_t s) {
+                                    const void* src, int src_bits, float2* xf, uint8_t* flags, hipStream_t s) {
   if (nf == 0) return RXPHY_OK;
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
-  const int G = fr.n_sc / fr.K;
-  hipLaunchKernelGGL(precode_general_kernel, dim3(G, nf), dim3(64), 0, s, yf, pil, sym, xf, flags, fr.M, fr.K,
-                     fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  const dim3 grid(fr.n_sc / fr.K, nf);
+  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
+#define RXPHY_PRECODE_GENERAL(QQ)                                                                               \
+  hipLaunchKernelGGL(precode_general_kernel<QQ>, grid, dim3(64), 0, s, yf, pil, src, xf, flags, fr.M, fr.K, \
+                     fr.n_sym, fr.n_sc, fr.n0, mmse)
+  switch (src_bits) {
+    case 0: RXPHY_PRECODE_GENERAL(0); break;
+    case 2: RXPHY_PRECODE_GENERAL(2); break;
+    case 4: RXPHY_PRECODE_GENERAL(4); break;
+    case 6: RXPHY_PRECODE_GENERAL(6); break;
+    default: return fail(RXPHY_EINVAL, "qam_bits = %d", src_bits);
+  }
+#undef RXPHY_PRECODE_GENERAL
   return launch_status("precode kernel (general K)");
 }
 

@@ -219,3 +219,33 @@ def test_empty_calls_are_no_ops(rx):
         assert lib.rxphy_ifft(c, -1, p, p, None) == 1
         torch.cuda.synchronize()
         assert (sentinel == 7).all()
+
+
+@pytest.mark.parametrize("sh,det", [(synth.Shape(64, 16, 2048, 1200, 14, 0, 4), 0),
+                                    (synth.Shape(21, 16, 512, 500, 17, 0, 2), 1),
+                                    (synth.Shape(64, 16, 4096, 3276, 5, 0, 6), 0),
+                                    (synth.Shape(32, 8, 1024, 600, 14, 0, 6), 1),
+                                    (synth.Shape(13, 5, 512, 301, 6, 0, 2), 0),
+                                    (synth.Shape(8, 1, 512, 64, 3, 0, 4), 1)])
+def test_modulate_precode_equals_the_two_calls(rx, sh, det):
+    """The fused call maps each point from its bit bytes where the precoder
+    reads it: xf and flags equal modulate + precode bit for bit (also with
+    the uplink's factor records reused for 16 users)."""
+    frs = [synth.make_frame(4, 30 + f, shape=sh) for f in range(2)]
+    x = dev(np.stack([f.x for f in frs]))
+    p = dev(np.stack([f.pilots for f in frs]))
+    p[1, 5] = 0
+    fr = rx.Frame.of(sh, det, 1.0)
+    yf = rx.fft(fr, x)
+    rng = np.random.default_rng([25, sh.K, sh.qam_bits])
+    bits = dev((rng.integers(0, 2, (2, sh.K, sh.n_data, sh.n_sc, sh.qam_bits)) * rng.integers(1, 4, 1)[0]).astype(np.uint8))
+    ref_x, ref_f = rx.precode(fr, yf, p, rx.modulate(fr, bits))
+    xf, fl = rx.modulate_precode(fr, yf, p, bits)
+    torch.cuda.synchronize()
+    assert torch.equal(xf, ref_x) and torch.equal(fl, ref_f)
+    if sh.K == 16:
+        ws = torch.empty((rx.workspace_bytes(fr, 2, rx.WS_CSI_DETECT_DEMOD, "fp32"),), dtype=torch.uint8, device="cuda")
+        rx.csi_detect_demod(fr, yf, p, ws=ws)
+        xr, flr = rx.modulate_precode(fr, yf, p, bits, ws=ws, reuse_factors=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xr, ref_x) and torch.equal(flr, ref_f)
