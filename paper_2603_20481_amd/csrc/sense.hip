@@ -34,7 +34,6 @@ namespace rxphy {
 namespace {
 
 constexpr int SG_MAX = 63;
-constexpr int PIX_BLK = 1024;                  // pixels per flatten / assign workgroup
 
 // Per 64x64 tile: its local components (after the morphology), each with its
 // root (the component's first pixel, a plot-local index) and its bounding box
@@ -564,63 +563,100 @@ merge_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int T,
   }
 }
 
-__device__ __forceinline__ int block_count(int v, int* red) {
-  // sum of v over the 256 threads (every thread gets it)
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const int s = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  return s;
-}
-
-__global__ void __launch_bounds__(256)
-flatten_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int32_t* __restrict__ cnt, int T,
-               int F, int nblk) {
-  __shared__ int red[4];
-  const int64_t p = blockIdx.y;
-  const int n = T * F;
-  const uint8_t* m = mask + p * n;
-  int* L = lab + p * n;
-  int roots = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int q = blockIdx.x * PIX_BLK + threadIdx.x * 4 + i;
-    if (q < n && m[q]) {
-      const int r = find_root(L, q);
-      L[q] = r;
-      roots += r == q;
+// Global roots are counted per (row, tile column): in that order the counts
+// follow the raster order of the roots, so their prefix sum gives each root
+// its raster ordinal.  One wave per 64x64 tile.  A tile with a component list
+// resolves only its listed local roots (every other pixel of the tile still
+// points at its local root, which the box kernel follows); a tile whose list
+// overflowed resolves every labelled pixel.  A root is the component's first
+// pixel, so it sits in the tile that holds it and is counted there once.
+__global__ void __launch_bounds__(64)
+flatten_kernel(int32_t* __restrict__ lab, const TileList* __restrict__ tl, int32_t* __restrict__ cnt, int T, int F) {
+  __shared__ int rc[64];
+  const int64_t p = blockIdx.z;
+  const int t0 = blockIdx.y * 64, f0 = blockIdx.x * 64;
+  const int TX = gridDim.x;
+  int* L = lab + p * T * F;
+  int32_t* C = cnt + p * T * TX;
+  const int lane = threadIdx.x;
+  const int n = tl[(p * gridDim.y + blockIdx.y) * TX + blockIdx.x].n;
+  if (n >= 0) {
+    const TileEntry* te = tl[(p * gridDim.y + blockIdx.y) * TX + blockIdx.x].e;
+    rc[lane] = 0;
+    __syncthreads();
+    if (lane < n) {
+      const int x = te[lane].root;
+      const int r = find_root(L, x);
+      if (r != x)
+        L[x] = r;
+      else
+        atomicAdd(&rc[x / F - t0], 1);
     }
+    __syncthreads();
+    if (t0 + lane < T) C[(t0 + lane) * TX + blockIdx.x] = rc[lane];
+    return;
   }
-  roots = block_count(roots, red);
-  if (threadIdx.x == 0) cnt[p * nblk + blockIdx.x] = roots;
+  for (int r = 0; r < 64 && t0 + r < T; ++r) {
+    const int q = (t0 + r) * F + f0 + lane;
+    const int l = L[q];
+    bool root = false;
+    if (l >= 0) {
+      const int g = find_root(L, q);
+      if (g != q) L[q] = g;
+      root = g == q;
+    }
+    const uint64_t rb = __ballot(root);
+    if (lane == 0) C[(t0 + r) * TX + blockIdx.x] = __builtin_popcountll(rb);
+  }
 }
 
+// Exclusive prefix sum of a plot's counts (n a multiple of 4, 16-byte
+// aligned): 4096 counts per pass, four per thread, wave scans by shuffles and
+// one LDS exchange of the 16 wave totals; four passes' loads are issued
+// before their sums.  Also sets the plot's box count and clears its boxes.
 __global__ void __launch_bounds__(1024)
 scan_kernel(const int32_t* __restrict__ cnt, int32_t* __restrict__ off, int32_t* __restrict__ n_boxes,
-            int32_t* __restrict__ boxes, int max_boxes, int nblk) {
-  __shared__ int part[1024];
-  const int tid = threadIdx.x;
+            int32_t* __restrict__ boxes, int max_boxes, int ncnt) {
+  __shared__ int wsum[2][16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t p = blockIdx.x;
-  const int per = (nblk + 1023) / 1024;
-  const int b0 = tid * per, b1 = min(nblk, b0 + per);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += cnt[p * nblk + b];
-  part[tid] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {          // inclusive Hillis-Steele scan
-    const int v = tid >= o ? part[tid - o] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  const int4* c4 = reinterpret_cast<const int4*>(cnt + p * ncnt);
+  int4* o4 = reinterpret_cast<int4*>(off + p * ncnt);
+  const int n4 = ncnt / 4;
+  int carry = 0, buf = 0;
+  for (int c0 = 0; c0 < n4; c0 += 4 * 1024) {
+    int4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = c0 + k * 1024 + tid;
+      v[k] = i < n4 ? c4[i] : make_int4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = c0 + k * 1024 + tid;
+      const int s4 = v[k].x + v[k].y + v[k].z + v[k].w;
+      int inc = s4;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+      }
+      if (lane == 63) wsum[buf][w] = inc;
+      __syncthreads();
+      int below = 0, total = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int ws = wsum[buf][j];
+        below += j < w ? ws : 0;
+        total += ws;
+      }
+      buf ^= 1;                                   // the next pass writes the other half: one barrier per pass
+      const int ex = carry + below + inc - s4;
+      if (i < n4) o4[i] = make_int4(ex, ex + v[k].x, ex + v[k].x + v[k].y, ex + v[k].x + v[k].y + v[k].z);
+      carry += total;
+    }
   }
-  int run = part[tid] - s;
-  for (int b = b0; b < b1; ++b) {
-    off[p * nblk + b] = run;
-    run += cnt[p * nblk + b];
-  }
-  if (tid == 1023) n_boxes[p] = part[1023];
+  if (tid == 0) n_boxes[p] = carry;
   for (int i = tid; i < max_boxes; i += 1024) {
     int32_t* bx = boxes + (p * max_boxes + i) * 4;
     bx[0] = INT_MAX;
@@ -630,40 +666,45 @@ scan_kernel(const int32_t* __restrict__ cnt, int32_t* __restrict__ off, int32_t*
   }
 }
 
-__global__ void __launch_bounds__(256)
-assign_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, const int32_t* __restrict__ off,
-              int T, int F, int nblk) {
-  __shared__ int wsum[4];
-  const int64_t p = blockIdx.y;
-  const int n = T * F;
-  const uint8_t* m = mask + p * n;
-  int* L = lab + p * n;
-  bool root[4];
-  int mine = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int q = blockIdx.x * PIX_BLK + threadIdx.x * 4 + i;
-    root[i] = q < n && m[q] && L[q] == q;
-    mine += root[i];
+// Each global root of the tile takes -2 - its raster ordinal: the prefix of
+// its (row, tile column) count plus the tile's roots left of it in its row.
+__global__ void __launch_bounds__(64)
+assign_kernel(int32_t* __restrict__ lab, const TileList* __restrict__ tl, const int32_t* __restrict__ off, int T,
+              int F) {
+  __shared__ int key[TL_CAP];                   // row * 64 + column of a global root, -1 for the others
+  const int64_t p = blockIdx.z;
+  const int t0 = blockIdx.y * 64, f0 = blockIdx.x * 64;
+  const int TX = gridDim.x;
+  int* L = lab + p * T * F;
+  const int32_t* O = off + p * T * TX;
+  const int lane = threadIdx.x;
+  const TileList& tile = tl[(p * gridDim.y + blockIdx.y) * TX + blockIdx.x];
+  const int n = tile.n;
+  if (n >= 0) {
+    int x = -1, k = -1;
+    if (lane < n) {
+      x = tile.e[lane].root;
+      if (L[x] == x) k = (x / F - t0) * 64 + (x % F - f0);
+    }
+    key[lane] = k;
+    __syncthreads();
+    if (k >= 0) {
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        const int kj = key[j];
+        rank += kj >= 0 && (kj >> 6) == (k >> 6) && kj < k;
+      }
+      L[x] = -2 - (O[(t0 + (k >> 6)) * TX + blockIdx.x] + rank);
+    }
+    return;
   }
-  // exclusive prefix of `mine` over the workgroup (thread order = raster order)
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int inc = mine;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += v;
-  }
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  int base = off[p * nblk + blockIdx.x];
-  for (int i = 0; i < w; ++i) base += wsum[i];
-  int ord = base + inc - mine;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (root[i]) {
-      L[blockIdx.x * PIX_BLK + threadIdx.x * 4 + i] = -2 - ord;   // a root holds -2 - its ordinal
-      ++ord;
+  for (int r = 0; r < 64 && t0 + r < T; ++r) {
+    const int q = (t0 + r) * F + f0 + lane;
+    const bool root = L[q] == q;
+    const uint64_t rb = __ballot(root);
+    if (root) {
+      const int rank = __builtin_popcountll(rb & ((1ull << lane) - 1ull));
+      L[q] = -2 - (O[(t0 + r) * TX + blockIdx.x] + rank);
     }
   }
 }
@@ -788,7 +829,7 @@ struct SenseLayout {
 
 SenseLayout layout(const rxphy_sense_config& c, int32_t P) {
   const size_t TF = (size_t)c.n_rows * c.n_fft, F = c.n_fft;
-  const size_t nblk = (TF + PIX_BLK - 1) / PIX_BLK;
+  const size_t ncnt = (size_t)c.n_rows * (c.n_fft / 64);   // root counts per (row, tile column)
   SenseLayout L{};
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -806,8 +847,8 @@ SenseLayout layout(const rxphy_sense_config& c, int32_t P) {
   L.mask = put(P * TF);
   L.mask_mo = put(P * TF);
   L.lab = put(P * TF * 4);
-  L.cnt = put(P * nblk * 4);
-  L.off = put(P * nblk * 4);
+  L.cnt = put(P * ncnt * 4);
+  L.off = put(P * ncnt * 4);
   L.tl = put(P * (size_t)(c.n_fft / 64) * ((c.n_rows + 63) / 64) * sizeof(TileList));
   L.total = o;
   return L;
@@ -840,7 +881,7 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   const rxphy_sense_config& c = *cfg;
   const int T = c.n_rows, F = c.n_fft, P = n_plots;
   const int64_t TF = (int64_t)T * F;
-  const int nblk = (int)((TF + PIX_BLK - 1) / PIX_BLK);
+  const int ncnt = T * (F / 64);
   char* w = (char*)ws;
   rxphy_sense_outputs o{};
   if (out) o = *out;
@@ -874,11 +915,11 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   if ((st = launch_status("morph kernel"))) return st;
   hipLaunchKernelGGL(merge_kernel, dim3(strips, (T + 63) / 64, P), dim3(128), 0, stream, mask_mo, lab, T, F);
   if ((st = launch_status("merge kernel"))) return st;
-  hipLaunchKernelGGL(flatten_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, cnt, T, F, nblk);
+  hipLaunchKernelGGL(flatten_kernel, dim3(strips, (T + 63) / 64, P), dim3(64), 0, stream, lab, tl, cnt, T, F);
   if ((st = launch_status("flatten kernel"))) return st;
-  hipLaunchKernelGGL(scan_kernel, dim3(P), dim3(1024), 0, stream, cnt, off, n_boxes, boxes, max_boxes, nblk);
+  hipLaunchKernelGGL(scan_kernel, dim3(P), dim3(1024), 0, stream, cnt, off, n_boxes, boxes, max_boxes, ncnt);
   if ((st = launch_status("scan kernel"))) return st;
-  hipLaunchKernelGGL(assign_kernel, dim3(nblk, P), dim3(256), 0, stream, mask_mo, lab, off, T, F, nblk);
+  hipLaunchKernelGGL(assign_kernel, dim3(strips, (T + 63) / 64, P), dim3(64), 0, stream, lab, tl, off, T, F);
   if ((st = launch_status("assign kernel"))) return st;
   if (max_boxes > 0) {
     hipLaunchKernelGGL(boxes_kernel, dim3(strips, (T + 63) / 64, P), dim3(256), 0, stream, mask_mo, lab, tl, boxes,
