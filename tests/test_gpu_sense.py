@@ -184,3 +184,44 @@ def test_sense_dense_lattice_overflows_the_tile_lists(rx):
     say("lattice", T, F, "boxes", len(bx), "mask equals lattice", bool(np.array_equal(g["mask_mo"][0], lat)))
     assert np.array_equal(g["mask_mo"][0], lat.astype(np.uint8))
     assert len(bx) > 64 * (T // 64) * (F // 64) // 4
+
+
+def test_sense_components_across_listed_and_overflowed_tiles(rx):
+    """Lattice tiles (lists overflowed, resolved pixel by pixel) next to
+    tiles with component lists, with components that cross between them in
+    both directions (first pixel in a listed tile with pixels in overflowed
+    tiles, and the reverse), and a partial last tile row: boxes equal the
+    oracle's."""
+    ndimage = pytest.importorskip("scipy.ndimage")
+    T, F = 250, 512
+    t, f = np.arange(T)[:, None], np.arange(F)[None, :]
+    on = (((t - 2) % 6) < 3) & (((f - 2) % 6) < 3) & (t >= 64) & (f < 256)
+    on[150:171, 0:421] = True                    # band from the lattice into listed tiles
+    on[40:71, 200:301] = True                    # first pixel in a listed tile, reaches the lattice
+    on[20:51, 300:401] = True
+    on[180:241, 440:481] = True
+    cols = (np.arange(F) - F // 2) % F
+    Xb = np.zeros((T, F), np.complex128)
+    Xb[:, cols] = np.where(on, 100.0, 1.0)
+    x = np.fft.ifft(Xb, axis=1).astype(np.complex64)
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ocfg = S.SenseConfig(F=F, T=T)
+    out = rx.sense(cfg, torch.from_numpy(x[None]).cuda(), max_boxes=2048, intermediates=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    retained, bx = check_plot(cfg, ocfg, x, g, 0, 2048)
+    mo = g["mask_mo"][0].astype(bool)
+    ov = np.zeros((T, F), bool)
+    for ty in range(0, T, 64):
+        for tx in range(0, F, 64):
+            ov[ty:ty + 64, tx:tx + 64] = ndimage.label(mo[ty:ty + 64, tx:tx + 64])[1] > 64
+    lab, nc = ndimage.label(mo)
+    kinds = set()
+    for c in range(1, nc + 1):
+        pix = np.argwhere(lab == c)
+        o = ov[pix[:, 0], pix[:, 1]]
+        if o.any() and (~o).any():
+            kinds.add(bool(ov[pix[0][0], pix[0][1]]))
+    say("mixed lattice", T, F, "boxes", len(bx), "overflowed tiles", int(ov[::64, ::64].sum()), "crossings", kinds)
+    assert 0 < ov[::64, ::64].sum() < ov[::64, ::64].size
+    assert kinds == {True, False}
