@@ -68,6 +68,7 @@ __device__ __forceinline__ float wave_min(float v) {
 // Column kernels: 64 columns per workgroup (lane = column, 256-byte row
 // loads), CW waves over the rows.
 constexpr int CW = 16;
+constexpr int OU = 8;                         // rows per wave whose loads the Otsu passes issue together
 
 __global__ void __launch_bounds__(64 * CW)
 colstat_kernel(const float* __restrict__ tf, float* __restrict__ psd, float* __restrict__ lo,
@@ -196,9 +197,20 @@ otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const f
   const uint32_t* hc = hist + lane * stride;
   __syncthreads();
   if (keep) {
-    for (int t = w; t < T; t += CW) {
-      const int b = value_bin(col[(int64_t)t * F], lo, scale, bins);
-      atomicAdd(hist + lane * stride + (b >> 1), 1u << ((b & 1) * 16));
+    for (int t0 = w; t0 < T; t0 += CW * OU) {    // OU loads in flight per wave before their bins
+      float v[OU];
+#pragma unroll
+      for (int u = 0; u < OU; ++u) {
+        const int t = t0 + u * CW;
+        v[u] = t < T ? col[(int64_t)t * F] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < OU; ++u) {
+        if (t0 + u * CW < T) {
+          const int b = value_bin(v[u], lo, scale, bins);
+          atomicAdd(hist + lane * stride + (b >> 1), 1u << ((b & 1) * 16));
+        }
+      }
     }
   }
   __syncthreads();
@@ -256,8 +268,19 @@ otsu_kernel(const float* __restrict__ tf, const float* __restrict__ psd, const f
   __syncthreads();
   const int k = kk[lane];
   uint8_t* mc = mask + p * T * F + c;
-  for (int t = w; t < T; t += CW)
-    mc[(int64_t)t * F] = (k >= 0 && value_bin(col[(int64_t)t * F], lo, scale, bins) > k) ? 1 : 0;
+  for (int t0 = w; t0 < T; t0 += CW * OU) {
+    float v[OU];
+#pragma unroll
+    for (int u = 0; u < OU; ++u) {
+      const int t = t0 + u * CW;
+      v[u] = t < T && k >= 0 ? col[(int64_t)t * F] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < OU; ++u) {
+      const int t = t0 + u * CW;
+      if (t < T) mc[(int64_t)t * F] = (k >= 0 && value_bin(v[u], lo, scale, bins) > k) ? 1 : 0;
+    }
+  }
 }
 
 // ------------------------------------------------------------ morphology
@@ -348,9 +371,10 @@ __device__ void lunite(volatile int* lab, int a, int b) {
 }
 
 // After the morphology the tile's components are labelled in LDS (union-find
-// over row runs) and every pixel's global label is its local root's global
-// index (-1: background); only unions across tile borders are left for the
-// global pass.
+// over row runs); a pixel's global label is its local root's global index
+// (-1: background), written for the tile's border pixels and roots (for every
+// pixel if the tile's list overflows); only unions across tile borders are
+// left for the global pass.
 __global__ void __launch_bounds__(256)
 morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab,
              TileList* __restrict__ tl, int T, int F) {
@@ -434,24 +458,6 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
     }
   }
   __syncthreads();
-  uint8_t* o = out + p * T * F;
-  int32_t* L = lab + p * T * F;
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    const int r = idx >> 6, c = idx & 63;
-    const int t = t0 + r, f = f0 + c;
-    if (t < T) {
-      const uint64_t row = crow[r];
-      const bool fg = ((row >> c) & 1ull) != 0;
-      o[(int64_t)t * F + f] = fg ? 1 : 0;
-      int g = -1;
-      if (fg) {
-        const uint64_t st = row & ~(row << 1) & lowmask(c + 1);
-        const int root = lfind(vl, r * 64 + 63 - __builtin_clzll(st));
-        g = (t0 + (root >> 6)) * F + f0 + (root & 63);
-      }
-      L[(int64_t)t * F + f] = g;
-    }
-  }
   // the tile's component list: roots numbered in any order, boxes reduced per
   // row run with LDS atomics
   if (threadIdx.x == 0) nroots = 0;
@@ -496,8 +502,33 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
     }
   }
   __syncthreads();
-  TileList& out_l = tl[(p * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  // Labels: the tile's border pixels (the merge reads them) and, below, its
+  // listed roots; every pixel when the list overflows (the later passes then
+  // read the tile pixel by pixel).  Interior labels of a listed tile are never
+  // read.
   const int n = nroots;
+  const bool all_px = n > TL_CAP;
+  uint8_t* o = out + p * T * F;
+  int32_t* L = lab + p * T * F;
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int r = idx >> 6, c = idx & 63;
+    const int t = t0 + r, f = f0 + c;
+    if (t < T) {
+      const uint64_t row = crow[r];
+      const bool fg = ((row >> c) & 1ull) != 0;
+      o[(int64_t)t * F + f] = fg ? 1 : 0;
+      if (all_px || r == 0 || r == 63 || c == 0 || c == 63) {
+        int g = -1;
+        if (fg) {
+          const uint64_t st = row & ~(row << 1) & lowmask(c + 1);
+          const int root = lfind(vl, r * 64 + 63 - __builtin_clzll(st));
+          g = (t0 + (root >> 6)) * F + f0 + (root & 63);
+        }
+        L[(int64_t)t * F + f] = g;
+      }
+    }
+  }
+  TileList& out_l = tl[(p * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
   if (threadIdx.x == 0) out_l.n = n <= TL_CAP ? n : -1;
   if (n <= TL_CAP) {
     for (int e = threadIdx.x; e < n; e += 256) {
@@ -509,6 +540,7 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
       te.t1 = (int16_t)(t0 + bb[e][2]);
       te.f1 = (int16_t)(f0 + bb[e][3]);
       out_l.e[e] = te;
+      L[te.root] = te.root;
     }
   }
 }
@@ -544,7 +576,9 @@ __device__ void unite(int* L, int a, int b) {
 
 // Unions across tile borders: thread i < 64 takes the tile's top row pixel i
 // and the pixel above it, thread 64 + i the left column pixel i and the pixel
-// to its left.
+// to its left.  Only the first pixel of each run of such pairs along the
+// border unites: its neighbour along the border pairs pixels of the same two
+// local components (one row or column run on each side).
 __global__ void __launch_bounds__(128)
 merge_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int T, int F) {
   const int f0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
@@ -553,14 +587,20 @@ merge_kernel(const uint8_t* __restrict__ mask, int32_t* __restrict__ lab, int T,
   const uint8_t* m = mask + p * n;
   int* L = lab + p * n;
   const int i = threadIdx.x & 63;
+  int q = 0, nb = 0;
+  bool pair = false;
   if (threadIdx.x < 64) {
-    const int q = t0 * F + f0 + i;
-    if (t0 > 0 && m[q] && m[q - F]) unite(L, q, q - F);
+    q = t0 * F + f0 + i;
+    nb = q - F;
+    pair = t0 > 0 && m[q] && m[nb];
   } else {
     const int t = t0 + i;
-    const int q = t * F + f0;
-    if (f0 > 0 && t < T && m[q] && m[q - 1]) unite(L, q, q - 1);
+    q = t * F + f0;
+    nb = q - 1;
+    pair = f0 > 0 && t < T && m[q] && m[nb];
   }
+  const uint64_t pb = __ballot(pair);
+  if (pair && (i == 0 || !((pb >> (i - 1)) & 1ull))) unite(L, q, nb);
 }
 
 // Global roots are counted per (row, tile column): in that order the counts
