@@ -79,11 +79,18 @@ colstat_kernel(const float* __restrict__ tf, float* __restrict__ psd, float* __r
   const int64_t p = blockIdx.y;
   const float* col = tf + p * T * F + c;
   float s = 0.f, mn = INFINITY, mx = -INFINITY;
-  for (int t = w; t < T; t += CW) {
-    const float v = col[(int64_t)t * F];
-    s += v;
-    mn = fminf(mn, v);
-    mx = fmaxf(mx, v);
+  for (int t0 = w; t0 < T; t0 += CW * OU) {      // OU loads in flight; summed in row order as they arrive
+    float v[OU];
+#pragma unroll
+    for (int u = 0; u < OU; ++u) v[u] = col[(int64_t)min(t0 + u * CW, T - 1) * F];
+#pragma unroll
+    for (int u = 0; u < OU; ++u) {
+      if (t0 + u * CW < T) {
+        s += v[u];
+        mn = fminf(mn, v[u]);
+        mx = fmaxf(mx, v[u]);
+      }
+    }
   }
   ss[w][lane] = s;
   smn[w][lane] = mn;
@@ -389,15 +396,25 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
   const int64_t p = blockIdx.z;
   const uint8_t* m = mask + p * T * F;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int r = w; r < MR; r += 4) {               // one region row per wave step: two ballots each
-    const int t = t0 - 4 + r;
+  // region row w + 4 j per wave step j, two ballots each; every load of the
+  // wave is issued before the first ballot
+  constexpr int RW = MR / 4;
+  uint8_t va[RW], vb[RW];
+  const int fa = f0 - 6 + lane, fb = f0 - 6 + 64 + lane;
+  const bool ca = fa >= 0 && fa < F, cb = lane < MC - 64 && fb >= 0 && fb < F;
+  const int fa_c = min(max(fa, 0), F - 1), fb_c = min(max(fb, 0), F - 1);   // in-plot addresses: no branches
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const int t = min(max(t0 - 4 + w + 4 * j, 0), T - 1);
+    va[j] = m[(int64_t)t * F + fa_c];
+    vb[j] = m[(int64_t)t * F + fb_c];
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const int r = w + 4 * j, t = t0 - 4 + r;
     const bool trow = t >= 0 && t < T;
-    const int fa = f0 - 6 + lane, fb = f0 - 6 + 64 + lane;
-    const bool ina = trow && fa >= 0 && fa < F;
-    const bool inb = trow && lane < MC - 64 && fb >= 0 && fb < F;
-    const bool va = ina && m[(int64_t)t * F + fa];
-    const bool vb = inb && m[(int64_t)t * F + fb];
-    const uint64_t ba = __ballot(va), bb = __ballot(vb), ia = __ballot(ina), ib = __ballot(inb);
+    const uint64_t ba = __ballot(trow && ca && va[j] != 0), bb = __ballot(trow && cb && vb[j] != 0);
+    const uint64_t ia = __ballot(trow && ca), ib = __ballot(trow && cb);
     if (lane == 0) {
       bufA[r] = Row{ba, bb};
       inm[r] = Row{ia, ib};
