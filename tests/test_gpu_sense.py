@@ -225,3 +225,28 @@ def test_sense_components_across_listed_and_overflowed_tiles(rx):
     say("mixed lattice", T, F, "boxes", len(bx), "overflowed tiles", int(ov[::64, ::64].sum()), "crossings", kinds)
     assert 0 < ov[::64, ::64].sum() < ov[::64, ::64].size
     assert kinds == {True, False}
+
+
+def test_sense_largest_plot_many_components(rx):
+    """The largest plot (4096 x 4096): lattice squares on a checkerboard of
+    512 x 512 regions (tiles with overflowed and with listed components) and
+    a band across them, about 227,000 components, so the ordinal scan runs
+    over every one of its 262,144 counts; every box equals the oracle's."""
+    T = F = 4096
+    t, f = np.arange(T)[:, None], np.arange(F)[None, :]
+    on = (((t - 2) % 6) < 3) & (((f - 2) % 6) < 3) & ((t // 512 + f // 512) % 2 == 0)
+    on[1000:1100, 100:4000] = True
+    cols = (np.arange(F) - F // 2) % F
+    Xb = np.zeros((T, F), np.complex128)
+    Xb[:, cols] = np.where(on, 100.0, 1.0)
+    x = np.fft.ifft(Xb, axis=1).astype(np.complex64)
+    del Xb
+    cfg = rx.SenseConfig(n_fft=F, n_rows=T)
+    ocfg = S.SenseConfig(F=F, T=T)
+    mb = 1 << 18
+    out = rx.sense(cfg, torch.from_numpy(x[None]).cuda(), max_boxes=mb, intermediates=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    retained, bx = check_plot(cfg, ocfg, x, g, 0, mb)
+    say("largest plot", T, F, "boxes", len(bx))
+    assert 100_000 < len(bx) < mb
