@@ -417,12 +417,15 @@ SENSE_DEADLINE_US = 20480.0   # (T, F) = (2000, 1024) at 100 MS/s: T * F / f_s
 
 
 def sense_bytes(T, F):
-    """Compulsory HBM bytes of one plot per kernel of rxphy_sense (the label
-    array is 4 bytes per pixel; the union-find's own label traffic on
-    foreground pixels is not counted)."""
+    """Compulsory HBM bytes of one plot per kernel of rxphy_sense.  The
+    morphology reads the mask and writes the morphed mask, plus per 64x64
+    tile its component list (784 bytes) and its border labels (1 KiB); the
+    labelling passes read the lists three times and touch pixels only in
+    tiles whose list overflowed (not counted, nor the union-find's chains)."""
     px = T * F
+    tiles = -(-T // 64) * (F // 64)
     return {"fft_mag": px * 12, "colstat": px * 4 + F * 12, "otsu": px * 5 + F * 4,
-            "morph": px * 6, "ccl": px * (1 + 1 + 1 + 4 + 1 + 4)}
+            "morph": px * 2 + tiles * (784 + 1024), "ccl": tiles * 784 * 3}
 
 
 def run_sensing(rx, torch, args):
