@@ -385,10 +385,18 @@ __device__ void lunite(volatile int* lab, int a, int b) {
 __global__ void __launch_bounds__(256)
 morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_t* __restrict__ lab,
              TileList* __restrict__ tl, int T, int F) {
-  __shared__ Row bufA[MR], bufB[MR], hb[MR], inm[MR];
+  // the four morphology row buffers; once the core rows are in crow, their
+  // 4608 bytes hold idof: the list position of a local root (255: past the
+  // list), one byte per core pixel (fewer LDS bytes per workgroup: seven
+  // workgroups per CU instead of six)
+  __shared__ Row mb[4][MR];
+  static_assert(sizeof(mb) >= 64 * 64, "idof must fit in the row buffers");
+  Row* const bufA = mb[0];
+  Row* const inm = mb[3];
+  Row* const hb = mb[2];
+  uint8_t* const idof = reinterpret_cast<uint8_t*>(&mb[0][0]);
   __shared__ uint64_t crow[64];
   __shared__ int loc[64 * 64];
-  __shared__ uint8_t idof[64 * 64];             // list position of a local root (255: past the list)
   __shared__ int bb[TL_CAP][4];                 // local box: min row, min column, max row, max column
   __shared__ int16_t rootof[TL_CAP];
   __shared__ int nroots;
@@ -421,8 +429,8 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
     }
   }
   __syncthreads();
-  Row(*A)[MR] = &bufA;
-  Row(*B)[MR] = &bufB;
+  Row(*A)[MR] = &mb[0];
+  Row(*B)[MR] = &mb[1];
   row_op<true, true>(A, B, hb, inm);               // closing 3x3
   row_op<false, true>(B, A, hb, inm);
   row_op<false, true>(A, B, hb, inm);              // opening 3x3
