@@ -60,9 +60,15 @@ __device__ __forceinline__ double2 d2(float2 v) { return make_double2((double)v.
 constexpr int RP = 17;   // row pitch (double2) of the 16 x 16 work matrices
 
 // One wavefront per listed subcarrier (grid-stride over the list): A and
-// b = H^H y are re-formed in FP64 from the FP32 inputs, A = L L^H in FP64, one
-// refinement step x1 = x0 + A^{-1} (b - A x0) from the low-precision x0, and
+// b = H^H y are re-formed in FP64 from the FP32 inputs, A = L L^H in FP64,
+// refinement x <- x + A^{-1} (b - A x) from the low-precision x0, and
 // d = diag(A^{-1}) from the FP64 factor; then the unbiasing, nu and flags.
+// A start that is not finite (the low-precision factor broke down) becomes
+// x0 = 0.  Two steps are taken: one step leaves a relative error of about
+// kappa * eps64 times that of x0, and x0 carries no correct digit once
+// kappa * u exceeds 1 (u = 2^-8 for BF16 operands, 2^-11 for FP16), which the
+// refined subcarriers come close to or pass by construction; the second
+// step brings every subcarrier with kappa * eps64 << 1 to FP64 accuracy.
 __global__ void __launch_bounds__(64)
 refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
               const float2* __restrict__ pil, float2* __restrict__ xt,
@@ -70,7 +76,9 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
               int M, int K, int S, int n_sc, float n0f, int mmse) {
   __shared__ double2 Hs[64 * 16];
   __shared__ double2 Ys[64 * 16];
-  __shared__ double2 A[16 * RP];
+  __shared__ double2 A[16 * RP];    // A, kept for the residuals
+  __shared__ double2 Lf[16 * RP];   // its FP64 Cholesky factor
+  __shared__ double2 Bv[16 * RP];   // b = H^H Y
   __shared__ double2 R[16 * RP];
   __shared__ double2 X[16 * RP];
   __shared__ double2 V[16 * RP];
@@ -98,9 +106,10 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
       const int m = q / D, s = q - m * D;
       Ys[m * 16 + s] = d2(Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i]);
     }
-    for (int q = tid; q < K * D; q += 64) {
+    for (int q = tid; q < K * D; q += 64) {     // x0; a non-finite start becomes 0
       const int u = q / D, s = q - u * D;
-      X[u * RP + s] = d2(xt[((int64_t)(f * K + u) * D + s) * n_sc + i]);
+      const float2 v = xt[((int64_t)(f * K + u) * D + s) * n_sc + i];
+      X[u * RP + s] = (isfinite(v.x) && isfinite(v.y)) ? d2(v) : make_double2(0.0, 0.0);
     }
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -110,65 +119,68 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
       for (int m = 0; m < M; ++m) acc = dadd(acc, dmulcj(Hs[m * 16 + r], Hs[m * 16 + c]));
       if (r == c && mmse) acc.x += n0;
       A[r * RP + c] = acc;
+      Lf[r * RP + c] = acc;
     }
     for (int q = tid; q < K * D; q += 64) {                       // b = H^H Y
       const int r = q / D, s = q - r * D;
       double2 acc = make_double2(0.0, 0.0);
       for (int m = 0; m < M; ++m) acc = dadd(acc, dmulcj(Hs[m * 16 + r], Ys[m * 16 + s]));
-      R[r * RP + s] = acc;
+      Bv[r * RP + s] = acc;
     }
     __syncthreads();
-    for (int q = tid; q < K * D; q += 64) {                       // residual b - A x0
-      const int r = q / D, s = q - r * D;
-      double2 acc = R[r * RP + s];
-      for (int k = 0; k < K; ++k) acc = dsub(acc, dmul(A[r * RP + k], X[k * RP + s]));
-      R[r * RP + s] = acc;
-    }
-    __syncthreads();
-    for (int j = 0; j < K; ++j) {                                 // A = L L^H in place
+    for (int j = 0; j < K; ++j) {                                 // Lf = L, A = L L^H
       if (tid == 0) {
-        const double dj = A[j * RP + j].x;
+        const double dj = Lf[j * RP + j].x;
         if (!(dj > 0.0) || !isfinite(dj)) bad = 1;
-        A[j * RP + j] = make_double2(sqrt(dj), 0.0);
+        Lf[j * RP + j] = make_double2(sqrt(dj), 0.0);
       }
       __syncthreads();
-      const double ljj = A[j * RP + j].x;
-      for (int r = j + 1 + tid; r < K; r += 64) A[r * RP + j] = dsc(A[r * RP + j], 1.0 / ljj);
+      const double ljj = Lf[j * RP + j].x;
+      for (int r = j + 1 + tid; r < K; r += 64) Lf[r * RP + j] = dsc(Lf[r * RP + j], 1.0 / ljj);
       __syncthreads();
       const int w2 = K - j - 1;
       for (int q = tid; q < w2 * w2; q += 64) {
         const int r = j + 1 + q / w2, c = j + 1 + q % w2;
-        if (c <= r) A[r * RP + c] = dsub(A[r * RP + c], dmul(A[r * RP + j], make_double2(A[c * RP + j].x, -A[c * RP + j].y)));
+        if (c <= r) Lf[r * RP + c] = dsub(Lf[r * RP + c], dmul(Lf[r * RP + j], make_double2(Lf[c * RP + j].x, -Lf[c * RP + j].y)));
       }
       __syncthreads();
     }
-    if (tid < D) {                                                // delta = A^{-1} residual, per column
-      const int s = tid;
-      for (int r = 0; r < K; ++r) {
-        double2 acc = R[r * RP + s];
-        for (int k = 0; k < r; ++k) acc = dsub(acc, dmul(A[r * RP + k], R[k * RP + s]));
-        R[r * RP + s] = dsc(acc, 1.0 / A[r * RP + r].x);
+    for (int step = 0; step < 2; ++step) {
+      for (int q = tid; q < K * D; q += 64) {                     // residual b - A x
+        const int r = q / D, s = q - r * D;
+        double2 acc = Bv[r * RP + s];
+        for (int k = 0; k < K; ++k) acc = dsub(acc, dmul(A[r * RP + k], X[k * RP + s]));
+        R[r * RP + s] = acc;
       }
-      for (int r = K - 1; r >= 0; --r) {
-        double2 acc = R[r * RP + s];
-        for (int k = r + 1; k < K; ++k) acc = dsub(acc, dmulcj(A[k * RP + r], R[k * RP + s]));
-        R[r * RP + s] = dsc(acc, 1.0 / A[r * RP + r].x);
-        X[r * RP + s] = dadd(X[r * RP + s], R[r * RP + s]);
+      __syncthreads();
+      if (tid < D) {                                              // x += A^{-1} residual, per column
+        const int s = tid;
+        for (int r = 0; r < K; ++r) {
+          double2 acc = R[r * RP + s];
+          for (int k = 0; k < r; ++k) acc = dsub(acc, dmul(Lf[r * RP + k], R[k * RP + s]));
+          R[r * RP + s] = dsc(acc, 1.0 / Lf[r * RP + r].x);
+        }
+        for (int r = K - 1; r >= 0; --r) {
+          double2 acc = R[r * RP + s];
+          for (int k = r + 1; k < K; ++k) acc = dsub(acc, dmulcj(Lf[k * RP + r], R[k * RP + s]));
+          R[r * RP + s] = dsc(acc, 1.0 / Lf[r * RP + r].x);
+          X[r * RP + s] = dadd(X[r * RP + s], R[r * RP + s]);
+        }
+      } else if (step == 0 && tid >= 32 && tid - 32 < K) {        // column u of L^{-1}: d_u
+        const int u = tid - 32;
+        double acc2 = 0.0;
+        for (int r = 0; r < K; ++r) {
+          double2 acc = make_double2(r == u ? 1.0 : 0.0, 0.0);
+          for (int k = u; k < r; ++k) acc = dsub(acc, dmul(Lf[r * RP + k], V[k * RP + u]));
+          const double2 vr = r < u ? make_double2(0.0, 0.0) : dsc(acc, 1.0 / Lf[r * RP + r].x);
+          V[r * RP + u] = vr;
+          acc2 += vr.x * vr.x + vr.y * vr.y;
+        }
+        dd[u] = acc2;
+        if (mmse && !(1.0 - n0 * acc2 > 0.0)) bad = 1;
       }
-    } else if (tid >= 32 && tid - 32 < K) {                       // column u of L^{-1}: d_u
-      const int u = tid - 32;
-      double acc2 = 0.0;
-      for (int r = 0; r < K; ++r) {
-        double2 acc = make_double2(r == u ? 1.0 : 0.0, 0.0);
-        for (int k = u; k < r; ++k) acc = dsub(acc, dmul(A[r * RP + k], V[k * RP + u]));
-        const double2 vr = r < u ? make_double2(0.0, 0.0) : dsc(acc, 1.0 / A[r * RP + r].x);
-        V[r * RP + u] = vr;
-        acc2 += vr.x * vr.x + vr.y * vr.y;
-      }
-      dd[u] = acc2;
-      if (mmse && !(1.0 - n0 * acc2 > 0.0)) bad = 1;
+      __syncthreads();
     }
-    __syncthreads();
     const bool erase = bad != 0;
     for (int q = tid; q < K * D; q += 64) {
       const int u = q / D, s = q - u * D;

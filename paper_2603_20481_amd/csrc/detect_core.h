@@ -667,10 +667,12 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
       const uint32_t slot = atomicAdd(rlist, 1u);
       rlist[RL_OFF + slot] = sub_base + (uint32_t)i;
     }
+    // a low-precision breakdown leaves z non-finite: start the FP64 step from
+    // x0 = 0 instead, which makes it a full FP64 solve
     if (row < D) {
 #pragma unroll
       for (int uu = 0; uu < 16; ++uu)
-        if (uu < K) xt[((int64_t)uu * D + row) * n_sc + i] = z[uu];
+        if (uu < K) xt[((int64_t)uu * D + row) * n_sc + i] = ok ? z[uu] : make_float2(0.f, 0.f);
     }
     return;
   }

@@ -1,5 +1,6 @@
-// Fused CSI + ZF / MMSE detector for K = 16 users, FP32 (Sec. III-B LS
-// estimate with the comb pilots, Sec. III-C equaliser, Eq. (4)-(6)).
+// Fused CSI + ZF / MMSE detector for K = 16 users, FP32: the comb-pilot
+// least-squares channel estimate and textbook linear (zero-forcing / MMSE)
+// detection, the stages named csi and equal in the paper's preamble.
 //
 // With 16 users a pilot group spans exactly one 16-subcarrier tile, and the
 // LS estimate is held over the group, so every subcarrier of a tile sees the

@@ -41,3 +41,16 @@ def hard_bits_outside_guard(llr, llr_ref, rel_tau=1e-5):
     outside = np.abs(ref) > tau
     mism = ((llr < 0) != (ref < 0)) & outside
     return int(np.sum(mism)), int(np.sum(~outside))
+
+
+def elem_rel(got, ref, floor=0.01):
+    """Element-wise relative error of a real or complex array,
+    max |got - ref| / max(|ref|, floor * RMS(|ref|)): the LLR metric applied
+    to gradients, so that one wrong element fails where a norm would not."""
+    got = np.asarray(got, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    if ref.size == 0:
+        return 0.0
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    den = np.maximum(np.abs(ref), floor * rms)
+    return float(np.max(np.abs(got - ref) / np.maximum(den, 1e-300)))

@@ -95,6 +95,39 @@ def test_ill_conditioned_subcarriers_are_refined(rx, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_low_precision_breakdown_is_solved_in_fp64(rx, prec):
+    """Users 0 and 1 get channel columns that differ only below the operand
+    precision: column 0 holds values exact in BF16 (so in FP16 too) and
+    column 1 = column 0 (1 + 2e-4 r), |r| <= 1, which rounds back to column 0.  The
+    low-precision Gram matrix is then exactly rank deficient and its FP32
+    Cholesky factor breaks down or nearly does, while the FP64 factor of the
+    FP32 inputs exists (kappa ~ 1e8-1e9).  Every such subcarrier must come
+    back REFINED with finite outputs equal to the FP64 solution."""
+    rng = np.random.default_rng(35)
+    M, K, n_sc, S = 16, 4, 64, 6
+    h = (rng.standard_normal((1, M, K, n_sc)) + 1j * rng.standard_normal((1, M, K, n_sc))) * 4
+    c0 = np.ascontiguousarray(h[:, :, 0, :]).astype(np.complex64)
+    t = torch.from_numpy(c0.view(np.float32).copy())
+    c0 = t.to(torch.bfloat16).to(torch.float32).numpy().view(np.complex64).astype(np.complex128)
+    h[:, :, 0, :] = c0
+    h[:, :, 1, :] = c0 * (1 + 2e-4 * rng.uniform(-1, 1, c0.shape))
+    h = h.astype(np.complex64)
+    yf = ((rng.standard_normal((1, M, S, n_sc)) + 1j * rng.standard_normal((1, M, S, n_sc))) * 10).astype(np.complex64)
+    fr = rx.Frame(M, K, 512, n_sc, S, 0, 4, O.ZF, 1.0)
+    xt, nu, fl = (host(t) for t in rx.detect(fr, dev(h), dev(yf), prec, 1e3))
+    ref = O.detect_stage(h[0], yf[0, :, 1:, :], 1.0, O.ZF, want_kappa=True)
+    say(prec, "kappa range", float(ref["kappa"].min()), float(ref["kappa"].max()), "oracle flags",
+        int(np.sum(ref["flags"] != 0)))
+    assert np.all(ref["flags"] == 0)                  # FP64 factors every subcarrier
+    assert np.all(fl[0] == O.FLAG_REFINED)
+    assert np.all(np.isfinite(xt)) and np.all(np.isfinite(nu))
+    e = evm_rel(xt[0], ref["xt"], np.ones(n_sc, bool))
+    en = rel_rms(nu[0], ref["nu"])
+    say("  evm_rel", e, "nu_rel", en)
+    assert e < 1e-5 and en < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_kronecker_64qam_workload_report(rx, prec):
     """64x16, N 4096, 3276 subcarriers, 64-QAM, Kronecker (0.7, 0.3), 25 dB."""
     sh = synth.config_shape(3)

@@ -357,6 +357,37 @@ def test_detect_adjoint_matches_torch_autograd(det):
     np.testing.assert_allclose(gY, np.moveaxis(Yt.grad.numpy(), 0, -1), rtol=1e-9, atol=1e-10)
 
 
+def test_bce_loss_value_and_gradient():
+    """The loss of the differentiation workload: mean binary cross-entropy with
+    logit(bit = 1) = -LLR.  Pinned by closed forms (LLR 0 gives ln 2 and
+    gradient (bit - 1/2)/n; a confident right decision costs about 0 and a
+    confident wrong one |LLR|/n) and by torch's own BCE-with-logits and its
+    autograd gradient, in float64 on the CPU."""
+    torch = pytest.importorskip("torch")
+    n = 8
+    bits = np.array([0, 1, 0, 1, 1, 0, 0, 1], dtype=np.uint8)
+    loss, g = O.bce_loss(np.zeros(n), bits)
+    assert loss == pytest.approx(math.log(2), rel=1e-15)
+    np.testing.assert_allclose(g, (bits - 0.5) / n, rtol=0, atol=1e-17)
+    # LLR = +40 says bit 0: right for bit 0 (cost ~ e^-40), wrong for bit 1 (cost ~ 40)
+    l_right, _ = O.bce_loss(np.array([40.0]), np.array([0]))
+    l_wrong, g_wrong = O.bce_loss(np.array([40.0]), np.array([1]))
+    assert l_right == pytest.approx(math.exp(-40), rel=1e-12)
+    assert l_wrong == pytest.approx(40 + math.exp(-40), rel=1e-15)
+    assert g_wrong[0] == pytest.approx(1.0 / (1.0 + math.exp(-40)), rel=1e-15)  # d/dLLR of -log(sigmoid(-LLR))
+    rng = np.random.default_rng(31)
+    llr = rng.standard_normal((3, 5, 7, 4)) * 8.0
+    llr[0, 0, 0, 0] = 750.0                      # exp overflow territory for a naive form
+    llr[0, 0, 0, 1] = -750.0
+    bits = rng.integers(0, 2, llr.shape).astype(np.uint8)
+    loss, g = O.bce_loss(llr, bits)
+    lt = torch.tensor(llr, requires_grad=True)
+    ref = torch.nn.functional.binary_cross_entropy_with_logits(-lt, torch.tensor(bits, dtype=torch.float64))
+    ref.backward()
+    assert loss == pytest.approx(float(ref), rel=1e-13)
+    np.testing.assert_allclose(g, lt.grad.numpy(), rtol=1e-12, atol=1e-18)
+
+
 def test_torch_gradient_convention():
     torch = pytest.importorskip("torch")
     z = torch.tensor(1 + 1j, dtype=torch.complex128, requires_grad=True)
