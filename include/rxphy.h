@@ -165,6 +165,27 @@ rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames,
                                     float cond_threshold, void* ws, size_t ws_bytes,
                                     hipStream_t stream);
 
+/* rxphy_csi_detect_demod without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It calls no allocating routine:
+ * the workspace is a scratch array of RXPHY_NOALLOC_SCRATCH_BYTES (32 MiB)
+ * inside the library, one per GPU, held until the process ends; its device
+ * address is looked up on the first call on each device.  Arguments, outputs
+ * and results are those of rxphy_csi_detect_demod (the same kernels run).
+ * Returns RXPHY_EWORKSPACE, with nothing launched, when that call would need
+ * more than RXPHY_NOALLOC_SCRATCH_BYTES of workspace (the 16-user FP32 path
+ * needs 2304 bytes per 16-subcarrier tile: up to 194 frames of 64 x 16
+ * antennas/users with 1200 subcarriers).  Every call on one GPU shares that
+ * GPU's scratch, so calls that overlap in time on one GPU (on different
+ * streams, or from different threads) race; calls ordered on one stream do
+ * not.  Nothing in the scratch needs to start at zero: the kernels write every
+ * byte they read within the call.                                           */
+#define RXPHY_NOALLOC_SCRATCH_BYTES (32u << 20)
+rxphy_status rxphy_csi_detect_demod_noalloc(const rxphy_frame* frame, int32_t n_frames,
+                                            const void* yf, const void* pilots, void* xt, float* nu,
+                                            uint8_t* flags, float* llr, rxphy_precision precision,
+                                            float cond_threshold, hipStream_t stream);
+
 /* demod stage (`demod` macro): max-log LLRs over the Gray square-QAM set
  * with unit average energy (bits b0 .. b_{Q-1}; b0, b2, b4 select the
  * in-phase level, b1, b3, b5 the quadrature level):

@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rxphy_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect": [FR, I32, P, P, P, P, P, I32, F32, P, SZ, P],
         "rxphy_csi_detect_demod": [FR, I32, P, P, P, P, P, P, I32, F32, P, SZ, P],
+        "rxphy_csi_detect_demod_noalloc": [FR, I32, P, P, P, P, P, P, I32, F32, P],
         "rxphy_modulate": [FR, I32, P, P, P],
         "rxphy_precode": [FR, I32, P, P, P, P, P, P, SZ, ctypes.c_uint32, P],
         "rxphy_modulate_precode": [FR, I32, P, P, P, P, P, P, SZ, ctypes.c_uint32, P],
@@ -351,6 +352,31 @@ def csi_detect_demod(fr: Frame, yf, pilots, precision: str = "fp32", cond_thresh
                                          _ptr(llr), PRECISIONS[precision], float(cond_threshold),
                                          _ptr(ws), ws.numel() if ws is not None else 0, _stream()),
            "rxphy_csi_detect_demod")
+    return llr, nu, flags, xt
+
+
+def csi_detect_demod_noalloc(fr: Frame, yf, pilots, precision: str = "fp32", cond_threshold: float = 1e3,
+                             llr=None, nu=None, flags=None, xt=None):
+    """csi_detect_demod with the library's own per-GPU scratch as workspace
+    (the call allocates nothing itself; outputs are allocated here only when
+    not passed in) -> (llr, nu, flags, xt or None)."""
+    F = _nf(yf)
+    D = fr.n_data
+    _need(yf, "yf", (F, fr.M, fr.n_sym, fr.n_sc), torch.complex64)
+    _need(pilots, "pilots", (F, fr.n_sc), torch.complex64)
+    llr = _empty((F, fr.K, D, fr.n_sc, fr.qam_bits), torch.float32, yf) if llr is None else llr
+    nu = _empty((F, fr.K, fr.n_sc), torch.float32, yf) if nu is None else nu
+    flags = _empty((F, fr.n_sc), torch.uint8, yf) if flags is None else flags
+    _need(llr, "llr", (F, fr.K, D, fr.n_sc, fr.qam_bits), torch.float32)
+    _need(nu, "nu", (F, fr.K, fr.n_sc), torch.float32)
+    _need(flags, "flags", (F, fr.n_sc), torch.uint8)
+    if xt is not None:
+        _need(xt, "xt", (F, fr.K, D, fr.n_sc), torch.complex64)
+    _check(load().rxphy_csi_detect_demod_noalloc(ctypes.byref(fr.c()), F, _ptr(yf), _ptr(pilots),
+                                                 _ptr(xt) if xt is not None else None, _ptr(nu), _ptr(flags),
+                                                 _ptr(llr), PRECISIONS[precision], float(cond_threshold),
+                                                 _stream()),
+           "rxphy_csi_detect_demod_noalloc")
     return llr, nu, flags, xt
 
 

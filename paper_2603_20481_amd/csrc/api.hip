@@ -216,6 +216,51 @@ rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames, 
   return launch_demod(fr, n_frames, x, nu, llr, stream);
 }
 
+// Scratch memory of the allocation-free entry point: one copy per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address); it passes the address hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[RXPHY_NOALLOC_SCRATCH_BYTES];
+
+static rxphy_status scratch_address(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RXPHY_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(RXPHY_EHIP, "scratch address: %s", hipGetErrorString(e));
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return RXPHY_OK;
+}
+
+rxphy_status rxphy_csi_detect_demod_noalloc(const rxphy_frame* frame, int32_t n_frames, const void* yf,
+                                            const void* pilots, void* xt, float* nu, uint8_t* flags,
+                                            float* llr, rxphy_precision precision, float cond_threshold,
+                                            hipStream_t stream) {
+  clear_error();
+  rxphy_status st = check_frame(frame, n_frames);
+  if (st) return st;
+  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
+    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  const size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD, precision);
+  if (need > (size_t)RXPHY_NOALLOC_SCRATCH_BYTES)
+    return fail(RXPHY_EWORKSPACE,
+                "csi_detect_demod_noalloc needs %zu scratch bytes for %d frames; its scratch holds %zu",
+                need, n_frames, (size_t)RXPHY_NOALLOC_SCRATCH_BYTES);
+  if (n_frames == 0) return RXPHY_OK;
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws))) return st;
+  return rxphy_csi_detect_demod(frame, n_frames, yf, pilots, xt, nu, flags, llr, precision, cond_threshold, ws,
+                                (size_t)RXPHY_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 rxphy_status rxphy_modulate(const rxphy_frame* frame, int32_t n_frames, const uint8_t* bits, void* sym,
                             hipStream_t stream) {
   clear_error();

@@ -119,6 +119,29 @@ def test_fused_call_checks(lib):
     assert f(ctypes.byref(fr), 0, None, None, None, None, None, None, 0, 1e3, None, 0, None) == 0
 
 
+def test_noalloc_call_rejects_work_beyond_its_scratch(lib):
+    """rxphy_csi_detect_demod_noalloc: a call whose workspace would exceed the
+    library's 32 MiB scratch fails with RXPHY_EWORKSPACE before any HIP call;
+    194 frames of 64 x 16 with 1200 subcarriers is the most that fits."""
+    fr = frame(M=64, K=16, n_fft=2048, n_sc=1200, n_sym=14, qam_bits=4)
+    p = ctypes.c_void_p(256)
+    f = lib.rxphy_csi_detect_demod_noalloc
+    f.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32] + [ctypes.c_void_p] * 6 + \
+        [ctypes.c_int32, ctypes.c_float, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    lib.rxphy_workspace_bytes.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.rxphy_workspace_bytes.restype = ctypes.c_size_t
+    cap = 32 << 20
+    assert lib.rxphy_workspace_bytes(ctypes.byref(fr), 194, 3, 0) <= cap
+    assert lib.rxphy_workspace_bytes(ctypes.byref(fr), 195, 3, 0) > cap
+    assert f(ctypes.byref(fr), 195, p, p, None, p, p, p, 0, 1e3, None) == 3
+    lib.rxphy_last_error.restype = ctypes.c_char_p
+    assert b"scratch" in lib.rxphy_last_error()
+    assert f(ctypes.byref(fr), 1, p, p, None, p, p, p, 9, 1e3, None) == 1          # precision
+    assert f(ctypes.byref(frame(K=17)), 1, p, p, None, p, p, p, 0, 1e3, None) == 2
+    assert f(ctypes.byref(fr), 0, None, None, None, None, None, None, 0, 1e3, None) == 0
+
+
 def test_status_strings(lib):
     lib.rxphy_status_string.restype = ctypes.c_char_p
     assert lib.rxphy_status_string(0) == b"RXPHY_OK"
