@@ -97,28 +97,147 @@ def measured_traffic(kernel):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(cfg, det, budget_s):
-    import oracle as O
+# GPU outputs of sampled frames of each form, kept (on the host, outside the
+# timed regions) for the oracle leg: {form: dict(kind, ...)}
+SAMPLES = {}
+
+
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
-    except Exception:  # pragma: no cover
-        lim = None
-    t_total, n, dets = 0.0, 0, 0
-    while t_total < budget_s:
-        fo = synth.make_frame(cfg, n)
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_frame(job):
+    """One frame through the FP64 oracle on one thread; returns the seconds."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    cfg, f, det = job
+    fo = synth.make_frame(cfg, f)
+    with threadpool_limits(1):
         t0 = time.perf_counter()
         O.forward(fo.x, fo.pilots, fo.shape, 1.0, det)
-        t_total += time.perf_counter() - t0
-        dets += fo.shape.detections
-        n += 1
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
-    return {"value": dets / t_total, "unit": "subcarrier-detections/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d frame(s) of the same workload through the FP64 oracle "
-                      "(fft, csi, %s, brute-force max-log), %.1f s of one core" %
-                      (n, "ZF" if det == 0 else "MMSE", t_total)}
+        return time.perf_counter() - t0
+
+
+def _errors(ref, llr, xt=None, nu=None, flags=None, band_u=None):
+    """Error of one frame's GPU outputs against the oracle's: EVM over the
+    subcarriers with kappa_2 <= 1e3 that neither side erased, the relative LLR
+    error |d| / max(|ref|, 0.01 RMS), the largest absolute LLR error and the
+    hard-bit mismatches outside the guard band (1e-5 RMS, or band_u * kappa
+    RMS for the mixed forms)."""
+    r = ref["llr"]
+    rms = float(np.sqrt(np.mean(r ** 2)))
+    d = np.abs(llr.astype(np.float64) - r)
+    out = {"llr_rel": float(np.max(d / np.maximum(np.abs(r), 0.01 * rms))), "llr_max_abs": float(d.max())}
+    good = ref["flags"] == 0
+    if "kappa" in ref:
+        good &= ref["kappa"] <= 1e3
+    if flags is not None:
+        good &= (flags & 6) == 0
+    if xt is not None and np.any(good):
+        a, b = xt[..., good].astype(np.complex128), ref["xt"][..., good]
+        out["evm_rel"] = float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+    if nu is not None and np.any(good):
+        out["nu_rel"] = float(np.sqrt(np.sum((nu[:, good] - ref["nu"][:, good]) ** 2)
+                                      / np.sum(ref["nu"][:, good] ** 2)))
+    tau = 1e-5 * rms
+    if band_u is not None and "kappa" in ref:
+        tau = max(tau, band_u * float(ref["kappa"][ref["flags"] == 0].max()) * rms)
+    outside = np.abs(r) > tau
+    out["hard_bit_mismatches"] = int(np.sum(((llr < 0) != (r < 0)) & outside))
+    out["bits_in_band"] = int(np.sum(~outside))
+    return out
+
+
+def cpu_baseline(cfg, det, budget_s, workers):
+    """The FP64 oracle as it stands, timed on the host: the headline workload on
+    one core and on `workers` cores (one process per core, frames spread over
+    them); then each kept sample of the other forms, timed on one core, with
+    the GPU's error on that sample."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    head = SAMPLES.get("headline")
+    errs = []
+    t_total, n, dets = 0.0, 0, 0
+    with threadpool_limits(1):
+        while t_total < budget_s:
+            fo = synth.make_frame(cfg, n)
+            t0 = time.perf_counter()
+            O.forward(fo.x, fo.pilots, fo.shape, 1.0, det)
+            t_total += time.perf_counter() - t0
+            dets += fo.shape.detections
+            if head is not None and n in head["frames"]:          # untimed: with the exact kappa_2
+                k = head["frames"].index(n)
+                ref = O.forward(fo.x, fo.pilots, fo.shape, 1.0, det, want_kappa=True)
+                errs.append(_errors(ref, head["llr"][k], head["xt"][k], head["nu"][k], head["flags"][k]))
+            n += 1
+    one = dets / t_total
+    # all cores: a process per core, each frame on one thread
+    per_frame = fo.shape.detections
+    jobs = [(cfg, f, det) for f in range(max(workers * 8, 1))]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        list(ex.map(_oracle_frame, [(cfg, 0, det)] * workers))        # start the workers
+        t0 = time.perf_counter()
+        secs = list(ex.map(_oracle_frame, jobs))
+        wall = time.perf_counter() - t0
+    many = len(jobs) * per_frame / wall
+    out = {"value": many, "unit": "subcarrier-detections/s", "cores": workers, "kind": "oracle",
+           "sample": "%d frames of the headline workload through the FP64 oracle (fft, csi, %s, brute-force "
+                     "max-log), one process per core, one thread each, %.1f s wall" %
+                     (len(jobs), "ZF" if det == 0 else "MMSE", wall),
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "single_core": {"value": one, "cores": 1,
+                           "sample": "%d frame(s), %.1f s of one core" % (n, t_total)},
+           "mean_frame_s_per_core": float(np.mean(secs))}
+    if errs:
+        out["headline_error"] = {k: max(e[k] for e in errs) for k in errs[0]}
+        out["headline_error"]["frames"] = head["frames"]
+    forms = {}
+    with threadpool_limits(1):
+        for name, smp in SAMPLES.items():
+            if name == "headline":
+                continue
+            t0 = time.perf_counter()
+            if smp["kind"] == "forward":
+                per = []
+                dets = 0
+                for k, fo in enumerate(smp["inputs"]):
+                    ref = O.forward(fo.x, fo.pilots, fo.shape, 1.0, smp["det"][k], want_kappa=True)
+                    dets += fo.shape.detections
+                    for lab, o in smp["outputs"][k].items():
+                        per.append((lab, _errors(ref, o["llr"], o.get("xt"), o.get("nu"), o.get("flags"),
+                                                 o.get("band_u"))))
+                secs = time.perf_counter() - t0
+                res = {}
+                for lab, e in per:
+                    cur = res.setdefault(lab, {})
+                    for key, v in e.items():
+                        cur[key] = max(cur.get(key, v), v)
+                forms[name] = {"oracle_1core": {"value": dets / secs, "unit": "subcarrier-detections/s",
+                                                "seconds": round(secs, 2), "frames": len(smp["inputs"])},
+                               "error": res}
+            else:                                   # backward: dL/dx against the oracle adjoint
+                fo = smp["input"]
+                gx, _ = O.backward(fo.x, fo.pilots, fo.shape, 1.0, smp["det"], smp["dllr"].astype(np.float64))
+                secs = time.perf_counter() - t0
+                got = smp["dx"].astype(np.complex128)
+                rms = float(np.sqrt(np.mean(np.abs(gx) ** 2)))
+                forms[name] = {"oracle_1core": {"value": fo.shape.detections / secs,
+                                                "unit": "subcarrier-detections/s (forward + adjoint)",
+                                                "seconds": round(secs, 2), "frames": 1},
+                               "error": {"dx_rel_rms": float(np.sqrt(np.sum(np.abs(got - gx) ** 2)
+                                                                     / np.sum(np.abs(gx) ** 2))),
+                                         "dx_elem_rel": float(np.max(np.abs(got - gx)
+                                                                     / np.maximum(np.abs(gx), 0.01 * rms)))}}
+    out["forms"] = forms
+    return out
 
 
 class Chain:
@@ -587,6 +706,17 @@ def run_batched(rx, torch, args):
                       "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "device_status": status}
         del plan
+    # frames 0 and 1 of the last replay for the oracle leg
+    plan = rx.Plan(frames)
+    keep = {}
+    for f in (0, 1):
+        keep[f] = {k: plan.view(bufs, k, f).cpu().numpy() for k in ("llr", "xt", "nu", "flags")}
+    del plan
+    SAMPLES["batched_256_uneven"] = {
+        "kind": "forward", "inputs": [synth.make_frame(4, f, shape=shapes[f]) for f in (0, 1)],
+        "det": [rx.MMSE, rx.MMSE],
+        "outputs": [{"fp32": {"llr": keep[f]["llr"], "xt": keep[f]["xt"], "nu": keep[f]["nu"],
+                              "flags": keep[f]["flags"]}} for f in (0, 1)]}
     # each stage alone over the same buffers (a plan with one stage in its mask)
     tiles = tuner.tiles_for(frames)
     stage_ms = {}
@@ -642,6 +772,26 @@ def run_batched(rx, torch, args):
     return out
 
 
+def backward_bytes(s):
+    """Compulsory HBM bytes of each kernel of rxphy_backward for one frame,
+    given the forward's yf, h, x_tilde and nu (its interface tensors; the
+    detector adjoint keeps X_hat, V = A^-1 G, A^-1 and the weights e of every
+    subcarrier for the C kernel, and V and C for the apply kernel)."""
+    M, K, N, n_sc, S, cp, Q = s.M, s.K, s.n_fft, s.n_sc, s.n_sym, s.cp_len, s.qam_bits
+    D = S - 1
+    xt, nu = K * D * n_sc * 8, K * n_sc * 4
+    h, yd = M * K * n_sc * 8, M * D * n_sc * 8
+    kd, kk = n_sc * K * D * 8, n_sc * K * K * 8
+    return {
+        "demod_adjoint": xt + nu + K * D * n_sc * Q * 4 + xt + nu,
+        "detect_adjoint": h + yd + xt + nu + 2 * kd + kk + n_sc * K * 4,
+        "detect_adjoint_c": 2 * kd + kk + n_sc * K * 4 + kk,
+        "detect_adjoint_apply": h + yd + kd + kk + yd + h,
+        "csi_adjoint": h + n_sc * 8 + M * n_sc * 8,
+        "ifft": M * S * n_sc * 8 + M * S * (cp + N) * 8,
+    }
+
+
 def run_fwd_bwd(rx, torch, args):
     cfg = 5
     shape = synth.config_shape(cfg)
@@ -650,26 +800,46 @@ def run_fwd_bwd(rx, torch, args):
     fr = rx.Frame.of(shape, rx.MMSE, 1.0)
     x = torch.from_numpy(x_h).cuda()
     p = torch.from_numpy(p_h).cuda()
+    del x_h, p_h
     g = torch.Generator(device="cuda")
     g.manual_seed(5)
     dllr = torch.randn((F, shape.K, shape.n_data, shape.n_sc, shape.qam_bits), generator=g,
                        device="cuda")
 
-    def step():
+    def step(ev=None):
+        if ev: ev[0].record()
         out = rx.forward(fr, x, p)
-        rx.backward(fr, x, p, dllr, saved=dict(yf=out["yf"], h=out["h"]))
+        if ev: ev[1].record()
+        dx = rx.backward(fr, x, p, dllr, saved=dict(yf=out["yf"], h=out["h"], xt=out["xt"], nu=out["nu"]))
+        if ev: ev[2].record()
+        return dx
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.form_steps):
-        step()
-    e1.record()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.form_steps)]
+    for k in range(args.form_steps):
+        dx = step(evs[k])
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.form_steps
+    fwd = sum(e[0].elapsed_time(e[1]) for e in evs) / args.form_steps
+    bwd = sum(e[1].elapsed_time(e[2]) for e in evs) / args.form_steps
+    ms = fwd + bwd
+    sb, bb = stage_bytes(shape), backward_bytes(shape)
+    fbytes = sum(sb[k] for k in MODES["staged"]) * F
+    bbytes = sum(bb.values()) * F
+    SAMPLES["fwd_bwd_64x8_cascaded"] = {"kind": "backward", "input": synth.make_frame(cfg, 0),
+                                         "det": rx.MMSE, "dllr": dllr[0].cpu().numpy(),
+                                         "dx": dx[0].cpu().numpy()}
     out = {"value": F * shape.detections / (ms * 1e-3), "unit": "subcarrier-detections/s",
            "ms_per_step": round(ms, 4), "frames": F,
+           "forward": {"ms": round(fwd, 4), "algorithmic_bytes": fbytes,
+                       "GBps": round(fbytes / (fwd * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(fbytes / (fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "calls": "fft, csi, detect, demod (H, x_tilde and nu kept for the adjoint)"},
+           "backward": {"ms": round(bwd, 4), "algorithmic_bytes": bbytes,
+                        "bytes_per_kernel_per_frame": bb,
+                        "GBps": round(bbytes / (bwd * 1e-3) / 1e9, 1),
+                        "hbm_frac": round(bbytes / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "calls": "rxphy_backward with the forward's yf, h, x_tilde and nu"},
            "workload": "64x8 MIMO, N_FFT 2048, 1200 subcarriers, 16-QAM, cascaded channel "
                        "(256-element phase vector), 5 dB, MMSE; forward + adjoint to dL/dx, FP32"}
     del x, p, dllr
@@ -688,7 +858,7 @@ def main():
     ap.add_argument("--form-steps", type=int, default=10)
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
-    ap.add_argument("--bwd-frames", type=int, default=50)
+    ap.add_argument("--bwd-frames", type=int, default=100)
     ap.add_argument("--forms", default="staged,mmse,sc16,streaming,downlink,mixed,batched,fwd_bwd,sensing",
                     help="comma list of extra forms to time ('' for the headline only)")
     ap.add_argument("--sense-plots", type=int, default=64)
@@ -698,6 +868,8 @@ def main():
     ap.add_argument("--tile-cache", default=None)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
+                    help="processes of the all-cores oracle timing (one thread each)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the plain device copy timed as the bandwidth reference (0: skip)")
@@ -763,6 +935,16 @@ def main():
         "forms": {},
     }
     print("[bench] headline %.4g det/s (%.3f ms/step)" % (value, ms_per_step), file=sys.stderr, flush=True)
+    # outputs of the first and last frame for the oracle leg (one more untimed
+    # call that also writes x_tilde)
+    rx.csi_detect_demod(fr, chain.yf, chain.p, "fp32", 1e3, llr=chain.llr, nu=chain.nu, flags=chain.fl,
+                        xt=chain.xt, ws=chain.ws)
+    torch.cuda.synchronize()
+    keep = [0, 1]
+    SAMPLES["headline"] = {"frames": keep, "llr": [chain.llr[k].cpu().numpy() for k in keep],
+                           "xt": [chain.xt[k].cpu().numpy() for k in keep],
+                           "nu": [chain.nu[k].cpu().numpy() for k in keep],
+                           "flags": [chain.fl[k].cpu().numpy() for k in keep]}
     if "staged" in forms:
         ms, per = chain.time(fr, "fp32", args.form_steps, 1, mode="staged")
         out["forms"]["staged_fp32"] = form_summary(
@@ -796,15 +978,24 @@ def main():
         c3 = Chain(rx, torch, s3, x3, p3)
         del x3, p3
         fr3 = rx.Frame.of(s3, rx.ZF, 1.0)
+        kept = {}
         for prec in ("fp32", "bf16", "fp16"):
             ms, per = c3.time(fr3, prec, args.form_steps, 1, mode="full")
             refined = int((c3.fl & rx.FLAG_REFINED).ne(0).sum().item())
+            rx.csi_detect_demod(fr3, c3.yf, c3.p, prec, 1e3, llr=c3.llr, nu=c3.nu, flags=c3.fl, xt=c3.xt,
+                                ws=c3.ws)
+            torch.cuda.synchronize()
+            kept[prec] = {"llr": c3.llr[0].cpu().numpy(), "xt": c3.xt[0].cpu().numpy(),
+                          "nu": c3.nu[0].cpu().numpy(), "flags": c3.fl[0].cpu().numpy(),
+                          "band_u": {"fp32": None, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11}[prec]}
             out["forms"]["kronecker_64x16_n4096_64qam_" + prec] = form_summary(
                 s3, args.mixed_frames, ms, per,
                 {"refined_subcarriers": refined, "refined_fraction": refined / c3.fl.numel(),
                  "workload": "64x16 MIMO, N_FFT 4096, 3276 subcarriers, 64-QAM, Kronecker "
                              "(0.7, 0.3), 25 dB, ZF, %s products, FP64 refinement above "
                              "condition estimate 1e3" % prec})
+        SAMPLES["kronecker_64x16_n4096_64qam"] = {"kind": "forward", "inputs": [synth.make_frame(3, 0)],
+                                                  "det": [rx.ZF], "outputs": [kept]}
         del c3
         torch.cuda.empty_cache()
         print("[bench] mixed done", file=sys.stderr, flush=True)
@@ -837,7 +1028,7 @@ def main():
                                  "GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}
         del src, dst
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, det, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(cfg, det, args.cpu_budget, args.cpu_workers)
     print(json.dumps(out), flush=True)
 
 

@@ -264,14 +264,24 @@ rxphy_status rxphy_ifft_sc16(const rxphy_frame* frame, int64_t n_rows, const voi
                             hipStream_t stream);
 
 /* Intermediate results of the forward stages that rxphy_backward may reuse;
- * any member may be NULL, in which case it is recomputed into the workspace. */
+ * any member may be NULL, in which case it is recomputed into the workspace
+ * (xt and nu are used only as a pair: if either is NULL both are recomputed
+ * with the FP32 detector).  Each must be the output of the FP32 forward call
+ * on the same x and pilots (rxphy_fft, rxphy_csi, rxphy_detect); the
+ * Cholesky factors are never saved (always recomputed from h).             */
 typedef struct {
-  const void* yf;    /* c64 [F][M][n_sym][n_sc]  */
-  const void* h;     /* c64 [F][M][K][n_sc]      */
+  const void* yf;    /* c64 [F][M][n_sym][n_sc]    */
+  const void* h;     /* c64 [F][M][K][n_sc]        */
+  const void* xt;    /* c64 [F][K][n_sym-1][n_sc]  */
+  const float* nu;   /* f32 [F][K][n_sc]           */
 } rxphy_saved;
 
 /* Adjoint of the whole forward map x -> llr (FP32 forward), for gradients
- * with PyTorch's complex convention grad = dL/dRe + j dL/dIm.  Given
+ * with PyTorch's complex convention grad = dL/dRe + j dL/dIm.  The paper
+ * differentiates nothing: this call is the exact derivative of the forward
+ * map the four stage calls above define (wherever no argmin of the max-log
+ * demapper switches), the differentiable form of the receiver through
+ * demod -> equalise -> ZF / MMSE -> CSI -> FFT.  Given
  * dllr = dL/dllr it runs the demod adjoint (through the argmin points, ties
  * to the lowest point index, and through nu), the detector adjoint
  *   dL/dY = H V,  dL/dH = Y V^H - H (X_hat V^H + V X_hat^H + 2 A^{-1} diag(e) A^{-1})

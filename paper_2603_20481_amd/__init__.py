@@ -34,7 +34,7 @@ class _Frame(ctypes.Structure):
 
 
 class _Saved(ctypes.Structure):
-    _fields_ = [("yf", ctypes.c_void_p), ("h", ctypes.c_void_p)]
+    _fields_ = [("yf", ctypes.c_void_p), ("h", ctypes.c_void_p), ("xt", ctypes.c_void_p), ("nu", ctypes.c_void_p)]
 
 
 class _Tiles(ctypes.Structure):
@@ -510,8 +510,7 @@ def backward(fr: Frame, x, pilots, dllr, saved=None, want_dh: bool = False):
     dh = _empty((F, fr.M, fr.K, fr.n_sc), torch.complex64, x) if want_dh else None
     sv = None
     if saved is not None:
-        sv = _Saved(saved["yf"].data_ptr() if saved.get("yf") is not None else None,
-                    saved["h"].data_ptr() if saved.get("h") is not None else None)
+        sv = _Saved(*[saved[k].data_ptr() if saved.get(k) is not None else None for k in ("yf", "h", "xt", "nu")])
     need = workspace_bytes(fr, F, WS_BACKWARD)
     ws = _empty((max(need, 1),), torch.uint8, x)
     _check(load().rxphy_backward(ctypes.byref(fr.c()), F, _ptr(x), _ptr(pilots),
@@ -529,13 +528,13 @@ class RxphyFunction(torch.autograd.Function):
     def forward(ctx, x, pilots, fr):
         out = forward(fr, x.detach(), pilots)
         ctx.fr = fr
-        ctx.save_for_backward(x.detach(), pilots, out["yf"], out["h"])
+        ctx.save_for_backward(x.detach(), pilots, out["yf"], out["h"], out["xt"], out["nu"])
         return out["llr"]
 
     @staticmethod
     def backward(ctx, dllr):
-        x, pilots, yf, h = ctx.saved_tensors
-        dx = backward(ctx.fr, x, pilots, dllr.contiguous(), saved=dict(yf=yf, h=h))
+        x, pilots, yf, h, xt, nu = ctx.saved_tensors
+        dx = backward(ctx.fr, x, pilots, dllr.contiguous(), saved=dict(yf=yf, h=h, xt=xt, nu=nu))
         return dx, None, None
 
 

@@ -403,8 +403,9 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
   char* w = (char*)ws;
   const float2* yf = (saved && saved->yf) ? (const float2*)saved->yf : (const float2*)(w + L.yf);
   const float2* h = (saved && saved->h) ? (const float2*)saved->h : (const float2*)(w + L.h);
-  float2* xt = (float2*)(w + L.xt);
-  float* nu = (float*)(w + L.nu);
+  const bool have_xt = saved && saved->xt && saved->nu;
+  const float2* xt = have_xt ? (const float2*)saved->xt : (const float2*)(w + L.xt);
+  const float* nu = have_xt ? saved->nu : (const float*)(w + L.nu);
   uint8_t* flags = (uint8_t*)(w + L.flags);
   float2* gxt = (float2*)(w + L.gxt);
   float* gnu = (float*)(w + L.gnu);
@@ -421,8 +422,10 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
     if ((st = launch_fft(fr, n_tr, (const float2*)x, (float2*)(w + L.yf), false, stream))) return st;
   if (!(saved && saved->h))
     if ((st = launch_csi(fr, n_frames, yf, (const float2*)pilots, (float2*)(w + L.h), stream))) return st;
-  if ((st = launch_detect(fr, n_frames, h, yf, nullptr, xt, nu, flags, RXPHY_FP32, 0.f, nullptr, stream)))
-    return st;
+  if (!have_xt)
+    if ((st = launch_detect(fr, n_frames, h, yf, nullptr, (float2*)(w + L.xt), (float*)(w + L.nu), flags,
+                            RXPHY_FP32, 0.f, nullptr, stream)))
+      return st;
 
   const int D = fr.n_sym - 1;
   const int64_t n_fu = (int64_t)n_frames * fr.K;

@@ -83,7 +83,9 @@ def test_backward_saved_equals_recomputed(rx):
     dllr = torch.randn_like(out["llr"])
     a = rx.backward(fr, x, p, dllr)
     b = rx.backward(fr, x, p, dllr, saved=dict(yf=out["yf"], h=out["h"]))
-    assert torch.equal(a, b)
+    c = rx.backward(fr, x, p, dllr, saved=dict(yf=out["yf"], h=out["h"], xt=out["xt"], nu=out["nu"]))
+    d = rx.backward(fr, x, p, dllr, saved=dict(xt=out["xt"]))        # xt without nu: recomputed
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, d)
 
 
 def _bce(llr, bits):
