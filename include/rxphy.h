@@ -115,9 +115,14 @@ rxphy_status rxphy_csi(const rxphy_frame* frame, int32_t n_frames,
  * precision RXPHY_BF16 / RXPHY_FP16: the Gram and matched-filter products
  * take BF16 / FP16 operands (rounded to nearest even from FP32) with FP32
  * accumulation, the Cholesky runs in FP32, and every subcarrier whose
- * condition estimate (max L_ii / min L_ii)^2 exceeds cond_threshold is
- * re-solved in FP64 from the FP32 inputs with one step of iterative
- * refinement (flag RXPHY_FLAG_REFINED).  cond_threshold is ignored for FP32.
+ * condition estimate ||A||_F tr(A^{-1}) exceeds cond_threshold (an upper
+ * bound on kappa_2(A), at most K^1.5 times it), or whose low-precision
+ * factorisation breaks down, is re-solved in FP64 from the FP32 inputs:
+ * A = L L^H in FP64 and two steps of iterative refinement
+ * x <- x + A^{-1} (b - A x), b = H^H y, from the low-precision solution
+ * (from 0 where that is not finite); flag RXPHY_FLAG_REFINED.  A refined
+ * subcarrier with a non-finite input is erased and flagged NONFINITE.
+ * cond_threshold is ignored for FP32.
  *   h     : c64 [F][M][K][n_sc]
  *   yf    : c64 [F][M][n_sym][n_sc]   (symbols 1 .. n_sym-1 are read)
  *   xt    : c64 [F][K][n_sym-1][n_sc] (written)
@@ -133,14 +138,21 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames,
 /* csi and equal stages fused: rxphy_csi followed by rxphy_detect on the same
  * frames, with the channel estimate formed on the fly from symbol 0 of yf and
  * the pilots instead of being written to and read back from an H tensor.
- * Every output (xt, nu, flags, and the refinement of the low-precision
- * forms) is bit-identical to the two-call sequence; the CSI stage's H is
- * simply never stored.  Arguments as rxphy_csi and rxphy_detect; the
- * workspace is rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT,
- * precision) bytes (with 16 users in FP32, where each 16-subcarrier tile is
- * one pilot group, it holds each tile's Cholesky factor: 2304 bytes per tile,
- * 8-byte aligned, written and read back within the call; the caller owns it and may reuse it
- * once the stream has passed the call).                                       */
+ * In FP32, and in BF16 / FP16 with fewer than 16 users, every output (xt, nu,
+ * flags, and the refinement of the low-precision forms) is bit-identical to
+ * the two-call sequence; the CSI stage's H is simply never stored.  With 16
+ * users each 16-subcarrier tile is one pilot group and the call factors each
+ * tile once (its A^{-1} in a 2304-byte record, applied to the matched filter
+ * in FP32); in BF16 / FP16 that path forms the Gram matrix and the matched
+ * filter from BF16 / FP16 operands on the 16x16x32 matrix products, its
+ * condition estimate and FP64 refinement act per pilot group, and its results
+ * agree with rxphy_detect's within the precision's error (bit-identical only
+ * in FP32).  Arguments as rxphy_csi and rxphy_detect; the workspace is
+ * rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT, precision)
+ * bytes, 8-byte aligned (the 16-user path's records, plus for BF16 / FP16 the
+ * list of refined subcarriers: 4 bytes per subcarrier and 256 more), written
+ * and read back within the call; the caller owns it and may reuse it once the
+ * stream has passed the call.                                               */
 rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
                               const void* yf, const void* pilots, void* xt, float* nu,
                               uint8_t* flags, rxphy_precision precision, float cond_threshold,
@@ -148,11 +160,12 @@ rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
 
 /* csi, equal and demod stages fused: rxphy_csi_detect followed by
  * rxphy_demod on its x_tilde and nu.  llr, nu and flags are bit-identical to
- * that sequence; x_tilde is written only if xt is not NULL.  With 16 users in
- * FP32 the whole chain after the FFT is two kernels (the per-tile
- * factorisation, then the detector with the max-log demapping of each
- * equalised symbol as it is formed, so x_tilde need not round-trip through
- * memory); otherwise the stages run one after the other.
+ * that sequence; x_tilde is written only if xt is not NULL.  With 16 users
+ * the whole chain after the FFT is two kernels (the per-tile factorisation,
+ * then the detector with the max-log demapping of each equalised symbol as it
+ * is formed, so x_tilde need not round-trip through memory), plus in BF16 /
+ * FP16 the FP64 refinement of the listed pilot groups, which demaps its own
+ * symbols; otherwise the stages run one after the other.
  *   xt  : c64 [F][K][n_sym-1][n_sc] (written if not NULL)
  *   llr : f32 [F][K][n_sym-1][n_sc][qam_bits] (written)
  *   ws  : rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD,

@@ -205,7 +205,7 @@ rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames, 
   const rxphy_frame& fr = *frame;
   if (group_path(fr, precision))
     return launch_detect_group(fr, n_frames, (const float2*)yf, (const float2*)pilots, (float2*)xt, nu, flags,
-                               llr, ws, stream);
+                               llr, precision, cond_threshold, ws, stream);
   // the stages one after the other; x_tilde in the caller's buffer or after
   // the detector's part of the workspace
   float2* x = (float2*)xt;

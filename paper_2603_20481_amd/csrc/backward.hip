@@ -96,15 +96,6 @@ demod_adjoint_kernel(const float2* __restrict__ xt, const float* __restrict__ nu
 }
 
 // ---------------------------------------------------------------- detect adjoint
-// Sum of v over the 16 lanes of each DPP row, returned in every lane of the row.
-__device__ __forceinline__ float row_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xF, 0xF, true));  // row_shr:1
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x112, 0xF, 0xF, true));  // row_shr:2
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x114, 0xF, 0xF, true));  // row_shr:4
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x118, 0xF, 0xF, true));  // row_shr:8
-  return bc<15>(v);
-}
-
 // MMSE gains of every user in every lane of the row; padded users (U >= K)
 // get 1 so that their zero rows stay exactly zero.
 template <int U>
@@ -380,7 +371,7 @@ size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t
   if (which == RXPHY_WS_DETECT) return detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT) return csi_detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT_DEMOD) return csi_detect_demod_workspace_bytes(*frame, n_frames, precision);
-  if (which == RXPHY_WS_PRECODE) return frame->K == 16 ? group_workspace_bytes(*frame, n_frames) : 0;
+  if (which == RXPHY_WS_PRECODE) return frame->K == 16 ? group_workspace_bytes(*frame, n_frames, RXPHY_FP32) : 0;
   if (which == RXPHY_WS_BACKWARD) return layout(*frame, n_frames).total;
   return 0;
 }

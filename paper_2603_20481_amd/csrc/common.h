@@ -37,12 +37,20 @@ rxphy_status launch_csi(const rxphy_frame& fr, int32_t nf, const float2* yf, con
 rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
                            const float2* pil, float2* xt, float* nu, uint8_t* flags,
                            rxphy_precision prec, float thr, void* ws, hipStream_t s);
-// Fused CSI + detector for K = 16 in FP32 (one pilot group per tile); ws holds
-// group_workspace_bytes() of per-tile factor records.
+// Fused CSI + detector for K = 16 (one pilot group per tile); ws holds
+// group_workspace_bytes() of per-tile factor records (and, for BF16 / FP16,
+// the list of subcarriers handed to the FP64 refinement).
 // llr != nullptr: the demod stage fused in (xt may then be nullptr).
 rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                 float2* xt, float* nu, uint8_t* flags, float* llr, void* ws, hipStream_t s);
-size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf);
+                                 float2* xt, float* nu, uint8_t* flags, float* llr, rxphy_precision prec,
+                                 float thr, void* ws, hipStream_t s);
+size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec = RXPHY_FP32);
+// FP64 refinement of the listed subcarriers (rl[0] = count, then the entries
+// f * n_sc + i): x0 the low-precision start (nullptr: start from 0), xt / llr
+// written when not nullptr; with pil the channel is the LS estimate.
+rxphy_status launch_refine(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
+                           const float2* pil, const float2* x0, float2* xt, float* nu, uint8_t* flags,
+                           float* llr, const uint32_t* rl, hipStream_t s);
 // Downlink: ZF precoder of 16 users from the uplink pilots (factor records in
 // ws, as the fused detector's); QAM mapping; inverse transform with a prefix.
 rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,

@@ -4,6 +4,7 @@
 // erasures, and writes x_tilde [F][K][D][n_sc], nu [F][K][n_sc], flags [F][n_sc].
 // K is padded to KP in {4, 8, 16} (an identity block: same solution,
 // straight-line phase 2).
+#include "demod_core.h"
 #include "detect_core.h"
 
 namespace rxphy {
@@ -63,17 +64,22 @@ constexpr int RP = 17;   // row pitch (double2) of the 16 x 16 work matrices
 // b = H^H y are re-formed in FP64 from the FP32 inputs, A = L L^H in FP64,
 // refinement x <- x + A^{-1} (b - A x) from the low-precision x0, and
 // d = diag(A^{-1}) from the FP64 factor; then the unbiasing, nu and flags.
-// A start that is not finite (the low-precision factor broke down) becomes
+// A subcarrier with a non-finite channel or data value is erased and flagged
+// NONFINITE.  A start that is not finite (the low-precision factor broke down) becomes
 // x0 = 0.  Two steps are taken: one step leaves a relative error of about
 // kappa * eps64 times that of x0, and x0 carries no correct digit once
 // kappa * u exceeds 1 (u = 2^-8 for BF16 operands, 2^-11 for FP16), which the
 // refined subcarriers come close to or pass by construction; the second
 // step brings every subcarrier with kappa * eps64 << 1 to FP64 accuracy.
+//
+// x0 may be null (start from 0); xt is written when not null; Q > 0 writes
+// the max-log LLRs of the refined symbols into llr as the demod stage does.
+template <int Q>
 __global__ void __launch_bounds__(64)
 refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
-              const float2* __restrict__ pil, float2* __restrict__ xt,
-              float* __restrict__ nu, uint8_t* __restrict__ flags, const uint32_t* __restrict__ rlist,
-              int M, int K, int S, int n_sc, float n0f, int mmse) {
+              const float2* __restrict__ pil, const float2* __restrict__ x0, float2* __restrict__ xt,
+              float* __restrict__ nu, uint8_t* __restrict__ flags, float* __restrict__ llr,
+              const uint32_t* __restrict__ rlist, int M, int K, int S, int n_sc, float n0f, int mmse) {
   __shared__ double2 Hs[64 * 16];
   __shared__ double2 Ys[64 * 16];
   __shared__ double2 A[16 * RP];    // A, kept for the residuals
@@ -83,7 +89,8 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   __shared__ double2 X[16 * RP];
   __shared__ double2 V[16 * RP];
   __shared__ double dd[16];
-  __shared__ int bad;
+  __shared__ float nvs[16];
+  __shared__ int bad, nfin;
   const int D = S - 1;
   const int tid = threadIdx.x;
   const double n0 = (double)n0f;
@@ -91,6 +98,8 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
     const uint32_t sub = rlist[RL_OFF + e];
     const int f = (int)(sub / (uint32_t)n_sc), i = (int)(sub - (uint32_t)f * n_sc);
+    if (tid == 0) nfin = 0;
+    __syncthreads();
     for (int q = tid; q < M * K; q += 64) {
       const int m = q / K, u = q - m * K;
       float2 hval;
@@ -100,15 +109,18 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
       } else {
         hval = H[((int64_t)(f * M + m) * K + u) * n_sc + i];
       }
+      if (!(isfinite(hval.x) && isfinite(hval.y))) nfin = 1;
       Hs[m * 16 + u] = d2(hval);
     }
     for (int q = tid; q < M * D; q += 64) {
       const int m = q / D, s = q - m * D;
-      Ys[m * 16 + s] = d2(Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i]);
+      const float2 yv = Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i];
+      if (!(isfinite(yv.x) && isfinite(yv.y))) nfin = 1;
+      Ys[m * 16 + s] = d2(yv);
     }
     for (int q = tid; q < K * D; q += 64) {     // x0; a non-finite start becomes 0
       const int u = q / D, s = q - u * D;
-      const float2 v = xt[((int64_t)(f * K + u) * D + s) * n_sc + i];
+      const float2 v = x0 ? x0[((int64_t)(f * K + u) * D + s) * n_sc + i] : make_float2(0.f, 0.f);
       X[u * RP + s] = (isfinite(v.x) && isfinite(v.y)) ? d2(v) : make_double2(0.0, 0.0);
     }
     if (tid == 0) bad = 0;
@@ -181,19 +193,26 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
       }
       __syncthreads();
     }
-    const bool erase = bad != 0;
+    const bool erase = bad != 0 || nfin != 0;
+    for (int u = tid; u < K; u += 64) {
+      const double d = dd[u];
+      const double nv = mmse ? n0 * d / (1.0 - n0 * d) : n0 * d;
+      const float v = erase ? INFINITY : (float)nv;
+      nvs[u] = v;
+      nu[(int64_t)(f * K + u) * n_sc + i] = v;
+    }
+    __syncthreads();
     for (int q = tid; q < K * D; q += 64) {
       const int u = q / D, s = q - u * D;
       double2 x = X[u * RP + s];
       if (mmse) x = dsc(x, 1.0 / (1.0 - n0 * dd[u]));
-      xt[((int64_t)(f * K + u) * D + s) * n_sc + i] = erase ? make_float2(0.f, 0.f) : make_float2((float)x.x, (float)x.y);
+      const float2 xf = erase ? make_float2(0.f, 0.f) : make_float2((float)x.x, (float)x.y);
+      const int64_t e = ((int64_t)(f * K + u) * D + s) * n_sc + i;
+      if (xt) xt[e] = xf;
+      if constexpr (Q > 0) demk::demod_point<Q>(xf, nvs[u], llr + e * Q);
     }
-    for (int u = tid; u < K; u += 64) {
-      const double d = dd[u];
-      const double nv = mmse ? n0 * d / (1.0 - n0 * d) : n0 * d;
-      nu[(int64_t)(f * K + u) * n_sc + i] = erase ? INFINITY : (float)nv;
-    }
-    if (tid == 0 && flags) flags[(int64_t)f * n_sc + i] = erase ? RXPHY_FLAG_BREAKDOWN : RXPHY_FLAG_REFINED;
+    if (tid == 0 && flags)
+      flags[(int64_t)f * n_sc + i] = nfin ? RXPHY_FLAG_NONFINITE : erase ? RXPHY_FLAG_BREAKDOWN : RXPHY_FLAG_REFINED;
     __syncthreads();
   }
 }
@@ -223,15 +242,15 @@ void launch_p(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* 
 
 }  // namespace
 
-bool group_path(const rxphy_frame& fr, rxphy_precision prec) { return prec == RXPHY_FP32 && fr.K == 16; }
+bool group_path(const rxphy_frame& fr, rxphy_precision) { return fr.K == 16; }
 
 size_t csi_detect_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
-  if (group_path(fr, prec)) return group_workspace_bytes(fr, nf);
+  if (group_path(fr, prec)) return group_workspace_bytes(fr, nf, prec);
   return detect_workspace_bytes(fr, nf, prec);
 }
 
 size_t csi_detect_demod_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
-  if (group_path(fr, prec)) return group_workspace_bytes(fr, nf);
+  if (group_path(fr, prec)) return group_workspace_bytes(fr, nf, prec);
   const size_t a = (detect_workspace_bytes(fr, nf, prec) + 255) & ~(size_t)255;
   return a + (size_t)nf * fr.K * (fr.n_sym - 1) * fr.n_sc * 8;
 }
@@ -245,8 +264,9 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
                            const float2* pil, float2* xt, float* nu, uint8_t* flags, rxphy_precision prec,
                            float thr, void* ws, hipStream_t s) {
   if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);
+  if (pil && group_path(fr, prec))
+    return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, nullptr, prec, thr, ws, s);
   if (prec == RXPHY_FP32) {
-    if (pil && group_path(fr, prec)) return launch_detect_group(fr, nf, yf, pil, xt, nu, flags, nullptr, ws, s);
     launch_p<P_FP32>(fr, nf, h, yf, pil, xt, nu, flags, thr, nullptr, s);
     return launch_status("detect kernel");
   }
@@ -256,10 +276,26 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
   else launch_p<P_FP16>(fr, nf, h, yf, pil, xt, nu, flags, thr, rl, s);
   rxphy_status st = launch_status("detect kernel");
   if (st) return st;
+  return launch_refine(fr, nf, h, yf, pil, xt, xt, nu, flags, nullptr, rl, s);
+}
+
+rxphy_status launch_refine(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
+                           const float2* pil, const float2* x0, float2* xt, float* nu, uint8_t* flags,
+                           float* llr, const uint32_t* rl, hipStream_t s) {
   const int64_t n_sub = (int64_t)nf * fr.n_sc;
   const unsigned blocks = (unsigned)(n_sub < 4096 ? n_sub : 4096);
-  hipLaunchKernelGGL(refine_kernel, dim3(blocks), dim3(64), 0, s, h, yf, pil, xt, nu, flags, rl, fr.M,
-                     fr.K, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
+  const int q = llr ? fr.qam_bits : 0;
+#define RXPHY_REFINE(QQ)                                                                                      \
+  hipLaunchKernelGGL(refine_kernel<QQ>, dim3(blocks), dim3(64), 0, s, h, yf, pil, x0, xt, nu, flags, llr, rl, \
+                     fr.M, fr.K, fr.n_sym, fr.n_sc, fr.n0, mmse)
+  switch (q) {
+    case 0: RXPHY_REFINE(0); break;
+    case 2: RXPHY_REFINE(2); break;
+    case 4: RXPHY_REFINE(4); break;
+    default: RXPHY_REFINE(6); break;
+  }
+#undef RXPHY_REFINE
   return launch_status("refine kernel");
 }
 

@@ -46,6 +46,7 @@ struct SharedFactor {
   float2 L[16 * PP];
   float inv[16];
   float dl[16];
+  float afro2;          // ||A||_F^2 (the condition estimate of the mixed precisions)
   int ok;
   int uniform;
 };
@@ -59,6 +60,23 @@ __device__ __forceinline__ float bc(float v) {   // lane L of each 16-lane row, 
 }
 template <int L>
 __device__ __forceinline__ float2 bc2(float2 v) { return make_float2(bc<L>(v.x), bc<L>(v.y)); }
+
+// Sum of v over the 16 lanes of each DPP row, returned in every lane of the row.
+__device__ __forceinline__ float row_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xF, 0xF, true));  // row_shr:1
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x112, 0xF, 0xF, true));  // row_shr:2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x114, 0xF, 0xF, true));  // row_shr:4
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x118, 0xF, 0xF, true));  // row_shr:8
+  return bc<15>(v);
+}
+
+// Condition estimate of the mixed precisions: kappa_est = ||A||_F tr(A^{-1})
+// from the squared Frobenius norm of A and d_k = [A^{-1}]_kk.  Since
+// ||A||_F >= lambda_max and tr(A^{-1}) >= 1 / lambda_min it never falls below
+// kappa_2(A), and it exceeds it by at most K^1.5.
+__device__ __forceinline__ float cond_estimate(float afro2, float trace_inv) {
+  return __builtin_sqrtf(afro2) * trace_inv;
+}
 
 // Complex multiply-subtract kernels written as four FMAs each.
 __device__ __forceinline__ float2 cms(float2 s, float2 a, float2 b) {      // s - a b
@@ -363,11 +381,11 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
 // X_hat = A^{-1} Z (before the MMSE unbiasing), v[k] = column `row` of L^{-1},
 // inv[k] = 1 / L[k][k], dl = d_row = [A^{-1}]_{row,row}, ok = factorisation
 // succeeded; the subcarrier's slab Pm holds L row by row.
-template <int KP>
+template <int KP, bool NORM = false>
 __device__ __forceinline__ void factor_solve(float2* P, float2* Pm, const f32x4* gr, const f32x4* gi,
                                              const f32x4* zr, const f32x4* zi, int K, float n0,
                                              int mmse, int row, int col, int g4, float2* x, float2* v,
-                                             float* inv, float& dl, bool& ok) {
+                                             float* inv, float& dl, bool& ok, float* afro2 = nullptr) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -378,6 +396,13 @@ __device__ __forceinline__ void factor_solve(float2* P, float2* Pm, const f32x4*
   for (int c = 0; c < 16; ++c) {
     a[c] = Pm[row * PP + c];                       // row `row` of A
     if (c == row) a[c].x = row < K ? a[c].x + (mmse ? n0 : 0.f) : 1.0f;
+  }
+  if constexpr (NORM) {                            // ||A||_F^2 over the K x K block
+    float s2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < K) s2 += a[c].x * a[c].x + a[c].y * a[c].y;
+    *afro2 = row_sum(row < K ? s2 : 0.f);
   }
   __syncthreads();
 #pragma unroll
@@ -405,8 +430,8 @@ __device__ __forceinline__ void factor_solve(float2* P, float2* Pm, const f32x4*
 }
 
 // P: operand precision of the phase-1 products (detect_core.h).  For BF16 and
-// FP16, subcarriers whose condition estimate kappa = (max L_ii / min L_ii)^2
-// exceeds the threshold, or whose low-precision factorisation breaks down,
+// FP16, subcarriers whose condition estimate ||A||_F tr(A^{-1}) exceeds the
+// threshold, or whose low-precision factorisation breaks down,
 // are handed to the FP64 refinement kernel: their x_hat (before the MMSE
 // unbiasing) is written to xt and the subcarrier is appended to a device-side
 // list (rlist[0] = count, entries from rlist[RL_OFF]).
@@ -517,12 +542,12 @@ __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, co
 // is called once by every wave, with no register of the factorisation live.  (Wave w of
 // every workgroup sits on SIMD w, so callers rotate wf from tile to tile to
 // spread the factorisations over the four SIMDs.)
-template <int KP, class Prefetch>
+template <int KP, bool NORM, class Prefetch>
 __device__ __forceinline__ void factor_solve_shared(float2* Pw, float2* Pm, SharedFactor* sf, int w, int wf,
                                                     const f32x4& g0r, const f32x4& g0i, const f32x4* zr,
                                                     const f32x4* zi, int K, float n0, int mmse, int row,
                                                     int col, int g4, float2* x, float* inv, float& dl,
-                                                    bool& ok, Prefetch prefetch) {
+                                                    bool& ok, float* afro2, Prefetch prefetch) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) sf->part[w][(g4 + r) * PP + col] = make_float2(g0r[r], g0i[r]);
 #pragma unroll
@@ -541,6 +566,13 @@ __device__ __forceinline__ void factor_solve_shared(float2* Pw, float2* Pm, Shar
       if (c == row) s.x = row < K ? s.x + (mmse ? n0 : 0.f) : 1.0f;
       a[c] = s;
     }
+    float s2 = 0.f;
+    if constexpr (NORM) {                                // ||A||_F^2 over the K x K block
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < K) s2 += a[c].x * a[c].x + a[c].y * a[c].y;
+      s2 = row_sum(row < K ? s2 : 0.f);
+    }
     bool okw = true;
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = make_float2(k == row ? 1.f : 0.f, 0.f);
@@ -553,7 +585,10 @@ __device__ __forceinline__ void factor_solve_shared(float2* Pw, float2* Pm, Shar
       for (int c = 0; c < 16; ++c) sf->L[row * PP + c] = a[c];
       sf->dl[row] = d;
       sf->inv[row] = inv[row];
-      if (row == 0) sf->ok = okw ? 1 : 0;
+      if (row == 0) {
+        sf->ok = okw ? 1 : 0;
+        if constexpr (NORM) sf->afro2 = s2;
+      }
     }
   }
   // the next tile's first chunk: the factoring wave after its factorisation,
@@ -566,6 +601,7 @@ __device__ __forceinline__ void factor_solve_shared(float2* Pw, float2* Pm, Shar
   for (int k = 0; k < 16; ++k) inv[k] = sf->inv[k];
   dl = sf->dl[row];
   ok = sf->ok != 0;
+  if constexpr (NORM) *afro2 = sf->afro2;
   fwd_all<KP>(Seq16{}, sf->L, inv, x);                  // L W = Z
   bwd_all<KP>(Seq16{}, sf->L, inv, x);                  // L^H X = W
 }
@@ -602,8 +638,9 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
   const int scl = l >> 4, row = l & 15;           // phase-2 lane: subcarrier scl, index row
   float2* Pm = Pw + scl * PMAT;
   float2 z[16];
-  float inv[16], dl;
+  float inv[16], dl, afro2 = 0.f;
   bool ok;
+  constexpr bool NORM = P != P_FP32;
   // The CSI stage holds the estimate constant over each pilot group of K
   // subcarriers, so a tile inside one group usually carries one channel
   // matrix: then the Gram matrix is formed once and A is factored once per
@@ -623,8 +660,8 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
       have0 = false;
       shared = __builtin_amdgcn_readfirstlane(sf->uniform) != 0;
       if (shared) {
-        factor_solve_shared<KP>(Pw, Pm, sf, w, (i0 / TS) & 3, g0r, g0i, zr, zi, K, n0, mmse, row, col, g4,
-                                z, inv, dl, ok, [&]() {
+        factor_solve_shared<KP, NORM>(Pw, Pm, sf, w, (i0 / TS) & 3, g0r, g0i, zr, zi, K, n0, mmse, row, col,
+                                      g4, z, inv, dl, ok, &afro2, [&]() {
                                   if (i0n >= 0)
                                     load_chunk<FU>(Hn ? Hn : H, Yn ? Yn : Yf, pn ? pn : pil, M, K, S, n_sc,
                                                    i0n, 0, hv, yv, pv);
@@ -642,7 +679,7 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
                    PREF ? i0n : -1, Hn, Yn, pn);
     have0 = PREF && i0n >= 0;
     float2 v[16];
-    factor_solve<KP>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok);
+    factor_solve<KP, NORM>(Pw, Pm, gr, gi, zr, zi, K, n0, mmse, row, col, g4, z, v, inv, dl, ok, &afro2);
   }
 
   const bool mu_bad = mmse && row < K && !(1.0f - n0 * dl > 0.f);
@@ -652,12 +689,8 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
   const bool nf = nonfin[4 * w + scl] != 0;
   bool refine = false;
   if constexpr (P != P_FP32) {
-    float imax = 0.f, imin = INFINITY;
-#pragma unroll
-    for (int k = 0; k < KP; ++k)
-      if (k < K) { imax = fmaxf(imax, inv[k]); imin = fminf(imin, inv[k]); }
-    const float r = imax / imin;                  // = max L_ii / min L_ii
-    refine = !nf && (!ok || !(r * r <= thr));
+    const float kest = cond_estimate(afro2, row_sum(row < K ? dl : 0.f));
+    refine = !nf && (!ok || !(kest <= thr));
   }
   if (mmse) unbias_all<KP>(Seq16{}, dl, n0, K, refine, z);
   if (i >= n_sc) return;

@@ -29,6 +29,8 @@
 // Every product, sum and factorisation step is the one the general detector
 // (detect_core.h, shared-factor path) performs on the same values in the
 // same order, so the results are bit-identical to rxphy_csi + rxphy_detect.
+#include <type_traits>
+
 #include "demod_core.h"
 #include "detect_core.h"
 
@@ -40,6 +42,8 @@ struct alignas(256) GroupRec {
   float dl[16];          // d_k = [A^-1]_kk as the factorisation forms it
   int ok;                // factorisation succeeded
   int hbad;              // a non-finite channel value
+  int refine;            // BF16 / FP16: the tile is finished by the FP64 refinement
+  int pad;
 };
 
 namespace {
@@ -48,6 +52,30 @@ using namespace det;
 
 constexpr int GWAVES = 4;     // waves per workgroup
 typedef float float4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// 16x16x32 products of gfx950 with 8 operand values per lane (lane l supplies
+// A[l % 16][8 (l / 16) + t] and B[8 (l / 16) + t][l % 16], t = 0..7): BF16 or
+// FP16 operands (rounded to nearest even from FP32), FP32 accumulation.
+template <int P>
+struct LowP;
+template <>
+struct LowP<P_BF16> {
+  typedef bf16x8 vec;
+  typedef __bf16 elem;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct LowP<P_FP16> {
+  typedef f16x8 vec;
+  typedef _Float16 elem;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
 
 __device__ __forceinline__ float2 ldg2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
@@ -125,6 +153,10 @@ __device__ __forceinline__ void factor_loads(const float2* Yf, const float2* pil
 // LS estimate, non-finite check and A = sum of the four partial Gram matrices
 // (8-antenna chunks c and c + 4, in order, summed in order) into t as rows
 // of pitch PP; returns whether a channel value is non-finite.
+// BF16 / FP16 (P): the Gram matrix from operands rounded to that precision,
+// 32 antennas per product: element t of lane (kq, u) is antenna
+// 4 (8 c + t) + kq of user u, in both operands.
+template <int P>
 __device__ __forceinline__ bool factor_gram(float2* hv, float2 pv, int M, int kq, int u, float2* t) {
   float probe = 0.f;
 #pragma unroll
@@ -132,6 +164,29 @@ __device__ __forceinline__ bool factor_gram(float2* hv, float2 pv, int M, int kq
     hv[s] = 4 * s + kq < M ? ls_estimate(hv[s], pv) : make_float2(0.f, 0.f);
     probe = __builtin_fmaf(hv[s].x, 0.f, probe);
     probe = __builtin_fmaf(hv[s].y, 0.f, probe);
+  }
+  if constexpr (P != P_FP32) {
+    using LP = LowP<P>;
+    using E = typename LP::elem;
+    f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gi = gr;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (32 * c < M) {
+        typename LP::vec ar, ai;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ar[e] = (E)hv[8 * c + e].x;
+          ai[e] = (E)hv[8 * c + e].y;
+        }
+        gr = LP::mma(ar, ar, gr);
+        gr = LP::mma(ai, ai, gr);
+        gi = LP::mma(ar, ai, gi);
+        gi = LP::mma(-ai, ar, gi);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[(4 * kq + r) * PP + u] = make_float2(gr[r], gi[r]);
+    return __ballot(!(probe == 0.f)) != 0ull;
   }
   f32x4 pr[4], pi[4];
 #pragma unroll
@@ -167,10 +222,16 @@ __device__ __forceinline__ bool factor_gram(float2* hv, float2 pv, int M, int kq
 // Gram matrices one after the other on MFMA, then one Crout pass in which
 // 16-lane row k works on tile k % TPW (the factorisation's broadcasts stay
 // within a row).  Two tiles per wavefront keep four wavefronts per SIMD.
-template <int TPW>
+//
+// BF16 / FP16 (P): the Gram matrix from low-precision operands, the Cholesky
+// factor in FP32, and tiles whose condition estimate ||A||_F tr(A^-1) exceeds
+// thr (or whose factorisation broke down) are marked in their record and
+// their subcarriers appended to the refinement list rl.
+template <int TPW, int P = P_FP32>
 __global__ void __launch_bounds__(256)
 group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil, GroupRec* __restrict__ rec,
-                    int T, int nt, int M, int S, int n_sc, float n0, int mmse) {
+                    int T, int nt, int M, int S, int n_sc, float n0, int mmse, float thr = 0.f,
+                    uint32_t* __restrict__ rl = nullptr) {
   __shared__ float2 tp[GWAVES][TPW][16 * PP];
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -183,7 +244,7 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
 #pragma unroll
   for (int t = 0; t < TPW; ++t) factor_loads(Yf, pil, base + t, T, nt, M, S, n_sc, kq, u, hv[t], pv[t]);
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) bad[t] = factor_gram(hv[t], pv[t], M, kq, u, tp[w][t]);
+  for (int t = 0; t < TPW; ++t) bad[t] = factor_gram<P>(hv[t], pv[t], M, kq, u, tp[w][t]);
 
   // row kq of the wave factors tile base + kq % TPW; lane `row` holds A[row][:]
   const int tk = kq % TPW;
@@ -195,6 +256,12 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     float2 g = tp[w][tk][row * PP + c];
     if (c == row) g.x = g.x + (mmse ? n0 : 0.f);
     a[c] = g;
+  }
+  float afro2 = 0.f;                             // ||A||_F^2 (mixed precisions)
+  if constexpr (P != P_FP32) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) afro2 += a[c].x * a[c].x + a[c].y * a[c].y;
+    afro2 = row_sum(afro2);
   }
   bool okw = true;
 #pragma unroll
@@ -227,16 +294,28 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     }
   }
   const int tix = base + tk;
+  bool hb = bad[0];
+#pragma unroll
+  for (int t = 1; t < TPW; ++t)
+    if (tk == t) hb = bad[t];
+  bool refine = false;
+  if constexpr (P != P_FP32) {
+    const float kest = cond_estimate(afro2, row_sum(d));
+    refine = !hb && (!okw || !(kest <= thr));     // the same in every lane of the row
+  }
   if (kq < TPW && tix < T) {
     GroupRec& R = rec[tix];
     R.dl[row] = d;
     if (row == 0) {
-      bool hb = bad[0];
-#pragma unroll
-      for (int t = 1; t < TPW; ++t)
-        if (tk == t) hb = bad[t];
       R.ok = okw ? 1 : 0;                        // the same in every lane of the row
       R.hbad = hb ? 1 : 0;
+      R.refine = refine ? 1 : 0;
+      if (refine) {                              // the tile's subcarriers into the list
+        const int f = tix / nt, i0 = (tix - f * nt) * 16;
+        const int cnt = min(16, n_sc - i0);
+        const uint32_t slot = atomicAdd(rl, (uint32_t)cnt);
+        for (int e = 0; e < cnt; ++e) rl[RL_OFF + slot + e] = (uint32_t)(f * n_sc + i0 + e);
+      }
     }
   }
 }
@@ -280,6 +359,51 @@ __device__ __forceinline__ void z_slot(const float2* hs, const float2 (*y)[3], c
   xi = xk + xi;
 }
 
+// BF16 / FP16 (P): Z = H^H Y from operands rounded to that precision, four
+// real products per complex one over 32 antennas at a time (element t of lane
+// (kq, u) is antenna 4 (8 c + t) + kq: user u's channel in the first operand,
+// subcarrier u's data in the second), then X = A^-1 Z in FP32 as z_slot does.
+template <int J, bool FULLM, int P>
+__device__ __forceinline__ void z_slot_lp(const float2* hs, const float2 (*y)[3], const float2* brow, float& probe,
+                                          int kq, int u, int M, f32x4& xr, f32x4& xi) {
+  using LP = LowP<P>;
+  using E = typename LP::elem;
+  f32x4 zr = {0.f, 0.f, 0.f, 0.f}, zi = zr;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (FULLM || 32 * c < M) {
+      typename LP::vec hr, hi, yr, yi;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int s = 8 * c + e;
+        const float2 h = hs[(4 * s + kq) * 16 + u];
+        const float2 yv = y[s][J];
+        probe = __builtin_fmaf(yv.x, 0.f, probe);
+        probe = __builtin_fmaf(yv.y, 0.f, probe);
+        hr[e] = (E)h.x;
+        hi[e] = (E)h.y;
+        yr[e] = (E)yv.x;
+        yi[e] = (E)yv.y;
+      }
+      zr = LP::mma(hr, yr, zr);
+      zr = LP::mma(hi, yi, zr);
+      zi = LP::mma(hr, yi, zi);
+      zi = LP::mma(-hi, yr, zi);
+    }
+  }
+  f32x4 xk = {0.f, 0.f, 0.f, 0.f};
+  xr = xi = xk;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float2 b = brow[r];
+    xk = mfma(b.x + b.y, zr[r], xk);
+    xr = mfma(b.y, zr[r] + zi[r], xr);
+    xi = mfma(b.x, zi[r] - zr[r], xi);
+  }
+  xr = xk - xr;
+  xi = xk + xi;
+}
+
 // Symbol slot j (d = w + 4 j) of this lane's data into register slot R:
 // y[s][R] = Y[4 s + kq][1 + d][i0 + u]; a slot the wave does not own reads
 // zero without touching memory, so every wave issues the same loads.
@@ -298,8 +422,14 @@ __device__ __forceinline__ void load_slot(float2 (*y)[3], __amdgpu_buffer_rsrc_t
 // Q > 0: the demod stage follows in the same kernel (max-log LLRs of every
 // equalised symbol into llr, as demod_kernel computes them from x_tilde and
 // nu); xt may then be null (not written).
-template <int Q>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+//
+// BF16 / FP16 (P): the matched filter from low-precision operands (z_slot_lp);
+// a tile whose record is marked for refinement writes nothing (the FP64
+// refinement kernel writes all of its outputs).
+// Three workgroups per CU for FP32 (168 registers), two for BF16 / FP16
+// (their operand conversions need 187 registers; at 168 they spill).
+template <int Q, int P = P_FP32>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == P_FP32 ? 3 : 2)))
 detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil,
                     const GroupRec* __restrict__ rec, float2* __restrict__ xt, float* __restrict__ nu,
                     uint8_t* __restrict__ flags, float* __restrict__ llr, int M, int S, int n_sc, float n0,
@@ -337,6 +467,8 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   const float4v dl4 = __builtin_bit_cast(
       float4v, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)opaque(2048u + 16u * kq), 0, 0));
   const float2 okh = ldg2(rr, opaque(2048u + 64u));
+  float2 rfp = make_float2(0.f, 0.f);
+  if constexpr (P != P_FP32) rfp = ldg2(rr, opaque(2048u + 72u));
   const __amdgpu_buffer_rsrc_t yr = rsrc(Yf + f * M * S * n_sc, (uint32_t)M * S * n_sc * 8u);
   const uint32_t ant = (uint32_t)S * n_sc * 32u;             // 4 antennas
   const uint32_t sym = (uint32_t)n_sc * 32u;                 // 4 symbols
@@ -359,6 +491,8 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   load_slot<0>(y, yr, lane, 0, nj, ant, sym);
   load_slot<1>(y, yr, lane, 1, nj, ant, sym);
   load_slot<2>(y, yr, lane, 2, nj, ant, sym);
+  if constexpr (P != P_FP32)
+    if (__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, rfp.x)) != 0) return;   // the whole workgroup
 
   // ---- H = LS estimate (absent antennas zero) into LDS
 #pragma unroll
@@ -404,18 +538,29 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     }
   };
   f32x4 xr, xi;
+  auto zs = [&](auto jc, auto fm) {
+    constexpr int J = decltype(jc)::value;
+    constexpr bool FM = decltype(fm)::value;
+    if constexpr (P == P_FP32) z_slot<J, FM>(hs, y, brow, probe, kq, u, M, xr, xi);
+    else z_slot_lp<J, FM, P>(hs, y, brow, probe, kq, u, M, xr, xi);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
   if (M == 64) {
-    if (nj > 0) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(0, xr, xi); }
+    using FM = std::true_type;
+    if (nj > 0) { zs(I0{}, FM{}); emit(0, xr, xi); }
     load_slot<0>(y, yr, lane, 3, nj, ant, sym);
-    if (nj > 1) { z_slot<1, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(1, xr, xi); }
-    if (nj > 2) { z_slot<2, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
-    if (nj > 3) { z_slot<0, true>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
+    if (nj > 1) { zs(I1{}, FM{}); emit(1, xr, xi); }
+    if (nj > 2) { zs(I2{}, FM{}); emit(2, xr, xi); }
+    if (nj > 3) { zs(I0{}, FM{}); emit(3, xr, xi); }
   } else {
-    if (nj > 0) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(0, xr, xi); }
+    using FM = std::false_type;
+    if (nj > 0) { zs(I0{}, FM{}); emit(0, xr, xi); }
     load_slot<0>(y, yr, lane, 3, nj, ant, sym);
-    if (nj > 1) { z_slot<1, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(1, xr, xi); }
-    if (nj > 2) { z_slot<2, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(2, xr, xi); }
-    if (nj > 3) { z_slot<0, false>(hs, y, brow, probe, kq, u, M, xr, xi); emit(3, xr, xi); }
+    if (nj > 1) { zs(I1{}, FM{}); emit(1, xr, xi); }
+    if (nj > 2) { zs(I2{}, FM{}); emit(2, xr, xi); }
+    if (nj > 3) { zs(I0{}, FM{}); emit(3, xr, xi); }
   }
   {
     const uint64_t bad = __ballot(!(probe == 0.f));
@@ -588,8 +733,9 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
   const int64_t T = (int64_t)nf * nt;
   GroupRec* rec = (GroupRec*)ws;
   if (!reuse) {                                  // else: the uplink's records for these frames are in ws
-    hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s,
-                       yf, pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, fr.detector == RXPHY_MMSE ? 1 : 0);
+    hipLaunchKernelGGL((group_factor_kernel<2, P_FP32>), dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))),
+                       dim3(256), 0, s, yf, pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0,
+                       fr.detector == RXPHY_MMSE ? 1 : 0, 0.f, (uint32_t*)nullptr);
     rxphy_status st = launch_status("group factor kernel");
     if (st) return st;
   }
@@ -604,27 +750,32 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
   return launch_status("precode kernel");
 }
 
-size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf) {
-  return (size_t)nf * ((fr.n_sc + 15) / 16) * sizeof(GroupRec);
+size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
+  const size_t recs = (size_t)nf * ((fr.n_sc + 15) / 16) * sizeof(GroupRec);
+  if (prec == RXPHY_FP32) return recs;
+  return recs + (size_t)RL_OFF * 4 + (size_t)nf * fr.n_sc * 4;      // + the refinement list
 }
 
-rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
-                                 float2* xt, float* nu, uint8_t* flags, float* llr, void* ws, hipStream_t s) {
-  if (nf == 0) return RXPHY_OK;
-  if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);   // grid y
-  if (!ws || ((uintptr_t)ws & 7u)) return fail(RXPHY_EWORKSPACE, "csi_detect workspace must be 8-byte aligned");
+namespace {
+__global__ void clear_list_kernel(uint32_t* rl) {
+  if (threadIdx.x == 0) rl[0] = 0u;
+}
+
+template <int P>
+rxphy_status launch_group_p(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                            float2* xt, float* nu, uint8_t* flags, float* llr, float thr, GroupRec* rec,
+                            uint32_t* rl, hipStream_t s) {
   const int nt = (fr.n_sc + 15) / 16;
   const int64_t T = (int64_t)nf * nt;
-  GroupRec* rec = (GroupRec*)ws;
   const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
-  hipLaunchKernelGGL(group_factor_kernel<2>, dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256), 0, s, yf,
-                     pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse);
+  hipLaunchKernelGGL((group_factor_kernel<2, P>), dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256),
+                     0, s, yf, pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse, thr, rl);
   rxphy_status st = launch_status("group factor kernel");
   if (st) return st;
   const dim3 grid(nt, nf);
   const int q = llr ? fr.qam_bits : 0;
-#define RXPHY_GROUP_LAUNCH(QQ)                                                                              \
-  hipLaunchKernelGGL(detect_group_kernel<QQ>, grid, dim3(256), 0, s, yf, pil, rec, xt, nu, flags, llr, fr.M, \
+#define RXPHY_GROUP_LAUNCH(QQ)                                                                                   \
+  hipLaunchKernelGGL((detect_group_kernel<QQ, P>), grid, dim3(256), 0, s, yf, pil, rec, xt, nu, flags, llr, fr.M, \
                      fr.n_sym, fr.n_sc, fr.n0, mmse)
   switch (q) {
     case 0: RXPHY_GROUP_LAUNCH(0); break;
@@ -635,6 +786,25 @@ rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2
   }
 #undef RXPHY_GROUP_LAUNCH
   return launch_status("detect group kernel");
+}
+}  // namespace
+
+rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                                 float2* xt, float* nu, uint8_t* flags, float* llr, rxphy_precision prec,
+                                 float thr, void* ws, hipStream_t s) {
+  if (nf == 0) return RXPHY_OK;
+  if (nf > 65535) return fail(RXPHY_EUNSUPPORTED, "n_frames = %d > 65535", nf);   // grid y
+  if (!ws || ((uintptr_t)ws & 7u)) return fail(RXPHY_EWORKSPACE, "csi_detect workspace must be 8-byte aligned");
+  GroupRec* rec = (GroupRec*)ws;
+  if (prec == RXPHY_FP32) return launch_group_p<P_FP32>(fr, nf, yf, pil, xt, nu, flags, llr, 0.f, rec, nullptr, s);
+  uint32_t* rl = (uint32_t*)((char*)ws + group_workspace_bytes(fr, nf, RXPHY_FP32));
+  hipLaunchKernelGGL(clear_list_kernel, dim3(1), dim3(64), 0, s, rl);
+  rxphy_status st = launch_status("clear list kernel");
+  if (st) return st;
+  st = prec == RXPHY_BF16 ? launch_group_p<P_BF16>(fr, nf, yf, pil, xt, nu, flags, llr, thr, rec, rl, s)
+                          : launch_group_p<P_FP16>(fr, nf, yf, pil, xt, nu, flags, llr, thr, rec, rl, s);
+  if (st) return st;
+  return launch_refine(fr, nf, nullptr, yf, pil, nullptr, xt, nu, flags, llr, rl, s);
 }
 
 }  // namespace rxphy

@@ -178,14 +178,16 @@ def test_demod_stage(rx, q):
     nu[0, 1, 7] = np.inf
     fr = rx.Frame(8, K, 512, n_sc, D + 1, 0, q)
     llr = host(rx.demod(fr, dev(xt), dev(nu)))
-    # Two bounds: the relative metric below 1e-5 (a hundredth of the stated
-    # LLR target of 1e-3), and each LLR within the FP32 forward-error bound of
-    # its definition (a difference of two squared distances along one axis,
-    # divided by nu): every operand is at most |x| + l_max, so any evaluation
-    # order in FP32 errs by at most a few units of 2^-24 (|x| + l_max)^2 / nu,
-    # plus the rounding of the result.  The inputs are Gaussian, wider than
-    # the constellation, with nu down to 0.01, so the second bound is the
-    # tighter one on the LLRs near zero.
+    # Each LLR within the FP32 forward-error bound of its definition (a
+    # difference of two squared distances along one axis, divided by nu):
+    # every operand is at most |x| + l_max, so any evaluation order in FP32
+    # errs by at most a few units of 2^-24 (|x| + l_max)^2 / nu, plus the
+    # rounding of the result; and the relative metric below 1e-4, a tenth of
+    # the stated LLR target.  The metric cannot be held to 1e-5 here: the
+    # inputs are Gaussian, wider than the constellation, with nu down to
+    # 0.01, so an LLR near zero at the smallest nu carries an absolute error
+    # of that bound, up to 1.4e-5 of the metric's floor (0.01 RMS) for 64-QAM,
+    # while staying within a quarter of its own FP32 bound.
     lmax = {2: 1 / math.sqrt(2), 4: 3 / math.sqrt(10), 6: 7 / math.sqrt(42)}[q]
     u = 2.0 ** -24
     for f in range(F):
@@ -196,7 +198,7 @@ def test_demod_stage(rx, q):
         fin = ~np.broadcast_to(np.isinf(nu[f])[:, None, :, None], ref.shape)
         worst = float(np.max(np.abs(llr[f] - ref)[fin] / bound[fin]))
         say("  llr_rel", e, "max error / FP32 bound", worst)
-        assert e < 1e-5
+        assert e < 1e-4
         assert worst <= 1.0
         assert np.all(llr[f][~fin] == 0)            # erased points
         mism, band = hard_bits_outside_guard(llr[f], ref)
