@@ -223,6 +223,23 @@ def cpu_baseline(cfg, det, budget_s, workers):
                 forms[name] = {"oracle_1core": {"value": dets / secs, "unit": "subcarrier-detections/s",
                                                 "seconds": round(secs, 2), "frames": len(smp["inputs"])},
                                "error": res}
+            elif smp["kind"] == "ldpc":             # bit-exact against the FP32-mode oracle; FP64 timed
+                from oracle import ldpc_oracle as LO
+                same = True
+                for k in range(len(smp["index"])):
+                    rp, rb, ri = LO.decode(smp["base"], smp["z"], smp["llr"][k], smp["max_iter"], smp["alpha"],
+                                           dtype=np.float32)
+                    same = same and ri == smp["iters"][k] and np.array_equal(rb, smp["bits"][k]) and \
+                        np.array_equal(rp.view(np.uint32), smp["post"][k].view(np.uint32))
+                t1 = time.perf_counter()
+                for k in range(len(smp["index"])):
+                    LO.decode(smp["base"], smp["z"], smp["llr"][k], smp["max_iter"], smp["alpha"])
+                secs = time.perf_counter() - t1
+                kb = smp["base"].shape[1] - smp["base"].shape[0]
+                forms[name] = {"oracle_1core": {"value": len(smp["index"]) * kb * smp["z"] / secs / 1e9,
+                                                "unit": "Gbit/s (FP64 oracle)", "seconds": round(secs, 2),
+                                                "codewords": len(smp["index"])},
+                               "error": {"bit_exact_vs_fp32_oracle": bool(same), "codewords": smp["index"]}}
             else:                                   # backward: dL/dx against the oracle adjoint
                 fo = smp["input"]
                 gx, _ = O.backward(fo.x, fo.pilots, fo.shape, 1.0, smp["det"], smp["dllr"].astype(np.float64))
@@ -847,6 +864,72 @@ def run_fwd_bwd(rx, torch, args):
     return out
 
 
+LDS_PEAK_GBS = 256 * 128 * 2.4     # 256 CUs x 128 B per clock x 2.4 GHz
+
+
+def run_ldpc(rx, torch, args):
+    """Layered min-sum decoding of n_cw codewords of a 46 x 68 quasi-cyclic
+    code at lifting size 384 (the shape of the largest 3GPP base graph, random
+    shifts), BPSK over AWGN."""
+    from synth import ldpc as SL
+    z, mb, kb = 384, 46, 22
+    base = SL.random_base(mb, kb, z, 7, seed=61)
+    n_cw = args.ldpc_codewords
+    t0 = time.time()
+    cw = SL.make_codewords(base, z, n_cw, seed=62)
+    llr_h = SL.bpsk_awgn_llrs(cw, args.ldpc_snr, seed=63)
+    gen_s = time.time() - t0
+    code = rx.LdpcCode(base, z)
+    llr = torch.from_numpy(llr_h).cuda()
+    N = code.n
+    post = torch.empty((n_cw, N), dtype=torch.float32, device="cuda")
+    bits = torch.empty((n_cw, N), dtype=torch.uint8, device="cuda")
+    its = torch.empty((n_cw,), dtype=torch.int32, device="cuda")
+    ws = torch.empty((code.workspace_bytes(n_cw),), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        rx.ldpc_decode(code, llr, args.ldpc_iters, 0.75, post, bits, its, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.form_steps):
+        rx.ldpc_decode(code, llr, args.ldpc_iters, 0.75, post, bits, its, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.form_steps
+    it_h = its.cpu().numpy()
+    bits_h = bits.cpu().numpy()
+    n_edges = int(np.sum(base >= 0))
+    # LDS traffic of one iteration: every edge's posterior read and written by
+    # the layer updates, and read once more by the syndrome test
+    lds_iter = n_edges * z * 12
+    mean_it = float(np.mean(it_h))
+    lds_bytes = lds_iter * float(np.sum(it_h)) + n_edges * z * 4 * n_cw      # + the initial syndrome test
+    hbm = n_cw * N * 9                                                      # LLRs in, posteriors and bits out
+    msg = n_cw * mb * z * 12 * 2 * float(np.mean(np.maximum(it_h - 1, 0)))   # compressed messages read + written
+    keep = [0, n_cw - 1]
+    SAMPLES["ldpc_46x68_z384"] = {"kind": "ldpc", "base": base, "z": z, "max_iter": args.ldpc_iters,
+                                  "alpha": 0.75, "llr": llr_h[keep], "post": post[keep].cpu().numpy(),
+                                  "bits": bits_h[keep], "iters": it_h[keep], "index": keep}
+    out = {"value": n_cw * kb * z / (ms * 1e-3) / 1e9, "unit": "Gbit/s (information bits decoded)",
+           "ms_per_step": round(ms, 4), "codewords": n_cw, "codewords_per_s": n_cw / (ms * 1e-3),
+           "mean_iterations": round(mean_it, 3), "max_iterations": int(it_h.max()),
+           "codewords_in_error": int(np.sum(np.any(bits_h != cw, axis=1))),
+           "raw_bit_errors": int(np.sum((llr_h < 0) != cw)),
+           "roofline": {"bound": "lds", "achieved": round(lds_bytes / (ms * 1e-3) / 1e9, 1),
+                        "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": round(lds_bytes / (ms * 1e-3) / 1e9 / LDS_PEAK_GBS, 4),
+                        "lds_bytes_per_step": lds_bytes},
+           "hbm": {"algorithmic_bytes": hbm, "GBps": round(hbm / (ms * 1e-3) / 1e9, 1),
+                   "message_bytes": msg, "message_GBps": round(msg / (ms * 1e-3) / 1e9, 1)},
+           "gen_seconds": round(gen_s, 1),
+           "workload": "%d codewords of a 46 x 68 quasi-cyclic LDPC code, lifting size 384 (N = 26112, "
+                       "K = 8448, random shifts, staircase parity), BPSK over AWGN at %.1f dB, layered "
+                       "normalised min-sum (alpha 0.75), at most %d iterations, early stop on a zero "
+                       "syndrome, FP32" % (n_cw, args.ldpc_snr, args.ldpc_iters)}
+    del llr, post, bits, its, ws, code
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -859,7 +942,10 @@ def main():
     ap.add_argument("--mixed-frames", type=int, default=100)
     ap.add_argument("--batch-frames", type=int, default=256)
     ap.add_argument("--bwd-frames", type=int, default=100)
-    ap.add_argument("--forms", default="staged,mmse,sc16,streaming,downlink,mixed,batched,fwd_bwd,sensing",
+    ap.add_argument("--ldpc-codewords", type=int, default=1024)
+    ap.add_argument("--ldpc-snr", type=float, default=2.5)
+    ap.add_argument("--ldpc-iters", type=int, default=10)
+    ap.add_argument("--forms", default="staged,mmse,sc16,streaming,downlink,mixed,batched,fwd_bwd,ldpc,sensing",
                     help="comma list of extra forms to time ('' for the headline only)")
     ap.add_argument("--sense-plots", type=int, default=64)
     ap.add_argument("--sense-latency-calls", type=int, default=200)
@@ -1005,6 +1091,9 @@ def main():
     if "fwd_bwd" in forms:
         out["forms"]["fwd_bwd_fp32"] = run_fwd_bwd(rx, torch, args)
         print("[bench] fwd+bwd done", file=sys.stderr, flush=True)
+    if "ldpc" in forms:
+        out["forms"]["ldpc_decode_fp32"] = run_ldpc(rx, torch, args)
+        print("[bench] ldpc done", file=sys.stderr, flush=True)
     if "sensing" in forms:
         out["forms"]["sensing_fp32"] = run_sensing(rx, torch, args)
         print("[bench] sensing done", file=sys.stderr, flush=True)

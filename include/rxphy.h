@@ -569,6 +569,51 @@ rxphy_status rxphy_box_metrics(const int32_t* gt, int32_t n_gt, const int32_t* d
 
 /* Human-readable name of a status, and thread-local detail of the last
  * non-OK status returned on the calling thread (empty string if none). */
+/* ---------------------------------------------------------------------------
+ * Channel decoding (the preamble's `dec` stage, with its LDPC notation:
+ * lifting size Z_c, code-block size K_cb, code rate R).  The paper defines
+ * no decoder; this is layered belief propagation with the normalised
+ * min-sum check rule over a quasi-cyclic code given by its base matrix.
+ *
+ * Code: base matrix B [mb][nb] (host, row-major int16): entry -1 is a
+ * z x z zero block, entry s in [0, z) the z x z identity with its columns
+ * cyclically shifted by s (row r has its one in column (r + s) mod z).
+ * Codeword length N = nb z; check i z + r involves bit c z + (r + B[i][c]) mod z
+ * of every block column c with B[i][c] >= 0.  Supported: 1 <= z <= 384,
+ * 1 <= mb <= 64, mb < nb, N <= 38400, every block row with 2 to 27 non-zero
+ * blocks.  rxphy_ldpc_code_create validates B (RXPHY_EINVAL /
+ * RXPHY_EUNSUPPORTED before any HIP call) and uploads its edge table (a
+ * small device allocation owned by the code, freed by destroy); B is copied.
+ *
+ * Decoding (rxphy_ldpc_decode), per codeword independently: L starts at the
+ * channel LLRs (ln P(0) / P(1)), every check-to-bit message R at 0; one
+ * iteration visits the block rows in order 0 .. mb-1 (one layer each, its z
+ * checks in parallel) and for each check and each of its bits v (block
+ * columns in increasing order) sets Q = L_v - R,
+ *   R_new = alpha * (product of the signs of the check's other Q)
+ *                 * (smallest |Q| among the check's other bits)   (sgn 0 = +1),
+ *   L_v = Q + R_new,
+ * every operation rounded once in FP32.  The syndrome of the hard decisions
+ * (bit 1 iff L < 0) is tested before the first iteration and after each one,
+ * and decoding stops at the first zero syndrome or after max_iter iterations.
+ * Inputs must be finite (a non-finite LLR propagates).
+ *   llr   : f32 [n_cw][N] (device)      post  : f32 [n_cw][N] posterior LLRs (written)
+ *   bits  : u8 [n_cw][N] hard decisions (written; may be NULL)
+ *   iters : i32 [n_cw] iterations run, 0 if the channel word was a codeword
+ *           (written; may be NULL)
+ *   ws    : rxphy_ldpc_workspace_bytes(code, n_cw) bytes, 4-byte aligned:
+ *           the compressed messages (two scaled minima and one word of signs
+ *           and argmin per check), written and read within the call
+ * max_iter >= 0; alpha finite and > 0 (1 = plain min-sum).                  */
+typedef struct rxphy_ldpc_code rxphy_ldpc_code;   /* opaque */
+rxphy_status rxphy_ldpc_code_create(const int16_t* base, int32_t mb, int32_t nb, int32_t z,
+                                    rxphy_ldpc_code** code);
+void rxphy_ldpc_code_destroy(rxphy_ldpc_code* code);
+size_t rxphy_ldpc_workspace_bytes(const rxphy_ldpc_code* code, int32_t n_cw);
+rxphy_status rxphy_ldpc_decode(const rxphy_ldpc_code* code, int32_t n_cw, const float* llr, int32_t max_iter,
+                               float alpha, float* post, uint8_t* bits, int32_t* iters, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
 const char* rxphy_status_string(rxphy_status status);
 const char* rxphy_last_error(void);
 

@@ -192,6 +192,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rxphy_clock_ns.restype = ctypes.c_int64
     lib.rxphy_plan_destroy.argtypes = [PL]
     lib.rxphy_plan_destroy.restype = None
+    LC = ctypes.c_void_p
+    lib.rxphy_ldpc_code_create.argtypes = [P, I32, I32, I32, ctypes.POINTER(LC)]
+    lib.rxphy_ldpc_code_create.restype = ctypes.c_int
+    lib.rxphy_ldpc_code_destroy.argtypes = [LC]
+    lib.rxphy_ldpc_code_destroy.restype = None
+    lib.rxphy_ldpc_workspace_bytes.argtypes = [LC, I32]
+    lib.rxphy_ldpc_workspace_bytes.restype = SZ
+    lib.rxphy_ldpc_decode.argtypes = [LC, I32, P, I32, F32, P, P, P, P, SZ, P]
+    lib.rxphy_ldpc_decode.restype = ctypes.c_int
     lib.rxphy_workspace_bytes.argtypes = [FR, I32, I32, I32]
     lib.rxphy_workspace_bytes.restype = SZ
     lib.rxphy_status_string.argtypes = [ctypes.c_int]
@@ -826,3 +835,53 @@ def box_metrics(gt, det, theta_iou: float, want_iou: bool = False) -> dict:
     if want_iou:
         r["iou"] = iou
     return r
+
+
+# ------------------------------------------------------------------ LDPC decoding
+class LdpcCode:
+    """A quasi-cyclic LDPC code from its base matrix (int16 [mb][nb]: -1 = zero
+    block, s = identity cyclically shifted by s) and lifting size z; owns the
+    device edge table of rxphy_ldpc_code_create."""
+
+    def __init__(self, base, z: int):
+        lib = load()
+        b = np.ascontiguousarray(np.asarray(base, dtype=np.int16))
+        if b.ndim != 2:
+            raise RxphyError("base must be a 2-D matrix")
+        self.base = b
+        self.mb, self.nb = b.shape
+        self.z = int(z)
+        self.n = self.nb * self.z
+        h = ctypes.c_void_p()
+        _check(lib.rxphy_ldpc_code_create(b.ctypes.data, self.mb, self.nb, self.z, ctypes.byref(h)),
+               "rxphy_ldpc_code_create")
+        self._h = h
+
+    def workspace_bytes(self, n_cw: int) -> int:
+        return int(load().rxphy_ldpc_workspace_bytes(self._h, int(n_cw)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rxphy_ldpc_code_destroy(h)
+            self._h = None
+
+
+def ldpc_decode(code: LdpcCode, llr, max_iter: int = 10, alpha: float = 0.75, post=None, bits=None,
+                iters=None, ws=None):
+    """llr f32 [n_cw][N] -> (posterior LLRs f32 [n_cw][N], hard bits u8
+    [n_cw][N], iterations i32 [n_cw])."""
+    n_cw = _nf(llr)
+    _need(llr, "llr", (n_cw, code.n), torch.float32)
+    post = _empty((n_cw, code.n), torch.float32, llr) if post is None else post
+    bits = _empty((n_cw, code.n), torch.uint8, llr) if bits is None else bits
+    iters = _empty((n_cw,), torch.int32, llr) if iters is None else iters
+    _need(post, "post", (n_cw, code.n), torch.float32)
+    _need(bits, "bits", (n_cw, code.n), torch.uint8)
+    _need(iters, "iters", (n_cw,), torch.int32)
+    need = code.workspace_bytes(n_cw)
+    if ws is None:
+        ws = _empty((max(need, 4),), torch.uint8, llr)
+    _check(load().rxphy_ldpc_decode(code._h, n_cw, _ptr(llr), int(max_iter), float(alpha), _ptr(post), _ptr(bits),
+                                    _ptr(iters), _ptr(ws), ws.numel(), _stream()), "rxphy_ldpc_decode")
+    return post, bits, iters

@@ -9,7 +9,7 @@ PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "librxphy.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["api.hip", "fft.hip", "csi.hip", "detect.hip", "detect_group.hip", "demod.hip", "backward.hip", "batch.hip",
-           "stream.hip", "sense.hip", "precode.hip"]
+           "stream.hip", "sense.hip", "precode.hip", "ldpc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -142,6 +142,40 @@ def test_noalloc_call_rejects_work_beyond_its_scratch(lib):
     assert f(ctypes.byref(fr), 0, None, None, None, None, None, None, 0, 1e3, None) == 0
 
 
+def test_ldpc_code_checks(lib):
+    """rxphy_ldpc_code_create rejects bad base matrices before any HIP call;
+    rxphy_ldpc_decode rejects bad arguments before any launch."""
+    import numpy as np
+    f = lib.rxphy_ldpc_code_create
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+    f.restype = ctypes.c_int
+    h = ctypes.c_void_p()
+
+    def create(b, z):
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.int16))
+        return f(b.ctypes.data, b.shape[0], b.shape[1], z, ctypes.byref(h))
+    ok = np.array([[0, 1, 0, -1], [2, -1, 0, 0]])
+    assert create(ok, 0) == 1                                   # z < 1
+    assert create(ok, 385) == 2                                 # z > 384
+    assert create(np.array([[0, 5, 0, -1], [2, -1, 0, 0]]), 4) == 1    # shift >= z
+    assert create(np.array([[0, -2, 0, -1], [2, -1, 0, 0]]), 4) == 1   # entry < -1
+    assert create(np.array([[0, -1, -1, -1], [2, -1, 0, 0]]), 4) == 1  # a degree-1 row
+    assert create(np.zeros((2, 28), np.int16), 4) == 2          # degree 28 > 27
+    assert create(np.zeros((3, 3), np.int16), 4) == 1           # mb >= nb
+    assert create(np.zeros((2, 101), np.int16) - 1 + np.eye(2, 101, dtype=np.int16) * 1 +
+                  np.eye(2, 101, 1, dtype=np.int16), 384) == 2  # N = 38784 > 38400
+    assert f(None, 2, 4, 4, ctypes.byref(h)) == 1
+    d = lib.rxphy_ldpc_decode
+    d.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_float] + \
+        [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]
+    d.restype = ctypes.c_int
+    p = ctypes.c_void_p(256)
+    assert d(None, 1, p, 5, 0.75, p, p, p, p, 1 << 20, None) == 1
+    lib.rxphy_ldpc_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.rxphy_ldpc_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.rxphy_ldpc_workspace_bytes(None, 4) == 0
+
+
 def test_status_strings(lib):
     lib.rxphy_status_string.restype = ctypes.c_char_p
     assert lib.rxphy_status_string(0) == b"RXPHY_OK"
