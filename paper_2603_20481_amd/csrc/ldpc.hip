@@ -33,7 +33,7 @@ namespace {
 
 constexpr int LDPC_ZMAX = 384;
 constexpr int LDPC_DMAX = 27;          // message signs in bits 0..26, argmin in bits 27..31
-constexpr int LDPC_NMAX = 38400;       // posterior LLRs held in LDS (150 KB)
+constexpr int LDPC_NMAX = 38400;       // posterior LLRs held in LDS (150 KB; the edge table takes 7 KB more)
 constexpr int LDPC_MBMAX = 64;
 
 // Bit of check row r for the block (column c, shift s): c z + (r + s) mod z.
@@ -43,39 +43,159 @@ __device__ __forceinline__ int bit_of(uint32_t e, int r, int z) {
   return c * z + (t < z ? t : t - z);
 }
 
-// Syndrome test: does any check (all layers) see an odd number of hard ones?
-__device__ bool any_check_unsatisfied(const float* L, const uint32_t* tab, int mb, int z, int* flag) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *flag = 0;
-  __syncthreads();
-  int bad = 0;
-  if (tid < z) {
-    for (int i = 0; i < mb; ++i) {
-      const int o0 = (int)tab[i], o1 = (int)tab[i + 1];
-      int par = 0;
-      for (int k = o0; k < o1; ++k) par ^= L[bit_of(tab[mb + 1 + k], tid, z)] < 0.f ? 1 : 0;
-      bad |= par;
-    }
-  }
-  if (bad) *flag = 1;
-  __syncthreads();
-  const bool any = *flag != 0;
-  __syncthreads();
-  return any;
+constexpr int LDPC_CH = 8;             // edges per chunk of table and posterior reads
+constexpr int LDPC_PF = 4;             // layers of compressed messages in flight
+constexpr int LDPC_DPAD = (LDPC_DMAX + LDPC_CH - 1) / LDPC_CH * LDPC_CH;
+// layer offsets, edges, and padding for the widest chunk (zero entries: column 0, shift 0)
+constexpr int LDPC_TABMAX = LDPC_MBMAX + 1 + LDPC_MBMAX * LDPC_DMAX + 4 * LDPC_CH;
+
+// S lanes (adjacent, within one quad) share a check row: lane part h takes
+// the row's edges k = h, h + S, h + 2S, ...; the parts' partial results are
+// combined through DPP quad permutes.  More waves per codeword hide the
+// latency of the per-edge dependency chains, at no cost in LDS.
+template <int OFF>
+__device__ __forceinline__ uint32_t quad_xor_u(uint32_t v) {
+  // quad_perm [1,0,3,2] for OFF = 1, [2,3,0,1] for OFF = 2
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, OFF == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int OFF>
+__device__ __forceinline__ float quad_xor_f(float v) {
+  return __uint_as_float(quad_xor_u<OFF>(__float_as_uint(v)));
 }
 
-template <int NMAX>
-__global__ void __launch_bounds__(LDPC_ZMAX)
+// Syndrome test on the posteriors in LDS: does any check (all layers) see an
+// odd number of hard ones?  T is the edge table in LDS.
+template <int S>
+__device__ __forceinline__ bool any_check_unsatisfied(const float* L, const uint32_t* T, int mb, int z) {
+  const int tid = threadIdx.x, r = tid / S, h = tid % S;
+  const bool row = r < z;
+  int bad = 0;
+  for (int i = 0; i < mb; ++i) {
+    const int e0 = __builtin_amdgcn_readfirstlane((int)T[i]);
+    const int d = __builtin_amdgcn_readfirstlane((int)T[i + 1]) - e0;
+    const uint32_t* E = T + mb + 1 + e0;
+    uint32_t par = 0;
+    if (row) {
+#pragma unroll
+      for (int c = 0; c < LDPC_DPAD / (LDPC_CH * S); ++c) {
+        if (c * LDPC_CH * S < d) {
+          float lv[LDPC_CH];
+#pragma unroll
+          for (int t = 0; t < LDPC_CH; ++t) lv[t] = L[bit_of(E[(c * LDPC_CH + t) * S + h], r, z)];
+#pragma unroll
+          for (int t = 0; t < LDPC_CH; ++t) par ^= ((c * LDPC_CH + t) * S + h < d && lv[t] < 0.f) ? 1u : 0u;
+        }
+      }
+    }
+    par ^= quad_xor_u<1>(par);
+    if constexpr (S == 4) par ^= quad_xor_u<2>(par);
+    bad |= (int)par;
+  }
+  return __syncthreads_or(row ? bad : 0) != 0;
+}
+
+// The two smallest magnitudes of the union of this part's and the partner's,
+// the first argmin, the parity of the negative signs.
+template <int OFF>
+__device__ __forceinline__ void combine_parts(float& m1, float& m2, int& idx, uint32_t& neg) {
+  const float p1 = quad_xor_f<OFF>(m1), p2 = quad_xor_f<OFF>(m2);
+  const int pidx = (int)quad_xor_u<OFF>((uint32_t)idx);
+  const uint32_t pneg = quad_xor_u<OFF>(neg);
+  const float n2 = fminf(fmaxf(m1, p1), fminf(m2, p2));
+  if (p1 < m1 || (p1 == m1 && pidx < idx)) idx = pidx;
+  m1 = fminf(m1, p1);
+  m2 = n2;
+  neg ^= pneg;
+}
+
+// One layer (block row i) for check row r (lane part h): the old messages of
+// its check come in compressed (o1, o2, om); the lane's edges are read in
+// chunks of LDPC_CH, each chunk's table entries and posteriors requested
+// together; slots past the layer's degree read padding or the next layer's
+// entries (valid addresses) and take Q = +inf, which changes no minimum and
+// no sign.  Writes the new posteriors to L and (part 0) the new compressed
+// messages.
+template <int S>
+__device__ __forceinline__ void layer_update(float* L, const uint32_t* T, float* A1, float* A2, uint32_t* MT,
+                                             int mb, int z, int i, int r, int h, bool row, float o1, float o2,
+                                             uint32_t om, float alpha) {
+  constexpr int J = LDPC_DPAD / S;               // edge slots per lane
+  const int e0 = __builtin_amdgcn_readfirstlane((int)T[i]);
+  const int d = __builtin_amdgcn_readfirstlane((int)T[i + 1]) - e0;
+  const uint32_t* E = T + mb + 1 + e0;
+  const int oidx = (int)(om >> 27);
+  float q[J];
+  int vv[J];
+  float m1 = INFINITY, m2 = INFINITY;
+  int idx = 0;
+  uint32_t neg = 0u;
+  if (row) {
+#pragma unroll
+    for (int c = 0; c < J / LDPC_CH; ++c) {
+      if (c * LDPC_CH * S < d) {
+        float lv[LDPC_CH];
+#pragma unroll
+        for (int t = 0; t < LDPC_CH; ++t) {
+          const int j = c * LDPC_CH + t;
+          vv[j] = bit_of(E[j * S + h], r, z);
+          lv[t] = L[vv[j]];
+        }
+#pragma unroll
+        for (int t = 0; t < LDPC_CH; ++t) {
+          const int j = c * LDPC_CH + t, k = j * S + h;
+          const float mag = k == oidx ? o2 : o1;
+          const float r_old = ((om >> k) & 1u) ? -mag : mag;
+          const float qk = k < d ? lv[t] - r_old : INFINITY;
+          q[j] = qk;
+          const float a = __builtin_fabsf(qk);
+          if (a < m1) { m2 = m1; m1 = a; idx = k; }
+          else if (a < m2) { m2 = a; }
+          neg ^= qk < 0.f ? 1u : 0u;
+        }
+      }
+    }
+  }
+  // combine the parts: the two smallest of the union, the first argmin, the parity of the signs
+  combine_parts<1>(m1, m2, idx, neg);
+  if constexpr (S == 4) combine_parts<2>(m1, m2, idx, neg);
+  if (!row) return;
+  const float a1 = alpha * m1;
+  const float a2 = alpha * m2;
+  uint32_t sg = 0u;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int k = j * S + h;
+    if (j * S < d && k < d) {
+      const uint32_t sk = neg ^ (q[j] < 0.f ? 1u : 0u);
+      const float mag = k == idx ? a2 : a1;
+      L[vv[j]] = q[j] + (sk ? -mag : mag);
+      sg |= sk << k;
+    }
+  }
+  sg |= quad_xor_u<1>(sg);
+  if constexpr (S == 4) sg |= quad_xor_u<2>(sg);
+  if (h == 0) {
+    const int64_t x = (int64_t)i * z + r;
+    A1[x] = a1;
+    A2[x] = a2;
+    MT[x] = sg | ((uint32_t)idx << 27);
+  }
+}
+
+template <int NMAX, int S>
+__global__ void __launch_bounds__(S == 2 ? 2 * LDPC_ZMAX : 1024)
 ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, const float* __restrict__ llr,
                    int max_iter, float alpha, float* __restrict__ post, uint8_t* __restrict__ bits,
                    int32_t* __restrict__ iters, float* __restrict__ msg) {
   __shared__ float L[NMAX];
-  __shared__ int flag;
+  __shared__ uint32_t T[LDPC_TABMAX];
   const int N = nb * z;
   const int64_t cw = blockIdx.x;
   const int tid = threadIdx.x;
   const float* in = llr + cw * N;
   for (int v = tid; v < N; v += blockDim.x) L[v] = in[v];
+  const int tlen = mb + 1 + (int)tab[mb];
+  for (int t = tid; t < tlen + LDPC_CH * S; t += blockDim.x) T[t] = t < tlen ? tab[t] : 0u;
   // compressed messages of this codeword: a1 [mb][z], a2 [mb][z], meta [mb][z]
   float* A1 = msg + cw * 3 * (int64_t)mb * z;
   float* A2 = A1 + (int64_t)mb * z;
@@ -83,66 +203,42 @@ ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, cons
   __syncthreads();
 
   int it = 0;
-  bool more = any_check_unsatisfied(L, tab, mb, z, &flag);
-  const bool row = tid < z;
+  bool more = any_check_unsatisfied<S>(L, T, mb, z);
+  const int r = tid / S, h = tid % S;
+  const bool row = r < z;
+  const int trow = row ? r : z - 1;            // message address of this lane (in range)
   while (more && it < max_iter) {
     ++it;
     const bool first = it == 1;
-    // this thread's compressed messages of layer 0 (zero messages in the first iteration)
-    float n1 = 0.f, n2 = 0.f;
-    uint32_t nm = 0u;
-    if (row && !first) { n1 = A1[tid]; n2 = A2[tid]; nm = MT[tid]; }
-    for (int i = 0; i < mb; ++i) {
-      const float o1 = n1, o2 = n2;
-      const uint32_t om = nm;
-      if (row && !first && i + 1 < mb) {       // the next layer's, in flight during this one
-        const int64_t x = (int64_t)(i + 1) * z + tid;
-        n1 = A1[x]; n2 = A2[x]; nm = MT[x];
-      }
-      const int e0 = (int)tab[i], d = (int)tab[i + 1] - e0;
-      if (row) {
-        const uint32_t* E = tab + mb + 1 + e0;
-        const int oidx = (int)(om >> 27);
-        float q[LDPC_DMAX];
-        float m1 = INFINITY, m2 = INFINITY;
-        int idx = 0;
-        uint32_t neg = 0u;
+    // the compressed messages of the next LDPC_PF layers in flight, one
+    // register slot per layer (zero messages in the first iteration); the
+    // layer loop is unrolled by LDPC_PF so that every slot is a fixed
+    // register and each load is waited for only when its layer starts (the
+    // loads are unconditional, at clamped addresses, and their values are
+    // discarded at the use when not wanted: a load under a branch would be
+    // waited for at the branch's end)
+    float s1[LDPC_PF], s2[LDPC_PF];
+    uint32_t sm[LDPC_PF];
 #pragma unroll
-        for (int k = 0; k < LDPC_DMAX; ++k) {
-          if (k < d) {
-            const int v = bit_of(E[k], tid, z);
-            float r_old = k == oidx ? o2 : o1;
-            if ((om >> k) & 1u) r_old = -r_old;
-            const float qk = L[v] - r_old;
-            q[k] = qk;
-            const float a = __builtin_fabsf(qk);
-            if (a < m1) { m2 = m1; m1 = a; idx = k; }
-            else if (a < m2) { m2 = a; }
-            neg ^= qk < 0.f ? 1u : 0u;
-          }
-        }
-        const float a1 = alpha * m1;
-        const float a2 = alpha * m2;
-        uint32_t sg = 0u;
-#pragma unroll
-        for (int k = 0; k < LDPC_DMAX; ++k) {
-          if (k < d) {
-            const int v = bit_of(E[k], tid, z);
-            const uint32_t sk = neg ^ (q[k] < 0.f ? 1u : 0u);
-            float rk = k == idx ? a2 : a1;
-            if (sk) rk = -rk;
-            L[v] = q[k] + rk;
-            sg |= sk << k;
-          }
-        }
-        const int64_t x = (int64_t)i * z + tid;
-        A1[x] = a1;
-        A2[x] = a2;
-        MT[x] = sg | ((uint32_t)idx << 27);
-      }
-      __syncthreads();                          // the next layer reads this one's L
+    for (int u = 0; u < LDPC_PF; ++u) {
+      const int64_t x = (int64_t)min(u, mb - 1) * z + trow;
+      s1[u] = A1[x]; s2[u] = A2[x]; sm[u] = MT[x];
     }
-    more = any_check_unsatisfied(L, tab, mb, z, &flag);
+    for (int i0 = 0; i0 < mb; i0 += LDPC_PF) {
+#pragma unroll
+      for (int u = 0; u < LDPC_PF; ++u) {
+        const int i = i0 + u;
+        const float o1 = first ? 0.f : s1[u], o2 = first ? 0.f : s2[u];
+        const uint32_t om = first ? 0u : sm[u];
+        const int64_t x = (int64_t)min(i + LDPC_PF, mb - 1) * z + trow;   // layer i + LDPC_PF
+        s1[u] = A1[x]; s2[u] = A2[x]; sm[u] = MT[x];
+        if (i < mb) {
+          layer_update<S>(L, T, A1, A2, MT, mb, z, i, r, h, row, o1, o2, om, alpha);
+          __syncthreads();                       // the next layer reads this one's L
+        }
+      }
+    }
+    more = any_check_unsatisfied<S>(L, T, mb, z);
   }
   float* out = post + cw * N;
   uint8_t* hb = bits ? bits + cw * N : nullptr;
@@ -157,9 +253,16 @@ ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, cons
 template <int NMAX>
 void launch_ldpc(const rxphy_ldpc_code& c, int32_t n_cw, const float* llr, int max_iter, float alpha,
                  float* post, uint8_t* bits, int32_t* iters, float* msg, hipStream_t s) {
-  const int threads = (c.z + 63) / 64 * 64;
-  hipLaunchKernelGGL(ldpc_decode_kernel<NMAX>, dim3((unsigned)n_cw), dim3(threads), 0, s, c.d_tab, c.mb, c.nb, c.z,
-                     llr, max_iter, alpha, post, bits, iters, msg);
+  // two lanes per check row above z = 256, four up to it (at most 1024 threads)
+  if (c.z > 256) {
+    const int threads = (2 * c.z + 63) / 64 * 64;
+    hipLaunchKernelGGL((ldpc_decode_kernel<NMAX, 2>), dim3((unsigned)n_cw), dim3(threads), 0, s, c.d_tab, c.mb,
+                       c.nb, c.z, llr, max_iter, alpha, post, bits, iters, msg);
+  } else {
+    const int threads = (4 * c.z + 63) / 64 * 64;
+    hipLaunchKernelGGL((ldpc_decode_kernel<NMAX, 4>), dim3((unsigned)n_cw), dim3(threads), 0, s, c.d_tab, c.mb,
+                       c.nb, c.z, llr, max_iter, alpha, post, bits, iters, msg);
+  }
 }
 
 }  // namespace
