@@ -690,20 +690,28 @@ def run_batched(rx, torch, args):
     t0 = time.time()
     inputs = synth.draw_inputs(4, range(len(shapes)), shapes, args.workers)
     gen_s = time.time() - t0
-    tuner = Tuner(args.tile_cache)
+    tuner = Tuner(args.tile_cache, fuse=True)
     tinfo = tuner.tune(frames)
     tuner.save()
     res = {}
     dets = sum(s.detections for s in shapes)
-    byts = sum(stage_bytes(s)[k] for s in shapes for k in MODES["staged"])   # the four stages the plan runs
-    bufs = None
-    for label, tiles in (("tuned", tuner.tiles_for(frames)), ("default", None)):
-        plan = rx.Plan(frames, tiles=tiles)
-        if bufs is None:
-            bufs = plan.alloc()
-            for f, (x, p) in enumerate(inputs):
-                plan.view(bufs, "x", f).copy_(torch.from_numpy(x))
-                plan.view(bufs, "pilots", f).copy_(torch.from_numpy(p))
+    # algorithmic bytes of each dataflow: the four stages (H stored and read
+    # back), or the FFT, the detector forming the estimate itself, the demod
+    byts_staged = sum(stage_bytes(s)[k] for s in shapes for k in MODES["staged"])
+    byts_fused = sum(stage_bytes(s)[k] for s in shapes for k in MODES["csi_detect"])
+    bufs = rx.Plan(frames).alloc()
+    lay = rx.Plan(frames)
+    for f, (x, p) in enumerate(inputs):
+        lay.view(bufs, "x", f).copy_(torch.from_numpy(x))
+        lay.view(bufs, "pilots", f).copy_(torch.from_numpy(p))
+    del lay
+    pick = tuner.tune_plan(frames, bufs)
+    variants = (("tuned", dict(tiles=tuner.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"])),
+                ("default", dict()),
+                ("fused_default_tiles", dict(fuse_csi=True)))
+    for label, kw in variants:
+        plan = rx.Plan(frames, **kw)
+        byts = byts_fused if plan.fuse_csi else byts_staged
         plan.graph(bufs)
         for _ in range(args.warmup):
             plan.replay()
@@ -720,6 +728,9 @@ def run_batched(rx, torch, args):
         status = plan.device_status()
         res[label] = {"value": dets / (ms * 1e-3), "ms_per_step": round(ms, 4),
                       "wall_ms_per_step": round(wall, 4), "items": plan.counts, "grid": plan.grid,
+                      "dataflow": "csi fused into the detector (H never stored)" if plan.fuse_csi
+                      else "four stages (H stored and read back)",
+                      "algorithmic_bytes": byts,
                       "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "device_status": status}
         del plan
@@ -737,9 +748,10 @@ def run_batched(rx, torch, args):
     # each stage alone over the same buffers (a plan with one stage in its mask)
     tiles = tuner.tiles_for(frames)
     stage_ms = {}
-    for name, bit in (("fft", rx.STAGE_FFT), ("csi", rx.STAGE_CSI), ("detect", rx.STAGE_DETECT),
-                      ("demod", rx.STAGE_DEMOD)):
-        ps = rx.Plan(frames, tiles=tiles, stages=bit)
+    for name, bit, fu in (("fft", rx.STAGE_FFT, False), ("csi", rx.STAGE_CSI, False),
+                          ("detect", rx.STAGE_DETECT, False), ("csi_detect", rx.STAGE_DETECT, True),
+                          ("demod", rx.STAGE_DEMOD, False)):
+        ps = rx.Plan(frames, tiles=tiles, stages=bit, fuse_csi=fu)
         ps.forward(bufs)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -777,8 +789,9 @@ def run_batched(rx, torch, args):
     res["per_frame_calls"] = {"value": dets / (ms * 1e-3), "ms_per_step": round(ms, 4),
                               "launches_per_step": 4 * len(frames)}
     out = dict(res["tuned"])
-    out.update({"frames": len(frames), "detections_per_step": dets, "algorithmic_bytes": byts,
-                "default_tiles": res["default"], "per_frame_calls": res["per_frame_calls"],
+    out.update({"frames": len(frames), "detections_per_step": dets,
+                "default": res["default"], "fused_default_tiles": res["fused_default_tiles"],
+                "plan_knobs": pick, "per_frame_calls": res["per_frame_calls"],
                 "stages_alone": stage_ms,
                 "autotune": tinfo, "gen_seconds": round(gen_s, 1),
                 "workload": "256 uneven frames: M in {8,16,32,64}, K in 1..min(16,M), "

@@ -371,6 +371,12 @@ typedef struct {
   int32_t grid;        /* workgroups of the persistent launch (0 = every resident slot)       */
   uint32_t spin_limit; /* polls of a stage counter (about 0.1 us apart) before a wait gives up
                           (0 = 2^22, about half a second)                                   */
+  int32_t fuse_csi;    /* 1: the CSI stage runs inside the detector items, which form the LS
+                          estimate from the pilot symbol of yf and the pilots (as
+                          rxphy_csi_detect does) and wait for the frame's FFT items; H is
+                          never written (buffers.h may be NULL) and the CSI stage has no
+                          items.  Every other output is bit-identical to the staged plan's.
+                          0: four stages, H written.                                       */
 } rxphy_plan_options;
 
 /* Byte offsets of one frame's tensors in the packed buffers (or, for the

@@ -11,9 +11,18 @@ stage sees, so the search is split by stage and by shape class:
 A class is timed on a plan of identical frames of that class that runs only
 the stage being tuned (the other stages' outputs are filled once beforehand),
 every candidate with HIP events on the current stream, and the fastest median
-wins.  Every candidate gives bit-identical results (the K padding is never
-changed), so tuning affects speed only.  Results live in a JSON cache keyed
-by device name.
+wins.  The detector class is tuned in the dataflow the tuner is built for
+(fuse=True: the detector items form the channel estimate themselves, and the
+CSI stage has no items).
+
+tune_plan then chooses the plan-wide knobs on the actual frames and buffers:
+the dataflow (CSI fused into the detector, or four stages with H stored) and
+the grid of the persistent launch (one, two or three workgroups per CU),
+timing each combination with the tuned item sizes.
+
+Every candidate gives bit-identical results for every output but H (the K
+padding is never changed), so tuning affects speed only.  Results live in a
+JSON cache keyed by device name.
 """
 from __future__ import annotations
 
@@ -30,20 +39,21 @@ STAGE_BIT = {"fft": STAGE_FFT, "csi": STAGE_CSI, "detect": STAGE_DETECT, "demod"
 KNOB = {"fft": "fft_iters", "csi": "csi_tiles", "detect": "det_tiles", "demod": "dem_groups"}
 CANDIDATES = {"fft": (1, 2, 4, 8, 16), "csi": (1, 2, 4, 8), "detect": (1, 2, 4),
               "demod": (1, 2, 4, 8, 16)}
-CACHE_VERSION = 2
+CACHE_VERSION = 3
 
 
 def kp_of(K: int) -> int:
     return 4 if K <= 4 else 8 if K <= 8 else 16
 
 
-def class_key(stage: str, fr: Frame) -> str:
+def class_key(stage: str, fr: Frame, fused: bool = False) -> str:
     if stage == "fft":
         return "fft:N=%d,M=%d" % (fr.n_fft, fr.M)
     if stage == "csi":
         return "csi:M=%d,KP=%d" % (fr.M, kp_of(fr.K))
     if stage == "detect":
-        return "detect:M=%d,KP=%d,%s" % (fr.M, kp_of(fr.K), "mmse" if fr.detector else "zf")
+        return "detect:M=%d,KP=%d,%s%s" % (fr.M, kp_of(fr.K), "mmse" if fr.detector else "zf",
+                                           ",fused" if fused else "")
     return "demod:Q=%d,KP=%d" % (fr.qam_bits, kp_of(fr.K))
 
 
@@ -52,8 +62,9 @@ def default_cache_path() -> str:
 
 
 class Tuner:
-    def __init__(self, cache_path: str | None = None):
+    def __init__(self, cache_path: str | None = None, fuse: bool = True):
         self.path = cache_path or default_cache_path()
+        self.fuse = bool(fuse)
         self.device = torch.cuda.get_device_name() if torch.cuda.is_available() else "none"
         self.entries: dict = {}
         try:
@@ -78,7 +89,7 @@ class Tuner:
         for fr in frames:
             kw = {}
             for st in STAGES:
-                e = self.entries.get(class_key(st, fr))
+                e = self.entries.get(class_key(st, fr, self.fuse))
                 if e is not None:
                     kw[KNOB[st]] = int(e["value"])
             out.append(Tiles(**kw))
@@ -101,7 +112,7 @@ class Tuner:
 
     def tune_class(self, stage: str, fr: Frame, copies: int = 16, reps: int = 5) -> dict:
         frames = [fr] * copies
-        full = Plan(frames)
+        full = Plan(frames)                               # staged: fills every intermediate
         bufs = full.alloc()
         g = torch.Generator(device="cuda")
         g.manual_seed(1234)
@@ -112,14 +123,15 @@ class Tuner:
         full.forward(bufs)                                # realistic intermediates
         torch.cuda.synchronize()
         res = {}
+        fuse = self.fuse and stage == "detect"
         for v in CANDIDATES[stage]:
-            p = Plan(frames, tiles=Tiles(**{KNOB[stage]: v}), stages=STAGE_BIT[stage])
+            p = Plan(frames, tiles=Tiles(**{KNOB[stage]: v}), stages=STAGE_BIT[stage], fuse_csi=fuse)
             res[v] = self._time(p, bufs, reps)
             del p
         best = min(res, key=lambda v: (res[v], v))
         entry = {"value": best, "us": round(res[best], 2),
                  "candidates_us": {str(k): round(t, 2) for k, t in res.items()}}
-        self.entries[class_key(stage, fr)] = entry
+        self.entries[class_key(stage, fr, fuse)] = entry
         return entry
 
     def tune(self, frames, force: bool = False, copies: int = 16, reps: int = 5) -> dict:
@@ -127,11 +139,31 @@ class Tuner:
         t0 = time.time()
         done = 0
         for st in STAGES:
+            if st == "csi" and self.fuse:
+                continue                                   # no CSI items in the fused dataflow
             seen = {}
             for fr in frames:
-                seen.setdefault(class_key(st, fr), fr)
+                seen.setdefault(class_key(st, fr, self.fuse), fr)
             for key, fr in seen.items():
                 if force or key not in self.entries:
                     self.tune_class(st, fr, copies, reps)
                     done += 1
         return {"classes_tuned": done, "seconds": round(time.time() - t0, 2)}
+
+    def tune_plan(self, frames, bufs, reps: int = 5) -> dict:
+        """Plan-wide knobs on the given frames and packed buffers (x and the
+        pilots filled; allocated by a staged plan, so that H has room): the
+        dataflow and the grid (1, 2 or 3 workgroups per CU), with the cached
+        item sizes.  Returns the winner and every candidate's median time (us)."""
+        tiles = self.tiles_for(frames)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        res = {}
+        for fuse in (True, False):
+            for per_cu in (1, 2, 3):
+                p = Plan(frames, tiles=tiles, grid=per_cu * cus, fuse_csi=fuse)
+                res[(fuse, per_cu)] = self._time(p, bufs, reps)
+                del p
+        best = min(res, key=lambda k: res[k])
+        return {"fuse_csi": best[0], "grid": best[1] * cus,
+                "candidates_us": {"%s,%d/CU" % ("fused" if k[0] else "staged", k[1]): round(v, 1)
+                                  for k, v in res.items()}}

@@ -85,10 +85,12 @@ __device__ __forceinline__ void run_csi(const BFrame& d, int tile, const float2*
   }
 }
 
-template <int KP>
+// FU: the CSI stage fused in (the channel is the LS estimate formed from the
+// pilot symbol of yf and the pilots, bit-identical to the CSI stage's value)
+template <int KP, bool FU>
 __device__ __forceinline__ void run_detect(const BFrame& d, int tile, const float2* h, const float2* yf,
-                                           float2* xt, float* nu, uint8_t* flags, float2* pool,
-                                           int* nonfin) {
+                                           const float2* pil, float2* xt, float* nu, uint8_t* flags,
+                                           float2* pool, int* nonfin) {
   const int nt = (d.n_sc + det::TS - 1) / det::TS;
   const int t0 = tile * d.det_tiles;
   const int t1 = min(t0 + d.det_tiles, nt);
@@ -96,10 +98,11 @@ __device__ __forceinline__ void run_detect(const BFrame& d, int tile, const floa
   bool have0 = false;
   for (int t = t0; t < t1; ++t) {
     if (t > t0) __syncthreads();
-    det::detect_tile<KP, det::P_FP32>(h + d.h, yf + d.yf, xt + d.xt, nu + d.nu,
-                                      flags ? flags + d.flags : nullptr, d.M, d.K, d.n_sym, d.n_sc,
-                                      d.n0, d.mmse, 0.f, nullptr, 0u, t * det::TS, pool, nonfin, hv, yv,
-                                      pv, have0, t + 1 < t1 ? (t + 1) * det::TS : -1);
+    det::detect_tile<KP, det::P_FP32, FU>(FU ? nullptr : h + d.h, yf + d.yf, xt + d.xt, nu + d.nu,
+                                          flags ? flags + d.flags : nullptr, d.M, d.K, d.n_sym, d.n_sc,
+                                          d.n0, d.mmse, 0.f, nullptr, 0u, t * det::TS, pool, nonfin, hv, yv,
+                                          pv, have0, t + 1 < t1 ? (t + 1) * det::TS : -1, nullptr, nullptr,
+                                          FU ? pil + d.pil : nullptr);
   }
 }
 
@@ -185,6 +188,10 @@ __device__ __forceinline__ void publish(Pending& pd, uint32_t* __restrict__ ctl)
   __syncthreads();
 }
 
+// FUSE: the plan forms the channel estimate inside the detector items (one
+// instantiation per dataflow, so that each carries only its own detector
+// bodies and their register needs).
+template <bool FUSE>
 __global__ void __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(3)))
 batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
   __shared__ float2 pool[POOL];
@@ -213,8 +220,11 @@ batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
     if (__builtin_amdgcn_readfirstlane(pd.n) > 0 && __builtin_amdgcn_readfirstlane(pd.stage) != stage)
       publish(pd, ctl);
     if (stage > 0) {
-      const uint32_t need = (uint32_t)d.need[stage - 1];
-      uint32_t* cnt = &ctl[CTL_DONE + 4 * f + stage - 1];
+      // the stage this item waits for: the previous one, or the FFT for a
+      // detector item that forms the channel estimate itself
+      const int dep = (stage == 2 && FUSE) ? 0 : stage - 1;
+      const uint32_t need = (uint32_t)d.need[dep];
+      uint32_t* cnt = &ctl[CTL_DONE + 4 * f + dep];
       if (threadIdx.x == 0)
         s_ready = need == 0 || __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
       __syncthreads();
@@ -255,13 +265,14 @@ batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
       case 2: {
         const float2* h = (const float2*)hp->h;
         const float2* yf = (const float2*)hp->yf;
+        const float2* pil = (const float2*)hp->pil;
         float2* xt = (float2*)hp->xt;
         float* nu = (float*)hp->nu;
         uint8_t* flags = (uint8_t*)hp->flags;
         switch (d.kp) {
-          case 4: run_detect<4>(d, tile, h, yf, xt, nu, flags, pool, nonfin); break;
-          case 8: run_detect<8>(d, tile, h, yf, xt, nu, flags, pool, nonfin); break;
-          default: run_detect<16>(d, tile, h, yf, xt, nu, flags, pool, nonfin); break;
+          case 4: run_detect<4, FUSE>(d, tile, h, yf, pil, xt, nu, flags, pool, nonfin); break;
+          case 8: run_detect<8, FUSE>(d, tile, h, yf, pil, xt, nu, flags, pool, nonfin); break;
+          default: run_detect<16, FUSE>(d, tile, h, yf, pil, xt, nu, flags, pool, nonfin); break;
         }
         break;
       }
@@ -316,6 +327,7 @@ struct rxphy_plan {
   uint32_t n_items = 0;
   int32_t grid = 0;
   uint32_t spin_limit = 0;
+  int fuse_csi = 0;
   int n_ctl = 0;
   BFrame* d_desc = nullptr;
   uint32_t* d_items = nullptr;
@@ -344,8 +356,8 @@ rxphy_status check_batch(const rxphy_plan* p, const rxphy_batch* b) {
   if (!b) return fail(RXPHY_EINVAL, "buffers is NULL");
   rxphy_status st;
   if ((st = check_ptr(b->x, "x")) || (st = check_ptr(b->pilots, "pilots")) ||
-      (st = check_ptr(b->yf, "yf")) || (st = check_ptr(b->h, "h")) || (st = check_ptr(b->xt, "xt")) ||
-      (st = check_ptr(b->nu, "nu")) || (st = check_ptr(b->llr, "llr")))
+      (st = check_ptr(b->yf, "yf")) || (!p->fuse_csi && (st = check_ptr(b->h, "h"))) ||
+      (st = check_ptr(b->xt, "xt")) || (st = check_ptr(b->nu, "nu")) || (st = check_ptr(b->llr, "llr")))
     return st;
   return RXPHY_OK;
 }
@@ -405,15 +417,18 @@ rxphy_status rxphy_plan_create(const rxphy_frame* frames, int32_t n_frames, cons
   *plan = nullptr;
   if (!frames) return fail(RXPHY_EINVAL, "frames is NULL");
   if (n_frames < 1 || n_frames > 16384) return fail(RXPHY_EINVAL, "n_frames = %d outside [1, 16384]", n_frames);
-  rxphy_plan_options opt{0, 0, 0u};
+  rxphy_plan_options opt{0, 0, 0u, 0};
   if (options) opt = *options;
-  const int stages = opt.stages == 0 ? RXPHY_STAGE_ALL : opt.stages;
+  int stages = opt.stages == 0 ? RXPHY_STAGE_ALL : opt.stages;
   if (stages & ~RXPHY_STAGE_ALL) return fail(RXPHY_EINVAL, "stages = %d", opt.stages);
+  if (opt.fuse_csi != 0 && opt.fuse_csi != 1) return fail(RXPHY_EINVAL, "fuse_csi = %d", opt.fuse_csi);
+  if (opt.fuse_csi) stages &= ~RXPHY_STAGE_CSI;        // the detector items form the estimate
   if (opt.grid < 0) return fail(RXPHY_EINVAL, "grid = %d < 0", opt.grid);
 
   rxphy_plan* p = new rxphy_plan();
   p->n_frames = n_frames;
   p->spin_limit = opt.spin_limit ? opt.spin_limit : (1u << 22);
+  p->fuse_csi = opt.fuse_csi;
   p->desc.resize(n_frames);
   p->offs.resize(n_frames);
   std::vector<uint32_t> items[4];
@@ -515,7 +530,8 @@ rxphy_status rxphy_plan_create(const rxphy_frame* frames, int32_t n_frames, cons
   int grid = opt.grid;
   if (e == hipSuccess && grid == 0) {
     int per_cu = 0, cus = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, WGS, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, p->fuse_csi ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>, WGS, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->dev);
     grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
@@ -555,7 +571,8 @@ rxphy_status rxphy_plan_forward(rxphy_plan* plan, const rxphy_batch* buffers, hi
                      a.n_ctl, a.x, a.pil, a.yf, a.h, a.xt, a.nu, a.flags, a.llr);
   if ((st = launch_status("plan reset kernel"))) return st;
   if (plan->n_items == 0) return RXPHY_OK;
-  hipLaunchKernelGGL(batch_kernel, dim3(plan->grid), dim3(WGS), 0, stream, a.hdr, a.ctl);
+  if (plan->fuse_csi) hipLaunchKernelGGL(batch_kernel<true>, dim3(plan->grid), dim3(WGS), 0, stream, a.hdr, a.ctl);
+  else hipLaunchKernelGGL(batch_kernel<false>, dim3(plan->grid), dim3(WGS), 0, stream, a.hdr, a.ctl);
   return launch_status("batch kernel");
 }
 
@@ -574,7 +591,7 @@ rxphy_status rxphy_plan_graph(rxphy_plan* plan, const rxphy_batch* buffers) {
   rp.kernelParams = a.reset_args();
   rp.extra = nullptr;
   hipKernelNodeParams bp{};
-  bp.func = (void*)batch_kernel;
+  bp.func = plan->fuse_csi ? (void*)batch_kernel<true> : (void*)batch_kernel<false>;
   bp.gridDim = dim3(plan->grid);
   bp.blockDim = dim3(WGS);
   bp.sharedMemBytes = 0;

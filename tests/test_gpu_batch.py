@@ -100,6 +100,54 @@ def test_batch_tile_sizes_do_not_change_results(rx, batch, refs, tiles):
     assert_frames_equal(plan, bufs, refs)
 
 
+def assert_fused_frames_equal(plan, bufs, refs, frames_idx=None):
+    """A plan that forms the channel estimate inside the detector items: every
+    output but H equals the single-frame (staged) calls bit for bit."""
+    for f in (frames_idx if frames_idx is not None else range(len(plan.frames))):
+        for k in ("yf", "xt", "nu", "flags", "llr"):
+            got, ref = plan.view(bufs, k, f), refs[f][k]
+            same = torch.equal(torch.view_as_real(got), torch.view_as_real(ref)) if got.is_complex() else \
+                torch.equal(got, ref)
+            assert same, "frame %d (%s) %s differs" % (f, plan.frames[f], k)
+
+
+@pytest.mark.parametrize("tiles", [None, dict(fft_iters=1, det_tiles=1, dem_groups=1),
+                                   dict(fft_iters=13, det_tiles=5, dem_groups=29)])
+def test_batch_fused_csi_equals_staged_and_single_frame_fused_calls(rx, batch, refs, tiles):
+    """fuse_csi: no CSI items, H never written (its buffer is a one-byte
+    placeholder), detector items wait for the FFT items of their frame; the
+    outputs equal the staged calls bit for bit, and, frame by frame, the fused
+    single-frame calls rxphy_csi_detect + rxphy_demod where those take the
+    same per-subcarrier path (fewer than 16 users; with 16 users the
+    single-frame fused call factors each pilot group once, whose x_tilde
+    differs in the last bits: there nu and flags are equal and, where the
+    channel is well-conditioned (M >= 2K), the LLRs within the stated
+    tolerance)."""
+    frames, inputs = batch
+    plan = rx.Plan(frames, tiles=rx.Tiles(**tiles) if tiles else None, fuse_csi=True)
+    say("fused", tiles, "items", plan.counts, "grid", plan.grid)
+    assert plan.counts[1] == 0
+    bufs = pack(rx, plan, inputs)
+    assert bufs["h"].numel() == 1
+    plan.forward(bufs)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    assert_fused_frames_equal(plan, bufs, refs)
+    if tiles is None:
+        for f, fr in enumerate(frames):
+            yf = plan.view(bufs, "yf", f)[None]
+            p = plan.view(bufs, "pilots", f)[None]
+            xt, nu, fl = rx.csi_detect(fr, yf, p)
+            llr = rx.demod(fr, xt, nu)
+            if fr.K < 16:
+                assert torch.equal(torch.view_as_real(xt[0]), torch.view_as_real(plan.view(bufs, "xt", f)))
+                assert torch.equal(llr[0], plan.view(bufs, "llr", f))
+            elif fr.M >= 2 * fr.K:                # well-conditioned; square ZF channels reach kappa ~ 1e5
+                lr = llr_rel(plan.view(bufs, "llr", f).cpu().numpy(), llr[0].cpu().numpy())
+                assert lr < 1e-3, (f, lr)
+            assert torch.equal(nu[0], plan.view(bufs, "nu", f)) and torch.equal(fl[0], plan.view(bufs, "flags", f))
+
+
 def test_batch_wider_k_padding_within_tolerance(rx, batch, refs):
     frames, inputs = batch
     plan = rx.Plan(frames, tiles=rx.Tiles(det_kp=16))
@@ -139,9 +187,10 @@ def test_batch_stage_masks_compose(rx, batch, refs):
     assert_frames_equal(p2, bufs, refs)
 
 
-def test_batch_graph_replays_match_eager(rx, batch, refs):
+@pytest.mark.parametrize("fuse", [False, True])
+def test_batch_graph_replays_match_eager(rx, batch, refs, fuse):
     frames, inputs = batch
-    plan = rx.Plan(frames)
+    plan = rx.Plan(frames, fuse_csi=fuse)
     bufs = pack(rx, plan, inputs)
     plan.graph(bufs)
     for rep in range(3):
@@ -150,9 +199,12 @@ def test_batch_graph_replays_match_eager(rx, batch, refs):
         torch.cuda.synchronize()
         plan.replay()
         torch.cuda.synchronize()
-        say("replay", rep, "status", plan.device_status())
+        say("replay", rep, "fused" if fuse else "staged", "status", plan.device_status())
         assert plan.device_status() == 0
-        assert_frames_equal(plan, bufs, refs)
+        if fuse:
+            assert_fused_frames_equal(plan, bufs, refs)
+        else:
+            assert_frames_equal(plan, bufs, refs)
         # the program's own eager work between replays
         single(rx, frames[0], *inputs[0])
         torch.cuda.synchronize()
@@ -179,12 +231,14 @@ def test_batch_matches_oracle(rx, batch):
         assert rel_rms(plan.view(bufs, "yf", f).cpu().numpy(), ref["yf"]) < 1e-5
 
 
-def test_batch_uneven_256_frames_full_size(rx):
+@pytest.mark.parametrize("fuse", [True, False])
+def test_batch_uneven_256_frames_full_size(rx, fuse):
     """The 256-frame uneven workload in the launch configuration the benchmark
-    times; sampled frames are compared with the single-frame path."""
+    times (the channel estimate formed inside the detector items), and the
+    staged dataflow; sampled frames are compared with the single-frame path."""
     shapes = synth.draw_batch_shapes(256)
     frames = [rx.Frame.of(s, O.MMSE, 1.0) for s in shapes]
-    plan = rx.Plan(frames)
+    plan = rx.Plan(frames, fuse_csi=fuse)
     say("256 frames, items", plan.counts, "grid", plan.grid,
         "x GB", round(plan.totals["x"] / 1e9, 3))
     bufs = plan.alloc()
@@ -206,6 +260,8 @@ def test_batch_uneven_256_frames_full_size(rx):
         p = plan.view(bufs, "pilots", f)[None].contiguous()
         ref = rx.forward(fr, x, p)
         for k in OUTS:
+            if fuse and k == "h":
+                continue
             a, b = plan.view(bufs, k, f), ref[k][0]
             if a.is_complex():
                 a, b = torch.view_as_real(a), torch.view_as_real(b)
@@ -222,9 +278,19 @@ def test_autotuned_tiles_keep_results_bitwise(rx, batch, refs, tmp_path):
     t.save()
     t2 = Tuner(str(tmp_path / "tiles.json"))
     assert t2.tune(frames)["classes_tuned"] == 0          # everything cached
-    plan = rx.Plan(frames, tiles=t2.tiles_for(frames))
+    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), fuse_csi=True)
     bufs = pack(rx, plan, inputs)
     plan.forward(bufs)
     torch.cuda.synchronize()
     assert plan.device_status() == 0
-    assert_frames_equal(plan, bufs, refs)
+    assert_fused_frames_equal(plan, bufs, refs)
+    # the plan-wide knobs: every candidate dataflow and grid gives the same outputs
+    bufs = pack(rx, rx.Plan(frames), inputs)              # with an H buffer: staged candidates run too
+    pick = t2.tune_plan(frames, bufs, reps=2)
+    say("plan knobs", pick)
+    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"])
+    bufs = pack(rx, plan, inputs)
+    plan.forward(bufs)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    assert_fused_frames_equal(plan, bufs, refs)
