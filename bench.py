@@ -276,6 +276,7 @@ class Chain:
         self.fl = torch.empty((F, shape.n_sc), dtype=torch.uint8, device=dev)
         self.llr = torch.empty((F, shape.K, D, shape.n_sc, shape.qam_bits), dtype=f32, device=dev)
         self.ws = None
+        self.thr = 1e3                     # condition-estimate threshold of the BF16 / FP16 forms
 
     def step(self, fr, prec="fp32", ev=None, mode="full"):
         rx = self.rx
@@ -288,15 +289,16 @@ class Chain:
         rx.fft(fr, self.x, self.yf)
         if ev: ev[1].record()
         if mode == "full":
-            rx.csi_detect_demod(fr, self.yf, self.p, prec, 1e3, llr=self.llr, nu=self.nu, flags=self.fl, ws=ws)
+            rx.csi_detect_demod(fr, self.yf, self.p, prec, self.thr, llr=self.llr, nu=self.nu, flags=self.fl,
+                                ws=ws)
             if ev: ev[2].record()
             return
         if mode == "csi_detect":
-            rx.csi_detect(fr, self.yf, self.p, prec, 1e3, self.xt, self.nu, self.fl, ws)
+            rx.csi_detect(fr, self.yf, self.p, prec, self.thr, self.xt, self.nu, self.fl, ws)
         else:
             rx.csi(fr, self.yf, self.p, self.h)
             if ev: ev[2].record()
-            rx.detect(fr, self.h, self.yf, prec, 1e3, self.xt, self.nu, self.fl, ws)
+            rx.detect(fr, self.h, self.yf, prec, self.thr, self.xt, self.nu, self.fl, ws)
         if ev: ev[len(MODES[mode]) - 1].record()
         rx.demod(fr, self.xt, self.nu, self.llr)
         if ev: ev[len(MODES[mode])].record()
@@ -1093,6 +1095,19 @@ def main():
                  "workload": "64x16 MIMO, N_FFT 4096, 3276 subcarriers, 64-QAM, Kronecker "
                              "(0.7, 0.3), 25 dB, ZF, %s products, FP64 refinement above "
                              "condition estimate 1e3" % prec})
+        # the FP64 refinement's cost: lower thresholds refine a growing share
+        # of the pilot groups (0 refines every subcarrier)
+        sweep = []
+        for thr in (300.0, 100.0, 0.0):
+            c3.thr = thr
+            ms, per = c3.time(fr3, "bf16", args.form_steps, 1, mode="full")
+            refined = int((c3.fl & rx.FLAG_REFINED).ne(0).sum().item())
+            sweep.append({"cond_threshold": thr, "ms_per_step": round(ms, 4),
+                          "csi_detect_demod_us": round(per["csi_detect_demod"] * 1e3, 2),
+                          "refined_fraction": round(refined / c3.fl.numel(), 6),
+                          "value": s3.detections * args.mixed_frames / (ms * 1e-3)})
+        c3.thr = 1e3
+        out["forms"]["kronecker_64x16_n4096_64qam_bf16"]["refinement_sweep"] = sweep
         SAMPLES["kronecker_64x16_n4096_64qam"] = {"kind": "forward", "inputs": [synth.make_frame(3, 0)],
                                                   "det": [rx.ZF], "outputs": [kept]}
         del c3

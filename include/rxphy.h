@@ -48,6 +48,8 @@ typedef enum {
 
 typedef enum { RXPHY_ZF = 0, RXPHY_MMSE = 1 } rxphy_detector;
 
+/* Calls take the precision as an int32_t holding one of these values; any
+ * other value is rejected with RXPHY_EINVAL (rxphy_workspace_bytes returns 0). */
 typedef enum { RXPHY_FP32 = 0, RXPHY_BF16 = 1, RXPHY_FP16 = 2 } rxphy_precision;
 
 /* per-subcarrier flags written by rxphy_detect */
@@ -132,7 +134,7 @@ rxphy_status rxphy_csi(const rxphy_frame* frame, int32_t n_frames,
  *           precision) bytes (NULL when that is 0)                            */
 rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames,
                           const void* h, const void* yf, void* xt, float* nu, uint8_t* flags,
-                          rxphy_precision precision, float cond_threshold,
+                          int32_t precision, float cond_threshold,
                           void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* csi and equal stages fused: rxphy_csi followed by rxphy_detect on the same
@@ -155,7 +157,7 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames,
  * stream has passed the call.                                               */
 rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
                               const void* yf, const void* pilots, void* xt, float* nu,
-                              uint8_t* flags, rxphy_precision precision, float cond_threshold,
+                              uint8_t* flags, int32_t precision, float cond_threshold,
                               void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* csi, equal and demod stages fused: rxphy_csi_detect followed by
@@ -174,7 +176,7 @@ rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames,
  * Other arguments as rxphy_csi_detect.                                        */
 rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames,
                                     const void* yf, const void* pilots, void* xt, float* nu,
-                                    uint8_t* flags, float* llr, rxphy_precision precision,
+                                    uint8_t* flags, float* llr, int32_t precision,
                                     float cond_threshold, void* ws, size_t ws_bytes,
                                     hipStream_t stream);
 
@@ -196,7 +198,7 @@ rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames,
 #define RXPHY_NOALLOC_SCRATCH_BYTES (32u << 20)
 rxphy_status rxphy_csi_detect_demod_noalloc(const rxphy_frame* frame, int32_t n_frames,
                                             const void* yf, const void* pilots, void* xt, float* nu,
-                                            uint8_t* flags, float* llr, rxphy_precision precision,
+                                            uint8_t* flags, float* llr, int32_t precision,
                                             float cond_threshold, hipStream_t stream);
 
 /* demod stage (`demod` macro): max-log LLRs over the Gray square-QAM set
@@ -324,14 +326,17 @@ enum {
 /* Workspace bytes needed by rxphy_detect (which = RXPHY_WS_DETECT),
  * rxphy_backward (RXPHY_WS_BACKWARD), rxphy_csi_detect (RXPHY_WS_CSI_DETECT),
  * rxphy_csi_detect_demod (RXPHY_WS_CSI_DETECT_DEMOD) or rxphy_precode
- * (RXPHY_WS_PRECODE); 0 if none or if the shape is invalid.                  */
+ * (RXPHY_WS_PRECODE); 0 if none, or if the shape or the precision is invalid.  */
 size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
-                             rxphy_precision precision);
+                             int32_t precision);
 
 /* ---------------------------------------------------------------------------
- * Batched uneven frames.  A plan holds frames of differing shape (each one a
- * valid rxphy_frame) and runs all four forward stages of all of them in ONE
- * persistent launch: a fixed grid of workgroups pulls work items (a group of
+ * Batched uneven frames.  The paper batches nothing across frames (its
+ * Section IV-D spreads one stream's FFT segments over threads); this is the
+ * batched form of the four stage calls above, defined frame by frame as
+ * their results, for frames of differing shape.  A plan holds such frames
+ * (each one a valid rxphy_frame) and runs all four forward stages of all of
+ * them in ONE persistent launch: a fixed grid of workgroups pulls work items (a group of
  * FFT segments, of CSI tiles, of detector subcarrier tiles or of demod
  * elements of one frame) from a device queue in stage-major order, and an
  * item of stage s of frame f starts once every item of stage s-1 of frame f
@@ -559,6 +564,16 @@ size_t rxphy_sense_workspace_bytes(const rxphy_sense_config* cfg, int32_t n_plot
 rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const void* x,
                          const rxphy_sense_outputs* out, int32_t* n_boxes, int32_t* boxes, int32_t max_boxes,
                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* The Savitzky-Golay smoothing weights rxphy_sense applies to the PSD
+ * (Section IV-B names the filter; window and order are the config's):
+ * weights[k + window/2], k = -window/2 .. window/2, is the value at 0 of the
+ * least-squares polynomial of degree `order` through unit samples at offset
+ * k, i.e. the smoothed value is sum_k weights[k + window/2] psd[i + k].
+ * Computed on the host in FP64 and rounded to FP32 (the same routine the
+ * pipeline uses).  window odd in 3 .. 63, 0 <= order <= 6, order < window;
+ * weights: `window` floats (host).  Host only; no GPU needed. */
+rxphy_status rxphy_savgol_weights(int32_t window, int32_t order, float* weights);
 
 /* Detection metrics of Section III-A on the host: the IoU matrix of ground
  * truth boxes against detections (inclusive pixel boxes), N_t = ground

@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librxphy.so")
+# RXPHY_LIBRARY selects another build of the library (e.g. the host-sanitized one)
+LIB_PATH = os.environ.get("RXPHY_LIBRARY") or os.path.join(_HERE, "librxphy.so")
 
 ZF, MMSE = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
@@ -187,6 +188,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rxphy_sense.restype = ctypes.c_int
     lib.rxphy_box_metrics.argtypes = [P, I32, P, I32, ctypes.c_double, P, ctypes.POINTER(_Metrics)]
     lib.rxphy_box_metrics.restype = ctypes.c_int
+    lib.rxphy_savgol_weights.argtypes = [I32, I32, P]
+    lib.rxphy_savgol_weights.restype = ctypes.c_int
     lib.rxphy_stream_destroy.argtypes = [ST]
     lib.rxphy_stream_destroy.restype = None
     lib.rxphy_clock_ns.argtypes = []
@@ -826,6 +829,14 @@ def sense(cfg: SenseConfig, x, max_boxes: int = 1024, intermediates: bool = Fals
                               _stream()), "rxphy_sense")
     out.update(n_boxes=n_boxes, boxes=boxes)
     return out
+
+
+def savgol_weights(window: int, order: int) -> np.ndarray:
+    """The Savitzky-Golay weights the sensing pipeline smooths the PSD with
+    (float32, `window` values, offsets -window/2 .. window/2); host only."""
+    w = np.zeros(int(window), dtype=np.float32)
+    _check(load().rxphy_savgol_weights(int(window), int(order), w.ctypes.data), "rxphy_savgol_weights")
+    return w
 
 
 def box_metrics(gt, det, theta_iou: float, want_iou: bool = False) -> dict:

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <vector>
 
+#include "abi_checks.h"
 #include "common.h"
 
 namespace rxphy {
@@ -130,13 +131,13 @@ rxphy_status rxphy_csi(const rxphy_frame* frame, int32_t n_frames, const void* y
 
 rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames, const void* h,
                           const void* yf, void* xt, float* nu, uint8_t* flags,
-                          rxphy_precision precision, float cond_threshold, void* ws,
+                          int32_t precision_in, float cond_threshold, void* ws,
                           size_t ws_bytes, hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
-  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
-    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (!valid_precision(precision_in)) return fail(RXPHY_EINVAL, "precision = %d", (int)precision_in);
+  const rxphy_precision precision = (rxphy_precision)precision_in;
   if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
     return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
   size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_DETECT, precision);
@@ -152,13 +153,13 @@ rxphy_status rxphy_detect(const rxphy_frame* frame, int32_t n_frames, const void
 
 rxphy_status rxphy_csi_detect(const rxphy_frame* frame, int32_t n_frames, const void* yf,
                               const void* pilots, void* xt, float* nu, uint8_t* flags,
-                              rxphy_precision precision, float cond_threshold, void* ws,
+                              int32_t precision_in, float cond_threshold, void* ws,
                               size_t ws_bytes, hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
-  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
-    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (!valid_precision(precision_in)) return fail(RXPHY_EINVAL, "precision = %d", (int)precision_in);
+  const rxphy_precision precision = (rxphy_precision)precision_in;
   if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
     return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
   size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT, precision);
@@ -186,13 +187,13 @@ rxphy_status rxphy_fft_sc16(const rxphy_frame* frame, int32_t n_frames, const in
 
 rxphy_status rxphy_csi_detect_demod(const rxphy_frame* frame, int32_t n_frames, const void* yf,
                                     const void* pilots, void* xt, float* nu, uint8_t* flags, float* llr,
-                                    rxphy_precision precision, float cond_threshold, void* ws,
+                                    int32_t precision_in, float cond_threshold, void* ws,
                                     size_t ws_bytes, hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
-  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
-    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (!valid_precision(precision_in)) return fail(RXPHY_EINVAL, "precision = %d", (int)precision_in);
+  const rxphy_precision precision = (rxphy_precision)precision_in;
   if (precision != RXPHY_FP32 && !(cond_threshold >= 0.0f))
     return fail(RXPHY_EINVAL, "cond_threshold = %g must be >= 0", cond_threshold);
   size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD, precision);
@@ -242,13 +243,13 @@ static rxphy_status scratch_address(void** out) {
 
 rxphy_status rxphy_csi_detect_demod_noalloc(const rxphy_frame* frame, int32_t n_frames, const void* yf,
                                             const void* pilots, void* xt, float* nu, uint8_t* flags,
-                                            float* llr, rxphy_precision precision, float cond_threshold,
+                                            float* llr, int32_t precision_in, float cond_threshold,
                                             hipStream_t stream) {
   clear_error();
   rxphy_status st = check_frame(frame, n_frames);
   if (st) return st;
-  if (precision != RXPHY_FP32 && precision != RXPHY_BF16 && precision != RXPHY_FP16)
-    return fail(RXPHY_EINVAL, "precision = %d", (int)precision);
+  if (!valid_precision(precision_in)) return fail(RXPHY_EINVAL, "precision = %d", (int)precision_in);
+  const rxphy_precision precision = (rxphy_precision)precision_in;
   const size_t need = rxphy_workspace_bytes(frame, n_frames, RXPHY_WS_CSI_DETECT_DEMOD, precision);
   if (need > (size_t)RXPHY_NOALLOC_SCRATCH_BYTES)
     return fail(RXPHY_EWORKSPACE,

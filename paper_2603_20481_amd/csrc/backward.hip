@@ -19,6 +19,7 @@
 //                   (zero-padded grid), cyclic-prefix samples get 0.
 #include <cstring>
 
+#include "abi_checks.h"
 #include "detect_core.h"
 
 namespace rxphy {
@@ -365,9 +366,9 @@ using namespace rxphy;
 extern "C" {
 
 size_t rxphy_workspace_bytes(const rxphy_frame* frame, int32_t n_frames, int32_t which,
-                             rxphy_precision precision) {
-  (void)precision;
-  if (check_frame(frame, n_frames) != RXPHY_OK) return 0;
+                             int32_t precision_in) {
+  if (!valid_precision(precision_in) || check_frame(frame, n_frames) != RXPHY_OK) return 0;
+  const rxphy_precision precision = (rxphy_precision)precision_in;
   if (which == RXPHY_WS_DETECT) return detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT) return csi_detect_workspace_bytes(*frame, n_frames, precision);
   if (which == RXPHY_WS_CSI_DETECT_DEMOD) return csi_detect_demod_workspace_bytes(*frame, n_frames, precision);

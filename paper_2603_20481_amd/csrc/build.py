@@ -28,9 +28,26 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
 EXTRA = {"batch.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(HERE, src), "-o", obj]
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build for CPU-only
+# tests of the host code (argument checks, plan creation, the streaming
+# runtime, the sensing host helpers).  Each -fsanitize= applies to the host
+# pass only (-Xarch_host); the device code is compiled but never run from it.
+# Loading it needs the sanitizer runtime preloaded into the process.
+SAN_BUILD = os.path.join(PKG, "_build_san")
+SAN_OUT = os.path.join(SAN_BUILD, "librxphy_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on", "-pthread",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def _compile(src, sanitize=False):
+    if sanitize:
+        obj = os.path.join(SAN_BUILD, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + SAN_FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+    else:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(HERE, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
@@ -52,6 +69,34 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, OUT)
     return OUT
+
+
+def sanitized_is_current() -> bool:
+    """True when the sanitized library exists and is newer than every source."""
+    if not os.path.exists(SAN_OUT):
+        return False
+    t = os.path.getmtime(SAN_OUT)
+    deps = [os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith((".hip", ".h"))]
+    deps.append(os.path.join(os.path.dirname(PKG), "include", "rxphy.h"))
+    return all(os.path.getmtime(d) <= t for d in deps)
+
+
+def build_sanitized() -> str:
+    """The host-sanitized librxphy (SAN_OUT); rebuilt only when a source is newer."""
+    if sanitized_is_current():
+        return SAN_OUT
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        results = list(ex.map(lambda f: _compile(f, sanitize=True), SOURCES))
+    tmp = SAN_OUT + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-shared-libasan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", tmp] + \
+        [o for o, _ in results]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, SAN_OUT)
+    return SAN_OUT
 
 
 if __name__ == "__main__":

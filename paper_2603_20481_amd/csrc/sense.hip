@@ -994,6 +994,18 @@ rxphy_status rxphy_sense(const rxphy_sense_config* cfg, int32_t n_plots, const v
   return RXPHY_OK;
 }
 
+rxphy_status rxphy_savgol_weights(int32_t window, int32_t order, float* weights) {
+  using namespace rxphy;
+  clear_error();
+  if (!weights) return fail(RXPHY_EINVAL, "weights is NULL");
+  if (window < 3 || window > SG_MAX || !(window & 1) || order < 0 || order > 6 || order >= window)
+    return fail(RXPHY_EINVAL, "window = %d, order = %d (odd window 3 .. %d, 0 <= order <= 6, order < window)",
+                window, order, SG_MAX);
+  const SgCoef sg = sg_coeffs(window, order);
+  for (int k = 0; k < window; ++k) weights[k] = sg.c[k];
+  return RXPHY_OK;
+}
+
 rxphy_status rxphy_box_metrics(const int32_t* gt, int32_t n_gt, const int32_t* det, int32_t n_det,
                                double theta_iou, double* iou, rxphy_detection_metrics* out) {
   using namespace rxphy;

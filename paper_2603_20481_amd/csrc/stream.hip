@@ -1,25 +1,24 @@
 // Real-time streaming of receiver tasks (Section III-B's bounded-latency
 // rule, Section IV-D's ping-pong buffer): `depth` slots handed out in turn,
-// each with its own HIP stream, completion event and buffers, and a
-// completion thread that stamps every task's latency against its arrival.
-// Host code only: a task is the library's own fft + csi_detect_demod calls.
+// each with its own HIP stream, completion event and buffers; the slot ring
+// and its completion thread (stream_ring.h) stamp every task's latency
+// against its arrival.  Host code only: a task is the library's own fft +
+// csi_detect_demod calls.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
-#include <thread>
+#include <memory>
 #include <vector>
 
 #include "common.h"
+#include "stream_ring.h"
 
 namespace {
 
 struct Slot {
   hipStream_t st = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t done = nullptr;    // recorded after the task's last operation
   void* d_x = nullptr;          // host I/O staging of the inputs
   void* d_p = nullptr;
   void* d_yf = nullptr;         // FFT output (every stream)
@@ -32,17 +31,22 @@ struct Slot {
   float* h_llr = nullptr;
   float* h_nu = nullptr;
   uint8_t* h_fl = nullptr;
-  bool acquired = false;        // handed out by acquire, not yet submitted
-  bool busy = false;            // submitted, completion not yet seen
-  int64_t task = -1;
-  int64_t arrival = 0;
 };
 
-int64_t steady_ns() {
-  return std::chrono::duration_cast<std::chrono::nanoseconds>(
-             std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
+// Completion of a slot's task = its event.  The slots' events are created
+// before the completion thread starts and destroyed after it has stopped.
+struct HipPoller {
+  const std::vector<Slot>* slots = nullptr;
+  int device = 0;
+  void start() { (void)hipSetDevice(device); }
+  rxphy::Poll operator()(int i, char* msg, size_t cap) const {
+    const hipError_t e = hipEventQuery((*slots)[(size_t)i].done);
+    if (e == hipErrorNotReady) return rxphy::Poll::NotReady;
+    if (e == hipSuccess) return rxphy::Poll::Done;
+    snprintf(msg, cap, "%s", hipGetErrorString(e));
+    return rxphy::Poll::Failed;
+  }
+};
 
 }  // namespace
 
@@ -52,71 +56,21 @@ struct rxphy_stream {
   float sc16 = 0.f;                             // > 0: 16-bit I/Q samples with this scale
   size_t bx = 0, bp = 0, byf = 0, bws = 0, bllr = 0, bnu = 0, bfl = 0;
   std::vector<Slot> slots;
-  std::mutex mu;
-  std::condition_variable cv;
-  std::thread watcher;
-  bool stop = false;
-  int32_t next = 0;             // slot the next acquire hands out
-  int64_t outstanding = 0;
-  std::vector<double> lat;      // per submitted task, NaN until completed
-  rxphy_status async_err = RXPHY_OK;
-  char async_msg[256] = {0};
+  std::unique_ptr<rxphy::SlotRing<HipPoller>> ring;
 };
 
 namespace {
 
 using rxphy::fail;
-
-// Completion thread: polls the events of busy slots (outside the lock) and
-// stamps each completion with the steady clock.  It spins with yields while
-// tasks are outstanding (a sleeping poll would add the timer's slack to every
-// latency) and waits on the condition variable otherwise.
-void watch(rxphy_stream* s) {
-  hipSetDevice(s->device);
-  std::vector<int> busy;
-  std::unique_lock<std::mutex> lk(s->mu);
-  for (;;) {
-    if (s->outstanding == 0) {
-      if (s->stop) return;
-      s->cv.wait(lk);
-      continue;
-    }
-    busy.clear();
-    for (int i = 0; i < s->depth; ++i)
-      if (s->slots[i].busy) busy.push_back(i);
-    lk.unlock();
-    bool any = false;
-    for (int i : busy) {
-      const hipError_t e = hipEventQuery(s->slots[i].done);
-      if (e == hipErrorNotReady) continue;
-      const int64_t t = steady_ns();
-      lk.lock();
-      Slot& sl = s->slots[i];
-      if (e != hipSuccess && s->async_err == RXPHY_OK) {
-        s->async_err = RXPHY_EHIP;
-        snprintf(s->async_msg, sizeof(s->async_msg), "task %lld: %s", (long long)sl.task, hipGetErrorString(e));
-      }
-      s->lat[sl.task] = (double)(t - sl.arrival) * 1e-3;
-      sl.busy = false;
-      --s->outstanding;
-      lk.unlock();
-      any = true;
-    }
-    if (any)
-      s->cv.notify_all();
-    else
-      std::this_thread::yield();
-    lk.lock();
-  }
-}
+using rxphy::steady_ns;
 
 void free_slot(Slot& sl) {
-  if (sl.st) hipStreamDestroy(sl.st);
-  if (sl.done) hipEventDestroy(sl.done);
+  if (sl.st) (void)hipStreamDestroy(sl.st);
+  if (sl.done) (void)hipEventDestroy(sl.done);
   for (void* p : {sl.d_x, sl.d_p, sl.d_yf, sl.d_ws, (void*)sl.d_llr, (void*)sl.d_nu, (void*)sl.d_fl})
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   for (void* p : {sl.h_x, sl.h_p, (void*)sl.h_llr, (void*)sl.h_nu, (void*)sl.h_fl})
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   sl = Slot{};
 }
 
@@ -144,6 +98,7 @@ rxphy_status alloc_slot(rxphy_stream* s, Slot& sl) {
 }
 
 void destroy_all(rxphy_stream* s) {
+  if (s->ring) s->ring->shutdown();             // the completion thread stops before the events go
   for (Slot& sl : s->slots) free_slot(sl);
   delete s;
 }
@@ -193,7 +148,8 @@ rxphy_status rxphy_stream_create(const rxphy_frame* frame, int32_t n_frames, int
       return st;
     }
   }
-  s->watcher = std::thread(watch, s);
+  s->ring.reset(new rxphy::SlotRing<HipPoller>(depth));
+  s->ring->start(HipPoller{&s->slots, s->device});
   *stream = s;
   return RXPHY_OK;
 }
@@ -211,13 +167,9 @@ rxphy_status rxphy_stream_host_buffers(rxphy_stream* s, int32_t slot, rxphy_stre
 rxphy_status rxphy_stream_acquire(rxphy_stream* s, int32_t* slot) {
   rxphy::clear_error();
   if (!s || !slot) return fail(RXPHY_EINVAL, "stream or slot is NULL");
-  std::unique_lock<std::mutex> lk(s->mu);
-  Slot& sl = s->slots[s->next];
-  if (sl.acquired) return fail(RXPHY_EINVAL, "slot %d is acquired and not yet submitted", s->next);
-  s->cv.wait(lk, [&] { return !sl.busy; });
-  sl.acquired = true;
-  *slot = s->next;
-  s->next = (s->next + 1) % s->depth;
+  int k = -1;
+  if (!s->ring->acquire(&k)) return fail(RXPHY_EINVAL, "the next slot is acquired and not yet submitted");
+  *slot = k;
   return RXPHY_OK;
 }
 
@@ -228,10 +180,7 @@ rxphy_status rxphy_stream_submit(rxphy_stream* s, int32_t slot, int64_t arrival_
   if (slot < 0 || slot >= s->depth) return fail(RXPHY_EINVAL, "slot = %d (0 .. %d)", slot, s->depth - 1);
   if (arrival_ns < 0) return fail(RXPHY_EINVAL, "arrival_ns = %lld", (long long)arrival_ns);
   Slot& sl = s->slots[slot];
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (!sl.acquired) return fail(RXPHY_EINVAL, "slot %d was not acquired", slot);
-  }
+  if (!s->ring->acquired(slot)) return fail(RXPHY_EINVAL, "slot %d was not acquired", slot);
   if (s->host_io) {
     if (x || pilots || llr || nu || flags)
       return fail(RXPHY_EINVAL, "host I/O stream: x, pilots, llr, nu and flags must be NULL");
@@ -264,57 +213,36 @@ rxphy_status rxphy_stream_submit(rxphy_stream* s, int32_t slot, int64_t arrival_
   }
   e = hipEventRecord(sl.done, sl.st);
   if (e != hipSuccess) return fail(RXPHY_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    sl.acquired = false;
-    sl.busy = true;
-    sl.task = (int64_t)s->lat.size();
-    sl.arrival = arrival_ns ? arrival_ns : t_sub;
-    s->lat.push_back(NAN);
-    ++s->outstanding;
-  }
-  s->cv.notify_all();
+  s->ring->commit(slot, arrival_ns ? arrival_ns : t_sub);
   return RXPHY_OK;
 }
 
 rxphy_status rxphy_stream_drain(rxphy_stream* s) {
   rxphy::clear_error();
   if (!s) return fail(RXPHY_EINVAL, "stream is NULL");
-  std::unique_lock<std::mutex> lk(s->mu);
-  s->cv.wait(lk, [&] { return s->outstanding == 0; });
-  if (s->async_err) return fail(s->async_err, "%s", s->async_msg);
+  char msg[320];
+  if (!s->ring->drain(msg, sizeof(msg))) return fail(RXPHY_EHIP, "%s", msg);
   return RXPHY_OK;
 }
 
 rxphy_status rxphy_stream_latencies(rxphy_stream* s, double* lat_us, int64_t cap, int64_t* n) {
   rxphy::clear_error();
   if (!s || !n || cap < 0 || (cap > 0 && !lat_us)) return fail(RXPHY_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(s->mu);
-  const int64_t m = (int64_t)s->lat.size();
-  if (cap > 0) std::copy(s->lat.begin(), s->lat.begin() + std::min(cap, m), lat_us);
-  *n = m;
+  *n = s->ring->latencies(lat_us, cap);
   return RXPHY_OK;
 }
 
 rxphy_status rxphy_stream_reset_latencies(rxphy_stream* s) {
   rxphy::clear_error();
   if (!s) return fail(RXPHY_EINVAL, "stream is NULL");
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->outstanding) return fail(RXPHY_EINVAL, "%lld task(s) outstanding", (long long)s->outstanding);
-  s->lat.clear();
+  const int64_t busy = s->ring->reset_latencies();
+  if (busy) return fail(RXPHY_EINVAL, "%lld task(s) outstanding", (long long)busy);
   return RXPHY_OK;
 }
 
 void rxphy_stream_destroy(rxphy_stream* s) {
   if (!s) return;
-  {
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv.wait(lk, [&] { return s->outstanding == 0; });
-    s->stop = true;
-  }
-  s->cv.notify_all();
-  if (s->watcher.joinable()) s->watcher.join();
-  destroy_all(s);
+  destroy_all(s);                               // waits for outstanding tasks first
 }
 
 rxphy_status rxphy_latency_summarize(const double* lat_us, int64_t n, double bound_us, rxphy_latency_summary* out) {

@@ -8,7 +8,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rxphy.h")
-LIB = os.path.join(ROOT, "paper_2603_20481_amd", "librxphy.so")
+LIB = os.environ.get("RXPHY_LIBRARY") or os.path.join(ROOT, "paper_2603_20481_amd", "librxphy.so")
 
 
 def declared_functions():

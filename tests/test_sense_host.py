@@ -1,6 +1,7 @@
 """Host-only checks of the sensing entry points: the detection metrics of
 Section III-A (rxphy_box_metrics, host code) against the oracle on random
-boxes, and configuration checks made before any HIP call."""
+boxes, the Savitzky-Golay weights (rxphy_savgol_weights, host code) against
+scipy, and configuration checks made before any HIP call."""
 import ctypes
 
 import numpy as np
@@ -65,3 +66,22 @@ def test_argument_checks():
     assert lib.rxphy_sense(c, 2, p, None, n, p, 4, p, need - 1, None) == 3         # small workspace
     assert lib.rxphy_sense(c, 2, p, None, n, p, 4, ctypes.c_void_p(384), need, None) == 3   # misaligned
     assert lib.rxphy_box_metrics(None, 1, None, 0, 0.5, None, None) == 1
+
+
+@pytest.mark.parametrize("window,order", [(3, 0), (5, 2), (21, 1), (21, 3), (31, 6), (63, 4), (63, 6), (7, 6)])
+def test_savgol_weights_match_scipy(window, order):
+    """The host routine (scaled normal equations, Gaussian elimination with
+    partial pivoting in FP64, rounded to FP32) against scipy's least-squares
+    Savitzky-Golay coefficients."""
+    signal = pytest.importorskip("scipy.signal")
+    w = rx.savgol_weights(window, order)
+    ref = signal.savgol_coeffs(window, order)
+    assert w.dtype == np.float32 and w.shape == (window,)
+    assert np.max(np.abs(w - ref)) <= 4e-7 * np.max(np.abs(ref)) + 1e-9
+    assert abs(float(np.sum(w.astype(np.float64))) - 1.0) < 1e-5        # reproduces constants
+
+
+@pytest.mark.parametrize("window,order", [(2, 0), (4, 1), (65, 2), (5, 7), (5, 5), (5, -1), (1, 0)])
+def test_savgol_weights_argument_checks(window, order):
+    with pytest.raises(rx.RxphyError):
+        rx.savgol_weights(window, order)
