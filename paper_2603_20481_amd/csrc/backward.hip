@@ -243,8 +243,10 @@ detect_adjoint_c_kernel(const float2* __restrict__ Xw, const float2* __restrict_
 }
 
 // dL/dY = H V into the data symbols of gyf, dL/dH = Y V^H - H C into gh.
-// Workgroup: 16 subcarriers x 16 antennas of one frame; V and C of the 16
-// subcarriers are staged in LDS.
+// Workgroup: 16 subcarriers x 32 antennas of one frame, V and C of the 16
+// subcarriers staged in LDS; each thread takes one subcarrier and two
+// antennas (m and m + 16), so that every V and C value read from LDS serves
+// two antennas.
 template <int KP>
 __global__ void __launch_bounds__(256)
 detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
@@ -258,7 +260,7 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
   __shared__ float2 sc[16 * CP];
   const int D = S - 1;
   const int f = blockIdx.z;
-  const int i0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+  const int i0 = blockIdx.x * 16, m0 = blockIdx.y * 32;
   const int il = threadIdx.x & 15, ml = threadIdx.x >> 4;
   const int ntile = min(16, n_sc - i0);
   for (int e = threadIdx.x; e < ntile * K * D; e += 256) {
@@ -272,37 +274,61 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
     sc[t * CP + a * KP + b] = Cw[((int64_t)f * n_sc + i0 + t) * K * K + r];
   }
   __syncthreads();
-  const int i = i0 + il, m = m0 + ml;
-  if (i >= n_sc || m >= M) return;
-  float2 h[KP], y[16];
+  const int i = i0 + il;
+  if (i >= n_sc || m0 + ml >= M) return;
+  const bool two = m0 + ml + 16 < M;
+  float2 h[2][KP], y[2][16];
 #pragma unroll
-  for (int u = 0; u < KP; ++u)
-    h[u] = u < K ? H[((int64_t)(f * M + m) * K + u) * n_sc + i] : make_float2(0.f, 0.f);
+  for (int a = 0; a < 2; ++a) {
+    const int m = m0 + ml + 16 * a;
+    const bool in = a == 0 || two;
 #pragma unroll
-  for (int s = 0; s < 16; ++s)
-    y[s] = s < D ? Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] : make_float2(0.f, 0.f);
+    for (int u = 0; u < KP; ++u)
+      h[a][u] = (in && u < K) ? H[((int64_t)(f * M + m) * K + u) * n_sc + i] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+      y[a][s] = (in && s < D) ? Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] : make_float2(0.f, 0.f);
+  }
   const float2* V = sv + il * VP;
   const float2* C = sc + il * CP;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     if (s < D) {
-      float2 acc = make_float2(0.f, 0.f);
+      float2 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
 #pragma unroll
-      for (int u = 0; u < KP; ++u) if (u < K) acc = cms(acc, h[u], make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y));
-      gyf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] = acc;
+      for (int u = 0; u < KP; ++u) {
+        if (u < K) {
+          const float2 nv = make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y);
+          acc0 = cms(acc0, h[0][u], nv);
+          acc1 = cms(acc1, h[1][u], nv);
+        }
+      }
+      gyf[((int64_t)(f * M + m0 + ml) * S + 1 + s) * n_sc + i] = acc0;
+      if (two) gyf[((int64_t)(f * M + m0 + ml + 16) * S + 1 + s) * n_sc + i] = acc1;
     }
   }
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
     if (u < K) {
-      float2 acc = make_float2(0.f, 0.f);
+      float2 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
 #pragma unroll
-      for (int s = 0; s < 16; ++s)
-        if (s < D) acc = cms_bc(acc, y[s], make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y));  // + y conj(V)
+      for (int s = 0; s < 16; ++s) {
+        if (s < D) {
+          const float2 nv = make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y);
+          acc0 = cms_bc(acc0, y[0][s], nv);                                 // + y conj(V)
+          acc1 = cms_bc(acc1, y[1][s], nv);
+        }
+      }
 #pragma unroll
-      for (int v2 = 0; v2 < KP; ++v2)
-        if (v2 < K) acc = cms(acc, h[v2], C[v2 * KP + u]);                                    // - H C
-      gh[((int64_t)(f * M + m) * K + u) * n_sc + i] = acc;
+      for (int v2 = 0; v2 < KP; ++v2) {
+        if (v2 < K) {
+          const float2 c = C[v2 * KP + u];
+          acc0 = cms(acc0, h[0][v2], c);                                    // - H C
+          acc1 = cms(acc1, h[1][v2], c);
+        }
+      }
+      gh[((int64_t)(f * M + m0 + ml) * K + u) * n_sc + i] = acc0;
+      if (two) gh[((int64_t)(f * M + m0 + ml + 16) * K + u) * n_sc + i] = acc1;
     }
   }
 }
@@ -431,7 +457,7 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
 
   const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
   dim3 g1((fr.n_sc + TS - 1) / TS, n_frames);
-  dim3 g2((fr.n_sc + 15) / 16, (fr.M + 15) / 16, n_frames);
+  dim3 g2((fr.n_sc + 15) / 16, (fr.M + 31) / 32, n_frames);
   const int64_t n_sub = (int64_t)n_frames * fr.n_sc;
   const int c_ns = 256 / (fr.K * fr.K) < 64 ? 256 / (fr.K * fr.K) : 64;
   const unsigned gc = (unsigned)((n_sub + c_ns - 1) / c_ns);

@@ -48,6 +48,10 @@ size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision 
 // FP64 refinement of the listed subcarriers (rl[0] = count, then the entries
 // f * n_sc + i): x0 the low-precision start (nullptr: start from 0), xt / llr
 // written when not nullptr; with pil the channel is the LS estimate.
+// FP64 refinement of the 16-user group path: one workgroup per listed tile.
+rxphy_status launch_refine_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                                 float2* xt, float* nu, uint8_t* flags, float* llr, const uint32_t* rl,
+                                 hipStream_t s);
 rxphy_status launch_refine(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,
                            const float2* pil, const float2* x0, float2* xt, float* nu, uint8_t* flags,
                            float* llr, const uint32_t* rl, hipStream_t s);

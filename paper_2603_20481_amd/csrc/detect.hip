@@ -217,6 +217,179 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
   }
 }
 
+// The 16-user fused path's refinement: one workgroup per listed pilot group
+// (a 16-subcarrier tile, grid-stride over the list), whose subcarriers share
+// one channel estimate.  H = the LS estimate of the group (FP64 from the FP32
+// pilot symbol), A = H^H H (+ N0 I), its FP64 Cholesky factor and d =
+// diag(A^{-1}) are formed once for the tile.  Every (subcarrier, symbol)
+// right-hand side is then taken by 16 lanes, lane u holding row u, 32 of
+// them at a time (two data symbols of the tile per round): b = H^H y,
+// and from x = 0 two steps x <- x + A^{-1} (b - A x) (the steps of
+// refine_kernel), the triangular solves column by column with the solved
+// entry broadcast to the group.  The unbiased symbols wait in LDS until the
+// tile's non-finite data values are known; then x_tilde, the LLRs (as the
+// demod stage forms them), nu and the flags are written.  A non-finite
+// estimate erases the tile; a non-finite data value erases its subcarrier
+// (NONFINITE).
+constexpr int RG_SYM = 2;                      // data symbols per round
+constexpr int RG_THREADS = RG_SYM * 256;
+template <int Q>
+__global__ void __launch_bounds__(RG_THREADS)
+refine_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil, float2* __restrict__ xt,
+                    float* __restrict__ nu, uint8_t* __restrict__ flags, float* __restrict__ llr,
+                    const uint32_t* __restrict__ rlist, int M, int S, int n_sc, float n0f, int mmse) {
+  __shared__ double2 Hs[64 * 16];
+  __shared__ double2 A[16 * RP];
+  __shared__ double2 Lf[16 * RP];
+  __shared__ double2 V[16 * RP];
+  __shared__ float2 Xf[16 * 16 * 16];         // [subcarrier][symbol][user], unbiased
+  __shared__ float2 Ys[RG_SYM * 64 * 16];     // the round's data: [symbol][antenna][subcarrier]
+  __shared__ double dd[16];
+  __shared__ int bad, hnf;
+  __shared__ int snf[16];
+  const int D = S - 1;
+  const int tid = threadIdx.x, u = tid & 15, grp = tid >> 4;
+  const double n0 = (double)n0f;
+  const int nt = (n_sc + 15) / 16, G = n_sc / 16;
+  const uint32_t count = rlist[0];
+  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const uint32_t tile = rlist[RL_OFF + it];
+    const int f = (int)(tile / (uint32_t)nt), tt = (int)(tile - (uint32_t)f * nt);
+    const int i0 = tt * 16, cnt = min(16, n_sc - i0), g = min(tt, G - 1);
+    if (tid == 0) { bad = 0; hnf = 0; }
+    if (tid < 16) snf[tid] = 0;
+    __syncthreads();
+    for (int q = tid; q < M * 16; q += RG_THREADS) {     // the group's LS estimate
+      const int m = q >> 4, uu = q & 15, qq = g * 16 + uu;
+      const float2 hv = ls_estimate(Yf[((int64_t)(f * M + m) * S) * n_sc + qq], pil[(int64_t)f * n_sc + qq]);
+      if (!(isfinite(hv.x) && isfinite(hv.y))) hnf = 1;
+      Hs[m * 16 + uu] = d2(hv);
+    }
+    __syncthreads();
+    if (tid < 256) {                                     // A = H^H H (+ N0 I), one entry per thread
+      const int r = tid >> 4, c = tid & 15;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int m = 0; m < M; ++m) acc = dadd(acc, dmulcj(Hs[m * 16 + r], Hs[m * 16 + c]));
+      if (r == c && mmse) acc.x += n0;
+      A[r * RP + c] = acc;
+      Lf[r * RP + c] = acc;
+    }
+    __syncthreads();
+    for (int j = 0; j < 16; ++j) {                       // Lf = L, A = L L^H
+      if (tid == 0) {
+        const double dj = Lf[j * RP + j].x;
+        if (!(dj > 0.0) || !isfinite(dj)) bad = 1;
+        Lf[j * RP + j] = make_double2(sqrt(dj), 0.0);
+      }
+      __syncthreads();
+      const double ljj = Lf[j * RP + j].x;
+      if (tid > j && tid < 16) Lf[tid * RP + j] = dsc(Lf[tid * RP + j], 1.0 / ljj);
+      __syncthreads();
+      const int w2 = 15 - j;
+      if (tid < w2 * w2) {
+        const int r = j + 1 + tid / w2, c = j + 1 + tid % w2;
+        if (c <= r)
+          Lf[r * RP + c] = dsub(Lf[r * RP + c], dmul(Lf[r * RP + j], make_double2(Lf[c * RP + j].x, -Lf[c * RP + j].y)));
+      }
+      __syncthreads();
+    }
+    if (tid < 16) {                                      // column u of L^{-1}: d_u
+      double acc2 = 0.0;
+      for (int r = 0; r < 16; ++r) {
+        double2 acc = make_double2(r == tid ? 1.0 : 0.0, 0.0);
+        for (int k = tid; k < r; ++k) acc = dsub(acc, dmul(Lf[r * RP + k], V[k * RP + tid]));
+        const double2 vr = r < tid ? make_double2(0.0, 0.0) : dsc(acc, 1.0 / Lf[r * RP + r].x);
+        V[r * RP + tid] = vr;
+        acc2 += vr.x * vr.x + vr.y * vr.y;
+      }
+      dd[tid] = acc2;
+      if (mmse && !(1.0 - n0 * acc2 > 0.0)) bad = 1;
+    }
+    __syncthreads();
+    // right-hand sides: round s0 takes symbols s0 .. s0 + RG_SYM - 1; group grp the
+    // subcarrier e = grp % 16 of symbol s0 + grp / 16; lane u = row u
+    const double linv = 1.0 / Lf[u * RP + u].x;
+    const double ub = mmse ? 1.0 / (1.0 - n0 * dd[u]) : 1.0;
+    const int e = grp & 15, sl = grp >> 4;
+    for (int s0 = 0; s0 < D; s0 += RG_SYM) {
+      // the round's data into LDS, every load issued at once (consecutive
+      // threads, consecutive subcarriers)
+      {
+        float2 yv[2 * RG_SYM];
+#pragma unroll
+        for (int t = 0; t < 2 * RG_SYM; ++t) {
+          const int q = t * RG_THREADS + tid;            // [symbol][antenna][subcarrier]
+          const int m = (q >> 4) & 63, ee = q & 15, s = s0 + (q >> 10);
+          yv[t] = (s < D && m < M && ee < cnt) ? Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i0 + ee]
+                                               : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * RG_SYM; ++t) {
+          if (!(isfinite(yv[t].x) && isfinite(yv[t].y))) snf[tid & 15] = 1;
+          Ys[t * RG_THREADS + tid] = yv[t];
+        }
+      }
+      __syncthreads();
+      double2 b = make_double2(0.0, 0.0);
+      for (int m = 0; m < M; ++m) b = dadd(b, dmulcj(Hs[m * 16 + u], d2(Ys[(sl * 64 + m) * 16 + e])));
+      __syncthreads();                                   // Ys is rewritten by the next round
+      const int s = s0 + sl;
+      if (s >= D || e >= cnt) continue;                  // the group's 16 lanes together
+      double2 x = make_double2(0.0, 0.0);
+      for (int step = 0; step < 2; ++step) {
+        double2 r = b;                                   // b - A x
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {
+          const double2 xk = make_double2(__shfl(x.x, k, 16), __shfl(x.y, k, 16));
+          r = dsub(r, dmul(A[u * RP + k], xk));
+        }
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {                   // L^-1, column k: entry k final, then eliminated below
+          if (u == k) r = dsc(r, linv);
+          const double2 rk = make_double2(__shfl(r.x, k, 16), __shfl(r.y, k, 16));
+          if (u > k) r = dsub(r, dmul(Lf[u * RP + k], rk));
+        }
+#pragma unroll 4
+        for (int k = 15; k >= 0; --k) {                  // L^-H, column k of L^H = conj of row k of L
+          if (u == k) r = dsc(r, linv);
+          const double2 rk = make_double2(__shfl(r.x, k, 16), __shfl(r.y, k, 16));
+          if (u < k) r = dsub(r, dmulcj(Lf[k * RP + u], rk));
+        }
+        x = dadd(x, r);
+      }
+      const double2 xv = dsc(x, ub);
+      Xf[(e * 16 + s) * 16 + u] = make_float2((float)xv.x, (float)xv.y);
+    }
+    __syncthreads();                                     // Xf, snf complete
+    {
+      const int ee = tid & 15;                           // consecutive lanes, consecutive subcarriers
+      if (ee < cnt) {
+        const int i = i0 + ee;
+        const bool sub_nf = hnf != 0 || snf[ee] != 0;
+        const bool erase = bad != 0 || sub_nf;
+        for (int q = grp; q < 16 * D; q += RG_THREADS / 16) {
+          const int uu = q / D, s = q - uu * D;
+          const double d = dd[uu];
+          const float nv = erase ? INFINITY : (float)(mmse ? n0 * d / (1.0 - n0 * d) : n0 * d);
+          const float2 xf = erase ? make_float2(0.f, 0.f) : Xf[(ee * 16 + s) * 16 + uu];
+          const int64_t ex = ((int64_t)(f * 16 + uu) * D + s) * n_sc + i;
+          if (xt) xt[ex] = xf;
+          if constexpr (Q > 0) demk::demod_point<Q>(xf, nv, llr + ex * Q);
+        }
+        if (grp < 16) {
+          const int uu = grp;
+          const double d = dd[uu];
+          nu[(int64_t)(f * 16 + uu) * n_sc + i] = erase ? INFINITY : (float)(mmse ? n0 * d / (1.0 - n0 * d) : n0 * d);
+        }
+        if (grp == 0 && flags)
+          flags[(int64_t)f * n_sc + i] = sub_nf ? RXPHY_FLAG_NONFINITE : erase ? RXPHY_FLAG_BREAKDOWN
+                                                                              : RXPHY_FLAG_REFINED;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int KP, int P, bool FU>
 void launch_one(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf, const float2* pil,
                 float2* xt, float* nu, uint8_t* flags, float thr, uint32_t* rl, hipStream_t s) {
@@ -277,6 +450,26 @@ rxphy_status launch_detect(const rxphy_frame& fr, int32_t nf, const float2* h, c
   rxphy_status st = launch_status("detect kernel");
   if (st) return st;
   return launch_refine(fr, nf, h, yf, pil, xt, xt, nu, flags, nullptr, rl, s);
+}
+
+rxphy_status launch_refine_group(const rxphy_frame& fr, int32_t nf, const float2* yf, const float2* pil,
+                                 float2* xt, float* nu, uint8_t* flags, float* llr, const uint32_t* rl,
+                                 hipStream_t s) {
+  const int64_t n_tiles = (int64_t)nf * ((fr.n_sc + 15) / 16);
+  const unsigned blocks = (unsigned)(n_tiles < 2048 ? n_tiles : 2048);
+  const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
+  const int q = llr ? fr.qam_bits : 0;
+#define RXPHY_REFINE_G(QQ)                                                                                    \
+  hipLaunchKernelGGL(refine_group_kernel<QQ>, dim3(blocks), dim3(RG_THREADS), 0, s, yf, pil, xt, nu, flags, llr, rl, \
+                     fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse)
+  switch (q) {
+    case 0: RXPHY_REFINE_G(0); break;
+    case 2: RXPHY_REFINE_G(2); break;
+    case 4: RXPHY_REFINE_G(4); break;
+    default: RXPHY_REFINE_G(6); break;
+  }
+#undef RXPHY_REFINE_G
+  return launch_status("group refine kernel");
 }
 
 rxphy_status launch_refine(const rxphy_frame& fr, int32_t nf, const float2* h, const float2* yf,

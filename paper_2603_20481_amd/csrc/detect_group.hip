@@ -226,7 +226,8 @@ __device__ __forceinline__ bool factor_gram(float2* hv, float2 pv, int M, int kq
 // BF16 / FP16 (P): the Gram matrix from low-precision operands, the Cholesky
 // factor in FP32, and tiles whose condition estimate ||A||_F tr(A^-1) exceeds
 // thr (or whose factorisation broke down) are marked in their record and
-// their subcarriers appended to the refinement list rl.
+// appended to the refinement list rl (one entry per tile, frame * tiles +
+// tile), which the FP64 group refinement works through.
 template <int TPW, int P = P_FP32>
 __global__ void __launch_bounds__(256)
 group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pil, GroupRec* __restrict__ rec,
@@ -310,12 +311,7 @@ group_factor_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
       R.ok = okw ? 1 : 0;                        // the same in every lane of the row
       R.hbad = hb ? 1 : 0;
       R.refine = refine ? 1 : 0;
-      if (refine) {                              // the tile's subcarriers into the list
-        const int f = tix / nt, i0 = (tix - f * nt) * 16;
-        const int cnt = min(16, n_sc - i0);
-        const uint32_t slot = atomicAdd(rl, (uint32_t)cnt);
-        for (int e = 0; e < cnt; ++e) rl[RL_OFF + slot + e] = (uint32_t)(f * n_sc + i0 + e);
-      }
+      if (refine) rl[RL_OFF + atomicAdd(rl, 1u)] = (uint32_t)tix;   // the tile into the list
     }
   }
 }
@@ -753,7 +749,7 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
 size_t group_workspace_bytes(const rxphy_frame& fr, int32_t nf, rxphy_precision prec) {
   const size_t recs = (size_t)nf * ((fr.n_sc + 15) / 16) * sizeof(GroupRec);
   if (prec == RXPHY_FP32) return recs;
-  return recs + (size_t)RL_OFF * 4 + (size_t)nf * fr.n_sc * 4;      // + the refinement list
+  return recs + (size_t)RL_OFF * 4 + (size_t)nf * fr.n_sc * 4;      // + the refinement list (tiles)
 }
 
 namespace {
@@ -804,7 +800,7 @@ rxphy_status launch_detect_group(const rxphy_frame& fr, int32_t nf, const float2
   st = prec == RXPHY_BF16 ? launch_group_p<P_BF16>(fr, nf, yf, pil, xt, nu, flags, llr, thr, rec, rl, s)
                           : launch_group_p<P_FP16>(fr, nf, yf, pil, xt, nu, flags, llr, thr, rec, rl, s);
   if (st) return st;
-  return launch_refine(fr, nf, nullptr, yf, pil, nullptr, xt, nu, flags, llr, rl, s);
+  return launch_refine_group(fr, nf, yf, pil, xt, nu, flags, llr, rl, s);
 }
 
 }  // namespace rxphy

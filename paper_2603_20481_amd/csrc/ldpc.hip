@@ -43,11 +43,22 @@ __device__ __forceinline__ int bit_of(uint32_t e, int r, int z) {
   return c * z + (t < z ? t : t - z);
 }
 
-constexpr int LDPC_CH = 8;             // edges per chunk of table and posterior reads
 constexpr int LDPC_PF = 4;             // layers of compressed messages in flight
-constexpr int LDPC_DPAD = (LDPC_DMAX + LDPC_CH - 1) / LDPC_CH * LDPC_CH;
+// Edge slots per lane in one chunk of table and posterior reads, with S lanes
+// per check row: a chunk covers CH * S edges of the row (10 for S = 2, 12 for
+// S = 4, about one layer of a code with 8 - 12 edges per check), so that few
+// slots past the row's degree are processed; DPAD = the slots of all chunks.
+template <int S>
+struct LdpcChunk {
+  static constexpr int CH = S == 2 ? 5 : 3;
+  static constexpr int SPAN = CH * S;
+  static constexpr int DPAD = (LDPC_DMAX + SPAN - 1) / SPAN * SPAN;
+  static constexpr int J = DPAD / S;
+};
+constexpr int LDPC_PADMAX = 12;        // the widest chunk's span: table padding past the last layer
 // layer offsets, edges, and padding for the widest chunk (zero entries: column 0, shift 0)
-constexpr int LDPC_TABMAX = LDPC_MBMAX + 1 + LDPC_MBMAX * LDPC_DMAX + 4 * LDPC_CH;
+constexpr int LDPC_TABMAX = LDPC_MBMAX + 1 + LDPC_MBMAX * LDPC_DMAX + LDPC_PADMAX;
+static_assert(LdpcChunk<2>::SPAN <= LDPC_PADMAX && LdpcChunk<4>::SPAN <= LDPC_PADMAX, "table padding");
 
 // S lanes (adjacent, within one quad) share a check row: lane part h takes
 // the row's edges k = h, h + S, h + 2S, ...; the parts' partial results are
@@ -76,14 +87,15 @@ __device__ __forceinline__ bool any_check_unsatisfied(const float* L, const uint
     const uint32_t* E = T + mb + 1 + e0;
     uint32_t par = 0;
     if (row) {
+      using C = LdpcChunk<S>;
 #pragma unroll
-      for (int c = 0; c < LDPC_DPAD / (LDPC_CH * S); ++c) {
-        if (c * LDPC_CH * S < d) {
-          float lv[LDPC_CH];
+      for (int c = 0; c < C::DPAD / C::SPAN; ++c) {
+        if (c * C::SPAN < d) {
+          float lv[C::CH];
 #pragma unroll
-          for (int t = 0; t < LDPC_CH; ++t) lv[t] = L[bit_of(E[(c * LDPC_CH + t) * S + h], r, z)];
+          for (int t = 0; t < C::CH; ++t) lv[t] = L[bit_of(E[(c * C::CH + t) * S + h], r, z)];
 #pragma unroll
-          for (int t = 0; t < LDPC_CH; ++t) par ^= ((c * LDPC_CH + t) * S + h < d && lv[t] < 0.f) ? 1u : 0u;
+          for (int t = 0; t < C::CH; ++t) par ^= ((c * C::CH + t) * S + h < d && lv[t] < 0.f) ? 1u : 0u;
         }
       }
     }
@@ -110,7 +122,7 @@ __device__ __forceinline__ void combine_parts(float& m1, float& m2, int& idx, ui
 
 // One layer (block row i) for check row r (lane part h): the old messages of
 // its check come in compressed (o1, o2, om); the lane's edges are read in
-// chunks of LDPC_CH, each chunk's table entries and posteriors requested
+// chunks of LdpcChunk<S>::CH, each chunk's table entries and posteriors requested
 // together; slots past the layer's degree read padding or the next layer's
 // entries (valid addresses) and take Q = +inf, which changes no minimum and
 // no sign.  Writes the new posteriors to L and (part 0) the new compressed
@@ -119,7 +131,8 @@ template <int S>
 __device__ __forceinline__ void layer_update(float* L, const uint32_t* T, float* A1, float* A2, uint32_t* MT,
                                              int mb, int z, int i, int r, int h, bool row, float o1, float o2,
                                              uint32_t om, float alpha) {
-  constexpr int J = LDPC_DPAD / S;               // edge slots per lane
+  using C = LdpcChunk<S>;
+  constexpr int J = C::J;                        // edge slots per lane
   const int e0 = __builtin_amdgcn_readfirstlane((int)T[i]);
   const int d = __builtin_amdgcn_readfirstlane((int)T[i + 1]) - e0;
   const uint32_t* E = T + mb + 1 + e0;
@@ -131,18 +144,18 @@ __device__ __forceinline__ void layer_update(float* L, const uint32_t* T, float*
   uint32_t neg = 0u;
   if (row) {
 #pragma unroll
-    for (int c = 0; c < J / LDPC_CH; ++c) {
-      if (c * LDPC_CH * S < d) {
-        float lv[LDPC_CH];
+    for (int c = 0; c < J / C::CH; ++c) {
+      if (c * C::SPAN < d) {
+        float lv[C::CH];
 #pragma unroll
-        for (int t = 0; t < LDPC_CH; ++t) {
-          const int j = c * LDPC_CH + t;
+        for (int t = 0; t < C::CH; ++t) {
+          const int j = c * C::CH + t;
           vv[j] = bit_of(E[j * S + h], r, z);
           lv[t] = L[vv[j]];
         }
 #pragma unroll
-        for (int t = 0; t < LDPC_CH; ++t) {
-          const int j = c * LDPC_CH + t, k = j * S + h;
+        for (int t = 0; t < C::CH; ++t) {
+          const int j = c * C::CH + t, k = j * S + h;
           const float mag = k == oidx ? o2 : o1;
           const float r_old = ((om >> k) & 1u) ? -mag : mag;
           const float qk = k < d ? lv[t] - r_old : INFINITY;
@@ -195,7 +208,7 @@ ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, cons
   const float* in = llr + cw * N;
   for (int v = tid; v < N; v += blockDim.x) L[v] = in[v];
   const int tlen = mb + 1 + (int)tab[mb];
-  for (int t = tid; t < tlen + LDPC_CH * S; t += blockDim.x) T[t] = t < tlen ? tab[t] : 0u;
+  for (int t = tid; t < tlen + LdpcChunk<S>::SPAN; t += blockDim.x) T[t] = t < tlen ? tab[t] : 0u;
   // compressed messages of this codeword: a1 [mb][z], a2 [mb][z], meta [mb][z]
   float* A1 = msg + cw * 3 * (int64_t)mb * z;
   float* A2 = A1 + (int64_t)mb * z;
