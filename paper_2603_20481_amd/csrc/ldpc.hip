@@ -23,7 +23,7 @@
 
 struct rxphy_ldpc_code {
   int32_t mb, nb, z, n_edges, max_deg;
-  uint32_t* d_tab;      // [mb + 1] layer offsets, then [n_edges] (column << 16 | shift)
+  uint32_t* d_tab;      // [mb + 1] layer offsets, then [n_edges] ((z - shift) << 16 | column z + shift)
   std::vector<int16_t> base;
   int device;
 };
@@ -37,10 +37,12 @@ constexpr int LDPC_NMAX = 38400;       // posterior LLRs held in LDS (150 KB; th
 constexpr int LDPC_MBMAX = 64;
 
 // Bit of check row r for the block (column c, shift s): c z + (r + s) mod z.
+// A table entry holds lo = c z + s in its low half and hi = z - s in its high
+// half, so that the bit is lo + r, less z once r + s wraps (r >= hi); the
+// padding entry (column 0, shift 0) is z << 16.
 __device__ __forceinline__ int bit_of(uint32_t e, int r, int z) {
-  const int c = (int)(e >> 16), s = (int)(e & 0xffffu);
-  const int t = r + s;
-  return c * z + (t < z ? t : t - z);
+  const int lo = (int)(e & 0xffffu), hi = (int)(e >> 16);
+  return lo + r - (r >= hi ? z : 0);
 }
 
 constexpr int LDPC_PF = 4;             // layers of compressed messages in flight
@@ -56,7 +58,7 @@ struct LdpcChunk {
   static constexpr int J = DPAD / S;
 };
 constexpr int LDPC_PADMAX = 12;        // the widest chunk's span: table padding past the last layer
-// layer offsets, edges, and padding for the widest chunk (zero entries: column 0, shift 0)
+// layer offsets, edges, and padding for the widest chunk (entries of column 0, shift 0)
 constexpr int LDPC_TABMAX = LDPC_MBMAX + 1 + LDPC_MBMAX * LDPC_DMAX + LDPC_PADMAX;
 static_assert(LdpcChunk<2>::SPAN <= LDPC_PADMAX && LdpcChunk<4>::SPAN <= LDPC_PADMAX, "table padding");
 
@@ -114,7 +116,7 @@ __device__ __forceinline__ void combine_parts(float& m1, float& m2, int& idx, ui
   const int pidx = (int)quad_xor_u<OFF>((uint32_t)idx);
   const uint32_t pneg = quad_xor_u<OFF>(neg);
   const float n2 = fminf(fmaxf(m1, p1), fminf(m2, p2));
-  if (p1 < m1 || (p1 == m1 && pidx < idx)) idx = pidx;
+  idx = (p1 < m1 || (p1 == m1 && pidx < idx)) ? pidx : idx;
   m1 = fminf(m1, p1);
   m2 = n2;
   neg ^= pneg;
@@ -125,12 +127,14 @@ __device__ __forceinline__ void combine_parts(float& m1, float& m2, int& idx, ui
 // chunks of LdpcChunk<S>::CH, each chunk's table entries and posteriors requested
 // together; slots past the layer's degree read padding or the next layer's
 // entries (valid addresses) and take Q = +inf, which changes no minimum and
-// no sign.  Writes the new posteriors to L and (part 0) the new compressed
-// messages.
+// no sign.  Writes the new posteriors to L (a slot past the degree writes
+// the spare word L[spare] instead, so that no store needs a branch) and
+// (part 0) the new compressed messages.  The minimum, second minimum and
+// argmin are tracked with selects, not branches.
 template <int S>
 __device__ __forceinline__ void layer_update(float* L, const uint32_t* T, float* A1, float* A2, uint32_t* MT,
                                              int mb, int z, int i, int r, int h, bool row, float o1, float o2,
-                                             uint32_t om, float alpha) {
+                                             uint32_t om, float alpha, int spare) {
   using C = LdpcChunk<S>;
   constexpr int J = C::J;                        // edge slots per lane
   const int e0 = __builtin_amdgcn_readfirstlane((int)T[i]);
@@ -161,8 +165,12 @@ __device__ __forceinline__ void layer_update(float* L, const uint32_t* T, float*
           const float qk = k < d ? lv[t] - r_old : INFINITY;
           q[j] = qk;
           const float a = __builtin_fabsf(qk);
-          if (a < m1) { m2 = m1; m1 = a; idx = k; }
-          else if (a < m2) { m2 = a; }
+          // the two smallest magnitudes and the first argmin, without branches:
+          // a < m1 -> (a, m1, k); else (m1, min(m2, a), idx)
+          const bool lt = a < m1;
+          m2 = lt ? m1 : __builtin_fminf(m2, a);
+          m1 = lt ? a : m1;
+          idx = lt ? k : idx;
           neg ^= qk < 0.f ? 1u : 0u;
         }
       }
@@ -178,11 +186,12 @@ __device__ __forceinline__ void layer_update(float* L, const uint32_t* T, float*
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int k = j * S + h;
-    if (j * S < d && k < d) {
+    if (j * S < d) {                             // the same in every lane; k < d is not:
+      const bool in = k < d;                     // a slot past the degree writes the spare word
       const uint32_t sk = neg ^ (q[j] < 0.f ? 1u : 0u);
       const float mag = k == idx ? a2 : a1;
-      L[vv[j]] = q[j] + (sk ? -mag : mag);
-      sg |= sk << k;
+      L[in ? vv[j] : spare] = q[j] + (sk ? -mag : mag);
+      sg |= (in ? sk : 0u) << k;
     }
   }
   sg |= quad_xor_u<1>(sg);
@@ -200,7 +209,7 @@ __global__ void __launch_bounds__(S == 2 ? 2 * LDPC_ZMAX : 1024)
 ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, const float* __restrict__ llr,
                    int max_iter, float alpha, float* __restrict__ post, uint8_t* __restrict__ bits,
                    int32_t* __restrict__ iters, float* __restrict__ msg) {
-  __shared__ float L[NMAX];
+  __shared__ float L[NMAX + 1];                 // posteriors, and a spare word that masked slots write
   __shared__ uint32_t T[LDPC_TABMAX];
   const int N = nb * z;
   const int64_t cw = blockIdx.x;
@@ -208,7 +217,7 @@ ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, cons
   const float* in = llr + cw * N;
   for (int v = tid; v < N; v += blockDim.x) L[v] = in[v];
   const int tlen = mb + 1 + (int)tab[mb];
-  for (int t = tid; t < tlen + LdpcChunk<S>::SPAN; t += blockDim.x) T[t] = t < tlen ? tab[t] : 0u;
+  for (int t = tid; t < tlen + LdpcChunk<S>::SPAN; t += blockDim.x) T[t] = t < tlen ? tab[t] : (uint32_t)z << 16;
   // compressed messages of this codeword: a1 [mb][z], a2 [mb][z], meta [mb][z]
   float* A1 = msg + cw * 3 * (int64_t)mb * z;
   float* A2 = A1 + (int64_t)mb * z;
@@ -246,7 +255,7 @@ ldpc_decode_kernel(const uint32_t* __restrict__ tab, int mb, int nb, int z, cons
         const int64_t x = (int64_t)min(i + LDPC_PF, mb - 1) * z + trow;   // layer i + LDPC_PF
         s1[u] = A1[x]; s2[u] = A2[x]; sm[u] = MT[x];
         if (i < mb) {
-          layer_update<S>(L, T, A1, A2, MT, mb, z, i, r, h, row, o1, o2, om, alpha);
+          layer_update<S>(L, T, A1, A2, MT, mb, z, i, r, h, row, o1, o2, om, alpha, NMAX);
           __syncthreads();                       // the next layer reads this one's L
         }
       }
@@ -305,7 +314,7 @@ rxphy_status rxphy_ldpc_code_create(const int16_t* base, int32_t mb, int32_t nb,
       const int s = base[(int64_t)i * nb + j];
       if (s < -1 || s >= z) return fail(RXPHY_EINVAL, "base[%d][%d] = %d outside [-1, z)", i, j, s);
       if (s >= 0) {
-        edges.push_back(((uint32_t)j << 16) | (uint32_t)s);
+        edges.push_back(((uint32_t)(z - s) << 16) | (uint32_t)(j * z + s));   // see bit_of
         ++deg;
       }
     }
