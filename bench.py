@@ -697,10 +697,26 @@ def run_batched(rx, torch, args):
     tuner.save()
     res = {}
     dets = sum(s.detections for s in shapes)
-    # algorithmic bytes of each dataflow: the four stages (H stored and read
-    # back), or the FFT, the detector forming the estimate itself, the demod
+    # algorithmic bytes of each dataflow: the four stages (H and x_tilde
+    # stored and read back); the FFT, the detector forming the estimate
+    # itself, the demod; the FFT and the detector forming the estimate and
+    # demapping (neither H nor x_tilde stored); the four stages with the demod
+    # fused into the detector
     byts_staged = sum(stage_bytes(s)[k] for s in shapes for k in MODES["staged"])
     byts_fused = sum(stage_bytes(s)[k] for s in shapes for k in MODES["csi_detect"])
+    byts_full = sum(stage_bytes(s)[k] for s in shapes for k in MODES["full"])
+    byts_dm = sum(stage_bytes(s)[k] for s in shapes for k in ("fft", "csi")) + \
+        sum(stage_bytes(s)["csi_detect_demod"] - stage_bytes(s)["csi_detect"] + stage_bytes(s)["detect"]
+            for s in shapes)
+
+    def flow(plan):
+        if plan.fuse_csi and plan.fuse_demod:
+            return "csi and demod fused into the detector (neither H nor x_tilde stored)", byts_full
+        if plan.fuse_csi:
+            return "csi fused into the detector (H never stored)", byts_fused
+        if plan.fuse_demod:
+            return "demod fused into the detector (x_tilde never stored)", byts_dm
+        return "four stages (H and x_tilde stored and read back)", byts_staged
     bufs = rx.Plan(frames).alloc()
     lay = rx.Plan(frames)
     for f, (x, p) in enumerate(inputs):
@@ -708,12 +724,13 @@ def run_batched(rx, torch, args):
         lay.view(bufs, "pilots", f).copy_(torch.from_numpy(p))
     del lay
     pick = tuner.tune_plan(frames, bufs)
-    variants = (("tuned", dict(tiles=tuner.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"])),
-                ("default", dict()),
-                ("fused_default_tiles", dict(fuse_csi=True)))
+    variants = (("tuned", dict(tiles=tuner.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"],
+                               fuse_demod=pick["fuse_demod"])),
+                ("fused_default_tiles", dict(fuse_csi=True, fuse_demod=True)),
+                ("default", dict()))
     for label, kw in variants:
         plan = rx.Plan(frames, **kw)
-        byts = byts_fused if plan.fuse_csi else byts_staged
+        dataflow, byts = flow(plan)
         plan.graph(bufs)
         for _ in range(args.warmup):
             plan.replay()
@@ -730,13 +747,12 @@ def run_batched(rx, torch, args):
         status = plan.device_status()
         res[label] = {"value": dets / (ms * 1e-3), "ms_per_step": round(ms, 4),
                       "wall_ms_per_step": round(wall, 4), "items": plan.counts, "grid": plan.grid,
-                      "dataflow": "csi fused into the detector (H never stored)" if plan.fuse_csi
-                      else "four stages (H stored and read back)",
-                      "algorithmic_bytes": byts,
+                      "dataflow": dataflow, "algorithmic_bytes": byts,
                       "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "device_status": status}
         del plan
-    # frames 0 and 1 of the last replay for the oracle leg
+    # frames 0 and 1 of the last replay (the staged default plan, which writes
+    # every tensor) for the oracle leg
     plan = rx.Plan(frames)
     keep = {}
     for f in (0, 1):
@@ -750,10 +766,12 @@ def run_batched(rx, torch, args):
     # each stage alone over the same buffers (a plan with one stage in its mask)
     tiles = tuner.tiles_for(frames)
     stage_ms = {}
-    for name, bit, fu in (("fft", rx.STAGE_FFT, False), ("csi", rx.STAGE_CSI, False),
-                          ("detect", rx.STAGE_DETECT, False), ("csi_detect", rx.STAGE_DETECT, True),
-                          ("demod", rx.STAGE_DEMOD, False)):
-        ps = rx.Plan(frames, tiles=tiles, stages=bit, fuse_csi=fu)
+    for name, bit, fc, fd in (("fft", rx.STAGE_FFT, False, False), ("csi", rx.STAGE_CSI, False, False),
+                              ("detect", rx.STAGE_DETECT, False, False),
+                              ("csi_detect", rx.STAGE_DETECT, True, False),
+                              ("csi_detect_demod", rx.STAGE_DETECT, True, True),
+                              ("demod", rx.STAGE_DEMOD, False, False)):
+        ps = rx.Plan(frames, tiles=tiles, stages=bit, fuse_csi=fc, fuse_demod=fd)
         ps.forward(bufs)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -382,6 +382,11 @@ typedef struct {
                           never written (buffers.h may be NULL) and the CSI stage has no
                           items.  Every other output is bit-identical to the staged plan's.
                           0: four stages, H written.                                       */
+  int32_t fuse_demod;  /* 1: the demod stage runs inside the detector items, which demap each
+                          tile from x_tilde and nu held in LDS (the demod stage's arithmetic,
+                          so the LLRs are bit-identical); x_tilde is never written
+                          (buffers.xt may be NULL) and the demod stage has no items.
+                          0: x_tilde written and demapped by demod items.                  */
 } rxphy_plan_options;
 
 /* Byte offsets of one frame's tensors in the packed buffers (or, for the

@@ -46,7 +46,7 @@ class _Tiles(ctypes.Structure):
 
 class _PlanOptions(ctypes.Structure):
     _fields_ = [("stages", ctypes.c_int32), ("grid", ctypes.c_int32), ("spin_limit", ctypes.c_uint32),
-                ("fuse_csi", ctypes.c_int32)]
+                ("fuse_csi", ctypes.c_int32), ("fuse_demod", ctypes.c_int32)]
 
 
 _TENSORS = ("x", "pilots", "yf", "h", "xt", "nu", "flags", "llr")
@@ -579,7 +579,7 @@ class Plan:
     TENSORS = _TENSORS
 
     def __init__(self, frames, tiles=None, stages: int = 0, grid: int = 0, spin_limit: int = 0,
-                 fuse_csi: bool = False):
+                 fuse_csi: bool = False, fuse_demod: bool = False):
         lib = load()
         self.frames = list(frames)
         n = len(self.frames)
@@ -591,8 +591,9 @@ class Plan:
             if len(tl) != n:
                 raise RxphyError("tiles needs one entry per frame")
             tarr = (_Tiles * n)(*[t.c() for t in tl])
-        opt = _PlanOptions(int(stages), int(grid), int(spin_limit), 1 if fuse_csi else 0)
+        opt = _PlanOptions(int(stages), int(grid), int(spin_limit), 1 if fuse_csi else 0, 1 if fuse_demod else 0)
         self.fuse_csi = bool(fuse_csi)
+        self.fuse_demod = bool(fuse_demod)
         h = ctypes.c_void_p()
         _check(lib.rxphy_plan_create(arr, n, tarr, ctypes.byref(opt), ctypes.byref(h)),
                "rxphy_plan_create")
@@ -628,10 +629,15 @@ class Plan:
                 "h": torch.complex64, "xt": torch.complex64, "nu": torch.float32,
                 "flags": torch.uint8, "llr": torch.float32}[name]
 
+    def _placeholder(self, k: str) -> bool:
+        """h is never written when the plan fuses the CSI stage into the
+        detector, x_tilde never when it fuses the demod stage in."""
+        return (k == "h" and self.fuse_csi) or (k == "xt" and self.fuse_demod)
+
     def alloc(self, device="cuda"):
-        """One packed byte buffer per tensor (h is a placeholder when the plan
-        fuses the CSI stage into the detector: it is never written)."""
-        return {k: torch.empty((1 if (k == "h" and self.fuse_csi) else max(self.totals[k], 1),),
+        """One packed byte buffer per tensor (a one-byte placeholder for a
+        tensor the plan never writes)."""
+        return {k: torch.empty((1 if self._placeholder(k) else max(self.totals[k], 1),),
                                dtype=torch.uint8, device=device) for k in _TENSORS}
 
     def view(self, bufs, name: str, f: int):
@@ -647,7 +653,7 @@ class Plan:
     def _batch(self, bufs) -> _Batch:
         for k in _TENSORS:
             t = bufs[k]
-            need = 1 if (k == "h" and self.fuse_csi) else self.totals[k]
+            need = 1 if self._placeholder(k) else self.totals[k]
             if t.device.type != "cuda" or t.numel() * t.element_size() < need:
                 raise RxphyError("buffer %s must be a device tensor of >= %d bytes" % (k, need))
         return _Batch(*[bufs[k].data_ptr() for k in _TENSORS])

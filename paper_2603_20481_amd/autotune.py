@@ -12,17 +12,18 @@ A class is timed on a plan of identical frames of that class that runs only
 the stage being tuned (the other stages' outputs are filled once beforehand),
 every candidate with HIP events on the current stream, and the fastest median
 wins.  The detector class is tuned in the dataflow the tuner is built for
-(fuse=True: the detector items form the channel estimate themselves, and the
-CSI stage has no items).
+(fuse=True: the detector items form the channel estimate themselves and
+demap their tiles, and the CSI and demod stages have no items).
 
 tune_plan then chooses the plan-wide knobs on the actual frames and buffers:
-the dataflow (CSI fused into the detector, or four stages with H stored) and
+the dataflow (CSI, demod, both or neither fused into the detector items) and
 the grid of the persistent launch (one, two or three workgroups per CU),
 timing each combination with the tuned item sizes.
 
-Every candidate gives bit-identical results for every output but H (the K
-padding is never changed), so tuning affects speed only.  Results live in a
-JSON cache keyed by device name.
+Every candidate gives bit-identical results for every output but H and
+x_tilde (not written by the fused dataflows; the K padding is never
+changed), so tuning affects speed only.  Results live in a JSON cache keyed
+by device name.
 """
 from __future__ import annotations
 
@@ -39,7 +40,7 @@ STAGE_BIT = {"fft": STAGE_FFT, "csi": STAGE_CSI, "detect": STAGE_DETECT, "demod"
 KNOB = {"fft": "fft_iters", "csi": "csi_tiles", "detect": "det_tiles", "demod": "dem_groups"}
 CANDIDATES = {"fft": (1, 2, 4, 8, 16), "csi": (1, 2, 4, 8), "detect": (1, 2, 4),
               "demod": (1, 2, 4, 8, 16)}
-CACHE_VERSION = 3
+CACHE_VERSION = 4
 
 
 def kp_of(K: int) -> int:
@@ -125,7 +126,8 @@ class Tuner:
         res = {}
         fuse = self.fuse and stage == "detect"
         for v in CANDIDATES[stage]:
-            p = Plan(frames, tiles=Tiles(**{KNOB[stage]: v}), stages=STAGE_BIT[stage], fuse_csi=fuse)
+            p = Plan(frames, tiles=Tiles(**{KNOB[stage]: v}), stages=STAGE_BIT[stage], fuse_csi=fuse,
+                     fuse_demod=fuse)
             res[v] = self._time(p, bufs, reps)
             del p
         best = min(res, key=lambda v: (res[v], v))
@@ -139,8 +141,8 @@ class Tuner:
         t0 = time.time()
         done = 0
         for st in STAGES:
-            if st == "csi" and self.fuse:
-                continue                                   # no CSI items in the fused dataflow
+            if st in ("csi", "demod") and self.fuse:
+                continue                                   # no CSI or demod items in the fused dataflow
             seen = {}
             for fr in frames:
                 seen.setdefault(class_key(st, fr, self.fuse), fr)
@@ -152,18 +154,20 @@ class Tuner:
 
     def tune_plan(self, frames, bufs, reps: int = 5) -> dict:
         """Plan-wide knobs on the given frames and packed buffers (x and the
-        pilots filled; allocated by a staged plan, so that H has room): the
-        dataflow and the grid (1, 2 or 3 workgroups per CU), with the cached
-        item sizes.  Returns the winner and every candidate's median time (us)."""
+        pilots filled; allocated by a staged plan, so that H and x_tilde have
+        room): the dataflow (CSI and / or demod fused into the detector items)
+        and the grid (1, 2 or 3 workgroups per CU), with the cached item sizes.
+        Returns the winner and every candidate's median time (us)."""
         tiles = self.tiles_for(frames)
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         res = {}
-        for fuse in (True, False):
+        for fc, fd in ((True, True), (True, False), (False, True), (False, False)):
             for per_cu in (1, 2, 3):
-                p = Plan(frames, tiles=tiles, grid=per_cu * cus, fuse_csi=fuse)
-                res[(fuse, per_cu)] = self._time(p, bufs, reps)
+                p = Plan(frames, tiles=tiles, grid=per_cu * cus, fuse_csi=fc, fuse_demod=fd)
+                res[(fc, fd, per_cu)] = self._time(p, bufs, reps)
                 del p
         best = min(res, key=lambda k: res[k])
-        return {"fuse_csi": best[0], "grid": best[1] * cus,
-                "candidates_us": {"%s,%d/CU" % ("fused" if k[0] else "staged", k[1]): round(v, 1)
-                                  for k, v in res.items()}}
+        name = {(True, True): "csi+demod fused", (True, False): "csi fused", (False, True): "demod fused",
+                (False, False): "staged"}
+        return {"fuse_csi": best[0], "fuse_demod": best[1], "grid": best[2] * cus,
+                "candidates_us": {"%s,%d/CU" % (name[k[:2]], k[2]): round(v, 1) for k, v in res.items()}}

@@ -85,24 +85,50 @@ __device__ __forceinline__ void run_csi(const BFrame& d, int tile, const float2*
   }
 }
 
+// The demapping of one detector tile from the x_tilde and nu detect_tile left
+// in LDS: thread (user u, tile subcarrier e) takes every data symbol of
+// (u, i0 + e), as the demod stage's column loop does (the same demod_point,
+// so the LLRs are bit-identical); consecutive threads write consecutive
+// subcarriers' LLRs.
+template <int Q>
+__device__ __forceinline__ void demod_tile(const BFrame& d, int i0, const float2* pool, float* llr) {
+  const int D = d.n_sym - 1;
+  const int u = tid_x() >> 4, e = tid_x() & 15, i = i0 + e;
+  if (u >= d.K || i >= d.n_sc) return;
+  const float2* xs = pool + e * det::PMAT;        // the slab of tile subcarrier e
+  const float v = xs[256 + u].x;
+  float* dst = llr + d.llr + ((int64_t)u * D * d.n_sc + i) * Q;
+  for (int s = 0; s < D; ++s) demk::demod_point<Q>(xs[16 * u + s], v, dst + (int64_t)s * d.n_sc * Q);
+}
+
 // FU: the CSI stage fused in (the channel is the LS estimate formed from the
-// pilot symbol of yf and the pilots, bit-identical to the CSI stage's value)
-template <int KP, bool FU>
+// pilot symbol of yf and the pilots, bit-identical to the CSI stage's value).
+// DM: the demod stage fused in as well (x_tilde never written).
+template <int KP, bool FU, bool DM>
 __device__ __forceinline__ void run_detect(const BFrame& d, int tile, const float2* h, const float2* yf,
                                            const float2* pil, float2* xt, float* nu, uint8_t* flags,
-                                           float2* pool, int* nonfin) {
+                                           float* llr, float2* pool, int* nonfin) {
   const int nt = (d.n_sc + det::TS - 1) / det::TS;
   const int t0 = tile * d.det_tiles;
   const int t1 = min(t0 + d.det_tiles, nt);
+  constexpr bool dm = DM;
   float2 hv[8], yv[8], pv;
   bool have0 = false;
   for (int t = t0; t < t1; ++t) {
     if (t > t0) __syncthreads();
-    det::detect_tile<KP, det::P_FP32, FU>(FU ? nullptr : h + d.h, yf + d.yf, xt + d.xt, nu + d.nu,
+    det::detect_tile<KP, det::P_FP32, FU>(FU ? nullptr : h + d.h, yf + d.yf, dm ? nullptr : xt + d.xt, nu + d.nu,
                                           flags ? flags + d.flags : nullptr, d.M, d.K, d.n_sym, d.n_sc,
                                           d.n0, d.mmse, 0.f, nullptr, 0u, t * det::TS, pool, nonfin, hv, yv,
                                           pv, have0, t + 1 < t1 ? (t + 1) * det::TS : -1, nullptr, nullptr,
-                                          FU ? pil + d.pil : nullptr);
+                                          FU ? pil + d.pil : nullptr, nullptr, dm);
+    if constexpr (DM) {
+      __syncthreads();                              // every wave's slab written
+      switch (d.qam_bits) {
+        case 2: demod_tile<2>(d, t * det::TS, pool, llr); break;
+        case 4: demod_tile<4>(d, t * det::TS, pool, llr); break;
+        default: demod_tile<6>(d, t * det::TS, pool, llr); break;
+      }
+    }
   }
 }
 
@@ -188,10 +214,10 @@ __device__ __forceinline__ void publish(Pending& pd, uint32_t* __restrict__ ctl)
   __syncthreads();
 }
 
-// FUSE: the plan forms the channel estimate inside the detector items (one
-// instantiation per dataflow, so that each carries only its own detector
-// bodies and their register needs).
-template <bool FUSE>
+// FUSE: the plan forms the channel estimate inside the detector items; DM:
+// the detector items demap their tiles (one instantiation per dataflow, so
+// that each carries only its own detector bodies and their register needs).
+template <bool FUSE, bool DM>
 __global__ void __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(3)))
 batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
   __shared__ float2 pool[POOL];
@@ -269,21 +295,24 @@ batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
         float2* xt = (float2*)hp->xt;
         float* nu = (float*)hp->nu;
         uint8_t* flags = (uint8_t*)hp->flags;
+        float* llr = (float*)hp->llr;
         switch (d.kp) {
-          case 4: run_detect<4, FUSE>(d, tile, h, yf, pil, xt, nu, flags, pool, nonfin); break;
-          case 8: run_detect<8, FUSE>(d, tile, h, yf, pil, xt, nu, flags, pool, nonfin); break;
-          default: run_detect<16, FUSE>(d, tile, h, yf, pil, xt, nu, flags, pool, nonfin); break;
+          case 4: run_detect<4, FUSE, DM>(d, tile, h, yf, pil, xt, nu, flags, llr, pool, nonfin); break;
+          case 8: run_detect<8, FUSE, DM>(d, tile, h, yf, pil, xt, nu, flags, llr, pool, nonfin); break;
+          default: run_detect<16, FUSE, DM>(d, tile, h, yf, pil, xt, nu, flags, llr, pool, nonfin); break;
         }
         break;
       }
       default: {
-        const float2* xt = (const float2*)hp->xt;
-        const float* nu = (const float*)hp->nu;
-        float* llr = (float*)hp->llr;
-        switch (d.qam_bits) {
-          case 2: run_demod<2>(d, tile, xt, nu, llr); break;
-          case 4: run_demod<4>(d, tile, xt, nu, llr); break;
-          default: run_demod<6>(d, tile, xt, nu, llr); break;
+        if constexpr (!DM) {                       // a plan that demaps in the detector has no demod items
+          const float2* xt = (const float2*)hp->xt;
+          const float* nu = (const float*)hp->nu;
+          float* llr = (float*)hp->llr;
+          switch (d.qam_bits) {
+            case 2: run_demod<2>(d, tile, xt, nu, llr); break;
+            case 4: run_demod<4>(d, tile, xt, nu, llr); break;
+            default: run_demod<6>(d, tile, xt, nu, llr); break;
+          }
         }
         break;
       }
@@ -310,6 +339,12 @@ batch_kernel(const Header* __restrict__ hdr, uint32_t* __restrict__ ctl) {
 
 int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
+// The persistent kernel of a plan's dataflow.
+const void* plan_kernel(int fuse_csi, int fuse_demod) {
+  if (fuse_csi) return fuse_demod ? (const void*)batch_kernel<true, true> : (const void*)batch_kernel<true, false>;
+  return fuse_demod ? (const void*)batch_kernel<false, true> : (const void*)batch_kernel<false, false>;
+}
+
 int fft_tpw(int n) { return n <= 2048 ? WGS / (n / 8) : 1; }
 
 }  // namespace
@@ -327,7 +362,7 @@ struct rxphy_plan {
   uint32_t n_items = 0;
   int32_t grid = 0;
   uint32_t spin_limit = 0;
-  int fuse_csi = 0;
+  int fuse_csi = 0, fuse_demod = 0;
   int n_ctl = 0;
   BFrame* d_desc = nullptr;
   uint32_t* d_items = nullptr;
@@ -357,7 +392,8 @@ rxphy_status check_batch(const rxphy_plan* p, const rxphy_batch* b) {
   rxphy_status st;
   if ((st = check_ptr(b->x, "x")) || (st = check_ptr(b->pilots, "pilots")) ||
       (st = check_ptr(b->yf, "yf")) || (!p->fuse_csi && (st = check_ptr(b->h, "h"))) ||
-      (st = check_ptr(b->xt, "xt")) || (st = check_ptr(b->nu, "nu")) || (st = check_ptr(b->llr, "llr")))
+      (!p->fuse_demod && (st = check_ptr(b->xt, "xt"))) || (st = check_ptr(b->nu, "nu")) ||
+      (st = check_ptr(b->llr, "llr")))
     return st;
   return RXPHY_OK;
 }
@@ -417,18 +453,21 @@ rxphy_status rxphy_plan_create(const rxphy_frame* frames, int32_t n_frames, cons
   *plan = nullptr;
   if (!frames) return fail(RXPHY_EINVAL, "frames is NULL");
   if (n_frames < 1 || n_frames > 16384) return fail(RXPHY_EINVAL, "n_frames = %d outside [1, 16384]", n_frames);
-  rxphy_plan_options opt{0, 0, 0u, 0};
+  rxphy_plan_options opt{0, 0, 0u, 0, 0};
   if (options) opt = *options;
   int stages = opt.stages == 0 ? RXPHY_STAGE_ALL : opt.stages;
   if (stages & ~RXPHY_STAGE_ALL) return fail(RXPHY_EINVAL, "stages = %d", opt.stages);
   if (opt.fuse_csi != 0 && opt.fuse_csi != 1) return fail(RXPHY_EINVAL, "fuse_csi = %d", opt.fuse_csi);
+  if (opt.fuse_demod != 0 && opt.fuse_demod != 1) return fail(RXPHY_EINVAL, "fuse_demod = %d", opt.fuse_demod);
   if (opt.fuse_csi) stages &= ~RXPHY_STAGE_CSI;        // the detector items form the estimate
+  if (opt.fuse_demod) stages &= ~RXPHY_STAGE_DEMOD;    // ... and demap their tiles
   if (opt.grid < 0) return fail(RXPHY_EINVAL, "grid = %d < 0", opt.grid);
 
   rxphy_plan* p = new rxphy_plan();
   p->n_frames = n_frames;
   p->spin_limit = opt.spin_limit ? opt.spin_limit : (1u << 22);
   p->fuse_csi = opt.fuse_csi;
+  p->fuse_demod = opt.fuse_demod;
   p->desc.resize(n_frames);
   p->offs.resize(n_frames);
   std::vector<uint32_t> items[4];
@@ -531,7 +570,7 @@ rxphy_status rxphy_plan_create(const rxphy_frame* frames, int32_t n_frames, cons
   if (e == hipSuccess && grid == 0) {
     int per_cu = 0, cus = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, p->fuse_csi ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>, WGS, 0);
+        &per_cu, plan_kernel(p->fuse_csi, p->fuse_demod), WGS, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->dev);
     grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
@@ -571,8 +610,9 @@ rxphy_status rxphy_plan_forward(rxphy_plan* plan, const rxphy_batch* buffers, hi
                      a.n_ctl, a.x, a.pil, a.yf, a.h, a.xt, a.nu, a.flags, a.llr);
   if ((st = launch_status("plan reset kernel"))) return st;
   if (plan->n_items == 0) return RXPHY_OK;
-  if (plan->fuse_csi) hipLaunchKernelGGL(batch_kernel<true>, dim3(plan->grid), dim3(WGS), 0, stream, a.hdr, a.ctl);
-  else hipLaunchKernelGGL(batch_kernel<false>, dim3(plan->grid), dim3(WGS), 0, stream, a.hdr, a.ctl);
+  const hipError_t e = hipLaunchKernel(plan_kernel(plan->fuse_csi, plan->fuse_demod), dim3(plan->grid), dim3(WGS),
+                                       a.batch_args(), 0, stream);
+  if (e != hipSuccess) return fail(RXPHY_EHIP, "batch kernel: %s", hipGetErrorString(e));
   return launch_status("batch kernel");
 }
 
@@ -591,7 +631,7 @@ rxphy_status rxphy_plan_graph(rxphy_plan* plan, const rxphy_batch* buffers) {
   rp.kernelParams = a.reset_args();
   rp.extra = nullptr;
   hipKernelNodeParams bp{};
-  bp.func = plan->fuse_csi ? (void*)batch_kernel<true> : (void*)batch_kernel<false>;
+  bp.func = (void*)plan_kernel(plan->fuse_csi, plan->fuse_demod);
   bp.gridDim = dim3(plan->grid);
   bp.blockDim = dim3(WGS);
   bp.sharedMemBytes = 0;

@@ -617,6 +617,13 @@ constexpr int RL_OFF = 64;
 // set; if i0n >= 0 they carry chunk 0 of the tile at i0n out (of the frame at
 // Hn/Yn, default this one), with have0 set, so that its loads fly during this
 // tile's phase 2.  The caller synchronises before reusing smem.
+// xl: x_tilde is not written to xt but left in LDS for the caller (the
+// batched kernel's fused demapping), in the slab of each lane's subcarrier:
+// tile subcarrier e = 4 w + scl at smem + e * PMAT, x_tilde[u][s] at
+// [16 u + s] and nu[u] at [256 + u].x (the values the global outputs would
+// hold; nu is written to its output as well).  The caller reads them after a
+// barrier, before smem is reused.
+static_assert(PMAT >= 256 + 16, "slab too small for a subcarrier's x_tilde and nu");
 template <int KP, int P, bool FU = false>
 __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const float2* __restrict__ Yf,
                                             float2* __restrict__ xt, float* __restrict__ nu,
@@ -625,7 +632,8 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
                                             uint32_t sub_base, int i0, float2* smem, int* nonfin,
                                             float2* hv, float2* yv, float2& pv, bool& have0, int i0n,
                                             const float2* Hn = nullptr, const float2* Yn = nullptr,
-                                            const float2* pil = nullptr, const float2* pn = nullptr) {
+                                            const float2* pil = nullptr, const float2* pn = nullptr,
+                                            bool xl = false) {
   const int D = S - 1;
   const int tid = tid_x(), w = tid >> 6, l = tid & 63;
   SharedFactor* sf = reinterpret_cast<SharedFactor*>(smem + SMEM);
@@ -716,7 +724,8 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
       if (uu < K) {
         float2 x = z[uu];
         if (erase) x = make_float2(0.f, 0.f);
-        xt[((int64_t)uu * D + row) * n_sc + i] = x;
+        if (xl) Pm[16 * uu + row] = x;             // this wave's solves are done with Pm
+        else xt[((int64_t)uu * D + row) * n_sc + i] = x;
       }
     }
   }
@@ -730,6 +739,7 @@ __device__ __forceinline__ void detect_tile(const float2* __restrict__ H, const 
       nv = n0 * dl;
     }
     nu[(int64_t)row * n_sc + i] = erase ? INFINITY : nv;
+    if (xl) Pm[256 + row] = make_float2(erase ? INFINITY : nv, 0.f);
   }
   if (row == 0 && flags) flags[i] = nf ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
 }

@@ -197,7 +197,8 @@ class Tiles(ctypes.Structure):
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("stages", ctypes.c_int32), ("grid", ctypes.c_int32), ("spin_limit", ctypes.c_uint32)]
+    _fields_ = [("stages", ctypes.c_int32), ("grid", ctypes.c_int32), ("spin_limit", ctypes.c_uint32),
+                ("fuse_csi", ctypes.c_int32), ("fuse_demod", ctypes.c_int32)]
 
 
 def _plan_create(lib, frames, tiles=None, opts=None):
@@ -213,6 +214,7 @@ def _plan_create(lib, frames, tiles=None, opts=None):
 @pytest.mark.parametrize("case,code", [
     ("no frames", 1), ("bad frame", 1), ("unsupported frame", 2), ("negative tile", 1),
     ("kp below K", 1), ("kp not a size", 1), ("bad stage mask", 1), ("negative grid", 1),
+    ("bad fuse_csi", 1), ("bad fuse_demod", 1),
 ])
 def test_plan_create_rejects_before_touching_the_device(lib, case, code):
     fr = [frame(), frame(M=8, K=2, n_fft=512, n_sc=300, qam_bits=2)]
@@ -233,6 +235,10 @@ def test_plan_create_rejects_before_touching_the_device(lib, case, code):
         opts = PlanOptions(16, 0, 0)
     elif case == "negative grid":
         opts = PlanOptions(0, -1, 0)
+    elif case == "bad fuse_csi":
+        opts = PlanOptions(0, 0, 0, 2, 0)
+    elif case == "bad fuse_demod":
+        opts = PlanOptions(0, 0, 0, 0, 2)
     st, h = _plan_create(lib, fr, tiles, opts)
     assert st == code, (case, st)
     assert h.value is None                              # *plan cleared on failure

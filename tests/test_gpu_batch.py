@@ -101,10 +101,12 @@ def test_batch_tile_sizes_do_not_change_results(rx, batch, refs, tiles):
 
 
 def assert_fused_frames_equal(plan, bufs, refs, frames_idx=None):
-    """A plan that forms the channel estimate inside the detector items: every
-    output but H equals the single-frame (staged) calls bit for bit."""
+    """A plan that forms the channel estimate (and / or demaps) inside the
+    detector items: every output it writes (all but H, and x_tilde when the
+    demod is fused) equals the single-frame (staged) calls bit for bit."""
+    keys = [k for k in ("yf", "xt", "nu", "flags", "llr") if not (k == "xt" and plan.fuse_demod)]
     for f in (frames_idx if frames_idx is not None else range(len(plan.frames))):
-        for k in ("yf", "xt", "nu", "flags", "llr"):
+        for k in keys:
             got, ref = plan.view(bufs, k, f), refs[f][k]
             same = torch.equal(torch.view_as_real(got), torch.view_as_real(ref)) if got.is_complex() else \
                 torch.equal(got, ref)
@@ -148,6 +150,26 @@ def test_batch_fused_csi_equals_staged_and_single_frame_fused_calls(rx, batch, r
             assert torch.equal(nu[0], plan.view(bufs, "nu", f)) and torch.equal(fl[0], plan.view(bufs, "flags", f))
 
 
+@pytest.mark.parametrize("fuse_csi", [True, False])
+@pytest.mark.parametrize("tiles", [None, dict(fft_iters=1, det_tiles=1), dict(fft_iters=13, det_tiles=5)])
+def test_batch_fused_demod_equals_staged(rx, batch, refs, fuse_csi, tiles):
+    """fuse_demod: no demod items; each detector item demaps its tiles from
+    x_tilde and nu held in LDS, which is never written to memory (its buffer
+    is a one-byte placeholder); LLRs, nu and flags equal the staged calls bit
+    for bit, with and without the CSI stage fused in, for several item sizes
+    (tiles of several detector tiles per item reuse the LDS between tiles)."""
+    frames, inputs = batch
+    plan = rx.Plan(frames, tiles=rx.Tiles(**tiles) if tiles else None, fuse_csi=fuse_csi, fuse_demod=True)
+    say("fused demod", "csi fused" if fuse_csi else "csi items", tiles, "items", plan.counts)
+    assert plan.counts[3] == 0 and (plan.counts[1] == 0) == fuse_csi
+    bufs = pack(rx, plan, inputs)
+    assert bufs["xt"].numel() == 1
+    plan.forward(bufs)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    assert_fused_frames_equal(plan, bufs, refs)
+
+
 def test_batch_wider_k_padding_within_tolerance(rx, batch, refs):
     frames, inputs = batch
     plan = rx.Plan(frames, tiles=rx.Tiles(det_kp=16))
@@ -187,10 +209,10 @@ def test_batch_stage_masks_compose(rx, batch, refs):
     assert_frames_equal(p2, bufs, refs)
 
 
-@pytest.mark.parametrize("fuse", [False, True])
+@pytest.mark.parametrize("fuse", [False, True, "full"])
 def test_batch_graph_replays_match_eager(rx, batch, refs, fuse):
     frames, inputs = batch
-    plan = rx.Plan(frames, fuse_csi=fuse)
+    plan = rx.Plan(frames, fuse_csi=bool(fuse), fuse_demod=fuse == "full")
     bufs = pack(rx, plan, inputs)
     plan.graph(bufs)
     for rep in range(3):
@@ -231,14 +253,15 @@ def test_batch_matches_oracle(rx, batch):
         assert rel_rms(plan.view(bufs, "yf", f).cpu().numpy(), ref["yf"]) < 1e-5
 
 
-@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("fuse", ["full", True, False])
 def test_batch_uneven_256_frames_full_size(rx, fuse):
-    """The 256-frame uneven workload in the launch configuration the benchmark
-    times (the channel estimate formed inside the detector items), and the
-    staged dataflow; sampled frames are compared with the single-frame path."""
+    """The 256-frame uneven workload in the launch configurations the
+    benchmark times (the channel estimate formed and the tiles demapped inside
+    the detector items; the estimate alone; the staged dataflow); sampled
+    frames are compared with the single-frame path."""
     shapes = synth.draw_batch_shapes(256)
     frames = [rx.Frame.of(s, O.MMSE, 1.0) for s in shapes]
-    plan = rx.Plan(frames, fuse_csi=fuse)
+    plan = rx.Plan(frames, fuse_csi=bool(fuse), fuse_demod=fuse == "full")
     say("256 frames, items", plan.counts, "grid", plan.grid,
         "x GB", round(plan.totals["x"] / 1e9, 3))
     bufs = plan.alloc()
@@ -260,7 +283,7 @@ def test_batch_uneven_256_frames_full_size(rx, fuse):
         p = plan.view(bufs, "pilots", f)[None].contiguous()
         ref = rx.forward(fr, x, p)
         for k in OUTS:
-            if fuse and k == "h":
+            if (fuse and k == "h") or (fuse == "full" and k == "xt"):
                 continue
             a, b = plan.view(bufs, k, f), ref[k][0]
             if a.is_complex():
@@ -278,7 +301,7 @@ def test_autotuned_tiles_keep_results_bitwise(rx, batch, refs, tmp_path):
     t.save()
     t2 = Tuner(str(tmp_path / "tiles.json"))
     assert t2.tune(frames)["classes_tuned"] == 0          # everything cached
-    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), fuse_csi=True)
+    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), fuse_csi=True, fuse_demod=True)
     bufs = pack(rx, plan, inputs)
     plan.forward(bufs)
     torch.cuda.synchronize()
@@ -288,7 +311,8 @@ def test_autotuned_tiles_keep_results_bitwise(rx, batch, refs, tmp_path):
     bufs = pack(rx, rx.Plan(frames), inputs)              # with an H buffer: staged candidates run too
     pick = t2.tune_plan(frames, bufs, reps=2)
     say("plan knobs", pick)
-    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"])
+    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"],
+                   fuse_demod=pick["fuse_demod"])
     bufs = pack(rx, plan, inputs)
     plan.forward(bufs)
     torch.cuda.synchronize()
