@@ -438,8 +438,10 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
   row_op<false, false>(A, B, hb, inm);             // opening 1x3 along frequency (leaves a 3x3 opening unchanged)
   row_op<true, false>(B, A, hb, inm);
   // The tile's components from its row runs: a run's first pixel stands for
-  // it; lane r (one wave) unites each run of core row r with every run of row
-  // r - 1 it overlaps, found with bit operations on the row masks.
+  // it; thread (row r, quarter q) unites each run of core row r that starts
+  // in columns 16 q .. 16 q + 15 with every run of row r - 1 it overlaps,
+  // found with bit operations on the row masks (the four waves take the four
+  // quarters, so every run is handled by exactly one thread).
   if (threadIdx.x < 64) {
     const int r = threadIdx.x;
     const Row x = (*A)[r + 4];
@@ -448,21 +450,22 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
   for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) loc[idx] = -1;
   __syncthreads();
   volatile int* vl = loc;
-  if (threadIdx.x < 64) {
-    const int r = threadIdx.x;
-    uint64_t st = crow[r] & ~(crow[r] << 1);     // run starts
+  const int rr = threadIdx.x & 63;                 // this thread's core row
+  const uint64_t quarter = 0xffffull << (16 * (threadIdx.x >> 6));
+  {
+    uint64_t st = crow[rr] & ~(crow[rr] << 1) & quarter;     // run starts
     while (st) {
       const int c = __builtin_ctzll(st);
       st &= st - 1;
-      vl[r * 64 + c] = r * 64 + c;
+      vl[rr * 64 + c] = rr * 64 + c;
     }
   }
   __syncthreads();
-  if (threadIdx.x > 0 && threadIdx.x < 64) {
-    const int r = threadIdx.x;
+  if (rr > 0) {
+    const int r = rr;
     const uint64_t row = crow[r], prow = crow[r - 1];
     const uint64_t pst = prow & ~(prow << 1);
-    uint64_t st = row & ~(row << 1);
+    uint64_t st = row & ~(row << 1) & quarter;
     while (st) {
       const int c0 = __builtin_ctzll(st);
       st &= st - 1;
@@ -493,9 +496,9 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
     bb[i][3] = -1;
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const int r = threadIdx.x;
-    uint64_t st = crow[r] & ~(crow[r] << 1);
+  {
+    const int r = rr;
+    uint64_t st = crow[r] & ~(crow[r] << 1) & quarter;
     while (st) {
       const int c = __builtin_ctzll(st);
       st &= st - 1;
@@ -508,10 +511,10 @@ morph_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ out, int32_
     }
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const int r = threadIdx.x;
+  {
+    const int r = rr;
     const uint64_t row = crow[r];
-    uint64_t st = row & ~(row << 1);
+    uint64_t st = row & ~(row << 1) & quarter;
     while (st) {
       const int c0 = __builtin_ctzll(st);
       st &= st - 1;
