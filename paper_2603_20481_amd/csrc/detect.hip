@@ -100,23 +100,40 @@ refine_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
     const int f = (int)(sub / (uint32_t)n_sc), i = (int)(sub - (uint32_t)f * n_sc);
     if (tid == 0) nfin = 0;
     __syncthreads();
-    for (int q = tid; q < M * K; q += 64) {
-      const int m = q / K, u = q - m * K;
-      float2 hval;
-      if (pil) {                                  // fused CSI: the LS estimate, as the CSI stage forms it
-        const int G = n_sc / K, q = min(i / K, G - 1) * K + u;
-        hval = ls_estimate(Yf[((int64_t)(f * M + m) * S) * n_sc + q], pil[(int64_t)f * n_sc + q]);
-      } else {
-        hval = H[((int64_t)(f * M + m) * K + u) * n_sc + i];
+    // every lane's loads issued before the first is used: 16 channel and 16
+    // data values at most per lane (M K <= 1024, M D <= 1024)
+    {
+      float2 hv[16], yv[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int q = tid + 64 * t;
+        hv[t] = yv[t] = make_float2(0.f, 0.f);
+        if (q < M * K) {
+          const int m = q / K, u = q - m * K;
+          if (pil) {                              // fused CSI: the LS estimate, as the CSI stage forms it
+            const int G = n_sc / K, qq = min(i / K, G - 1) * K + u;
+            hv[t] = ls_estimate(Yf[((int64_t)(f * M + m) * S) * n_sc + qq], pil[(int64_t)f * n_sc + qq]);
+          } else {
+            hv[t] = H[((int64_t)(f * M + m) * K + u) * n_sc + i];
+          }
+        }
+        if (q < M * D) {
+          const int m = q / D, s = q - m * D;
+          yv[t] = Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i];
+        }
       }
-      if (!(isfinite(hval.x) && isfinite(hval.y))) nfin = 1;
-      Hs[m * 16 + u] = d2(hval);
-    }
-    for (int q = tid; q < M * D; q += 64) {
-      const int m = q / D, s = q - m * D;
-      const float2 yv = Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i];
-      if (!(isfinite(yv.x) && isfinite(yv.y))) nfin = 1;
-      Ys[m * 16 + s] = d2(yv);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int q = tid + 64 * t;
+        if (q < M * K) {
+          if (!(isfinite(hv[t].x) && isfinite(hv[t].y))) nfin = 1;
+          Hs[(q / K) * 16 + (q - (q / K) * K)] = d2(hv[t]);
+        }
+        if (q < M * D) {
+          if (!(isfinite(yv[t].x) && isfinite(yv[t].y))) nfin = 1;
+          Ys[(q / D) * 16 + (q - (q / D) * D)] = d2(yv[t]);
+        }
+      }
     }
     for (int q = tid; q < K * D; q += 64) {     // x0; a non-finite start becomes 0
       const int u = q / D, s = q - u * D;
