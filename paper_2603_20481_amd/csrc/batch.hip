@@ -97,8 +97,10 @@ __device__ __forceinline__ void demod_tile(const BFrame& d, int i0, const float2
   if (u >= d.K || i >= d.n_sc) return;
   const float2* xs = pool + e * det::PMAT;        // the slab of tile subcarrier e
   const float v = xs[256 + u].x;
+  const bool er = __builtin_isinf(v);
+  const float inv = er ? 0.f : 1.0f / v;
   float* dst = llr + d.llr + ((int64_t)u * D * d.n_sc + i) * Q;
-  for (int s = 0; s < D; ++s) demk::demod_point<Q>(xs[16 * u + s], v, dst + (int64_t)s * d.n_sc * Q);
+  for (int s = 0; s < D; ++s) demk::demod_point_inv<Q>(xs[16 * u + s], er, inv, dst + (int64_t)s * d.n_sc * Q);
 }
 
 // FU: the CSI stage fused in (the channel is the LS estimate formed from the

@@ -432,6 +432,7 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
                     int mmse) {
   __shared__ float2 hs[64 * 16];                // H of the tile: [antenna][user]
   __shared__ uint32_t nfmask[GWAVES];           // subcarriers with a non-finite data value
+  __shared__ float4v utab[16];                  // per user: 1 / mu (MMSE), nu, 1 / nu
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar branches
   const int u = l & 15, kq = l >> 4;
@@ -496,6 +497,17 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     const int m = 16 * w + 4 * a + kq;
     hs[m * 16 + u] = m < M ? ls_estimate(hv[a], pv) : make_float2(0.f, 0.f);
   }
+  // every user's MMSE gain and noise variance, the same for all 16 subcarriers
+  // (one factor per tile): formed once here, as the demod stage forms 1 / nu
+  // from the stored nu
+  if (w == 0 && u == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float dk = dl4[r];
+      const float nv = mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
+      utab[4 * kq + r] = float4v{__builtin_amdgcn_rcpf(1.0f - n0 * dk), nv, 1.0f / nv, 0.f};
+    }
+  }
   __syncthreads();
 
   // ---- per-subcarrier factor state: every user's mu counts (the four rows
@@ -520,15 +532,14 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
     const int d = w + 4 * j;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      const float4v ut = utab[4 * kq + r];
       float2 x = make_float2(xr[r], xi[r]);
-      if (mmse) x = cscale(x, __builtin_amdgcn_rcpf(1.0f - n0 * dl4[r]));
+      if (mmse) x = cscale(x, ut.x);
       if (!ok) x = make_float2(0.f, 0.f);
       const int64_t e = ((int64_t)(4 * kq + r) * D + d) * n_sc + i;
       if (xo) xo[e] = x;
       if constexpr (Q > 0) {
-        const float dk = dl4[r];
-        const float v = !ok ? INFINITY : mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
-        demk::demod_point<Q, true>(x, v, lo + e * Q);
+        demk::demod_point_inv<Q, true>(x, !ok || __builtin_isinf(ut.y), ut.z, lo + e * Q);
         __builtin_amdgcn_sched_barrier(0);       // one point at a time (registers)
       }
     }
@@ -584,11 +595,7 @@ detect_group_kernel(const float2* __restrict__ Yf, const float2* __restrict__ pi
   const bool erase = nf_i || !ok;
   if (col && w == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float dk = dl4[r];
-      const float nv = mmse ? n0 * dk * __builtin_amdgcn_rcpf(1.0f - n0 * dk) : n0 * dk;
-      nu[(f * 16 + 4 * kq + r) * n_sc + i] = erase ? INFINITY : nv;
-    }
+    for (int r = 0; r < 4; ++r) nu[(f * 16 + 4 * kq + r) * n_sc + i] = erase ? INFINITY : utab[4 * kq + r].y;
     if (kq == 0 && flags) flags[f * n_sc + i] = nf_i ? RXPHY_FLAG_NONFINITE : (ok ? 0 : RXPHY_FLAG_BREAKDOWN);
   }
 }
