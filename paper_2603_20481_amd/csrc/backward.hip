@@ -355,6 +355,60 @@ csi_adjoint_kernel(const float2* __restrict__ gh, const float2* __restrict__ pil
   gyf[((int64_t)(f * M + m) * S) * n_sc + q] = out;
 }
 
+// Sum over each aligned group of 2^LK lanes, returned in every lane of the
+// group: an xor butterfly on DPP (quad permutations [1,0,3,2] and [2,3,0,1],
+// then the half-row and row mirrors, which pair each 4- / 8-lane block with
+// the other one of its 8- / 16-lane group).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int LK>
+__device__ __forceinline__ float seg_sum(float v) {
+  if constexpr (LK >= 1) v += dpp_f<0xB1>(v);
+  if constexpr (LK >= 2) v += dpp_f<0x4E>(v);
+  if constexpr (LK >= 3) v += dpp_f<0x141>(v);
+  if constexpr (LK >= 4) v += dpp_f<0x140>(v);
+  return v;
+}
+
+// The CSI adjoint for K = 2^LK users: the pilot groups are aligned blocks of
+// K lanes (a workgroup's 256 subcarriers hold whole groups), so thread i
+// reads subcarrier i of every user's row (each load a contiguous 512-byte
+// wavefront segment), the group sums come from the butterfly, and lane
+// i = g K + u keeps user u's; the last group also takes the subcarriers past
+// G K, as csi_adjoint_kernel does.
+template <int LK>
+__global__ void __launch_bounds__(256)
+csi_adjoint_pow2_kernel(const float2* __restrict__ gh, const float2* __restrict__ pil,
+                        float2* __restrict__ gyf, int M, int S, int n_sc) {
+  constexpr int K = 1 << LK;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int m = blockIdx.y, f = blockIdx.z;
+  const int G = n_sc / K;
+  const int u_me = i & (K - 1);
+  const float2* rows = gh + (int64_t)(f * M + m) * K * n_sc;
+  float2 v[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) v[u] = i < n_sc ? rows[(int64_t)u * n_sc + i] : make_float2(0.f, 0.f);
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const float2 g = make_float2(seg_sum<LK>(v[u].x), seg_sum<LK>(v[u].y));
+    if (u == u_me) acc = g;
+  }
+  if (i >= n_sc) return;
+  float2 out = make_float2(0.f, 0.f);
+  if (i < G * K) {
+    if (i >= (G - 1) * K)
+      for (int j = G * K; j < n_sc; ++j) acc = cadd(acc, rows[(int64_t)u_me * n_sc + j]);
+    const float2 p = pil[(int64_t)f * n_sc + i];
+    const float pp = p.x * p.x + p.y * p.y;
+    if (pp > 0.f) out = cmul(acc, make_float2(p.x / pp, p.y / pp));
+  }
+  gyf[((int64_t)(f * M + m) * S) * n_sc + i] = out;
+}
+
 constexpr size_t ALIGN = 256;
 inline size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -475,8 +529,15 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
   if ((st = launch_status("detect adjoint apply kernel"))) return st;
 
   dim3 g3((fr.n_sc + 255) / 256, fr.M, n_frames);
-  hipLaunchKernelGGL(csi_adjoint_kernel, g3, dim3(256), 0, stream, gh, (const float2*)pilots, gyf,
-                     fr.M, fr.K, fr.n_sym, fr.n_sc);
+  const float2* pl = (const float2*)pilots;
+  switch (fr.K) {
+    case 1: hipLaunchKernelGGL(csi_adjoint_pow2_kernel<0>, g3, dim3(256), 0, stream, gh, pl, gyf, fr.M, fr.n_sym, fr.n_sc); break;
+    case 2: hipLaunchKernelGGL(csi_adjoint_pow2_kernel<1>, g3, dim3(256), 0, stream, gh, pl, gyf, fr.M, fr.n_sym, fr.n_sc); break;
+    case 4: hipLaunchKernelGGL(csi_adjoint_pow2_kernel<2>, g3, dim3(256), 0, stream, gh, pl, gyf, fr.M, fr.n_sym, fr.n_sc); break;
+    case 8: hipLaunchKernelGGL(csi_adjoint_pow2_kernel<3>, g3, dim3(256), 0, stream, gh, pl, gyf, fr.M, fr.n_sym, fr.n_sc); break;
+    case 16: hipLaunchKernelGGL(csi_adjoint_pow2_kernel<4>, g3, dim3(256), 0, stream, gh, pl, gyf, fr.M, fr.n_sym, fr.n_sc); break;
+    default: hipLaunchKernelGGL(csi_adjoint_kernel, g3, dim3(256), 0, stream, gh, pl, gyf, fr.M, fr.K, fr.n_sym, fr.n_sc);
+  }
   if ((st = launch_status("csi adjoint kernel"))) return st;
   return launch_fft(fr, n_tr, gyf, (float2*)dx, true, stream);
 }

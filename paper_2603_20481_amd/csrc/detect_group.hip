@@ -51,6 +51,7 @@ namespace {
 using namespace det;
 
 constexpr int GWAVES = 4;     // waves per workgroup
+constexpr int FTPW = 2;       // tiles per wavefront of the factor kernel
 typedef float float4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -736,7 +737,7 @@ rxphy_status launch_precode(const rxphy_frame& fr, int32_t nf, const float2* yf,
   const int64_t T = (int64_t)nf * nt;
   GroupRec* rec = (GroupRec*)ws;
   if (!reuse) {                                  // else: the uplink's records for these frames are in ws
-    hipLaunchKernelGGL((group_factor_kernel<2, P_FP32>), dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))),
+    hipLaunchKernelGGL((group_factor_kernel<FTPW, P_FP32>), dim3((unsigned)((T + FTPW * GWAVES - 1) / (FTPW * GWAVES))),
                        dim3(256), 0, s, yf, pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0,
                        fr.detector == RXPHY_MMSE ? 1 : 0, 0.f, (uint32_t*)nullptr);
     rxphy_status st = launch_status("group factor kernel");
@@ -771,7 +772,7 @@ rxphy_status launch_group_p(const rxphy_frame& fr, int32_t nf, const float2* yf,
   const int nt = (fr.n_sc + 15) / 16;
   const int64_t T = (int64_t)nf * nt;
   const int mmse = fr.detector == RXPHY_MMSE ? 1 : 0;
-  hipLaunchKernelGGL((group_factor_kernel<2, P>), dim3((unsigned)((T + 2 * GWAVES - 1) / (2 * GWAVES))), dim3(256),
+  hipLaunchKernelGGL((group_factor_kernel<FTPW, P>), dim3((unsigned)((T + FTPW * GWAVES - 1) / (FTPW * GWAVES))), dim3(256),
                      0, s, yf, pil, rec, (int)T, nt, fr.M, fr.n_sym, fr.n_sc, fr.n0, mmse, thr, rl);
   rxphy_status st = launch_status("group factor kernel");
   if (st) return st;

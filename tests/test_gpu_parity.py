@@ -205,6 +205,56 @@ def test_demod_stage(rx, q):
         assert mism == 0
 
 
+@pytest.mark.parametrize("q", [2, 4, 6])
+def test_demod_midpoints_and_large_values(rx, q):
+    """The nearest levels are found in closed form, not by a search: the LLRs
+    at and next to every decision midpoint (even multiples of the level unit)
+    and at large |x_tilde| still follow the definition within the FP32 bound
+    of test_demod_stage, and at huge |x_tilde|, where squared distances would
+    overflow FP32, they stay finite, carry the sign of the nearest outer
+    level and double when x_tilde doubles (the max-log LLR is affine there)."""
+    c = {2: 1 / math.sqrt(2), 4: 1 / math.sqrt(10), 6: 1 / math.sqrt(42)}[q]
+    lmax = {2: 1, 4: 3, 6: 7}[q] * c
+    mids = np.array([k * c for k in range(-8, 9, 2)], dtype=np.float32)
+    near = np.concatenate([mids, np.nextafter(mids, np.float32(np.inf)), np.nextafter(mids, np.float32(-np.inf))])
+    big = np.array([10.0, -37.5, 1e3, -1e3, 2.5e5, -1e6], dtype=np.float32)
+    axis = np.concatenate([near, big]).astype(np.float32)
+    n_ax = axis.size
+    re, im = np.meshgrid(axis, axis[::-1], indexing="ij")
+    n_sc = n_ax * n_ax
+    xt = (re + 1j * im).astype(np.complex64).reshape(1, 1, 1, n_sc)
+    nu = np.full((1, 1, n_sc), 0.37, dtype=np.float32)
+    fr = rx.Frame(8, 1, 4096, n_sc, 2, 0, q)
+    llr = host(rx.demod(fr, dev(xt), dev(nu)))[0]
+    ref = O.demod_stage(xt[0], nu[0], q)
+    u = 2.0 ** -24
+    ax = np.stack([(xt[0].real if j % 2 == 0 else xt[0].imag) for j in range(q)], axis=-1).astype(np.float64)
+    # plus the oracle's own rounding: it differences complex squared
+    # distances in FP64, in which the other axis' term (up to (1e6)^2 here)
+    # cancels only to a few units of 2^-53 of its size
+    both = (np.abs(xt[0].real) + np.abs(xt[0].imag) + 2 * lmax)[..., None].astype(np.float64)
+    bound = 8 * u * (np.abs(ax) + lmax) ** 2 / 0.37 + 2 * u * np.abs(ref) + 8 * 2.0 ** -53 * both ** 2 / 0.37
+    worst = float(np.max(np.abs(llr - ref) / bound))
+    say("demod midpoints / large", q, "max error / FP32 bound", worst)
+    assert worst <= 1.0
+
+    huge = np.array([1e15, -3e20, 7e25, -1e30], dtype=np.float32)
+    hc = (huge + 1j * huge[::-1]).astype(np.complex64)
+    x2 = np.concatenate([hc, 2 * hc]).astype(np.complex64)
+    xt2 = x2.reshape(1, 1, 1, -1)
+    nu2 = np.full((1, 1, x2.size), 0.37, dtype=np.float32)
+    fr2 = rx.Frame(8, 1, 512, x2.size, 2, 0, q)
+    l2 = host(rx.demod(fr2, dev(xt2), dev(nu2)))[0, 0, 0]           # [n, q]
+    assert np.all(np.isfinite(l2))
+    n = huge.size
+    assert np.array_equal(l2[n:], 2 * l2[:n])                        # affine with no offset at this scale
+    sgn = np.sign(np.stack([x2.real, x2.imag], axis=-1))             # in-phase, quadrature coordinate
+    assert np.array_equal(np.sign(l2[:, 0]), sgn[:, 0])             # sign bits: positive axis -> b = 0
+    assert np.array_equal(np.sign(l2[:, 1]), sgn[:, 1])
+    if q > 2:                                                        # inner bits of the outer level are ones
+        assert np.all(l2[:, 2:] < 0)
+
+
 # ------------------------------------------------------------------ full chain
 CHAIN_CASES = [(1, O.ZF, 1), (2, O.ZF, 2), (2, O.MMSE, 2), (3, O.ZF, 1)]
 
