@@ -200,46 +200,84 @@ detect_adjoint_kernel(const float2* __restrict__ H, const float2* __restrict__ Y
   }
 }
 
-// C = X_hat V^H + V X_hat^H + 2 A^{-1} diag(e) A^{-1}, one thread per
-// (frame, subcarrier, i, j) entry.  A workgroup stages the X_hat, V, A^{-1}
-// and e of NS = min(64, 256 / K^2) consecutive subcarriers in LDS (they are
-// contiguous in the workspace, so the loads coalesce).  Cw: [F][n_sc][K][K].
+// C = X_hat V^H + V X_hat^H + 2 A^{-1} diag(e) A^{-1} per (frame, subcarrier)
+// entry (i, j).  A workgroup stages the X_hat, V, A^{-1} and e of c_ns(K, D)
+// consecutive subcarriers in LDS (they are contiguous in the workspace, so
+// the loads coalesce) and its threads take the ns K^2 entries in turn: up to
+// 1024 entries and 2048 X_hat / V values per workgroup, so that each one
+// moves enough bytes to keep the loads of a CU's few workgroups in flight.
+// Cw: [F][n_sc][K][K].
 constexpr int C_NS_MAX = 64;
+constexpr int C_XV = 2048;       // X_hat (and V) values staged per workgroup
+constexpr int C_ENT = 1024;      // C entries per workgroup
+inline __host__ __device__ int c_ns(int K, int D) {
+  int ns = C_NS_MAX;
+  ns = ns < C_ENT / (K * K) ? ns : C_ENT / (K * K);
+  ns = ns < C_XV / (K * D) ? ns : C_XV / (K * D);
+  return ns > 0 ? ns : 1;
+}
 __global__ void __launch_bounds__(256)
 detect_adjoint_c_kernel(const float2* __restrict__ Xw, const float2* __restrict__ Vw,
                         const float2* __restrict__ Aw, const float* __restrict__ Ew,
                         float2* __restrict__ Cw, int64_t n_sub, int K, int D) {
-  __shared__ float2 sx[2048], sv[2048], sa[256];
-  __shared__ float se[256];
+  __shared__ float2 sx[C_XV], sv[C_XV], sa[C_ENT];
+  __shared__ float se[C_ENT];
   const int KK = K * K;
-  const int NS = min(C_NS_MAX, 256 / KK);
+  const int NS = c_ns(K, D);
   const int64_t s0 = (int64_t)blockIdx.x * NS;
   const int ns = (int)min((int64_t)NS, n_sub - s0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < ns * K * D; e += 256) {
-    sx[e] = Xw[s0 * K * D + e];
-    sv[e] = Vw[s0 * K * D + e];
+  {
+    // every load of the workgroup issued before the first LDS store
+    const int nxv = ns * K * D, na = ns * KK, ne = ns * K;
+    float2 rx[C_XV / 256], rv[C_XV / 256], ra[C_ENT / 256];
+    float re[C_ENT / 256];
+#pragma unroll
+    for (int k = 0; k < C_XV / 256; ++k) {
+      const int e = tid + k * 256;
+      rx[k] = e < nxv ? Xw[s0 * K * D + e] : make_float2(0.f, 0.f);
+      rv[k] = e < nxv ? Vw[s0 * K * D + e] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < C_ENT / 256; ++k) {
+      const int e = tid + k * 256;
+      ra[k] = e < na ? Aw[s0 * KK + e] : make_float2(0.f, 0.f);
+      re[k] = e < ne ? Ew[s0 * K + e] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < C_XV / 256; ++k) {
+      const int e = tid + k * 256;
+      if (e < nxv) {
+        sx[e] = rx[k];
+        sv[e] = rv[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < C_ENT / 256; ++k) {
+      const int e = tid + k * 256;
+      if (e < na) sa[e] = ra[k];
+      if (e < ne) se[e] = re[k];
+    }
   }
-  for (int e = tid; e < ns * KK; e += 256) sa[e] = Aw[s0 * KK + e];
-  for (int e = tid; e < ns * K; e += 256) se[e] = Ew[s0 * K + e];
   __syncthreads();
-  if (tid >= ns * KK) return;
-  const int sl = tid / KK, r = tid - sl * KK;
-  const int ii = r / K, j = r - ii * K;
-  const float2* X = sx + sl * K * D;
-  const float2* V = sv + sl * K * D;
-  const float2* A = sa + sl * KK;
-  const float* E = se + sl * K;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int s = 0; s < D; ++s) {
-    acc = cms_bc(acc, X[ii * D + s], make_float2(-V[j * D + s].x, -V[j * D + s].y));  // + x[ii][s] conj(v[j][s])
-    acc = cms_bc(acc, V[ii * D + s], make_float2(-X[j * D + s].x, -X[j * D + s].y));  // + v[ii][s] conj(x[j][s])
+  for (int t = tid; t < ns * KK; t += 256) {
+    const int sl = t / KK, r = t - sl * KK;
+    const int ii = r / K, j = r - ii * K;
+    const float2* X = sx + sl * K * D;
+    const float2* V = sv + sl * K * D;
+    const float2* A = sa + sl * KK;
+    const float* E = se + sl * K;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int s = 0; s < D; ++s) {
+      acc = cms_bc(acc, X[ii * D + s], make_float2(-V[j * D + s].x, -V[j * D + s].y));  // + x[ii][s] conj(v[j][s])
+      acc = cms_bc(acc, V[ii * D + s], make_float2(-X[j * D + s].x, -X[j * D + s].y));  // + v[ii][s] conj(x[j][s])
+    }
+    for (int k = 0; k < K; ++k) {
+      const float2 a = A[k * K + ii];
+      acc = cms_ac(acc, make_float2(-a.x, -a.y), cscale(A[k * K + j], 2.f * E[k]));  // + conj(A[k][ii]) 2 e_k A[k][j]
+    }
+    Cw[(s0 + sl) * KK + r] = acc;
   }
-  for (int k = 0; k < K; ++k) {
-    const float2 a = A[k * K + ii];
-    acc = cms_ac(acc, make_float2(-a.x, -a.y), cscale(A[k * K + j], 2.f * E[k]));  // + conj(A[k][ii]) 2 e_k A[k][j]
-  }
-  Cw[(s0 + sl) * KK + r] = acc;
 }
 
 // dL/dY = H V into the data symbols of gyf, dL/dH = Y V^H - H C into gh.
@@ -513,8 +551,8 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
   dim3 g1((fr.n_sc + TS - 1) / TS, n_frames);
   dim3 g2((fr.n_sc + 15) / 16, (fr.M + 31) / 32, n_frames);
   const int64_t n_sub = (int64_t)n_frames * fr.n_sc;
-  const int c_ns = 256 / (fr.K * fr.K) < 64 ? 256 / (fr.K * fr.K) : 64;
-  const unsigned gc = (unsigned)((n_sub + c_ns - 1) / c_ns);
+  const int cns = c_ns(fr.K, D);
+  const unsigned gc = (unsigned)((n_sub + cns - 1) / cns);
 #define RXPHY_ADJ(KP)                                                                               \
   hipLaunchKernelGGL(detect_adjoint_kernel<KP>, g1, dim3(256), 0, stream, h, yf, gxt, gnu, Xw, Vw,  \
                      Aw, Ew, fr.M, fr.K, fr.n_sym, fr.n_sc, fr.n0, mmse);                          \
