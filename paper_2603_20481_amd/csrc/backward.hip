@@ -284,8 +284,13 @@ detect_adjoint_c_kernel(const float2* __restrict__ Xw, const float2* __restrict_
 // Workgroup: 16 subcarriers x 32 antennas of one frame, V and C of the 16
 // subcarriers staged in LDS; each thread takes one subcarrier and two
 // antennas (m and m + 16), so that every V and C value read from LDS serves
-// two antennas.
-template <int KP>
+// two antennas.  The staged V and C are zero past K users and D symbols (and
+// H and Y past them read as zero), so the products run over the compile-time
+// bounds KP and DP (DP = 13 for the 14-symbol slot, else 16) with no run-time
+// branch between a load and its use: the compiler's memory waits then count
+// down the loads in flight instead of draining them (and the stores) at
+// every branch join.
+template <int KP, int DP>
 __global__ void __launch_bounds__(256)
 detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restrict__ Yf,
                             const float2* __restrict__ Vw, const float2* __restrict__ Cw,
@@ -293,7 +298,7 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
                             int S, int n_sc) {
   // per-subcarrier pitches padded by one float2: the 16 subcarrier lanes of a
   // wave then read 16 different bank pairs
-  constexpr int VP = KP * 16 + 1, CP = KP * KP + 1;
+  constexpr int VP = KP * DP + 1, CP = KP * KP + 1;
   __shared__ float2 sv[16 * VP];
   __shared__ float2 sc[16 * CP];
   const int D = S - 1;
@@ -301,21 +306,23 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
   const int i0 = blockIdx.x * 16, m0 = blockIdx.y * 32;
   const int il = threadIdx.x & 15, ml = threadIdx.x >> 4;
   const int ntile = min(16, n_sc - i0);
-  for (int e = threadIdx.x; e < ntile * K * D; e += 256) {
-    const int t = e / (K * D), r = e - t * (K * D);
-    const int u = r / D, s = r - u * D;
-    sv[t * VP + u * 16 + s] = Vw[((int64_t)f * n_sc + i0 + t) * K * D + r];
+  for (int e = threadIdx.x; e < 16 * KP * DP; e += 256) {
+    const int t = e / (KP * DP), r = e - t * (KP * DP);
+    const int u = r / DP, s2 = r - u * DP;
+    sv[t * VP + r] = (t < ntile && u < K && s2 < D) ? Vw[((int64_t)f * n_sc + i0 + t) * K * D + u * D + s2]
+                                                     : make_float2(0.f, 0.f);
   }
-  for (int e = threadIdx.x; e < ntile * K * K; e += 256) {
-    const int t = e / (K * K), r = e - t * (K * K);
-    const int a = r / K, b = r - a * K;
-    sc[t * CP + a * KP + b] = Cw[((int64_t)f * n_sc + i0 + t) * K * K + r];
+  for (int e = threadIdx.x; e < 16 * KP * KP; e += 256) {
+    const int t = e / (KP * KP), r = e - t * (KP * KP);
+    const int a = r / KP, b = r - a * KP;
+    sc[t * CP + r] = (t < ntile && a < K && b < K) ? Cw[((int64_t)f * n_sc + i0 + t) * K * K + a * K + b]
+                                                    : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const int i = i0 + il;
   if (i >= n_sc || m0 + ml >= M) return;
   const bool two = m0 + ml + 16 < M;
-  float2 h[2][KP], y[2][16];
+  float2 h[2][KP], y[2][DP];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int m = m0 + ml + 16 * a;
@@ -324,49 +331,47 @@ detect_adjoint_apply_kernel(const float2* __restrict__ H, const float2* __restri
     for (int u = 0; u < KP; ++u)
       h[a][u] = (in && u < K) ? H[((int64_t)(f * M + m) * K + u) * n_sc + i] : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-      y[a][s] = (in && s < D) ? Yf[((int64_t)(f * M + m) * S + 1 + s) * n_sc + i] : make_float2(0.f, 0.f);
+    for (int s2 = 0; s2 < DP; ++s2)
+      y[a][s2] = (in && s2 < D) ? Yf[((int64_t)(f * M + m) * S + 1 + s2) * n_sc + i] : make_float2(0.f, 0.f);
   }
   const float2* V = sv + il * VP;
   const float2* C = sc + il * CP;
+  float2* gy0 = gyf + ((int64_t)(f * M + m0 + ml) * S + 1) * n_sc + i;
+  float2* gy1 = gy0 + (int64_t)16 * S * n_sc;
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    if (s < D) {
-      float2 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
+  for (int s2 = 0; s2 < DP; ++s2) {
+    float2 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
 #pragma unroll
-      for (int u = 0; u < KP; ++u) {
-        if (u < K) {
-          const float2 nv = make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y);
-          acc0 = cms(acc0, h[0][u], nv);
-          acc1 = cms(acc1, h[1][u], nv);
-        }
-      }
-      gyf[((int64_t)(f * M + m0 + ml) * S + 1 + s) * n_sc + i] = acc0;
-      if (two) gyf[((int64_t)(f * M + m0 + ml + 16) * S + 1 + s) * n_sc + i] = acc1;
+    for (int u = 0; u < KP; ++u) {
+      const float2 nv = make_float2(-V[u * DP + s2].x, -V[u * DP + s2].y);
+      acc0 = cms(acc0, h[0][u], nv);
+      acc1 = cms(acc1, h[1][u], nv);
+    }
+    if (s2 < D) {
+      gy0[(int64_t)s2 * n_sc] = acc0;
+      if (two) gy1[(int64_t)s2 * n_sc] = acc1;
     }
   }
+  float2* gh0 = gh + ((int64_t)(f * M + m0 + ml) * K) * n_sc + i;
+  float2* gh1 = gh0 + (int64_t)16 * K * n_sc;
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
+    float2 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
+#pragma unroll
+    for (int s2 = 0; s2 < DP; ++s2) {
+      const float2 nv = make_float2(-V[u * DP + s2].x, -V[u * DP + s2].y);
+      acc0 = cms_bc(acc0, y[0][s2], nv);                                    // + y conj(V)
+      acc1 = cms_bc(acc1, y[1][s2], nv);
+    }
+#pragma unroll
+    for (int v2 = 0; v2 < KP; ++v2) {
+      const float2 c = C[v2 * KP + u];
+      acc0 = cms(acc0, h[0][v2], c);                                        // - H C
+      acc1 = cms(acc1, h[1][v2], c);
+    }
     if (u < K) {
-      float2 acc0 = make_float2(0.f, 0.f), acc1 = acc0;
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        if (s < D) {
-          const float2 nv = make_float2(-V[u * 16 + s].x, -V[u * 16 + s].y);
-          acc0 = cms_bc(acc0, y[0][s], nv);                                 // + y conj(V)
-          acc1 = cms_bc(acc1, y[1][s], nv);
-        }
-      }
-#pragma unroll
-      for (int v2 = 0; v2 < KP; ++v2) {
-        if (v2 < K) {
-          const float2 c = C[v2 * KP + u];
-          acc0 = cms(acc0, h[0][v2], c);                                    // - H C
-          acc1 = cms(acc1, h[1][v2], c);
-        }
-      }
-      gh[((int64_t)(f * M + m0 + ml) * K + u) * n_sc + i] = acc0;
-      if (two) gh[((int64_t)(f * M + m0 + ml + 16) * K + u) * n_sc + i] = acc1;
+      gh0[(int64_t)u * n_sc] = acc0;
+      if (two) gh1[(int64_t)u * n_sc] = acc1;
     }
   }
 }
@@ -560,8 +565,12 @@ rxphy_status rxphy_backward(const rxphy_frame* frame, int32_t n_frames, const vo
   hipLaunchKernelGGL(detect_adjoint_c_kernel, dim3(gc), dim3(256), 0, stream, Xw, Vw, Aw, Ew, Cw,   \
                      n_sub, fr.K, D);                                                              \
   if ((st = launch_status("detect adjoint c kernel"))) return st;                                   \
-  hipLaunchKernelGGL(detect_adjoint_apply_kernel<KP>, g2, dim3(256), 0, stream, h, yf, Vw, Cw, gyf, \
-                     gh, fr.M, fr.K, fr.n_sym, fr.n_sc);
+  if (D == 13)                                                                                      \
+    hipLaunchKernelGGL((detect_adjoint_apply_kernel<KP, 13>), g2, dim3(256), 0, stream, h, yf, Vw, Cw, \
+                       gyf, gh, fr.M, fr.K, fr.n_sym, fr.n_sc);                                       \
+  else                                                                                              \
+    hipLaunchKernelGGL((detect_adjoint_apply_kernel<KP, 16>), g2, dim3(256), 0, stream, h, yf, Vw, Cw, \
+                       gyf, gh, fr.M, fr.K, fr.n_sym, fr.n_sc);
   if (fr.K <= 4) { RXPHY_ADJ(4) } else if (fr.K <= 8) { RXPHY_ADJ(8) } else { RXPHY_ADJ(16) }
 #undef RXPHY_ADJ
   if ((st = launch_status("detect adjoint apply kernel"))) return st;
