@@ -724,7 +724,7 @@ def run_batched(rx, torch, args):
         lay.view(bufs, "pilots", f).copy_(torch.from_numpy(p))
     del lay
     pick = tuner.tune_plan(frames, bufs)
-    variants = (("tuned", dict(tiles=tuner.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"],
+    variants = (("tuned", dict(tiles=pick["tiles"], grid=pick["grid"], fuse_csi=pick["fuse_csi"],
                                fuse_demod=pick["fuse_demod"])),
                 ("fused_default_tiles", dict(fuse_csi=True, fuse_demod=True)),
                 ("default", dict()))
@@ -811,7 +811,7 @@ def run_batched(rx, torch, args):
     out = dict(res["tuned"])
     out.update({"frames": len(frames), "detections_per_step": dets,
                 "default": res["default"], "fused_default_tiles": res["fused_default_tiles"],
-                "plan_knobs": pick, "per_frame_calls": res["per_frame_calls"],
+                "plan_knobs": {k: v for k, v in pick.items() if k != "tiles"}, "per_frame_calls": res["per_frame_calls"],
                 "stages_alone": stage_ms,
                 "autotune": tinfo, "gen_seconds": round(gen_s, 1),
                 "workload": "256 uneven frames: M in {8,16,32,64}, K in 1..min(16,M), "

@@ -17,8 +17,9 @@ demap their tiles, and the CSI and demod stages have no items).
 
 tune_plan then chooses the plan-wide knobs on the actual frames and buffers:
 the dataflow (CSI, demod, both or neither fused into the detector items) and
-the grid of the persistent launch (one, two or three workgroups per CU),
-timing each combination with the tuned item sizes.
+the grid of the persistent launch (one, two or three workgroups per CU)
+and the item sizes (the tuned ones or the defaults), timing each
+combination.
 
 Every candidate gives bit-identical results for every output but H and
 x_tilde (not written by the fused dataflows; the K padding is never
@@ -155,19 +156,23 @@ class Tuner:
     def tune_plan(self, frames, bufs, reps: int = 5) -> dict:
         """Plan-wide knobs on the given frames and packed buffers (x and the
         pilots filled; allocated by a staged plan, so that H and x_tilde have
-        room): the dataflow (CSI and / or demod fused into the detector items)
-        and the grid (1, 2 or 3 workgroups per CU), with the cached item sizes.
-        Returns the winner and every candidate's median time (us)."""
+        room): the dataflow (CSI and / or demod fused into the detector items),
+        the grid (1, 2 or 3 workgroups per CU) and the item sizes (the cached
+        per-class ones or the defaults: a class tuned alone on a plan of its
+        own can lose inside the mixed plan).  Returns the winner (tiles None
+        for the defaults) and every candidate's median time (us)."""
         tiles = self.tiles_for(frames)
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         res = {}
-        for fc, fd in ((True, True), (True, False), (False, True), (False, False)):
-            for per_cu in (1, 2, 3):
-                p = Plan(frames, tiles=tiles, grid=per_cu * cus, fuse_csi=fc, fuse_demod=fd)
-                res[(fc, fd, per_cu)] = self._time(p, bufs, reps)
-                del p
+        for ts, tl in (("tuned", tiles), ("default", None)):
+            for fc, fd in ((True, True), (True, False), (False, True), (False, False)):
+                for per_cu in (1, 2, 3):
+                    p = Plan(frames, tiles=tl, grid=per_cu * cus, fuse_csi=fc, fuse_demod=fd)
+                    res[(fc, fd, per_cu, ts)] = self._time(p, bufs, reps)
+                    del p
         best = min(res, key=lambda k: res[k])
         name = {(True, True): "csi+demod fused", (True, False): "csi fused", (False, True): "demod fused",
                 (False, False): "staged"}
-        return {"fuse_csi": best[0], "fuse_demod": best[1], "grid": best[2] * cus,
-                "candidates_us": {"%s,%d/CU" % (name[k[:2]], k[2]): round(v, 1) for k, v in res.items()}}
+        return {"fuse_csi": best[0], "fuse_demod": best[1], "grid": best[2] * cus, "item_sizes": best[3],
+                "tiles": tiles if best[3] == "tuned" else None,
+                "candidates_us": {"%s,%d/CU,%s" % (name[k[:2]], k[2], k[3]): round(v, 1) for k, v in res.items()}}

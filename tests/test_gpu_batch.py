@@ -311,7 +311,8 @@ def test_autotuned_tiles_keep_results_bitwise(rx, batch, refs, tmp_path):
     bufs = pack(rx, rx.Plan(frames), inputs)              # with an H buffer: staged candidates run too
     pick = t2.tune_plan(frames, bufs, reps=2)
     say("plan knobs", pick)
-    plan = rx.Plan(frames, tiles=t2.tiles_for(frames), grid=pick["grid"], fuse_csi=pick["fuse_csi"],
+    assert pick["item_sizes"] in ("tuned", "default") and len(pick["candidates_us"]) == 24
+    plan = rx.Plan(frames, tiles=pick["tiles"], grid=pick["grid"], fuse_csi=pick["fuse_csi"],
                    fuse_demod=pick["fuse_demod"])
     bufs = pack(rx, plan, inputs)
     plan.forward(bufs)
