@@ -34,6 +34,11 @@ BWD_CASES = [
     (16, 16, 512, 64, 0, 4, O.ZF, (25, 25)),
     (64, 16, 2048, 1200, 0, 4, O.MMSE, (10, 30)),
     (64, 8, 1024, 601, 0, 2, O.ZF, (10, 20)),
+    # the CSI adjoint's butterfly forms: one user, and pilot groups that leave
+    # a tail past G K (K = 4: 203 = 50 x 4 + 3; K = 16: 70 = 4 x 16 + 6)
+    (8, 1, 512, 131, 0, 2, O.ZF, (20, 20)),
+    (16, 4, 512, 203, 0, 4, O.MMSE, (15, 20)),
+    (32, 16, 512, 70, 0, 2, O.ZF, (25, 25)),
 ]
 
 
