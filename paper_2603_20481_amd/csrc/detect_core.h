@@ -314,8 +314,10 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
   const int u = l & 15, kq = l >> 4;
   const int rb = tid >> 4;
   // chunk 0 may already be in hv/yv (prefetched by the previous tile); the
-  // next chunk is loaded while the current one feeds the MFMAs, and after
-  // the last chunk the first chunk of tile i0n (if >= 0) is prefetched
+  // next chunk is loaded while the current one feeds the MFMAs (its loads
+  // issued as soon as this wave has staged the current one, before the
+  // barrier), and after the last chunk the first chunk of tile i0n (if >= 0)
+  // is prefetched
   float probe = 0.f;
   if (!have0) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, 0, hv, yv, pv);
   for (int m0 = 0; m0 < M; m0 += MC) {
@@ -330,10 +332,10 @@ __device__ __forceinline__ void gram_mf(const float2* __restrict__ Hf, const flo
       Hs[r * PITCH + c16] = h;
       Ys[r * PITCH + c16] = yv[it];
     }
-    __syncthreads();
     if (m0 + MC < M) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, m0 + MC, hv, yv, pv);
     else if (i0n >= 0)
       load_chunk<FU>(Hn ? Hn : Hf, Yn ? Yn : Yff, pn ? pn : pil, M, K, S, n_sc, i0n, 0, hv, yv, pv);
+    __syncthreads();
     if constexpr (P == P_FP32) {
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
@@ -480,8 +482,8 @@ __device__ __forceinline__ void gram_mf_shared(const float2* __restrict__ Hf, co
       Hs[r * PITCH + c16] = h;
       Ys[r * PITCH + c16] = yv[it];
     }
-    __syncthreads();
     if (m0 + MC < M) load_chunk<FU>(Hf, Yff, pil, M, K, S, n_sc, i0, m0 + MC, hv, yv, pv);
+    __syncthreads();
     const bool gram_here = ((m0 / MC) & 3) == w;
     if constexpr (P == P_FP32) {
 #pragma unroll
