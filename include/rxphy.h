@@ -206,7 +206,8 @@ rxphy_status rxphy_csi_detect_demod_noalloc(const rxphy_frame* frame, int32_t n_
  * in-phase level, b1, b3, b5 the quadrature level):
  *   llr_j = (min_{c: b_j = 1} |xt - c|^2 - min_{c: b_j = 0} |xt - c|^2) / nu,
  * i.e. ln P(b_j = 0) / P(b_j = 1) under max-log; an erased stream (nu = +inf)
- * gives 0, and a non-finite xt (nu finite) a non-finite LLR.  Each minimum is
+ * gives 0, and a non-finite coordinate of xt (nu finite) non-finite LLRs for
+ * the bits of that axis.  Each minimum is
  * found in closed form per axis (the nearest level of the bit's set), so a
  * large |xt| keeps its large, finite LLR.
  *   xt  : c64 [F][K][n_sym-1][n_sc]
