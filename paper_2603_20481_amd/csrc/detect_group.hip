@@ -5,30 +5,32 @@
 // With 16 users a pilot group spans exactly one 16-subcarrier tile, and the
 // LS estimate is held over the group, so every subcarrier of a tile sees the
 // same channel matrix H (64 x 16).  Per tile the work is
-//   G = H^H H (+ N0 I) once, its Cholesky factor once, and
-//   Z = H^H Y for 16 subcarriers x D data symbols, then L L^H X = Z.
+//   G = H^H H (+ N0 I) once, its Cholesky factor and A^-1 once, and
+//   Z = H^H Y for 16 subcarriers x D data symbols, then X = A^-1 Z.
 // Two kernels, so that the short serial factorisation never holds up the
 // streaming part:
 //
 //  group_factor_kernel  two tiles per wavefront: loads each tile's
 //    pilot-symbol row and pilots, forms H (LS), the Gram matrix on MFMA, and
-//    factors A = G (+ N0 I) (Cholesky-Crout with L^-1, one tile per 16-lane
-//    row); writes L, 1 / L_kk, d_k = [A^-1]_kk and flags into a 2.25 KiB
-//    record per tile.  Many independent wavefronts per SIMD hide each one's
-//    serial latency.
+//    factors A = G (+ N0 I) (Cholesky-Crout with V = L^-1, one tile per
+//    16-lane row), then A^-1 = V^H V on MFMA; writes A^-1, d_k = [A^-1]_kk
+//    and flags into a 2.25 KiB record per tile.  Many independent
+//    wavefronts per SIMD hide each one's serial latency.
 //  detect_group_kernel  one workgroup per tile: the data operands are loaded
 //    straight from HBM into the lanes that use them (lane (kq, u) of
 //    v_mfma_f32_16x16x4_f32: B = Y[4s + kq][1 + d][i0 + u], 16 lanes per
 //    128-byte row segment), all of a wave's loads issued at once, no LDS
 //    staging.  Wave w owns data symbols d = w, w + 4, w + 8, w + 12 and runs
 //    all 64 antennas for them (16 steps of 4 antennas); H is formed again
-//    (LS) into LDS as the A operand.  Each wave transposes its own Z through
-//    a wave-private LDS slab and solves its own right-hand sides (lane =
-//    (symbol, subcarrier)) with the record's factor.
+//    (LS) into LDS as the A operand.  X = A^-1 Z is formed from the same
+//    accumulator lanes with the record's A^-1 rows on MFMA (no transposition
+//    and no substitution chain), then unbiased, stored and (Q > 0) demapped.
 //
-// Every product, sum and factorisation step is the one the general detector
-// (detect_core.h, shared-factor path) performs on the same values in the
-// same order, so the results are bit-identical to rxphy_csi + rxphy_detect.
+// The Gram products, the factorisation, d_k, nu and the flags are the steps
+// the general detector (detect_core.h, shared-factor path) performs on the
+// same values in the same order, so they are bit-identical to rxphy_csi +
+// rxphy_detect; x_tilde comes from the explicit inverse instead of the two
+// triangular solves and agrees with it to rounding.
 #include <type_traits>
 
 #include "demod_core.h"
