@@ -42,10 +42,25 @@ BWD_CASES = [
 ]
 
 
+# slots of other lengths than 14 symbols (the apply kernel's generic symbol
+# bound): 8 symbols (D = 7) and the longest, 17 (D = 16)
+BWD_SLOT_CASES = [
+    # M, K, N, n_sc, n_sym, cp, Q, detector, snr
+    (16, 4, 512, 150, 8, 0, 4, O.MMSE, (15, 20)),
+    (32, 16, 512, 96, 17, 0, 2, O.ZF, (25, 25)),
+    (8, 3, 512, 100, 5, 4, 2, O.ZF, (20, 20)),
+]
+
+
+@pytest.mark.parametrize("M,K,N,n_sc,n_sym,cp,Q,det,snr", BWD_SLOT_CASES)
+def test_backward_other_slot_lengths(rx, M, K, N, n_sc, n_sym, cp, Q, det, snr):
+    test_backward_matches_oracle_adjoint(rx, M, K, N, n_sc, cp, Q, det, snr, n_sym=n_sym)
+
+
 @pytest.mark.parametrize("M,K,N,n_sc,cp,Q,det,snr", BWD_CASES)
-def test_backward_matches_oracle_adjoint(rx, M, K, N, n_sc, cp, Q, det, snr):
-    say("backward", M, K, N, n_sc, cp, Q, det)
-    sh = synth.Shape(M, K, N, n_sc, 14, cp, Q)
+def test_backward_matches_oracle_adjoint(rx, M, K, N, n_sc, cp, Q, det, snr, n_sym=14):
+    say("backward", M, K, N, n_sc, n_sym, cp, Q, det)
+    sh = synth.Shape(M, K, N, n_sc, n_sym, cp, Q)
     fo = synth.make_frame(21, 0, shape=sh, snr=snr)
     rng = np.random.default_rng(M * 1000 + n_sc)
     dllr = rng.standard_normal((1, K, sh.n_data, n_sc, Q)).astype(np.float32)
