@@ -43,12 +43,13 @@ BWD_CASES = [
 
 
 # slots of other lengths than 14 symbols (the apply kernel's generic symbol
-# bound): 8 symbols (D = 7) and the longest, 17 (D = 16)
+# bound, with 4, 8 and 16 padded users): 5, 8, 11 and the longest, 17 symbols
 BWD_SLOT_CASES = [
     # M, K, N, n_sc, n_sym, cp, Q, detector, snr
     (16, 4, 512, 150, 8, 0, 4, O.MMSE, (15, 20)),
     (32, 16, 512, 96, 17, 0, 2, O.ZF, (25, 25)),
     (8, 3, 512, 100, 5, 4, 2, O.ZF, (20, 20)),
+    (12, 6, 512, 90, 11, 0, 4, O.MMSE, (15, 25)),
 ]
 
 

@@ -255,6 +255,33 @@ def test_demod_midpoints_and_large_values(rx, q):
         assert np.all(l2[:, 2:] < 0)
 
 
+@pytest.mark.parametrize("q", [2, 4, 6])
+def test_demod_non_finite_coordinates(rx, q):
+    """A non-finite coordinate of x_tilde with a finite nu gives non-finite LLRs
+    for the bits of that axis only (the other axis' bits equal those of the
+    same point with that coordinate finite); an erased stream (nu = inf)
+    gives zeros whatever x_tilde holds."""
+    vals = np.array([np.nan, np.inf, -np.inf], dtype=np.float32)
+    fin = np.float32(0.3)
+    xt = np.empty(9, dtype=np.complex64)                 # parts set one by one (1j * inf is nan + inf j)
+    xt.real = np.concatenate([vals, np.full(3, fin), vals])
+    xt.imag = np.concatenate([np.full(3, fin), vals, vals])
+    ref_pt = np.full(xt.shape, fin + 1j * fin, dtype=np.complex64)
+    n = xt.size
+    nu = np.full((1, 1, 2 * n), 0.5, dtype=np.float32)
+    nu[0, 0, -1] = np.inf
+    x_all = np.concatenate([xt, ref_pt]).reshape(1, 1, 1, 2 * n)
+    x_all[0, 0, 0, -1] = np.complex64(np.nan + 1j * np.nan)        # erased stream with a NaN point
+    fr = rx.Frame(8, 1, 512, 2 * n, 2, 0, q)
+    llr = host(rx.demod(fr, dev(x_all), dev(nu)))[0, 0, 0]        # [2n, q]
+    bad, good = llr[:n], llr[n:]
+    re_bits, im_bits = np.arange(0, q, 2), np.arange(1, q, 2)
+    assert np.all(~np.isfinite(bad[:3][:, re_bits])) and np.array_equal(bad[:3][:, im_bits], good[:3][:, im_bits])
+    assert np.all(~np.isfinite(bad[3:6][:, im_bits])) and np.array_equal(bad[3:6][:, re_bits], good[3:6][:, re_bits])
+    assert np.all(~np.isfinite(bad[6:9]))
+    assert np.all(llr[-1] == 0)
+
+
 # ------------------------------------------------------------------ full chain
 CHAIN_CASES = [(1, O.ZF, 1), (2, O.ZF, 2), (2, O.MMSE, 2), (3, O.ZF, 1)]
 
