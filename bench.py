@@ -900,6 +900,43 @@ def run_fwd_bwd(rx, torch, args):
 ALU_PEAK_TOPS = 256 * 64 * 2.4e-3  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: vector lane operations, 1e12/s
 
 
+def run_detect_shapes(rx, torch, args):
+    """The staged general detector alone across (M, K): per-subcarrier
+    channels (random, so no tile shares a factor), 1200 subcarriers, 13 data
+    symbols, 16-QAM, MMSE, about 1 GB of interface bytes per call.  Shows the
+    per-tile floor that sets the uneven batch's detector rate (small M K
+    tiles move few bytes through the same serial chain)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    rows = []
+    for M, K in ((8, 1), (8, 2), (8, 4), (8, 8), (16, 4), (16, 12), (32, 2), (32, 8), (64, 4), (64, 8), (64, 16)):
+        s = synth.Shape(M, K, 2048, 1200, 14, 0, 4)
+        per = stage_bytes(s)["detect"]
+        F = max(1, int(1.0e9 // per))
+        fr = rx.Frame.of(s, rx.MMSE, 1.0)
+        h = torch.randn((F, M, K, s.n_sc), dtype=torch.complex64, device="cuda", generator=g)
+        yf = torch.randn((F, M, s.n_sym, s.n_sc), dtype=torch.complex64, device="cuda", generator=g)
+        xt, nu, fl = rx.detect(fr, h, yf)
+        for _ in range(2):
+            rx.detect(fr, h, yf, xt=xt, nu=nu, flags=fl)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.form_steps):
+            rx.detect(fr, h, yf, xt=xt, nu=nu, flags=fl)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / args.form_steps * 1e3
+        tiles = F * ((s.n_sc + 15) // 16)
+        rows.append({"M": M, "K": K, "frames": F, "us": round(us, 1), "GBps": round(F * per / us / 1e3, 1),
+                     "hbm_frac": round(F * per / us / 1e3 / 8000, 3), "ns_per_tile": round(us * 1e3 / tiles, 2)})
+        del h, yf, xt, nu, fl
+    torch.cuda.empty_cache()
+    return {"shapes": rows, "unit": "interface bytes / call time",
+            "workload": "rxphy_detect, per-subcarrier random channels, 1200 subcarriers, 13 data symbols, "
+                        "MMSE, FP32, about 1 GB per call"}
+
+
 def run_ldpc(rx, torch, args):
     """Layered min-sum decoding of n_cw codewords of a 46 x 68 quasi-cyclic
     code at lifting size 384 (the shape of the largest 3GPP base graph, random
@@ -982,7 +1019,8 @@ def main():
     ap.add_argument("--ldpc-codewords", type=int, default=1024)
     ap.add_argument("--ldpc-snr", type=float, default=2.5)
     ap.add_argument("--ldpc-iters", type=int, default=10)
-    ap.add_argument("--forms", default="staged,mmse,sc16,streaming,downlink,mixed,batched,fwd_bwd,ldpc,sensing",
+    ap.add_argument("--forms", default="staged,mmse,sc16,streaming,downlink,mixed,batched,detect_shapes,fwd_bwd,ldpc,"
+                    "sensing",
                     help="comma list of extra forms to time ('' for the headline only)")
     ap.add_argument("--sense-plots", type=int, default=64)
     ap.add_argument("--sense-latency-calls", type=int, default=200)
@@ -1141,6 +1179,9 @@ def main():
     if "fwd_bwd" in forms:
         out["forms"]["fwd_bwd_fp32"] = run_fwd_bwd(rx, torch, args)
         print("[bench] fwd+bwd done", file=sys.stderr, flush=True)
+    if "detect_shapes" in forms:
+        out["forms"]["detect_shapes_fp32"] = run_detect_shapes(rx, torch, args)
+        print("[bench] detect shapes done", file=sys.stderr, flush=True)
     if "ldpc" in forms:
         out["forms"]["ldpc_decode_fp32"] = run_ldpc(rx, torch, args)
         print("[bench] ldpc done", file=sys.stderr, flush=True)
